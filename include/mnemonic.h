@@ -1,0 +1,197 @@
+/*
+ * mnemonic.h -- C ABI of the MI355X (gfx950) streaming subgraph matcher.
+ *
+ * The library keeps a labelled, directed multigraph and a set of query graphs
+ * resident in HBM and, for every snapshot of edge insertions and deletions,
+ * reports exactly the embeddings that the snapshot creates or removes
+ * (paper, Section II-B, problem definition: S(G + dG) = S(G) + dS). A snapshot
+ * is processed as in Algorithm 1: insertions first, then deletions.
+ *
+ * Plain C: no C++ or torch types cross this boundary. Every function returns
+ * MNEMONIC_OK (0) or a negative MNEMONIC_E_* code and never throws. A context
+ * is single-threaded: calls on one context must not overlap. Separate
+ * contexts may run concurrently on separate HIP streams.
+ *
+ * Embedding definition (Section II-B): a vertex map f and an edge-instance map
+ * g (parallel data edges are distinct instances, Section I). A query vertex's
+ * required label set must be a subset of its image's label set (a required set
+ * of 0 is a wildcard); a query edge label must equal the data edge label or be
+ * -1 (any label). Isomorphism requires f injective; homomorphism drops that
+ * check, so one data edge may serve several query edges (Section III).
+ * Each embedding is reported as the tuple of the keys of g(q_0) .. g(q_{m-1})
+ * in query-edge index order. Embeddings of the initial graph are not reported.
+ */
+#ifndef MNEMONIC_H
+#define MNEMONIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define MNEMONIC_OK 0
+#define MNEMONIC_E_ARG -1        /* NULL pointer, zero-sized required array, bad flag */
+#define MNEMONIC_E_QUERY -2      /* query outside the supported shape (see mnemonic_query) */
+#define MNEMONIC_E_VERTEX -3     /* an edge endpoint >= n_vertices */
+#define MNEMONIC_E_LABEL -4      /* an edge label >= n_elabels */
+#define MNEMONIC_E_TS_ORDER -5   /* a timestamp smaller than the one before it */
+#define MNEMONIC_E_BAD_DELETE -6 /* deletion key not live, unknown or repeated */
+#define MNEMONIC_E_OOM -7        /* device allocation failed */
+#define MNEMONIC_E_CAPACITY -8   /* caller buffer too small (mnemonic_copy_keys) */
+#define MNEMONIC_E_HIP -9        /* a HIP runtime call failed; see mnemonic_last_error */
+#define MNEMONIC_E_LIMIT -10     /* graph larger than the packed adjacency format allows */
+
+typedef struct mnemonic_ctx mnemonic_ctx; /* opaque; owns every device buffer it uses */
+
+typedef enum { MNEMONIC_ISO = 0, MNEMONIC_HOMO = 1 } mnemonic_semantics;
+
+/* Data graph at creation (the input G of Algorithm 1). Host pointers. Initial
+ * edge i gets key i. Vertex labels are 64-bit sets (one bit per label).
+ * Limits: n_vertices <= 2^24 (neighbour ids and labels share 32 bits of an
+ * adjacency entry), labels < n_elabels <= 256 (0 means 256), fewer than 2^31
+ * live edges, timestamps non-decreasing in key order. */
+typedef struct {
+    uint32_t n_vertices;
+    uint32_t n_elabels;
+    const uint64_t *vlabel_mask; /* [n_vertices] */
+    uint64_t n_edges;
+    const uint32_t *src;         /* [n_edges] */
+    const uint32_t *dst;         /* [n_edges] */
+    const uint8_t *elabel;       /* [n_edges] */
+    const int64_t *ts;           /* [n_edges] */
+} mnemonic_graph;
+
+/* One query graph G_Q (Section II-A). Host pointers, copied at creation.
+ * Supported shape: 2..16 vertices, 1..32 edges, weakly connected, no
+ * self-loop, at most one edge per ordered vertex pair. Anything else returns
+ * MNEMONIC_E_QUERY. */
+typedef struct {
+    uint32_t n_qv;
+    const uint64_t *qv_require; /* [n_qv] required label set; 0 = any vertex */
+    uint32_t n_qe;
+    const uint32_t *qsrc;       /* [n_qe] */
+    const uint32_t *qdst;       /* [n_qe] */
+    const int32_t *qelabel;     /* [n_qe] label, or -1 for any label */
+    mnemonic_semantics sem;
+} mnemonic_query;
+
+/* A batch of insertions. Inserted edges get consecutive keys in array order.
+ * When on_device is non-zero, src/dst/elabel/ts and the deletion keys passed
+ * alongside are device pointers on the context's device (read in place);
+ * otherwise they are host pointers, copied before the call returns. */
+typedef struct {
+    uint64_t n;
+    const uint32_t *src;
+    const uint32_t *dst;
+    const uint8_t *elabel;
+    const int64_t *ts;
+    uint32_t on_device;
+} mnemonic_edges;
+
+#define MNEMONIC_F_EMIT 1u   /* write the embedding tuples (else counts and digests only) */
+#define MNEMONIC_F_TIMING 2u /* record HIP events around the enumeration kernels */
+
+typedef struct {
+    uint32_t flags;        /* MNEMONIC_F_* */
+    uint64_t out_capacity; /* initial tuples per (query, new/expired) buffer; 0 = 2^20 */
+} mnemonic_options;
+
+/* Result of the last successful mnemonic_apply_batch for one query.
+ * dig_* are order-independent 64-bit multiset digests of the tuples: with
+ * mix the SplitMix64 finaliser (Steele, Lea, Flood 2014), seeds
+ * A = 0x243F6A8885A308D3 and B = 0x13198A2E03707344 and q the query index,
+ * h_s(t) = mix(...mix(mix(s ^ q) + k_0)... + k_{m-1}) and dig[s] = sum of h_s
+ * over the tuples, modulo 2^64. new_keys / expired_keys are device pointers to
+ * n x n_qe row-major uint64 tuples in no particular order, valid until the
+ * next mnemonic_apply_batch or mnemonic_destroy; NULL without
+ * MNEMONIC_F_EMIT. */
+typedef struct {
+    uint64_t n_new, n_expired;
+    uint64_t dig_new[2], dig_expired[2];
+    const uint64_t *new_keys;
+    const uint64_t *expired_keys;
+    uint32_t n_qe;
+} mnemonic_result;
+
+/* Work and timing of the last successful batch. Per phase p (0 insert,
+ * 1 delete): enumeration work units (seeds), adjacency entries scanned,
+ * adjacency words read by binary searches, edge keys gathered, tuples
+ * emitted, and (with MNEMONIC_F_TIMING) the enumeration kernel time. */
+typedef struct {
+    uint64_t n_live_edges;
+    uint64_t slot_high_water;
+    uint64_t seeds[2];
+    uint64_t entries_scanned[2];
+    uint64_t probe_words[2];
+    uint64_t key_reads[2];
+    uint64_t tuples[2];
+    uint64_t tuple_words[2];
+    double ms_enumerate[2];
+    double ms_batch;
+} mnemonic_stats;
+
+/*
+ * InitializeIndex (Algorithm 1; Section III, preprocessing): uploads the data
+ * graph, builds the sorted out/in adjacency, evaluates edgeMatcher for every
+ * edge and every query edge, and the per-vertex local filters. Queries are
+ * preprocessed into one static matching order per start edge (Section VI).
+ * The initial embeddings are not enumerated.
+ *   g, q (n_q >= 1 entries), opt: host structures, read during the call only;
+ *     opt may be NULL (defaults: emit on, no timing).
+ *   hip_stream: the hipStream_t every kernel and copy of this context runs on
+ *     (NULL = the default stream). The current HIP device at creation is used.
+ *   out: receives the context; unchanged on failure.
+ * Errors: ARG, QUERY, VERTEX, LABEL, TS_ORDER, LIMIT, OOM, HIP.
+ */
+int mnemonic_create(const mnemonic_graph *g, const mnemonic_query *q, uint32_t n_q,
+                    const mnemonic_options *opt, void *hip_stream, mnemonic_ctx **out);
+
+/*
+ * One snapshot (Algorithm 1 loop body; Algorithm 2): batchInserts then
+ * batchDeletes.
+ *   ins: insertions (ins->n may be 0; ins may be NULL when there are none).
+ *   del_keys / n_del: keys to delete. A key may name an edge inserted earlier
+ *     in this same call. Host or device memory as ins->on_device says (host
+ *     when ins is NULL).
+ *   first_new_key: if not NULL, receives the key of the first inserted edge.
+ * New embeddings are those using >= 1 inserted edge; expired embeddings are
+ * those of the post-insert graph using >= 1 deleted edge (so an embedding
+ * created and removed within one snapshot appears in both lists).
+ * Validation (endpoint range, label range, timestamps non-decreasing across
+ * batches, deletion keys live and distinct) runs on the device before any
+ * state changes: a failed batch returns its error and changes nothing.
+ * Blocks until the batch's counts and digests are on the host.
+ * Errors: ARG, VERTEX, LABEL, TS_ORDER, BAD_DELETE, OOM, HIP.
+ */
+int mnemonic_apply_batch(mnemonic_ctx *ctx, const mnemonic_edges *ins, const uint64_t *del_keys,
+                         uint64_t n_del, uint64_t *first_new_key);
+
+/* Counts, digests and device tuple pointers of the last batch for one query
+ * (index in creation order). Errors: ARG (bad ctx, query or out). */
+int mnemonic_get_result(mnemonic_ctx *ctx, uint32_t query, mnemonic_result *out);
+
+/* Copies the new (expired != 0: expired) tuples of one query to host_buf,
+ * capacity counted in tuples. *needed (if not NULL) receives the tuple count.
+ * Returns MNEMONIC_E_CAPACITY, copying nothing, when capacity is too small;
+ * MNEMONIC_E_ARG without MNEMONIC_F_EMIT. */
+int mnemonic_copy_keys(mnemonic_ctx *ctx, uint32_t query, int expired, uint64_t *host_buf,
+                       uint64_t capacity, uint64_t *needed);
+
+/* Work and timing figures of the last batch. Errors: ARG. */
+int mnemonic_get_stats(mnemonic_ctx *ctx, mnemonic_stats *out);
+
+/* Text of the last error on this context ("" if none). The pointer stays
+ * valid until the next call on the context. A NULL ctx gives the last error of
+ * a failed mnemonic_create on this thread. */
+const char *mnemonic_last_error(const mnemonic_ctx *ctx);
+
+/* Frees every device and host buffer of the context. NULL is ignored. */
+void mnemonic_destroy(mnemonic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MNEMONIC_H */

@@ -1,0 +1,1076 @@
+// C ABI of the matcher: context state, query preprocessing and the per-snapshot
+// kernel sequence (Algorithm 1 loop body = Algorithm 2 batchInserts followed by
+// batchDeletes). All device work runs on the context's stream; one host
+// synchronisation per snapshot returns the counts and digests.
+//
+// Snapshot t on the device:
+//   validate(I_t, D_t)                     nothing below runs if it fails
+//   counters -= edges of D_{t-1}           (removal deferred from snapshot t-1)
+//   ingest I_t: slots, attributes, DEBI words, counters += edges of I_t
+//   sort I_t entries (out, in) and D_{t-1} positions
+//   merge: adjacency' = adjacency - D_{t-1} + I_t (I_t entries flagged)
+//   VF refresh for endpoints of D_{t-1} and I_t
+//   seeds(I_t) -> enumerate new embeddings on G + I_t
+//   unflag I_t, flag D_t; seeds(D_t) -> enumerate expired embeddings on G + I_t
+//   retire D_t keys, push D_t slots on the free stack
+// D_t's entries stay (flagged) in the adjacency until the next merge, and the
+// counters/VF keep counting them until then: the filters stay sound (a
+// superset), and an enumeration can be re-run on exactly the same state when
+// an output buffer was too small.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mnemonic.h"
+#include "mn_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) throw HipError{e_, #x}; \
+    } while (0)
+
+struct ApiError {
+    int code;
+    std::string msg;
+};
+
+inline uint32_t ceil_log2(uint64_t x) {
+    uint32_t b = 0;
+    while ((1ull << b) < x) b++;
+    return b;
+}
+
+template <typename T>
+void dev_alloc(T*& p, size_t n) {
+    void* q = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw ApiError{MNEMONIC_E_OOM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+    }
+    p = static_cast<T*>(q);
+}
+
+template <typename T>
+void dev_free(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// Grows a device array to hold `need` elements, keeping the first `keep`.
+template <typename T>
+void dev_grow(T*& p, uint64_t& cap, uint64_t need, uint64_t keep, hipStream_t s) {
+    if (need <= cap && p) return;
+    uint64_t nc = std::max<uint64_t>(need, cap + cap / 2);
+    nc = std::max<uint64_t>(nc, 256);
+    T* np = nullptr;
+    dev_alloc(np, nc);
+    if (p && keep) HIPCHK(hipMemcpyAsync(np, p, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(p);
+    p = np;
+    cap = nc;
+}
+
+}  // namespace
+
+struct mnemonic_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t flags = MNEMONIC_F_EMIT;
+    uint32_t nV = 0, n_elabels = 256, nbr_bits = 1, hb = 1;
+
+    // queries and their preprocessed tables
+    uint32_t n_q = 0;
+    std::vector<QueryDev> hq;
+    std::vector<SeedPlan> hplans;
+    std::vector<DebiBit> hdebi;
+    std::vector<VfBit> hvf;
+    std::vector<VfReq> hreq;
+    int16_t elab_idx[256];
+    int16_t vlab_idx[64];
+    uint32_t n_elab_c = 0, n_vlab_c = 0, n_cnt = 2;
+    uint32_t vf_words = 1, debi_words = 1, n_vf_bits = 0, n_debi_bits = 0, total_qe = 0;
+
+    // device: static tables and per-vertex state
+    uint64_t* d_vmask = nullptr;
+    QueryDev* d_q = nullptr;
+    SeedPlan* d_plans = nullptr;
+    DebiBit* d_debi_bits = nullptr;
+    VfBit* d_vf_bits = nullptr;
+    VfReq* d_req = nullptr;
+    int16_t* d_elab_idx = nullptr;
+    int16_t* d_vlab_idx = nullptr;
+    uint32_t* d_vf = nullptr;
+    uint32_t* d_cnt = nullptr;
+    uint4* d_meta[2] = {nullptr, nullptr};
+
+    // slot arrays
+    uint64_t cap_slots = 0;
+    uint32_t* d_src = nullptr;
+    uint32_t* d_dst = nullptr;
+    uint8_t* d_lab = nullptr;
+    int64_t* d_ts = nullptr;
+    uint64_t* d_key = nullptr;
+    uint32_t* d_debi = nullptr;
+    uint32_t* d_free = nullptr;
+    uint64_t cap_debi = 0, cap_free = 0, cap_lab = 0, cap_ts = 0, cap_key = 0, cap_dst = 0;
+
+    // key arrays
+    uint64_t cap_keys = 0, cap_delbits = 0;
+    uint32_t* d_key2slot = nullptr;
+    uint32_t* d_delbits = nullptr;
+
+    // adjacency, double-buffered
+    uint64_t cap_E = 0, cap_E2 = 0, cap_E3 = 0, cap_E4 = 0;
+    uint32_t* d_off[2] = {nullptr, nullptr};
+    uint32_t* d_off2[2] = {nullptr, nullptr};
+    uint64_t* d_adj[2] = {nullptr, nullptr};
+    uint64_t* d_adj2[2] = {nullptr, nullptr};
+
+    // batch scratch
+    uint64_t cap_ins = 0, cap_del = 0, cap_seed = 0, cap_touch = 0, cap_sort = 0;
+    uint32_t* d_in_src = nullptr;
+    uint32_t* d_in_dst = nullptr;
+    uint8_t* d_in_lab = nullptr;
+    int64_t* d_in_ts = nullptr;
+    uint64_t* d_del_keys = nullptr;
+    uint32_t* d_ins_slot = nullptr;
+    uint64_t* d_skey[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    uint32_t* d_sval[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    uint32_t* d_inspos[2] = {nullptr, nullptr};
+    uint32_t* d_touched = nullptr;
+    uint32_t* d_del_slot[2] = {nullptr, nullptr};        // [buffer]
+    uint32_t* d_delpos[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buffer][dir]
+    uint64_t cap_delbuf[2] = {0, 0};
+    uint64_t* d_dkey[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [dir][ping-pong]
+    uint32_t* d_dval[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    uint32_t hb_pos = 32;  // significant bits of an adjacency position
+    uint32_t* d_sort_scratch = nullptr;
+    uint64_t cap_sort_scratch = 0;
+    uint64_t* d_seeds[2] = {nullptr, nullptr};
+
+    // control block: err, last_ts, zeroed counters
+    uint32_t* d_err = nullptr;
+    int64_t* d_last_ts = nullptr;
+    unsigned long long* d_zr = nullptr;
+    uint32_t n_zr = 0;
+    std::vector<unsigned long long> h_zr;
+
+    // outputs
+    std::vector<OutView> houts;
+    OutView* d_outs = nullptr;
+
+    // host mirrors
+    uint64_t next_key = 0, n_live = 0, E = 0, n_pending = 0;
+    uint32_t n_free = 0, fresh = 0;
+    int pend = 0;  // which delete buffer holds the pending deletions
+    bool have_result = false;
+
+    mnemonic_stats stats;
+    std::string err;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+
+    // zero-region layout
+    uint32_t zr_nseeds(int p) const { return (uint32_t)p; }
+    uint32_t zr_cursor(int p) const { return 2u + (uint32_t)p; }
+    uint32_t zr_count(int p) const { return 4u + (uint32_t)p * n_q; }
+    uint32_t zr_digest(int p) const { return 4u + 2u * n_q + 2u * (uint32_t)p * n_q; }
+    uint32_t zr_stats(int p) const { return 4u + 6u * n_q + 8u * (uint32_t)p; }
+};
+
+namespace {
+
+// ----------------------------------------------------------------- planning
+// Static matching order for start edge j (Section VI): the start edge maps
+// both its endpoints; then, repeatedly, the unmapped query vertex with the most
+// edges to mapped vertices (ties: lowest index) is mapped through one of those
+// edges (a labelled one first, then the lowest index), and its other edges to
+// mapped vertices become closing edges checked at that level.
+void build_plan(const QueryDev& Q, uint32_t j, SeedPlan& P) {
+    memset(&P, 0, sizeof(P));
+    const uint32_t nqv = Q.n_qv, nqe = Q.n_qe;
+    bool mapped[MN_MAXQV] = {false};
+    bool used[MN_MAXQE] = {false};
+    uint32_t qa = Q.qsrc[j], qb = Q.qdst[j];
+    P.qa = (uint8_t)qa;
+    P.qb = (uint8_t)qb;
+    P.mapped[0] = (uint8_t)qa;
+    P.mapped[1] = (uint8_t)qb;
+    mapped[qa] = mapped[qb] = true;
+    used[j] = true;
+    uint32_t nc = 0;
+    auto make_close = [&](uint32_t k, uint32_t newv) {
+        CloseDesc c;
+        uint32_t other = Q.qsrc[k] == newv ? Q.qdst[k] : Q.qsrc[k];
+        c.qe = (uint8_t)k;
+        c.other = (uint8_t)other;
+        c.dir = Q.qsrc[k] == other ? 0 : 1;
+        c.masked = k < j ? 1 : 0;
+        c.label = Q.qlab[k];
+        return c;
+    };
+    for (uint32_t k = 0; k < nqe; k++) {
+        if (used[k]) continue;
+        if ((Q.qsrc[k] == qa && Q.qdst[k] == qb) || (Q.qsrc[k] == qb && Q.qdst[k] == qa)) {
+            P.close[nc++] = make_close(k, qb);
+            used[k] = true;
+        }
+    }
+    P.c0_end = (uint8_t)nc;
+    uint32_t L = 0;
+    while (L + 2 < nqv) {
+        int best = -1, best_conn = -1;
+        for (uint32_t u = 0; u < nqv; u++) {
+            if (mapped[u]) continue;
+            int conn = 0;
+            for (uint32_t k = 0; k < nqe; k++)
+                if (!used[k] && ((Q.qsrc[k] == u && mapped[Q.qdst[k]]) || (Q.qdst[k] == u && mapped[Q.qsrc[k]])))
+                    conn++;
+            if (conn > best_conn) {
+                best_conn = conn;
+                best = (int)u;
+            }
+        }
+        uint32_t n = (uint32_t)best;
+        int anchor = -1;
+        for (int pass = 0; pass < 2 && anchor < 0; pass++)
+            for (uint32_t k = 0; k < nqe; k++) {
+                if (used[k]) continue;
+                bool touches = (Q.qsrc[k] == n && mapped[Q.qdst[k]]) || (Q.qdst[k] == n && mapped[Q.qsrc[k]]);
+                if (touches && (pass == 1 || Q.qlab[k] >= 0)) {
+                    anchor = (int)k;
+                    break;
+                }
+            }
+        LevelDesc& lv = P.lv[L];
+        uint32_t ak = (uint32_t)anchor;
+        uint32_t from = Q.qsrc[ak] == n ? Q.qdst[ak] : Q.qsrc[ak];
+        lv.vtx = (uint8_t)n;
+        lv.qe = (uint8_t)ak;
+        lv.from = (uint8_t)from;
+        lv.dir = Q.qsrc[ak] == from ? 0 : 1;
+        lv.label = Q.qlab[ak];
+        lv.masked = ak < j ? 1 : 0;
+        lv.n_mapped = (uint8_t)(L + 2);
+        used[ak] = true;
+        lv.c_begin = (uint8_t)nc;
+        for (uint32_t k = 0; k < nqe; k++) {
+            if (used[k]) continue;
+            if ((Q.qsrc[k] == n && mapped[Q.qdst[k]]) || (Q.qdst[k] == n && mapped[Q.qsrc[k]])) {
+                P.close[nc++] = make_close(k, n);
+                used[k] = true;
+            }
+        }
+        lv.c_end = (uint8_t)nc;
+        mapped[n] = true;
+        P.mapped[L + 2] = (uint8_t)n;
+        L++;
+    }
+    P.n_levels = (uint8_t)L;
+    for (uint32_t k = 0; k < MN_MAXQE; k++) P.last_src[k] = 0xFF;
+    if (L > 0) {
+        const LevelDesc& last = P.lv[L - 1];
+        P.last_src[last.qe] = 0xFE;
+        for (uint32_t c = last.c_begin; c < last.c_end; c++) P.last_src[P.close[c].qe] = (uint8_t)(c - last.c_begin);
+    }
+}
+
+void check_query(const mnemonic_query& q) {
+    auto bad = [](const std::string& m) { throw ApiError{MNEMONIC_E_QUERY, m}; };
+    if (q.n_qv < 2 || q.n_qv > MN_MAXQV) bad("query needs 2..16 vertices");
+    if (q.n_qe < 1 || q.n_qe > MN_MAXQE) bad("query needs 1..32 edges");
+    if (!q.qv_require || !q.qsrc || !q.qdst || !q.qelabel) bad("query arrays must not be NULL");
+    if (q.sem != MNEMONIC_ISO && q.sem != MNEMONIC_HOMO) bad("unknown semantics");
+    for (uint32_t i = 0; i < q.n_qe; i++) {
+        if (q.qsrc[i] >= q.n_qv || q.qdst[i] >= q.n_qv) bad("query edge endpoint out of range");
+        if (q.qsrc[i] == q.qdst[i]) bad("query self-loop");
+        if (q.qelabel[i] < -1 || q.qelabel[i] > 255) bad("query edge label out of range");
+        for (uint32_t k = 0; k < i; k++)
+            if (q.qsrc[k] == q.qsrc[i] && q.qdst[k] == q.qdst[i]) bad("repeated query edge");
+    }
+    bool seen[MN_MAXQV] = {false};
+    seen[0] = true;
+    for (uint32_t it = 0; it < q.n_qv; it++)
+        for (uint32_t i = 0; i < q.n_qe; i++)
+            if (seen[q.qsrc[i]] || seen[q.qdst[i]]) seen[q.qsrc[i]] = seen[q.qdst[i]] = true;
+    for (uint32_t v = 0; v < q.n_qv; v++)
+        if (!seen[v]) bad("query not weakly connected");
+}
+
+void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
+    if (n_q == 0 || n_q > 255 || !qs) throw ApiError{MNEMONIC_E_ARG, "need 1..255 queries"};
+    for (uint32_t i = 0; i < n_q; i++) check_query(qs[i]);
+    c->n_q = n_q;
+    // compact label tables
+    for (int i = 0; i < 256; i++) c->elab_idx[i] = -1;
+    for (int i = 0; i < 64; i++) c->vlab_idx[i] = -1;
+    for (uint32_t i = 0; i < n_q; i++) {
+        for (uint32_t k = 0; k < qs[i].n_qe; k++) {
+            int l = qs[i].qelabel[k];
+            if (l >= 0 && c->elab_idx[l] < 0) c->elab_idx[l] = (int16_t)c->n_elab_c++;
+        }
+        for (uint32_t u = 0; u < qs[i].n_qv; u++)
+            for (int b = 0; b < 64; b++)
+                if (((qs[i].qv_require[u] >> b) & 1) && c->vlab_idx[b] < 0) c->vlab_idx[b] = (int16_t)c->n_vlab_c++;
+    }
+    const uint32_t E = c->n_elab_c, Lc = c->n_vlab_c;
+    c->n_cnt = 2 * (1 + E + Lc);
+    uint32_t vf_base = 0, debi_base = 0, plan_base = 0;
+    for (uint32_t i = 0; i < n_q; i++) {
+        const mnemonic_query& q = qs[i];
+        QueryDev Q;
+        memset(&Q, 0, sizeof(Q));
+        Q.n_qv = q.n_qv;
+        Q.n_qe = q.n_qe;
+        Q.sem = (uint32_t)q.sem;
+        Q.vf_base = vf_base;
+        Q.debi_base = debi_base;
+        Q.plan_base = plan_base;
+        Q.out_index = i;
+        for (uint32_t u = 0; u < q.n_qv; u++) Q.vreq[u] = q.qv_require[u];
+        for (uint32_t k = 0; k < q.n_qe; k++) {
+            Q.qsrc[k] = (uint8_t)q.qsrc[k];
+            Q.qdst[k] = (uint8_t)q.qdst[k];
+            Q.qlab[k] = q.qelabel[k];
+        }
+        const bool iso = q.sem == MNEMONIC_ISO;
+        // local filters per query vertex (Section V-A, f2 and f3)
+        for (uint32_t u = 0; u < q.n_qv; u++) {
+            Q.req_begin[u] = (uint16_t)c->hreq.size();
+            VfBit vb;
+            vb.vreq = q.qv_require[u];
+            vb.req_begin = (uint32_t)c->hreq.size();
+            for (uint32_t dir = 0; dir < 2; dir++) {
+                uint32_t tot = 0;
+                uint32_t per_lab[256] = {0};
+                uint32_t per_vl[64] = {0};
+                for (uint32_t k = 0; k < q.n_qe; k++) {
+                    uint32_t near = dir == 0 ? q.qsrc[k] : q.qdst[k];
+                    uint32_t far = dir == 0 ? q.qdst[k] : q.qsrc[k];
+                    if (near != u) continue;
+                    tot++;
+                    if (q.qelabel[k] >= 0) per_lab[q.qelabel[k]]++;
+                    for (int b = 0; b < 64; b++)
+                        if ((q.qv_require[far] >> b) & 1) per_vl[b]++;
+                }
+                auto need = [&](uint32_t n) { return (uint16_t)(iso ? n : (n ? 1 : 0)); };
+                if (tot) c->hreq.push_back(VfReq{(uint16_t)cnt_index(dir, 0, E, Lc), need(tot)});
+                for (int l = 0; l < 256; l++)
+                    if (per_lab[l])
+                        c->hreq.push_back(VfReq{(uint16_t)cnt_index(dir, 1 + c->elab_idx[l], E, Lc), need(per_lab[l])});
+                for (int b = 0; b < 64; b++)
+                    if (per_vl[b])
+                        c->hreq.push_back(
+                            VfReq{(uint16_t)cnt_index(dir, 1 + E + c->vlab_idx[b], E, Lc), need(per_vl[b])});
+            }
+            vb.req_end = (uint32_t)c->hreq.size();
+            c->hvf.push_back(vb);
+        }
+        Q.req_begin[q.n_qv] = (uint16_t)c->hreq.size();
+        for (uint32_t k = 0; k < q.n_qe; k++) {
+            DebiBit db;
+            db.label = q.qelabel[k];
+            db.pad = 0;
+            db.req_src = q.qv_require[q.qsrc[k]];
+            db.req_dst = q.qv_require[q.qdst[k]];
+            c->hdebi.push_back(db);
+        }
+        for (uint32_t j = 0; j < q.n_qe; j++) {
+            SeedPlan P;
+            build_plan(Q, j, P);
+            for (uint32_t L = 0; L < P.n_levels; L++)
+                if (P.lv[L].c_end - P.lv[L].c_begin > 8)
+                    throw ApiError{MNEMONIC_E_QUERY, "a query vertex closes more than 8 edges at once"};
+            c->hplans.push_back(P);
+        }
+        vf_base += q.n_qv;
+        debi_base += q.n_qe;
+        plan_base += q.n_qe;
+        c->hq.push_back(Q);
+    }
+    c->n_vf_bits = vf_base;
+    c->n_debi_bits = debi_base;
+    c->total_qe = debi_base;
+    c->vf_words = (vf_base + 31) / 32;
+    c->debi_words = (debi_base + 31) / 32;
+}
+
+template <typename T>
+void upload(T*& d, const std::vector<T>& h, hipStream_t s) {
+    dev_alloc(d, h.size());
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+GraphView make_view(const mnemonic_ctx* c, bool next) {
+    GraphView g;
+    memset(&g, 0, sizeof(g));
+    g.n_vertices = c->nV;
+    g.nbr_bits = c->nbr_bits;
+    g.nbr_mask = (1u << c->nbr_bits) - 1u;
+    g.n_cnt = c->n_cnt;
+    g.vf_words = c->vf_words;
+    g.debi_words = c->debi_words;
+    g.n_queries = c->n_q;
+    g.n_vfreq = (uint32_t)c->hreq.size();
+    g.vmask = c->d_vmask;
+    for (int d = 0; d < 2; d++) {
+        g.off[d] = next ? c->d_off2[d] : c->d_off[d];
+        g.adj[d] = next ? c->d_adj2[d] : c->d_adj[d];
+    }
+    g.vf = c->d_vf;
+    g.cnt = c->d_cnt;
+    g.s_src = c->d_src;
+    g.s_dst = c->d_dst;
+    g.s_lab = c->d_lab;
+    g.s_ts = c->d_ts;
+    g.s_key = c->d_key;
+    g.s_debi = c->d_debi;
+    g.queries = c->d_q;
+    g.plans = c->d_plans;
+    g.vfreq = c->d_req;
+    g.elab_idx = c->d_elab_idx;
+    g.vlab_idx = c->d_vlab_idx;
+    g.n_elab_c = c->n_elab_c;
+    g.n_vlab_c = c->n_vlab_c;
+    return g;
+}
+
+// Makes every buffer large enough for a snapshot of n_ins insertions and
+// n_del deletions.
+void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
+    hipStream_t s = c->stream;
+    uint64_t need_slots = (uint64_t)c->fresh + (n_ins > c->n_free ? n_ins - c->n_free : 0);
+    uint64_t live_slots = c->fresh;
+    if (need_slots >= (1ull << 31)) throw ApiError{MNEMONIC_E_LIMIT, "more than 2^31 edge slots"};
+    if (need_slots > c->cap_slots) {
+        uint64_t cap = c->cap_slots;
+        uint64_t t;
+        t = cap; dev_grow(c->d_src, t, need_slots, live_slots, s);
+        t = cap; dev_grow(c->d_dst, t, need_slots, live_slots, s);
+        t = cap; dev_grow(c->d_lab, t, need_slots, live_slots, s);
+        t = cap; dev_grow(c->d_ts, t, need_slots, live_slots, s);
+        t = cap; dev_grow(c->d_key, t, need_slots, live_slots, s);
+        t = cap; dev_grow(c->d_free, t, need_slots, c->n_free, s);
+        uint64_t dcap = cap * c->debi_words;
+        dev_grow(c->d_debi, dcap, t * c->debi_words, live_slots * c->debi_words, s);
+        c->cap_slots = t;
+    }
+    uint64_t need_keys = c->next_key + n_ins;
+    if (need_keys > c->cap_keys) {
+        uint64_t cap = c->cap_keys;
+        dev_grow(c->d_key2slot, cap, need_keys, c->next_key, s);
+        uint64_t bcap = c->cap_delbits;
+        dev_grow(c->d_delbits, bcap, (cap + 31) / 32 + 1, c->cap_delbits, s);
+        if (bcap > c->cap_delbits)
+            HIPCHK(hipMemsetAsync(c->d_delbits + c->cap_delbits, 0, (bcap - c->cap_delbits) * 4, s));
+        c->cap_delbits = bcap;
+        c->cap_keys = cap;
+    }
+    uint64_t need_E = c->E - c->n_pending + n_ins;
+    c->hb_pos = std::max<uint32_t>(1, ceil_log2(std::max<uint64_t>(c->E, need_E) + 1));
+    if (need_E >= (1ull << 32) - 1) throw ApiError{MNEMONIC_E_LIMIT, "more than 2^32 adjacency entries"};
+    for (int d = 0; d < 2; d++) {
+        uint64_t t = c->cap_E;
+        dev_grow(c->d_adj[d], t, need_E, c->E, s);
+        t = c->cap_E;
+        dev_grow(c->d_adj2[d], t, need_E, 0, s);
+        if (d == 1) c->cap_E = t;
+    }
+    if (n_ins > c->cap_ins) {
+        uint64_t nc = std::max<uint64_t>(n_ins, c->cap_ins + c->cap_ins / 2);
+        dev_free(c->d_in_src);
+        dev_free(c->d_in_dst);
+        dev_free(c->d_in_lab);
+        dev_free(c->d_in_ts);
+        dev_free(c->d_ins_slot);
+        dev_alloc(c->d_in_src, nc);
+        dev_alloc(c->d_in_dst, nc);
+        dev_alloc(c->d_in_lab, nc);
+        dev_alloc(c->d_in_ts, nc);
+        dev_alloc(c->d_ins_slot, nc);
+        for (int d = 0; d < 2; d++) {
+            for (int k = 0; k < 2; k++) {
+                dev_free(c->d_skey[d][k]);
+                dev_free(c->d_sval[d][k]);
+                dev_alloc(c->d_skey[d][k], nc);
+                dev_alloc(c->d_sval[d][k], nc);
+            }
+            dev_free(c->d_inspos[d]);
+            dev_alloc(c->d_inspos[d], nc);
+        }
+        c->cap_ins = nc;
+    }
+    if (n_del > c->cap_del) {
+        uint64_t nc = std::max<uint64_t>(n_del, c->cap_del + c->cap_del / 2);
+        dev_free(c->d_del_keys);
+        dev_alloc(c->d_del_keys, nc);
+        c->cap_del = nc;
+    }
+    // the delete buffer that receives this snapshot's deletions
+    int cur = 1 - c->pend;
+    if (n_del > c->cap_delbuf[cur]) {
+        uint64_t nc = std::max<uint64_t>(n_del, c->cap_delbuf[cur] + c->cap_delbuf[cur] / 2);
+        dev_free(c->d_del_slot[cur]);
+        dev_alloc(c->d_del_slot[cur], nc);
+        for (int d = 0; d < 2; d++) {
+            dev_free(c->d_delpos[cur][d]);
+            dev_alloc(c->d_delpos[cur][d], nc);
+        }
+        c->cap_delbuf[cur] = nc;
+    }
+    uint64_t n_sort = std::max<uint64_t>(n_ins, c->n_pending);
+    if (n_sort > c->cap_sort) {
+        uint64_t nc = std::max<uint64_t>(n_sort, c->cap_sort + c->cap_sort / 2);
+        for (int d = 0; d < 2; d++)
+            for (int k = 0; k < 2; k++) {
+                dev_free(c->d_dkey[d][k]);
+                dev_free(c->d_dval[d][k]);
+                dev_alloc(c->d_dkey[d][k], nc);
+                dev_alloc(c->d_dval[d][k], nc);
+            }
+        c->cap_sort = nc;
+    }
+    uint64_t ssw = mn_sort_scratch_words((uint32_t)std::max<uint64_t>(n_sort, 1));
+    if (ssw > c->cap_sort_scratch) {
+        dev_free(c->d_sort_scratch);
+        dev_alloc(c->d_sort_scratch, ssw);
+        c->cap_sort_scratch = ssw;
+    }
+    uint64_t n_touch = 2 * (c->n_pending + n_ins);
+    if (n_touch > c->cap_touch) {
+        uint64_t nc = std::max<uint64_t>(n_touch, c->cap_touch + c->cap_touch / 2);
+        dev_free(c->d_touched);
+        dev_alloc(c->d_touched, nc);
+        c->cap_touch = nc;
+    }
+    uint64_t n_seed = std::max<uint64_t>(n_ins, n_del) * c->total_qe;
+    if (n_seed > c->cap_seed) {
+        uint64_t nc = std::max<uint64_t>(n_seed, c->cap_seed + c->cap_seed / 2);
+        for (int p = 0; p < 2; p++) {
+            dev_free(c->d_seeds[p]);
+            dev_alloc(c->d_seeds[p], nc);
+        }
+        c->cap_seed = nc;
+    }
+}
+
+void grow_outputs(mnemonic_ctx* c, const std::vector<uint64_t>& need) {
+    bool changed = false;
+    for (uint32_t q = 0; q < c->n_q; q++)
+        for (int p = 0; p < 2; p++) {
+            uint64_t n = need[2 * q + p];
+            if (n <= c->houts[q].cap[p]) continue;
+            uint64_t nc = std::max<uint64_t>(n + n / 4, c->houts[q].cap[p] * 2);
+            dev_free(c->houts[q].keys[p]);
+            dev_alloc(c->houts[q].keys[p], nc * c->hq[q].n_qe);
+            c->houts[q].cap[p] = nc;
+            changed = true;
+        }
+    if (changed)
+        HIPCHK(hipMemcpyAsync(c->d_outs, c->houts.data(), c->houts.size() * sizeof(OutView),
+                              hipMemcpyHostToDevice, c->stream));
+}
+
+PhaseOut phase_out(mnemonic_ctx* c, int p) {
+    PhaseOut po;
+    po.count = c->d_zr + c->zr_count(p);
+    po.digest = c->d_zr + c->zr_digest(p);
+    po.stats = reinterpret_cast<EnumStats*>(c->d_zr + c->zr_stats(0));
+    po.outs = c->d_outs;
+    return po;
+}
+
+void reset_phase(mnemonic_ctx* c, int p) {
+    hipStream_t s = c->stream;
+    // counts, digests, cursor and stats of one phase (err is 0 whenever this runs)
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_count(p), c->n_q, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), 2 * c->n_q, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_cursor(p), 1, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), 8, s);
+}
+
+void enumerate_phase(mnemonic_ctx* c, int p, uint64_t max_seeds) {
+    GraphView g = make_view(c, false);
+    bool emit = (c->flags & MNEMONIC_F_EMIT) != 0;
+    bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
+    if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], c->stream));
+    mn_launch_enumerate(g, c->d_seeds[p], reinterpret_cast<uint32_t*>(c->d_zr + c->zr_nseeds(p)),
+                        (uint32_t)max_seeds, reinterpret_cast<uint32_t*>(c->d_zr + c->zr_cursor(p)),
+                        phase_out(c, p), p, emit ? 1 : 0, c->d_err, c->stream);
+    if (timing) HIPCHK(hipEventRecord(c->ev[2 * p + 1], c->stream));
+}
+
+// One snapshot; `enumerate` is false only for the initial load.
+int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32_t* dst,
+              const uint8_t* lab, const int64_t* ts, const uint64_t* del_keys, uint64_t n_del,
+              bool on_device, bool enumerate, uint64_t* first_new_key) {
+    hipStream_t s = c->stream;
+    if (n_ins + n_del >= (1ull << 31)) throw ApiError{MNEMONIC_E_ARG, "batch too large"};
+    ensure_capacity(c, n_ins, n_del);
+    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0 && enumerate;
+    if (timing) HIPCHK(hipEventRecord(c->ev[4], s));
+
+    const uint32_t* in_src = src;
+    const uint32_t* in_dst = dst;
+    const uint8_t* in_lab = lab;
+    const int64_t* in_ts = ts;
+    const uint64_t* dk = del_keys;
+    if (!on_device) {
+        if (n_ins) {
+            HIPCHK(hipMemcpyAsync(c->d_in_src, src, n_ins * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(c->d_in_dst, dst, n_ins * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(c->d_in_lab, lab, n_ins, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(c->d_in_ts, ts, n_ins * 8, hipMemcpyHostToDevice, s));
+        }
+        if (n_del) HIPCHK(hipMemcpyAsync(c->d_del_keys, del_keys, n_del * 8, hipMemcpyHostToDevice, s));
+        in_src = c->d_in_src;
+        in_dst = c->d_in_dst;
+        in_lab = c->d_in_lab;
+        in_ts = c->d_in_ts;
+        dk = c->d_del_keys;
+    }
+    const int pend = c->pend, cur = 1 - c->pend;
+    const uint32_t n_prev = (uint32_t)c->n_pending;
+    BatchView b;
+    memset(&b, 0, sizeof(b));
+    b.n_ins = (uint32_t)n_ins;
+    b.n_del = (uint32_t)n_del;
+    b.n_prev_del = n_prev;
+    b.n_free = c->n_free;
+    b.fresh = c->fresh;
+    b.hb = c->hb;
+    b.next_key = c->next_key;
+    b.n_elabels = c->n_elabels;
+    b.n_debi_bits = c->n_debi_bits;
+    b.n_vf_bits = c->n_vf_bits;
+    b.in_src = in_src;
+    b.in_dst = in_dst;
+    b.in_lab = in_lab;
+    b.in_ts = in_ts;
+    b.del_keys = dk;
+    b.free_stack = c->d_free;
+    b.key2slot = c->d_key2slot;
+    b.delbits = c->d_delbits;
+    b.err = c->d_err;
+    b.last_ts = c->d_last_ts;
+    b.ins_slot = c->d_ins_slot;
+    for (int d = 0; d < 2; d++) {
+        b.skey[d] = c->d_skey[d][0];
+        b.sval[d] = c->d_sval[d][0];
+        b.delpos[d] = c->d_delpos[cur][d];
+    }
+    b.touched = c->d_touched;
+    b.prev_del_slot = c->d_del_slot[pend];
+    b.del_slot = c->d_del_slot[cur];
+    b.debi_bits = c->d_debi_bits;
+    b.vf_bits = c->d_vf_bits;
+
+    GraphView g0 = make_view(c, false);
+    mn_launch_reset(c->d_err, c->d_zr, c->n_zr, s);
+    mn_launch_validate(g0, b, s);
+    mn_launch_prev_del(g0, b, s);
+    mn_launch_ingest(g0, b, s);
+
+    const bool merge = n_ins > 0 || n_prev > 0;
+    const uint64_t E_new = c->E - n_prev + n_ins;
+    if (merge) {
+        // sort the pending deletion positions and the batch entries per direction
+        uint64_t* dpos[2] = {nullptr, nullptr};
+        for (int d = 0; d < 2; d++) {
+            uint64_t* bk = c->d_skey[d][0];
+            uint32_t* bv = c->d_sval[d][0];
+            uint64_t* tk = c->d_skey[d][1];
+            uint32_t* tv = c->d_sval[d][1];
+            mn_radix_sort(bk, bv, tk, tv, (uint32_t)n_ins, c->hb + c->nbr_bits, c->d_sort_scratch, s);
+            b.skey[d] = bk;
+            b.sval[d] = bv;
+        }
+        // positions of the previous snapshot's deletions, sorted per direction
+        for (int d = 0; d < 2 && n_prev; d++) {
+            uint64_t* k0 = c->d_dkey[d][0];
+            uint32_t* v0 = c->d_dval[d][0];
+            uint64_t* k1 = c->d_dkey[d][1];
+            uint32_t* v1 = c->d_dval[d][1];
+            mn_launch_widen(c->d_delpos[pend][d], k0, n_prev, c->d_err, s);
+            mn_radix_sort(k0, v0, k1, v1, n_prev, c->hb_pos, c->d_sort_scratch, s);
+            dpos[d] = k0;
+        }
+        for (int d = 0; d < 2; d++) {
+            mn_launch_vertex_meta(c->d_off[d], c->nV, (uint32_t)c->E, b.skey[d], (uint32_t)n_ins, dpos[d],
+                                  n_prev, c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
+            mn_launch_merge(c->d_off[d], c->d_adj[d], c->nV, (uint32_t)c->E, c->d_off2[d], c->d_meta[d],
+                            b.skey[d], b.sval[d], (uint32_t)n_ins, dpos[d], c->hb, c->d_adj2[d],
+                            c->d_inspos[d], (uint32_t)E_new, c->d_err, s);
+        }
+    }
+    // from here on the kernels work on the merged adjacency
+    GraphView g1 = make_view(c, merge);
+    mn_launch_vf_refresh(g1, c->d_vf_bits, c->n_vf_bits, enumerate ? c->d_touched : nullptr,
+                         enumerate ? (uint32_t)(2 * (n_prev + n_ins)) : c->nV, c->d_err, s);
+    uint64_t* adjn[2] = {merge ? c->d_adj2[0] : c->d_adj[0], merge ? c->d_adj2[1] : c->d_adj[1]};
+    if (enumerate) {
+        mn_launch_seed(g1, c->d_debi_bits, c->d_ins_slot, (uint32_t)n_ins, c->d_seeds[0],
+                       reinterpret_cast<uint32_t*>(c->d_zr + c->zr_nseeds(0)), c->d_err, s);
+    }
+    // the enumerator reads the current view; point it at the merged arrays
+    auto swap_in = [&]() {
+        if (!merge) return;
+        for (int d = 0; d < 2; d++) {
+            std::swap(c->d_adj[d], c->d_adj2[d]);
+            std::swap(c->d_off[d], c->d_off2[d]);
+        }
+    };
+    swap_in();
+    uint32_t err = 0;
+    try {
+        if (enumerate) enumerate_phase(c, 0, n_ins * c->total_qe);
+        for (int d = 0; d < 2; d++) mn_launch_set_flags(adjn[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
+        GraphView g2 = make_view(c, false);
+        mn_launch_flag_del(g2, adjn[0], adjn[1], b, s);
+        if (enumerate) {
+            mn_launch_seed(g2, c->d_debi_bits, c->d_del_slot[cur], (uint32_t)n_del, c->d_seeds[1],
+                           reinterpret_cast<uint32_t*>(c->d_zr + c->zr_nseeds(1)), c->d_err, s);
+            enumerate_phase(c, 1, n_del * c->total_qe);
+        }
+        uint32_t n_free_after = c->n_free - (uint32_t)std::min<uint64_t>(n_ins, c->n_free);
+        mn_launch_finalize(b, n_free_after, s);
+        if (timing) HIPCHK(hipEventRecord(c->ev[5], s));
+        HIPCHK(hipMemcpyAsync(&err, c->d_err, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } catch (...) {
+        swap_in();  // a swap is its own inverse: back to the pre-batch arrays
+        throw;
+    }
+    if (err) {
+        swap_in();
+        switch (err) {
+            case MN_ERR_VERTEX: throw ApiError{MNEMONIC_E_VERTEX, "edge endpoint >= n_vertices"};
+            case MN_ERR_LABEL: throw ApiError{MNEMONIC_E_LABEL, "edge label >= n_elabels"};
+            case MN_ERR_TS: throw ApiError{MNEMONIC_E_TS_ORDER, "timestamps decrease"};
+            case MN_ERR_DELETE: throw ApiError{MNEMONIC_E_BAD_DELETE, "deletion key not live or repeated"};
+            default: throw ApiError{MNEMONIC_E_HIP, "internal consistency check failed on the device"};
+        }
+    }
+    // commit the host mirrors
+    if (first_new_key) *first_new_key = c->next_key;
+    uint32_t took = (uint32_t)std::min<uint64_t>(n_ins, c->n_free);
+    c->fresh += (uint32_t)(n_ins - took);
+    c->n_free = c->n_free - took + (uint32_t)n_del;
+    c->next_key += n_ins;
+    c->n_live = c->n_live + n_ins - n_del;
+    c->E = E_new;
+    c->n_pending = n_del;
+    c->pend = cur;
+
+    if (enumerate) {
+        // outputs too small: grow and enumerate again on the same state
+        bool emit = (c->flags & MNEMONIC_F_EMIT) != 0;
+        std::vector<uint64_t> need(2 * c->n_q, 0);
+        bool redo[2] = {false, false};
+        for (uint32_t q = 0; q < c->n_q; q++)
+            for (int p = 0; p < 2; p++) {
+                need[2 * q + p] = c->h_zr[c->zr_count(p) + q];
+                if (emit && need[2 * q + p] > c->houts[q].cap[p]) redo[p] = true;
+            }
+        if (redo[0] || redo[1]) {
+            grow_outputs(c, need);
+            if (redo[0]) {
+                for (int d = 0; d < 2; d++) {
+                    mn_launch_set_flags(c->d_adj[d], c->d_delpos[cur][d], (uint32_t)n_del, 0, c->d_err, s);
+                    mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 1, c->d_err, s);
+                }
+                reset_phase(c, 0);
+                enumerate_phase(c, 0, n_ins * c->total_qe);
+                for (int d = 0; d < 2; d++) {
+                    mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
+                    mn_launch_set_flags(c->d_adj[d], c->d_delpos[cur][d], (uint32_t)n_del, 1, c->d_err, s);
+                }
+            }
+            if (redo[1]) {
+                reset_phase(c, 1);
+                enumerate_phase(c, 1, n_del * c->total_qe);
+            }
+            HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        // stats
+        mnemonic_stats& st = c->stats;
+        st.n_live_edges = c->n_live;
+        st.slot_high_water = c->fresh;
+        for (int p = 0; p < 2; p++) {
+            const unsigned long long* z = c->h_zr.data() + c->zr_stats(p);
+            st.seeds[p] = z[0];
+            st.entries_scanned[p] = z[1];
+            st.probe_words[p] = z[2];
+            st.key_reads[p] = z[3];
+            st.tuples[p] = z[4];
+            uint64_t words = 0;
+            for (uint32_t q = 0; q < c->n_q; q++) words += c->h_zr[c->zr_count(p) + q] * c->hq[q].n_qe;
+            st.tuple_words[p] = words;
+        }
+        if (timing) {
+            float ms = 0;
+            for (int p = 0; p < 2; p++) {
+                HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * p], c->ev[2 * p + 1]));
+                st.ms_enumerate[p] = ms;
+            }
+            HIPCHK(hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
+            st.ms_batch = ms;
+        }
+        c->have_result = true;
+    }
+    return MNEMONIC_OK;
+}
+
+template <typename F>
+int guarded(mnemonic_ctx* c, F&& f) {
+    try {
+        if (c) c->err.clear();
+        return f();
+    } catch (const ApiError& e) {
+        if (c) c->err = e.msg;
+        else g_create_error = e.msg;
+        return e.code;
+    } catch (const HipError& e) {
+        std::string m = std::string(e.what) + ": " + hipGetErrorString(e.e);
+        if (c) c->err = m;
+        else g_create_error = m;
+        return MNEMONIC_E_HIP;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        else g_create_error = "host allocation failed";
+        return MNEMONIC_E_OOM;
+    }
+}
+
+void free_all(mnemonic_ctx* c) {
+    dev_free(c->d_vmask);
+    dev_free(c->d_q);
+    dev_free(c->d_plans);
+    dev_free(c->d_debi_bits);
+    dev_free(c->d_vf_bits);
+    dev_free(c->d_req);
+    dev_free(c->d_elab_idx);
+    dev_free(c->d_vlab_idx);
+    dev_free(c->d_vf);
+    dev_free(c->d_cnt);
+    dev_free(c->d_meta[0]);
+    dev_free(c->d_meta[1]);
+    dev_free(c->d_src);
+    dev_free(c->d_dst);
+    dev_free(c->d_lab);
+    dev_free(c->d_ts);
+    dev_free(c->d_key);
+    dev_free(c->d_debi);
+    dev_free(c->d_free);
+    dev_free(c->d_key2slot);
+    dev_free(c->d_delbits);
+    for (int d = 0; d < 2; d++) {
+        dev_free(c->d_off[d]);
+        dev_free(c->d_off2[d]);
+        dev_free(c->d_adj[d]);
+        dev_free(c->d_adj2[d]);
+        dev_free(c->d_inspos[d]);
+        dev_free(c->d_del_slot[d]);
+        dev_free(c->d_seeds[d]);
+        for (int k = 0; k < 2; k++) {
+            dev_free(c->d_dkey[d][k]);
+            dev_free(c->d_dval[d][k]);
+            dev_free(c->d_skey[d][k]);
+            dev_free(c->d_sval[d][k]);
+            dev_free(c->d_delpos[d][k]);
+        }
+    }
+    dev_free(c->d_in_src);
+    dev_free(c->d_in_dst);
+    dev_free(c->d_in_lab);
+    dev_free(c->d_in_ts);
+    dev_free(c->d_del_keys);
+    dev_free(c->d_ins_slot);
+    dev_free(c->d_touched);
+    dev_free(c->d_sort_scratch);
+    dev_free(c->d_err);
+    dev_free(c->d_last_ts);
+    dev_free(c->d_zr);
+    for (auto& o : c->houts)
+        for (int p = 0; p < 2; p++) dev_free(o.keys[p]);
+    dev_free(c->d_outs);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n_q,
+                    const mnemonic_options* opt, void* hip_stream, mnemonic_ctx** out) {
+    g_create_error.clear();
+    if (!g || !q || !out) {
+        g_create_error = "NULL argument";
+        return MNEMONIC_E_ARG;
+    }
+    mnemonic_ctx* c = new (std::nothrow) mnemonic_ctx();
+    if (!c) return MNEMONIC_E_OOM;
+    memset(&c->stats, 0, sizeof(c->stats));
+    int rc = guarded(nullptr, [&]() -> int {
+        if (g->n_vertices == 0 || (g->n_edges && (!g->src || !g->dst || !g->elabel || !g->ts)) || !g->vlabel_mask)
+            throw ApiError{MNEMONIC_E_ARG, "graph arrays must not be NULL and n_vertices must be > 0"};
+        if (g->n_vertices > (1u << 24)) throw ApiError{MNEMONIC_E_LIMIT, "n_vertices > 2^24"};
+        if (g->n_elabels > 256) throw ApiError{MNEMONIC_E_ARG, "n_elabels > 256"};
+        HIPCHK(hipGetDevice(&c->device));
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        if (opt) c->flags = opt->flags;
+        c->nV = g->n_vertices;
+        c->n_elabels = g->n_elabels ? g->n_elabels : 256;
+        c->nbr_bits = std::max<uint32_t>(1, ceil_log2(c->nV));
+        c->hb = c->nbr_bits + std::max<uint32_t>(1, ceil_log2(c->n_elabels));
+        prepare_queries(c, q, n_q);
+        for (uint32_t i = 0; i < n_q; i++)
+            for (uint32_t k = 0; k < q[i].n_qe; k++)
+                if (q[i].qelabel[k] >= (int32_t)c->n_elabels)
+                    throw ApiError{MNEMONIC_E_QUERY, "query edge label >= n_elabels"};
+        hipStream_t s = c->stream;
+        for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+        dev_alloc(c->d_vmask, c->nV);
+        HIPCHK(hipMemcpyAsync(c->d_vmask, g->vlabel_mask, (size_t)c->nV * 8, hipMemcpyHostToDevice, s));
+        upload(c->d_q, c->hq, s);
+        upload(c->d_plans, c->hplans, s);
+        upload(c->d_debi_bits, c->hdebi, s);
+        upload(c->d_vf_bits, c->hvf, s);
+        upload(c->d_req, c->hreq, s);
+        dev_alloc(c->d_elab_idx, 256);
+        dev_alloc(c->d_vlab_idx, 64);
+        HIPCHK(hipMemcpyAsync(c->d_elab_idx, c->elab_idx, sizeof(c->elab_idx), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->d_vlab_idx, c->vlab_idx, sizeof(c->vlab_idx), hipMemcpyHostToDevice, s));
+        dev_alloc(c->d_vf, (size_t)c->nV * c->vf_words);
+        dev_alloc(c->d_cnt, (size_t)c->nV * c->n_cnt);
+        mn_launch_init_vertices(c->d_vf, c->d_cnt, c->nV, c->vf_words, c->n_cnt, s);
+        dev_alloc(c->d_meta[0], c->nV);
+        dev_alloc(c->d_meta[1], c->nV);
+        for (int d = 0; d < 2; d++) {
+            dev_alloc(c->d_off[d], (size_t)c->nV + 1);
+            dev_alloc(c->d_off2[d], (size_t)c->nV + 1);
+            HIPCHK(hipMemsetAsync(c->d_off[d], 0, ((size_t)c->nV + 1) * 4, s));
+        }
+        dev_alloc(c->d_err, 1);
+        dev_alloc(c->d_last_ts, 1);
+        int64_t mn = INT64_MIN;
+        HIPCHK(hipMemcpyAsync(c->d_last_ts, &mn, 8, hipMemcpyHostToDevice, s));
+        c->n_zr = 4 + 6 * n_q + 16;
+        c->h_zr.assign(c->n_zr, 0);
+        dev_alloc(c->d_zr, c->n_zr);
+        // output buffers
+        uint64_t cap = opt && opt->out_capacity ? opt->out_capacity : (1ull << 20);
+        c->houts.resize(n_q);
+        for (uint32_t i = 0; i < n_q; i++)
+            for (int p = 0; p < 2; p++) {
+                c->houts[i].cap[p] = (c->flags & MNEMONIC_F_EMIT) ? cap : 0;
+                c->houts[i].keys[p] = nullptr;
+                if (c->flags & MNEMONIC_F_EMIT) dev_alloc(c->houts[i].keys[p], cap * c->hq[i].n_qe);
+            }
+        dev_alloc(c->d_outs, n_q);
+        HIPCHK(hipMemcpyAsync(c->d_outs, c->houts.data(), n_q * sizeof(OutView), hipMemcpyHostToDevice, s));
+        // initial graph: the same ingest/merge path without enumeration
+        run_batch(c, g->n_edges, g->src, g->dst, g->elabel, g->ts, nullptr, 0, false, false, nullptr);
+        HIPCHK(hipStreamSynchronize(s));
+        return MNEMONIC_OK;
+    });
+    if (rc != MNEMONIC_OK) {
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return MNEMONIC_OK;
+}
+
+int mnemonic_apply_batch(mnemonic_ctx* ctx, const mnemonic_edges* ins, const uint64_t* del_keys,
+                         uint64_t n_del, uint64_t* first_new_key) {
+    if (!ctx) return MNEMONIC_E_ARG;
+    return guarded(ctx, [&]() -> int {
+        uint64_t n_ins = ins ? ins->n : 0;
+        if (n_ins && (!ins->src || !ins->dst || !ins->elabel || !ins->ts))
+            throw ApiError{MNEMONIC_E_ARG, "insertion arrays must not be NULL"};
+        if (n_del && !del_keys) throw ApiError{MNEMONIC_E_ARG, "del_keys must not be NULL"};
+        bool dev = ins && ins->on_device;
+        return run_batch(ctx, n_ins, ins ? ins->src : nullptr, ins ? ins->dst : nullptr,
+                         ins ? ins->elabel : nullptr, ins ? ins->ts : nullptr, del_keys, n_del, dev, true,
+                         first_new_key);
+    });
+}
+
+int mnemonic_get_result(mnemonic_ctx* ctx, uint32_t query, mnemonic_result* out) {
+    if (!ctx || !out || query >= ctx->n_q) return MNEMONIC_E_ARG;
+    memset(out, 0, sizeof(*out));
+    out->n_qe = ctx->hq[query].n_qe;
+    if (!ctx->have_result) return MNEMONIC_OK;
+    out->n_new = ctx->h_zr[ctx->zr_count(0) + query];
+    out->n_expired = ctx->h_zr[ctx->zr_count(1) + query];
+    out->dig_new[0] = ctx->h_zr[ctx->zr_digest(0) + 2 * query];
+    out->dig_new[1] = ctx->h_zr[ctx->zr_digest(0) + 2 * query + 1];
+    out->dig_expired[0] = ctx->h_zr[ctx->zr_digest(1) + 2 * query];
+    out->dig_expired[1] = ctx->h_zr[ctx->zr_digest(1) + 2 * query + 1];
+    if (ctx->flags & MNEMONIC_F_EMIT) {
+        out->new_keys = ctx->houts[query].keys[0];
+        out->expired_keys = ctx->houts[query].keys[1];
+    }
+    return MNEMONIC_OK;
+}
+
+int mnemonic_copy_keys(mnemonic_ctx* ctx, uint32_t query, int expired, uint64_t* host_buf,
+                       uint64_t capacity, uint64_t* needed) {
+    if (!ctx || query >= ctx->n_q) return MNEMONIC_E_ARG;
+    return guarded(ctx, [&]() -> int {
+        if (!(ctx->flags & MNEMONIC_F_EMIT)) throw ApiError{MNEMONIC_E_ARG, "context does not emit tuples"};
+        int p = expired ? 1 : 0;
+        uint64_t n = ctx->have_result ? ctx->h_zr[ctx->zr_count(p) + query] : 0;
+        if (needed) *needed = n;
+        if (n > capacity) throw ApiError{MNEMONIC_E_CAPACITY, "host buffer too small"};
+        if (n) {
+            if (!host_buf) throw ApiError{MNEMONIC_E_ARG, "host_buf must not be NULL"};
+            HIPCHK(hipMemcpyAsync(host_buf, ctx->houts[query].keys[p], n * ctx->hq[query].n_qe * 8,
+                                  hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        }
+        return MNEMONIC_OK;
+    });
+}
+
+int mnemonic_get_stats(mnemonic_ctx* ctx, mnemonic_stats* out) {
+    if (!ctx || !out) return MNEMONIC_E_ARG;
+    *out = ctx->stats;
+    out->n_live_edges = ctx->n_live;
+    out->slot_high_water = ctx->fresh;
+    return MNEMONIC_OK;
+}
+
+const char* mnemonic_last_error(const mnemonic_ctx* ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+void mnemonic_destroy(mnemonic_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+// Shared device-side definitions of the gfx950 matcher (not part of the ABI).
+//
+// HBM layout
+//   slot arrays (edge attributes, Section IV-A: "attribute store indexed by
+//   edge id"): s_src u32, s_dst u32, s_lab u8, s_ts i64, s_key u64 and the
+//   DEBI words s_debi[slot * debi_words + w]. A slot is the recycled internal
+//   edge id (Section IV-A, memory recycling); the key is the caller's stable id.
+//   adjacency (Section II-A: every vertex keeps its in- and out-edges): two CSR
+//   arrays, direction 0 = out-edges, 1 = in-edges. An entry is one u64:
+//     high 32 bits  (label << nbr_bits) | neighbour
+//     low  32 bits  flag << 31 | slot
+//   Each vertex's segment is sorted by the high word, so a label's edges form
+//   one run, parallel edges to one neighbour form a contiguous sub-run, and a
+//   neighbour lookup is a binary search. The flag marks the edges of the batch
+//   the current phase enumerates (insert phase: the inserted edges; delete
+//   phase: the deleted ones, which stay in the arrays until the next merge).
+//   vertex filter VF[v * vf_words + w]: one bit per (query, query vertex).
+//   counters cnt[v * n_cnt + c]: per-direction degree, per-direction degree of
+//   each edge label the queries use, per-direction count of edges whose far
+//   endpoint carries each vertex label the queries use.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MN_MAXQV 16
+#define MN_MAXQE 32
+#define MN_MAXLV (MN_MAXQV - 2)
+#define MN_FLAG 0x80000000u
+#define MN_SLOTMASK 0x7FFFFFFFu
+#define MN_INVALID 0xFFFFFFFFu
+#define MN_BLOCK 256
+#define MN_WAVE 64
+
+#define MN_SEED_A 0x243F6A8885A308D3ULL
+#define MN_SEED_B 0x13198A2E03707344ULL
+
+// Error codes written by device validation (same values as the ABI).
+#define MN_ERR_VERTEX 3
+#define MN_ERR_LABEL 4
+#define MN_ERR_TS 5
+#define MN_ERR_DELETE 6
+#define MN_ERR_INTERNAL 99
+
+// A closing query edge: both endpoints are mapped when it is reached. Its
+// instances are looked up in the adjacency of the already-mapped endpoint
+// `other`: dir 0 = out-list of f(other) (query edge other -> new vertex),
+// dir 1 = in-list of f(other) (query edge new vertex -> other).
+struct CloseDesc {
+    uint8_t qe;
+    uint8_t other;
+    uint8_t dir;
+    uint8_t masked;  // query edge index < start position: batch edges forbidden
+    int32_t label;   // -1 = any label
+};
+
+// One level of the search maps one new query vertex `vtx` through its anchor
+// edge, whose candidates are the label run of f(from)'s out-list (dir 0, query
+// edge from -> vtx) or in-list (dir 1, query edge vtx -> from). Closing edges
+// close[c_begin, c_end) join vtx to vertices mapped earlier.
+struct LevelDesc {
+    uint8_t vtx;
+    uint8_t qe;
+    uint8_t from;
+    uint8_t dir;
+    int32_t label;
+    uint8_t masked;
+    uint8_t c_begin;
+    uint8_t c_end;
+    uint8_t n_mapped;  // query vertices mapped before this level (seed pair + earlier levels)
+};
+
+// Static matching order for one (query, start position j) pair (Section VI,
+// "matching order computation"): the start edge maps qa -> qb; closing edges
+// between qa and qb come first (close[0, c0_end)), then one level per
+// remaining query vertex.
+struct SeedPlan {
+    uint8_t qa, qb;
+    uint8_t n_levels;
+    uint8_t c0_end;
+    uint8_t mapped[MN_MAXQV];  // query vertices in mapping order: qa, qb, level vtx...
+    // where the last level finds each query edge's key when it emits:
+    // 0xFF = mapped above (LDS), 0xFE = the last level's anchor, c = its c-th closing edge
+    uint8_t last_src[MN_MAXQE];
+    LevelDesc lv[MN_MAXLV];
+    CloseDesc close[MN_MAXQE];
+};
+
+// One local-filter requirement of a query vertex: counter c must be >= need.
+struct VfReq {
+    uint16_t cnt;
+    uint16_t need;
+};
+
+struct QueryDev {
+    uint32_t n_qv, n_qe, sem;
+    uint32_t vf_base;    // first VF bit of this query
+    uint32_t debi_base;  // first DEBI bit of this query
+    uint32_t plan_base;  // index of the plan for start position 0
+    uint32_t out_index;  // index of this query's output slots
+    uint32_t pad;
+    uint64_t vreq[MN_MAXQV];
+    int32_t qlab[MN_MAXQE];
+    uint8_t qsrc[MN_MAXQE];
+    uint8_t qdst[MN_MAXQE];
+    uint16_t req_begin[MN_MAXQV + 1];  // VfReq range of each query vertex
+};
+
+// Device view of the graph state used by most kernels.
+struct GraphView {
+    uint32_t n_vertices;
+    uint32_t nbr_bits;
+    uint32_t nbr_mask;
+    uint32_t n_cnt;
+    uint32_t vf_words;
+    uint32_t debi_words;
+    uint32_t n_queries;
+    uint32_t n_vfreq;
+    const uint64_t* vmask;
+    const uint32_t* off[2];
+    const uint64_t* adj[2];
+    uint32_t* vf;
+    uint32_t* cnt;
+    uint32_t* s_src;
+    uint32_t* s_dst;
+    uint8_t* s_lab;
+    int64_t* s_ts;
+    uint64_t* s_key;
+    uint32_t* s_debi;
+    const QueryDev* queries;
+    const SeedPlan* plans;
+    const VfReq* vfreq;
+    const int16_t* elab_idx;   // [256] compact index of an edge label, -1 if unused
+    const int16_t* vlab_idx;   // [64] compact index of a vertex label bit, -1 if unused
+    uint32_t n_elab_c;         // compact edge labels
+    uint32_t n_vlab_c;         // compact vertex labels
+};
+
+// Counter layout of one vertex: [dir][0] degree, [dir][1 + e] edge label e,
+// [dir][1 + n_elab_c + l] neighbours' vertex label l; n_cnt = 2 * (1 + E + L).
+__host__ __device__ inline uint32_t cnt_index(uint32_t dir, uint32_t part, uint32_t n_elab_c,
+                                              uint32_t n_vlab_c) {
+    return dir * (1 + n_elab_c + n_vlab_c) + part;
+}
+
+__device__ inline uint32_t ent_hi(uint64_t e) { return (uint32_t)(e >> 32); }
+__device__ inline uint32_t ent_lo(uint64_t e) { return (uint32_t)e; }
+
+// SplitMix64 output finaliser (Steele, Lea, Flood 2014).
+__device__ inline uint64_t mn_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t lanemask_lt() {
+    uint32_t l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ inline uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// First index in [lo, hi) whose entry's high word is >= key.
+__device__ inline uint32_t lower_hi(const uint64_t* adj, uint32_t lo, uint32_t hi, uint32_t key) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(adj);
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (w[2 * (size_t)mid + 1] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// First index in [lo, hi) whose entry's high word is > key.
+__device__ inline uint32_t upper_hi(const uint64_t* adj, uint32_t lo, uint32_t hi, uint32_t key) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(adj);
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (w[2 * (size_t)mid + 1] <= key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ inline uint32_t lower_bound_dev(const T* a, uint32_t lo, uint32_t hi, T key) {
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ inline uint32_t upper_bound_dev(const T* a, uint32_t lo, uint32_t hi, T key) {
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}

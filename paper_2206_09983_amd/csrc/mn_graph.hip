@@ -1,0 +1,376 @@
+// Graph update kernels for one snapshot (Algorithm 2, batchInserts and
+// batchDeletes; Section IV-A, DEBI updating and memory recycling).
+//
+//   k_validate     endpoint/label/timestamp checks and deletion-key liveness,
+//                  before anything changes (a failing batch changes nothing:
+//                  every later kernel returns at once when the error word is set)
+//   k_prev_del     deferred removal bookkeeping of the previous snapshot's
+//                  deletions (counter decrements)
+//   k_ingest       slot allocation (recycled slots first), attribute writes,
+//                  edgeMatcher -> DEBI words, counter increments, sort keys
+//   k_vertex_meta  per-vertex new offsets of the merged adjacency
+//   k_merge_old/new  merged, sorted adjacency: old entries minus the deleted
+//                  ones, plus the batch entries (flagged)
+//   k_vf_refresh   per-vertex local filters (f2/f3 of Section V-A) as VF bits
+//   k_flag_del     locate and flag the deletion batch's adjacency entries
+//   k_finalize     retire deleted keys, push their slots on the free stack
+#include "mn_internal.h"
+
+namespace {
+
+__device__ inline bool failed(const uint32_t* err) { return *(volatile const uint32_t*)err != 0u; }
+
+__device__ inline void set_err(uint32_t* err, uint32_t code) { atomicCAS(err, 0u, code); }
+
+// Adds delta (+1 / -1 as u32) to the local-filter counters touched by one edge.
+__device__ void count_edge(const GraphView& g, uint32_t s, uint32_t d, uint32_t lab, uint32_t delta) {
+    const uint32_t E = g.n_elab_c, L = g.n_vlab_c;
+    uint32_t* cs = g.cnt + (size_t)s * g.n_cnt;
+    uint32_t* cd = g.cnt + (size_t)d * g.n_cnt;
+    atomicAdd(cs + cnt_index(0, 0, E, L), delta);
+    atomicAdd(cd + cnt_index(1, 0, E, L), delta);
+    int32_t e = g.elab_idx[lab];
+    if (e >= 0) {
+        atomicAdd(cs + cnt_index(0, 1 + e, E, L), delta);
+        atomicAdd(cd + cnt_index(1, 1 + e, E, L), delta);
+    }
+    if (L) {
+        uint64_t md = g.vmask[d], ms = g.vmask[s];
+        while (md) {
+            uint32_t b = __ffsll((unsigned long long)md) - 1;
+            md &= md - 1;
+            int32_t l = g.vlab_idx[b];
+            if (l >= 0) atomicAdd(cs + cnt_index(0, 1 + E + l, E, L), delta);
+        }
+        while (ms) {
+            uint32_t b = __ffsll((unsigned long long)ms) - 1;
+            ms &= ms - 1;
+            int32_t l = g.vlab_idx[b];
+            if (l >= 0) atomicAdd(cd + cnt_index(1, 1 + E + l, E, L), delta);
+        }
+    }
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_reset(uint32_t* err, unsigned long long* a, uint32_t n) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *err = 0;
+    if (i < n) a[i] = 0ull;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_validate(GraphView g, BatchView b) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < b.n_ins) {
+        uint32_t s = b.in_src[i], d = b.in_dst[i], l = b.in_lab[i];
+        if (s >= g.n_vertices || d >= g.n_vertices) set_err(b.err, MN_ERR_VERTEX);
+        if (l >= b.n_elabels) set_err(b.err, MN_ERR_LABEL);
+        int64_t prev = i ? b.in_ts[i - 1] : *b.last_ts;
+        if (b.in_ts[i] < prev) set_err(b.err, MN_ERR_TS);
+    } else if (i < b.n_ins + b.n_del) {
+        uint64_t k = b.del_keys[i - b.n_ins];
+        uint64_t lim = b.next_key + b.n_ins;
+        if (k >= lim) {
+            set_err(b.err, MN_ERR_DELETE);
+        } else if (k < b.next_key && b.key2slot[k] == MN_INVALID) {
+            set_err(b.err, MN_ERR_DELETE);
+        } else {
+            uint32_t bit = 1u << (uint32_t)(k & 31);
+            uint32_t old = atomicOr(&b.delbits[k >> 5], bit);
+            if (old & bit) set_err(b.err, MN_ERR_DELETE);
+        }
+    }
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_prev_del(GraphView g, BatchView b) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n_prev_del || failed(b.err)) return;
+    uint32_t slot = b.prev_del_slot[i];
+    uint32_t s = g.s_src[slot], d = g.s_dst[slot];
+    count_edge(g, s, d, g.s_lab[slot], 0xFFFFFFFFu);
+    b.touched[2 * i] = s;
+    b.touched[2 * i + 1] = d;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n_ins || failed(b.err)) return;
+    uint32_t slot = i < b.n_free ? b.free_stack[b.n_free - 1 - i] : b.fresh + (i - b.n_free);
+    uint32_t s = b.in_src[i], d = b.in_dst[i], l = b.in_lab[i];
+    uint64_t key = b.next_key + i;
+    g.s_src[slot] = s;
+    g.s_dst[slot] = d;
+    g.s_lab[slot] = (uint8_t)l;
+    g.s_ts[slot] = b.in_ts[i];
+    g.s_key[slot] = key;
+    b.key2slot[key] = slot;
+    // edgeMatcher (Section III): edge label equal or query label empty, and
+    // both endpoint label sets contain the query vertices' required sets.
+    uint64_t ms = g.vmask[s], md = g.vmask[d];
+    for (uint32_t w = 0; w < g.debi_words; w++) {
+        uint32_t word = 0;
+        uint32_t lo = w * 32, hi = min(lo + 32, b.n_debi_bits);
+        for (uint32_t bit = lo; bit < hi; bit++) {
+            DebiBit db = b.debi_bits[bit];
+            bool m = (db.label < 0 || (uint32_t)db.label == l) && (db.req_src & ~ms) == 0 &&
+                     (db.req_dst & ~md) == 0;
+            word |= (uint32_t)m << (bit - lo);
+        }
+        g.s_debi[(size_t)slot * g.debi_words + w] = word;
+    }
+    count_edge(g, s, d, l, 1u);
+    uint64_t hs = ((uint64_t)l << g.nbr_bits) | d;  // out-entry high word
+    uint64_t hd = ((uint64_t)l << g.nbr_bits) | s;  // in-entry high word
+    b.skey[0][i] = ((uint64_t)s << b.hb) | hs;
+    b.skey[1][i] = ((uint64_t)d << b.hb) | hd;
+    b.sval[0][i] = slot;
+    b.sval[1][i] = slot;
+    b.ins_slot[i] = slot;
+    b.touched[2 * b.n_prev_del + 2 * i] = s;
+    b.touched[2 * b.n_prev_del + 2 * i + 1] = d;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __restrict__ off, uint32_t nv,
+                                                          uint32_t e_old, const uint64_t* __restrict__ bk,
+                                                          uint32_t n_b, const uint64_t* __restrict__ dpos,
+                                                          uint32_t n_d, uint32_t hb,
+                                                          uint32_t* __restrict__ newoff,
+                                                          uint4* __restrict__ meta, const uint32_t* err) {
+    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv || failed(err)) return;
+    uint32_t bs = 0, be = 0, ds = 0, de = 0;
+    if (n_b) {
+        bs = lower_bound_dev<uint64_t>(bk, 0, n_b, (uint64_t)v << hb);
+        be = lower_bound_dev<uint64_t>(bk, bs, n_b, (uint64_t)(v + 1) << hb);
+    }
+    uint32_t o0 = off[v], o1 = off[v + 1];
+    if (n_d) {
+        ds = lower_bound_dev<uint64_t>(dpos, 0, n_d, (uint64_t)o0);
+        de = lower_bound_dev<uint64_t>(dpos, ds, n_d, (uint64_t)o1);
+    }
+    newoff[v] = o0 - ds + bs;
+    meta[v] = make_uint4(bs, be - bs, ds, de - ds);
+    if (v == nv - 1) newoff[nv] = e_old - n_d + n_b;
+}
+
+constexpr uint32_t MG_ITEMS = 8;
+constexpr uint32_t MG_TILE = MN_BLOCK * MG_ITEMS;
+
+// Old entries: each block takes a tile of the old flat array; the tile's
+// vertex range is found once, then each entry finds its vertex inside it.
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
+    const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj, uint32_t nv, uint32_t e_old,
+    const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
+    const uint64_t* __restrict__ bk, const uint64_t* __restrict__ dpos, uint32_t hb,
+    uint64_t* __restrict__ adj_new, uint32_t e_new, uint32_t* err) {
+    __shared__ uint32_t s_v[2];
+    if (failed(err)) return;
+    uint32_t p0 = blockIdx.x * MG_TILE;
+    uint32_t p1 = min(p0 + MG_TILE, e_old);
+    if (threadIdx.x == 0) s_v[0] = upper_bound_dev<uint32_t>(off, 0, nv + 1, p0) - 1;
+    if (threadIdx.x == 1) s_v[1] = upper_bound_dev<uint32_t>(off, 0, nv + 1, p1 - 1) - 1;
+    __syncthreads();
+    uint32_t vlo = s_v[0], vhi = s_v[1];
+    for (uint32_t k = 0; k < MG_ITEMS; k++) {
+        uint32_t p = p0 + k * MN_BLOCK + threadIdx.x;
+        if (p >= p1) break;
+        uint64_t e = adj[p];
+        if (ent_lo(e) & MN_FLAG) continue;  // deleted by the previous snapshot
+        uint32_t v = upper_bound_dev<uint32_t>(off, vlo, vhi + 1, p) - 1;
+        uint4 m = meta[v];
+        uint32_t kept = p - off[v];
+        if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, (uint64_t)p) - m.z;
+        uint32_t ins = 0;
+        if (m.y) ins = lower_bound_dev<uint64_t>(bk, m.x, m.x + m.y, ((uint64_t)v << hb) | ent_hi(e)) - m.x;
+        uint32_t dst = newoff[v] + kept + ins;
+        if (dst >= e_new) {  // never expected; refuse rather than write out of bounds
+            set_err(err, MN_ERR_INTERNAL);
+            continue;
+        }
+        adj_new[dst] = e;
+    }
+}
+
+// Batch entries: placed after every kept old entry with a high word <= theirs.
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
+    const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj,
+    const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
+    const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, uint32_t n_b,
+    const uint64_t* __restrict__ dpos, uint32_t hb, uint64_t* __restrict__ adj_new,
+    uint32_t* __restrict__ inspos, uint32_t e_new, uint32_t* err) {
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_b || failed(err)) return;
+    uint64_t key = bk[r];
+    uint32_t v = (uint32_t)(key >> hb);
+    uint32_t h = (uint32_t)(key & ((1ull << hb) - 1));
+    uint32_t o0 = off[v], o1 = off[v + 1];
+    uint32_t ub = upper_hi(adj, o0, o1, h);
+    uint4 m = meta[v];
+    uint32_t kept = ub - o0;
+    if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, (uint64_t)ub) - m.z;
+    uint32_t out = newoff[v] + kept + (r - m.x);
+    if (out >= e_new) {  // never expected; refuse rather than write out of bounds
+        set_err(err, MN_ERR_INTERNAL);
+        inspos[r] = 0;
+        return;
+    }
+    adj_new[out] = ((uint64_t)h << 32) | MN_FLAG | bv[r];
+    inspos[r] = out;
+}
+
+// VF bit of (query, vertex u) at data vertex v: label requirement plus the
+// counting filters of Section V-A (f2: edges per direction and label; f3:
+// edges per direction towards each neighbour label), thresholds prepared on
+// the host per semantics.
+__global__ __launch_bounds__(MN_BLOCK) void k_vf_refresh(GraphView g, const VfBit* __restrict__ bits,
+                                                         uint32_t n_bits, const uint32_t* __restrict__ list,
+                                                         uint32_t n, const uint32_t* err) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || failed(err)) return;
+    uint32_t v = list ? list[i] : i;
+    uint64_t mv = g.vmask[v];
+    const uint32_t* c = g.cnt + (size_t)v * g.n_cnt;
+    for (uint32_t w = 0; w < g.vf_words; w++) {
+        uint32_t word = 0;
+        uint32_t lo = w * 32, hi = min(lo + 32, n_bits);
+        for (uint32_t bit = lo; bit < hi; bit++) {
+            VfBit vb = bits[bit];
+            bool ok = (vb.vreq & ~mv) == 0;
+            for (uint32_t r = vb.req_begin; ok && r < vb.req_end; r++) {
+                VfReq q = g.vfreq[r];
+                ok = c[q.cnt] >= q.need;
+            }
+            word |= (uint32_t)ok << (bit - lo);
+        }
+        g.vf[(size_t)v * g.vf_words + w] = word;
+    }
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_set_flags(uint64_t* adj, const uint32_t* __restrict__ pos,
+                                                        uint32_t n, int set, const uint32_t* err) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || failed(err)) return;
+    uint32_t* lo = reinterpret_cast<uint32_t*>(adj) + 2 * (size_t)pos[i];
+    *lo = set ? (*lo | MN_FLAG) : (*lo & MN_SLOTMASK);
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_flag_del(GraphView g, uint64_t* adj_out, uint64_t* adj_in,
+                                                       BatchView b) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n_del || failed(b.err)) return;
+    uint64_t k = b.del_keys[i];
+    uint32_t slot = b.key2slot[k];
+    b.del_slot[i] = slot;
+    uint32_t s = g.s_src[slot], d = g.s_dst[slot], l = g.s_lab[slot];
+    for (uint32_t dir = 0; dir < 2; dir++) {
+        uint32_t v = dir ? d : s;
+        uint32_t h = (l << g.nbr_bits) | (dir ? s : d);
+        uint64_t* adj = dir ? adj_in : adj_out;
+        uint32_t end = g.off[dir][v + 1];
+        uint32_t pos = lower_hi(adj, g.off[dir][v], end, h);
+        uint32_t* w = reinterpret_cast<uint32_t*>(adj);
+        while (pos < end && (w[2 * (size_t)pos] & MN_SLOTMASK) != slot) pos++;  // the run holds this slot
+        if (pos == end) {  // internal inconsistency: never expected
+            set_err(b.err, MN_ERR_INTERNAL);
+            return;
+        }
+        w[2 * (size_t)pos] |= MN_FLAG;
+        b.delpos[dir][i] = pos;
+    }
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_finalize(BatchView b, uint32_t n_free_after) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = !failed(b.err);
+    if (i < b.n_del) {
+        uint64_t k = b.del_keys[i];
+        if (k < b.next_key + b.n_ins) atomicAnd(&b.delbits[k >> 5], ~(1u << (uint32_t)(k & 31)));
+        if (ok) {
+            b.key2slot[k] = MN_INVALID;
+            b.free_stack[n_free_after + i] = b.del_slot[i];
+        }
+    }
+    if (i == 0 && ok && b.n_ins) *b.last_ts = b.in_ts[b.n_ins - 1];
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_init_vertices(uint32_t* vf, uint32_t* cnt, uint32_t nv,
+                                                            uint32_t vf_words, uint32_t n_cnt) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (size_t)nv * vf_words) vf[i] = 0;
+    if (i < (size_t)nv * n_cnt) cnt[i] = 0;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_widen(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                    uint32_t n, const uint32_t* err) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !failed(err)) out[i] = in[i];
+}
+
+inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK); }
+
+}  // namespace
+
+void mn_launch_widen(const uint32_t* in, uint64_t* out, uint32_t n, const uint32_t* err, hipStream_t s) {
+    if (n) k_widen<<<nblocks(n), MN_BLOCK, 0, s>>>(in, out, n, err);
+}
+
+void mn_launch_reset(uint32_t* err, unsigned long long* zero_a, uint32_t n_a, hipStream_t s) {
+    k_reset<<<nblocks(n_a ? n_a : 1), MN_BLOCK, 0, s>>>(err, zero_a, n_a);
+}
+
+void mn_launch_validate(const GraphView& g, const BatchView& b, hipStream_t s) {
+    uint32_t n = b.n_ins + b.n_del;
+    if (n) k_validate<<<nblocks(n), MN_BLOCK, 0, s>>>(g, b);
+}
+
+void mn_launch_prev_del(const GraphView& g, const BatchView& b, hipStream_t s) {
+    if (b.n_prev_del) k_prev_del<<<nblocks(b.n_prev_del), MN_BLOCK, 0, s>>>(g, b);
+}
+
+void mn_launch_ingest(const GraphView& g, const BatchView& b, hipStream_t s) {
+    if (b.n_ins) k_ingest<<<nblocks(b.n_ins), MN_BLOCK, 0, s>>>(g, b);
+}
+
+void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_old,
+                           const uint64_t* bkeys, uint32_t n_b, const uint64_t* dpos, uint32_t n_d,
+                           uint32_t hb, uint32_t* newoff, uint4* meta, const uint32_t* err,
+                           hipStream_t s) {
+    k_vertex_meta<<<nblocks(n_vertices), MN_BLOCK, 0, s>>>(off, n_vertices, e_old, bkeys, n_b, dpos,
+                                                           n_d, hb, newoff, meta, err);
+}
+
+void mn_launch_merge(const uint32_t* off, const uint64_t* adj, uint32_t n_vertices, uint32_t e_old,
+                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
+                     const uint32_t* bvals, uint32_t n_b, const uint64_t* dpos, uint32_t hb,
+                     uint64_t* adj_new, uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s) {
+    if (e_old)
+        k_merge_old<<<(e_old + MG_TILE - 1) / MG_TILE, MN_BLOCK, 0, s>>>(
+            off, adj, n_vertices, e_old, newoff, meta, bkeys, dpos, hb, adj_new, e_new, err);
+    if (n_b)
+        k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, bvals, n_b, dpos,
+                                                      hb, adj_new, inspos, e_new, err);
+}
+
+void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
+                          const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s) {
+    if (n) k_vf_refresh<<<nblocks(n), MN_BLOCK, 0, s>>>(g, bits, n_bits, list, n, err);
+}
+
+void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
+                         const uint32_t* err, hipStream_t s) {
+    if (n) k_set_flags<<<nblocks(n), MN_BLOCK, 0, s>>>(adj, pos, n, set, err);
+}
+
+void mn_launch_flag_del(const GraphView& g, uint64_t* adj_out, uint64_t* adj_in, const BatchView& b,
+                        hipStream_t s) {
+    if (b.n_del) k_flag_del<<<nblocks(b.n_del), MN_BLOCK, 0, s>>>(g, adj_out, adj_in, b);
+}
+
+void mn_launch_finalize(const BatchView& b, uint32_t n_free_after, hipStream_t s) {
+    uint32_t n = b.n_del ? b.n_del : 1;
+    k_finalize<<<nblocks(n), MN_BLOCK, 0, s>>>(b, n_free_after);
+}
+
+void mn_launch_init_vertices(uint32_t* vf, uint32_t* cnt, uint32_t n_vertices, uint32_t vf_words,
+                             uint32_t n_cnt, hipStream_t s) {
+    uint64_t n = (uint64_t)n_vertices * (vf_words > n_cnt ? vf_words : n_cnt);
+    k_init_vertices<<<nblocks(n), MN_BLOCK, 0, s>>>(vf, cnt, n_vertices, vf_words, n_cnt);
+}

@@ -1,0 +1,119 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mn_common.h"
+
+// ------------------------------------------------------------------ sorting
+// Exclusive prefix sum of n u32 values (in may equal out). `scratch` must hold
+// mn_scan_scratch_words(n) words.
+size_t mn_scan_scratch_words(uint32_t n);
+void mn_scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* scratch,
+                       hipStream_t s);
+
+// Stable LSD radix sort of (u64 key, u32 value) pairs on bits [0, nbits).
+// Ping-pongs between (keys, vals) and (ktmp, vtmp); on return keys/vals point
+// at the sorted arrays (the pointers may have been swapped).
+size_t mn_sort_scratch_words(uint32_t n);
+void mn_radix_sort(uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp, uint32_t n,
+                   uint32_t nbits, uint32_t* scratch, hipStream_t s);
+
+// ------------------------------------------------------------------ batches
+// Per-bit descriptors precomputed on the host.
+struct DebiBit {  // one edgeMatcher bit: query edge label and endpoint requirements
+    int32_t label;
+    uint32_t pad;
+    uint64_t req_src;
+    uint64_t req_dst;
+};
+struct VfBit {  // one vertex-filter bit: label requirement and count requirements
+    uint64_t vreq;
+    uint32_t req_begin;
+    uint32_t req_end;
+};
+
+struct BatchView {
+    uint32_t n_ins, n_del, n_prev_del;
+    uint32_t n_free;        // free-slot stack height before this batch
+    uint32_t fresh;         // first never-used slot
+    uint32_t hb;            // composite sort key = (vertex << hb) | high word
+    uint64_t next_key;      // key of the first inserted edge
+    uint32_t n_elabels;
+    uint32_t n_debi_bits;
+    uint32_t n_vf_bits;
+    uint32_t pad;
+    const uint32_t* in_src;
+    const uint32_t* in_dst;
+    const uint8_t* in_lab;
+    const int64_t* in_ts;
+    const uint64_t* del_keys;
+    uint32_t* free_stack;
+    uint32_t* key2slot;
+    uint32_t* delbits;
+    uint32_t* err;
+    int64_t* last_ts;
+    uint32_t* ins_slot;
+    uint64_t* skey[2];
+    uint32_t* sval[2];
+    uint32_t* touched;
+    const uint32_t* prev_del_slot;
+    uint32_t* del_slot;
+    uint32_t* delpos[2];
+    const DebiBit* debi_bits;
+    const VfBit* vf_bits;
+};
+
+void mn_launch_reset(uint32_t* err, unsigned long long* zero_a, uint32_t n_a, hipStream_t s);
+void mn_launch_validate(const GraphView& g, const BatchView& b, hipStream_t s);
+void mn_launch_prev_del(const GraphView& g, const BatchView& b, hipStream_t s);
+void mn_launch_ingest(const GraphView& g, const BatchView& b, hipStream_t s);
+void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_old,
+                           const uint64_t* bkeys, uint32_t n_b, const uint64_t* dpos, uint32_t n_d,
+                           uint32_t hb, uint32_t* newoff, uint4* meta, const uint32_t* err,
+                           hipStream_t s);
+void mn_launch_merge(const uint32_t* off, const uint64_t* adj, uint32_t n_vertices, uint32_t e_old,
+                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
+                     const uint32_t* bvals, uint32_t n_b, const uint64_t* dpos, uint32_t hb,
+                     uint64_t* adj_new, uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s);
+void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
+                          const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
+void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
+                         const uint32_t* err, hipStream_t s);
+void mn_launch_flag_del(const GraphView& g, uint64_t* adj_out, uint64_t* adj_in, const BatchView& b,
+                        hipStream_t s);
+void mn_launch_finalize(const BatchView& b, uint32_t n_free_after, hipStream_t s);
+void mn_launch_init_vertices(uint32_t* vf, uint32_t* cnt, uint32_t n_vertices, uint32_t vf_words,
+                             uint32_t n_cnt, hipStream_t s);
+
+// ------------------------------------------------------------- enumeration
+struct OutView {
+    uint64_t* keys[2];            // [phase] base of this query's tuple buffer
+    uint64_t cap[2];              // tuples
+};
+
+struct EnumStats {  // per phase, accumulated by the enumerator
+    unsigned long long seeds;
+    unsigned long long entries;
+    unsigned long long probe_words;
+    unsigned long long key_reads;
+    unsigned long long tuples;
+    unsigned long long pad[3];
+};
+
+struct PhaseOut {
+    unsigned long long* count;    // [n_queries]
+    unsigned long long* digest;   // [n_queries][2]
+    EnumStats* stats;
+    const OutView* outs;          // [n_queries]
+};
+
+void mn_launch_seed(const GraphView& g, const DebiBit* bits, const uint32_t* slots, uint32_t n,
+                    uint64_t* seeds, uint32_t* n_seeds, const uint32_t* err, hipStream_t s);
+void mn_launch_enumerate(const GraphView& g, const uint64_t* seeds, const uint32_t* n_seeds,
+                         uint32_t max_seeds, uint32_t* cursor, PhaseOut po, int phase, int emit,
+                         const uint32_t* err, hipStream_t s);
+
+// Widens n u32 values into u64 (sort keys).
+void mn_launch_widen(const uint32_t* in, uint64_t* out, uint32_t n, const uint32_t* err, hipStream_t s);

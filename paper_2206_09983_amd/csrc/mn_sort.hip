@@ -1,0 +1,182 @@
+// Device-wide exclusive scan and stable LSD radix sort for gfx950.
+//
+// Both work on 256-thread blocks (four 64-lane waves). The radix sort's
+// scatter ranks keys stably inside a tile with wave ballots: eight ballots on
+// the digit bits give each lane the mask of lanes holding the same digit, and
+// per-wave digit counts in LDS order the four waves of a round.
+#include "mn_internal.h"
+
+namespace {
+
+constexpr uint32_t SC_ITEMS = 8;
+constexpr uint32_t SC_TILE = MN_BLOCK * SC_ITEMS;  // 2048
+constexpr uint32_t RS_ROUNDS = 16;
+constexpr uint32_t RS_TILE = MN_BLOCK * RS_ROUNDS;  // 4096
+constexpr uint32_t RS_WAVES = MN_BLOCK / MN_WAVE;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x) {
+    uint32_t lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < MN_WAVE; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, MN_WAVE);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_scan_local(const uint32_t* __restrict__ in,
+                                                         uint32_t* __restrict__ out,
+                                                         uint32_t* __restrict__ sums, uint32_t n) {
+    __shared__ uint32_t wsum[RS_WAVES];
+    uint32_t tid = threadIdx.x;
+    size_t base = (size_t)blockIdx.x * SC_TILE + (size_t)tid * SC_ITEMS;
+    uint32_t v[SC_ITEMS];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < SC_ITEMS; i++) {
+        size_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0u;
+        tsum += v[i];
+    }
+    uint32_t incl = wave_incl_scan(tsum);
+    uint32_t wave = tid / MN_WAVE;
+    if (__lane_id() == MN_WAVE - 1) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (uint32_t w = 0; w < wave; w++) wpre += wsum[w];
+    uint32_t run = wpre + incl - tsum;
+#pragma unroll
+    for (uint32_t i = 0; i < SC_ITEMS; i++) {
+        size_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    if (tid == MN_BLOCK - 1) sums[blockIdx.x] = wpre + incl;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_scan_add(uint32_t* __restrict__ out,
+                                                       const uint32_t* __restrict__ sums, uint32_t n) {
+    uint32_t add = sums[blockIdx.x];
+    size_t base = (size_t)blockIdx.x * SC_TILE;
+    for (uint32_t i = threadIdx.x; i < SC_TILE; i += MN_BLOCK) {
+        size_t idx = base + i;
+        if (idx < n) out[idx] += add;
+    }
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n,
+                                                      uint32_t shift, uint32_t* __restrict__ hist,
+                                                      uint32_t nblk) {
+    __shared__ uint32_t h[256];
+    uint32_t tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    size_t base = (size_t)blockIdx.x * RS_TILE;
+    for (uint32_t r = 0; r < RS_ROUNDS; r++) {
+        size_t idx = base + (size_t)r * MN_BLOCK + tid;
+        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)tid * nblk + blockIdx.x] = h[tid];
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint64_t* __restrict__ kout,
+                                                         uint32_t* __restrict__ vout, uint32_t n,
+                                                         uint32_t shift,
+                                                         const uint32_t* __restrict__ hist,
+                                                         uint32_t nblk) {
+    __shared__ uint32_t base_off[256];
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    uint32_t tid = threadIdx.x;
+    uint32_t wave = tid / MN_WAVE;
+    base_off[tid] = hist[(size_t)tid * nblk + blockIdx.x];
+    for (uint32_t w = 0; w < RS_WAVES; w++) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    size_t base = (size_t)blockIdx.x * RS_TILE;
+    for (uint32_t r = 0; r < RS_ROUNDS; r++) {
+        size_t idx = base + (size_t)r * MN_BLOCK + tid;
+        bool valid = idx < n;
+        uint64_t key = valid ? kin[idx] : 0ull;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; b++) {
+            uint32_t bit = (d >> b) & 1u;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        if (!valid) peers = 0;
+        bool leader = valid && (peers & lt) == 0;
+        if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t rank = base_off[d] + (uint32_t)__popcll(peers & lt);
+            for (uint32_t w = 0; w < wave; w++) rank += wcnt[w][d];
+            if (rank < n) {  // always true for a consistent histogram
+                kout[rank] = key;
+                vout[rank] = vin[idx];
+            }
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        for (uint32_t w = 0; w < RS_WAVES; w++) {
+            tot += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        base_off[tid] += tot;
+        __syncthreads();
+    }
+}
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+}  // namespace
+
+size_t mn_scan_scratch_words(uint32_t n) {
+    size_t words = 4;
+    uint64_t m = n;
+    while (m > 1) {
+        m = (m + SC_TILE - 1) / SC_TILE;
+        words += m + 1;
+    }
+    return words;
+}
+
+void mn_scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* scratch,
+                       hipStream_t s) {
+    if (n == 0) return;
+    uint32_t nb = ceil_div(n, SC_TILE);
+    uint32_t* sums = scratch;
+    k_scan_local<<<nb, MN_BLOCK, 0, s>>>(in, out, sums, n);
+    if (nb == 1) return;
+    mn_scan_exclusive(sums, sums, nb, scratch + nb + 1, s);
+    k_scan_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n);
+}
+
+size_t mn_sort_scratch_words(uint32_t n) {
+    uint32_t nblk = ceil_div(n ? n : 1, RS_TILE);
+    size_t hist = (size_t)256 * nblk;
+    return hist + mn_scan_scratch_words((uint32_t)hist);
+}
+
+void mn_radix_sort(uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp, uint32_t n,
+                   uint32_t nbits, uint32_t* scratch, hipStream_t s) {
+    if (n <= 1 || nbits == 0) return;
+    uint32_t nblk = ceil_div(n, RS_TILE);
+    uint32_t* hist = scratch;
+    uint32_t* sscr = scratch + (size_t)256 * nblk;
+    for (uint32_t shift = 0; shift < nbits; shift += 8) {
+        k_rs_hist<<<nblk, MN_BLOCK, 0, s>>>(keys, n, shift, hist, nblk);
+        mn_scan_exclusive(hist, hist, 256 * nblk, sscr, s);
+        k_rs_scatter<<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
+        uint64_t* tk = keys;
+        keys = ktmp;
+        ktmp = tk;
+        uint32_t* tv = vals;
+        vals = vtmp;
+        vtmp = tv;
+    }
+}

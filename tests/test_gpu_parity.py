@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Every test drives the same seeded stream through the C ABI (via the ctypes
+binding) and through the oracle, and compares per batch and per query the
+canonically sorted lists of new and expired embeddings (bit-exact keys), the
+counts, and the two 64-bit digests.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.core import Oracle
+from paper_2206_09983_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2206_09983_amd import binding
+    binding.load()
+    return binding
+
+
+def canon(rows):
+    rows = np.asarray(rows, dtype=np.uint64)
+    if len(rows) == 0:
+        return rows.reshape(0, rows.shape[1] if rows.ndim == 2 else 0)
+    order = np.lexsort(rows.T[::-1])
+    return rows[order]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_parity(B, case, batches=None, flags=None, out_capacity=0, n_elabels=0, check_lists=True):
+    batches = case["batches"] if batches is None else batches
+    flags = B.F_EMIT if flags is None else flags
+    qs = case["queries"]
+    say("parity case", case["name"], "queries", len(qs), "batches", len(batches))
+    o = Oracle(case["graph"], qs)
+    m = B.Matcher(case["graph"], qs, flags=flags, out_capacity=out_capacity, n_elabels=n_elabels)
+    total = 0
+    try:
+        for bi, b in enumerate(batches):
+            o.apply_batch(b)
+            first = m.apply_batch(b)
+            assert first == o.n_keys - len(b["src"])
+            for qi in range(len(qs)):
+                r = m.result(qi)
+                for ph, name in ((False, "new"), (True, "expired")):
+                    n = r["n_expired"] if ph else r["n_new"]
+                    assert n == o.count(qi, ph), (bi, qi, name)
+                    assert (r["dig_expired"] if ph else r["dig_new"]) == o.digest(qi, ph), (bi, qi, name)
+                    if check_lists and flags & B.F_EMIT:
+                        got = canon(m.keys(qi, ph))
+                        np.testing.assert_array_equal(got, o.result(qi, ph), err_msg="%d %d %s" % (bi, qi, name))
+                    total += n
+    finally:
+        m.close()
+        o.close()
+    return total
+
+
+# ------------------------------------------------------------------ small cases
+def test_paper_example(B):
+    with open(os.path.join(GOLDEN, "paper_example.json")) as f:
+        fx = json.load(f)
+    e = np.array(fx["initial_edges"], dtype=np.int64)
+    g = synth.make_graph(fx["n_vertices"], fx["vlabel_mask"], e[:, 0], e[:, 1], e[:, 2])
+    qd = fx["query"]
+    qs = [synth.make_query(qd["n_qv"], qd["vreq"], qd["edges"], sem) for sem in (synth.ISO, synth.HOMO)]
+    batches, nk = [], len(e)
+    for b in fx["batches"]:
+        ins = np.array(b["insert"], dtype=np.int64).reshape(-1, 3)
+        batches.append(synth.make_batch(ins[:, 0], ins[:, 1], ins[:, 2], np.arange(nk, nk + len(ins)), b["delete"]))
+        nk += len(ins)
+    case = {"name": "paper_example", "graph": g, "batches": batches, "queries": qs}
+    assert run_parity(B, case) > 0
+    # the two embeddings printed for t1, in the start-(u1,u3) order
+    m = B.Matcher(g, qs[:1])
+    m.apply_batch(batches[0])
+    pr = fx["printed"]["iso_new_at_t1_ids_start_order"]
+    got = sorted([[int(r[k]) for k in pr["order"]] for r in m.keys(0)])
+    assert got == sorted(pr["value"])
+    m.close()
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_tiny_random_multigraphs(B, block):
+    total = 0
+    for seed in range(block * 50, block * 50 + 50):
+        total += run_parity(B, synth.tiny_case(seed))
+    assert total > 0
+
+
+def test_tiny_dense_wildcard_queries(B):
+    total = 0
+    for seed in range(2000, 2040):
+        case = synth.tiny_case(seed, max_v=4, max_init=12, max_ins=6, n_vlabels=1, n_elabels=1, max_qv=5,
+                               wild_p=0.6)
+        total += run_parity(B, case)
+    assert total > 100
+
+
+def test_chung_lu_all_batches(B):
+    case = synth.chung_lu_case()
+    assert run_parity(B, case) > 0
+
+
+def test_rmat_small_with_deletions_all_queries(B):
+    case = synth.rmat_case(scale=12, n_init=40000, n_stream=8192, batch=2048, n_batches=4)
+    assert run_parity(B, case) > 0
+
+
+def test_rmat_ragged_batches_and_wide_labels(B):
+    # batch sizes that are not multiples of the tile sizes, and queries with
+    # wildcard edges and wildcard vertices
+    case = synth.rmat_case(scale=10, n_init=9000, n_stream=3000, batch=1000, n_batches=3,
+                           n_vlabels=3, n_elabels=4)
+    sizes = [1, 63, 64, 65, 777, 1000]
+    g = case["graph"]
+    rng = np.random.default_rng(5)
+    batches = []
+    nk = len(g["src"])
+    oldest = 0
+    for s in sizes:
+        src = rng.integers(0, g["n_vertices"], s)
+        dst = rng.integers(0, g["n_vertices"], s)
+        lab = rng.integers(0, 4, s)
+        nd = s // 7
+        batches.append(synth.make_batch(src, dst, lab, np.arange(nk, nk + s), np.arange(oldest, oldest + nd)))
+        oldest += nd
+        nk += s
+    qs = [synth.make_query(3, [0, 0, 0], [(0, 1, -1), (1, 2, 1), (2, 0, -1)], synth.ISO),
+          synth.make_query(3, [0, 0, 0], [(0, 1, -1), (1, 2, 1), (2, 0, -1)], synth.HOMO),
+          synth.make_query(4, [1, 0, 2, 0], [(0, 1, 0), (1, 2, -1), (2, 3, 2), (1, 3, -1)], synth.ISO),
+          synth.make_query(2, [0, 0], [(0, 1, 0), (1, 0, -1)], synth.HOMO)]
+    case = {"name": "ragged", "graph": g, "batches": batches, "queries": qs}
+    assert run_parity(B, case) > 0
+
+
+def test_output_overflow_regrows_and_reruns(B):
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
+    assert run_parity(B, case, out_capacity=1) > 0
+
+
+def test_count_only_mode_gives_same_counts_and_digests(B):
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
+    assert run_parity(B, case, flags=0, check_lists=False) > 0
+
+
+def test_empty_and_delete_only_batches(B):
+    case = synth.chung_lu_case(n=200, n_init=1500, n_stream=0, batch=1)
+    g = case["graph"]
+    e = synth.make_batch([], [], [], [], [])
+    d_only = synth.make_batch([], [], [], [], np.arange(0, 300))
+    ins = synth.make_batch([1, 2, 3], [2, 3, 1], [0, 1, 2], [2000, 2001, 2002], [])
+    del_own = synth.make_batch([4, 5], [5, 6], [0, 1], [2003, 2004], [1503, 1504, 300])
+    batches = [e, d_only, e, ins, del_own, e]
+    assert run_parity(B, dict(case, batches=batches)) >= 0
+
+
+def test_bad_batches_fail_atomically(B):
+    case = synth.chung_lu_case(n=300, n_init=2500, n_stream=512, batch=256)
+    g, qs = case["graph"], case["queries"]
+    good = case["batches"]
+    m = B.Matcher(g, qs, n_elabels=8)
+    o = Oracle(g, qs)
+    nv = g["n_vertices"]
+    try:
+        o.apply_batch(good[0])
+        m.apply_batch(good[0])
+        o.delete([7], enumerate=False)
+        m.apply_batch(synth.make_batch([], [], [], [], [7]))
+        nk = o.n_keys
+        t = int(good[0]["ts"][-1]) + 1
+        bad = [
+            (synth.make_batch([0, nv], [1, 2], [0, 0], [t, t + 1], []), "MNEMONIC_E_VERTEX"),
+            (synth.make_batch([0], [1], [8], [t], []), "MNEMONIC_E_LABEL"),
+            (synth.make_batch([0, 1], [1, 2], [0, 0], [t + 5, t], []), "MNEMONIC_E_TS_ORDER"),
+            (synth.make_batch([0], [1], [0], [t - 100], []), "MNEMONIC_E_TS_ORDER"),
+            (synth.make_batch([], [], [], [], [3, 3]), "MNEMONIC_E_BAD_DELETE"),
+            (synth.make_batch([], [], [], [], [10 ** 9]), "MNEMONIC_E_BAD_DELETE"),
+            (synth.make_batch([0], [1], [0], [t], [nk + 1]), "MNEMONIC_E_BAD_DELETE"),
+            (synth.make_batch([], [], [], [], [7]), "MNEMONIC_E_BAD_DELETE"),  # already deleted
+        ]
+        for b, name in bad:
+            with pytest.raises(B.MnemonicError) as ei:
+                m.apply_batch(b)
+            assert ei.value.name == name, (name, str(ei.value))
+        # nothing changed: the next good batch matches the oracle exactly
+        b = good[1]
+        o.apply_batch(b)
+        m.apply_batch(b)
+        for qi in range(len(qs)):
+            np.testing.assert_array_equal(canon(m.keys(qi)), o.result(qi))
+            assert m.result(qi)["dig_new"] == o.digest(qi)
+    finally:
+        m.close()
+        o.close()
+
+
+def test_unsupported_queries_are_rejected(B):
+    g = synth.make_graph(3, [1, 1, 1], [0], [1], [0])
+    with pytest.raises(B.MnemonicError) as ei:
+        B.Matcher(g, [synth.make_query(3, [0, 0, 0], [(0, 1, -1)], synth.ISO)])
+    assert ei.value.name == "MNEMONIC_E_QUERY"
+    with pytest.raises(B.MnemonicError) as ei:
+        B.Matcher(g, [synth.make_query(2, [0, 0], [(0, 0, -1)], synth.ISO)])
+    assert ei.value.name == "MNEMONIC_E_QUERY"
+
+
+def test_device_resident_inputs(B):
+    torch = pytest.importorskip("torch")
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
+    qs = case["queries"]
+    o = Oracle(case["graph"], qs)
+    m = B.Matcher(case["graph"], qs, stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        for b in case["batches"]:
+            db = {"src": torch.from_numpy(b["src"].astype(np.int32)).cuda(),
+                  "dst": torch.from_numpy(b["dst"].astype(np.int32)).cuda(),
+                  "elabel": torch.from_numpy(b["elabel"]).cuda(),
+                  "ts": torch.from_numpy(b["ts"]).cuda(),
+                  "del_keys": torch.from_numpy(b["del_keys"].astype(np.int64)).cuda()}
+            torch.cuda.synchronize()
+            o.apply_batch(b)
+            m.apply_batch(db)
+            for qi in range(len(qs)):
+                for ph in (False, True):
+                    np.testing.assert_array_equal(canon(m.keys(qi, ph)), o.result(qi, ph))
+    finally:
+        m.close()
+        o.close()
