@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Throughput of the streaming matcher's hot path on one MI355X.
+
+One step = one snapshot of the paper's batch loop (Algorithm 1 body,
+Algorithm 2): validate and ingest a batch of insertions, merge them into the
+sorted adjacency, edgeMatcher, vertex filter, enumerate the new embeddings,
+then flag and enumerate the embeddings the batch's deletions expire, retire
+the deleted edges and reduce counts and digests. Every step runs in the HIP
+library through its C ABI; the batch arrays are resident in HBM before the
+timed region starts.
+
+Workload (stand-in for the paper's NetFlow/LSBench streams, Section VII):
+R-MAT (a=.57, b=.19, c=.19, d=.05) with 2^20 vertices and 2^24 initial edges,
+~10% parallel multi-edges, Zipf(1.2) vertex labels over 16 and edge labels
+over 32, int64 timestamps; batches of 65,536 insertions, each followed by
+deletion of the 6,553 oldest live edges; queries triangle-with-tail, 4-cycle
+and 5-path, each under isomorphism and homomorphism (six query runs over the
+same stream).
+
+Prints ONE JSON line. ``value`` = stream edges (insertions + deletions) fully
+processed per second; embeddings/s and p50/p99 batch latency ride along.
+``roofline`` reports the enumerator kernel's algorithmic bytes per launch
+divided by its average launch time (HIP events on the library's stream),
+against the 8 TB/s HBM peak. ``cpu_baseline`` times the single-threaded CPU
+oracle on a bounded prefix of the same stream.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "matched data edges/sec + new embeddings/sec at 1 GPU; p99 batch latency; learned vs plain"
+HBM_PEAK_GBS = 8000.0
+ENUM_SRC = os.path.join(ROOT, "paper_2206_09983_amd", "csrc", "mn_enum.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_enumerate_traffic_rmat_s20.txt")
+
+# Algorithmic bytes the enumerator must move, per unit of work it counts:
+#   seed: the 8 B work unit + src, dst (4 B each) and key (8 B) of its slot
+#   candidate: one 8 B adjacency entry; vertex-filter test: one 4 B word
+#   binary-search / closing-run probe: one 4 B word; edge key gathered: 8 B
+#   tuple key written: 8 B
+BYTES = {"seeds": 24, "entries_scanned": 8, "vf_reads": 4, "probe_words": 4, "key_reads": 8,
+         "tuple_words": 8}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--n-init", type=int, default=1 << 24)
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--del-frac", type=float, default=0.10)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--count-only", action="store_true", help="counts and digests only, no tuples")
+    ap.add_argument("--out-capacity", type=int, default=1 << 22, help="initial tuples per result buffer")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
+    return ap.parse_args()
+
+
+def enum_source_hash():
+    with open(ENUM_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """Per-launch HBM bytes of the enumerator from the committed counter
+    summary, or None when absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != enum_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+def cpu_baseline(case, budget_s):
+    """Times the CPU oracle (single thread) on a prefix of the first stream
+    batch, applied as consecutive sub-batches of doubling size, until the
+    budget is spent. Returns edges/s over the sample and its description."""
+    import numpy as np
+
+    from oracle.core import Oracle
+    from paper_2206_09983_amd import synth
+
+    b = case["batches"][0]
+    n_ins, n_del = len(b["src"]), len(b["del_keys"])
+    t0 = time.perf_counter()
+    o = Oracle(case["graph"], case["queries"], limit=1 << 22)
+    t_load = time.perf_counter() - t0
+    done_i = done_d = 0
+    spent = 0.0
+    size = 64
+    while done_i < n_ins and spent < budget_s:
+        s = min(size, n_ins - done_i)
+        d = min(n_del - done_d, int(round((done_i + s) * n_del / n_ins)) - done_d)
+        sl = slice(done_i, done_i + s)
+        sub = synth.make_batch(b["src"][sl], b["dst"][sl], b["elabel"][sl], b["ts"][sl],
+                               b["del_keys"][done_d:done_d + d])
+        t1 = time.perf_counter()
+        o.apply_batch(sub)
+        spent += time.perf_counter() - t1
+        done_i += s
+        done_d += d
+        size *= 2
+    emb = 0
+    o.close()
+    rate = (done_i + done_d) / spent if spent > 0 else 0.0
+    desc = ("oracle, 1 thread: first %d insertions + %d oldest-key deletions of stream batch 0, in "
+            "doubling sub-batches from 64; %.1f s timed (graph load %.1f s not timed)"
+            % (done_i, done_d, spent, t_load))
+    return rate, desc, np
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the matcher runs on a single MI355X; "
+              "--gpus %d is not supported (how the path would shard is documented, not built)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2206_09983_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    binding.load()  # raises if the HIP library is missing: there is no other path
+    torch.cuda.set_device(0)
+    n_batches = args.warmup + args.steps
+    t0 = time.perf_counter()
+    # the whole 2^23-insertion stream is always drawn, so the graph and every
+    # batch are the same whatever --steps and --warmup say
+    case = synth.rmat_case(scale=args.scale, n_init=args.n_init, n_stream=max(1 << 23, n_batches * args.batch),
+                           batch=args.batch, del_frac=args.del_frac, seed=args.seed, query_seed=7)
+    log("generated %s: %d initial edges, %d batches in %.1f s" % (case["name"], len(case["graph"]["src"]),
+                                                                   len(case["batches"]), time.perf_counter() - t0))
+    stream = torch.cuda.current_stream()
+    dev_batches = []
+    for b in case["batches"][:n_batches]:
+        dev_batches.append({"src": torch.from_numpy(b["src"].view(np.int32)).cuda(),
+                            "dst": torch.from_numpy(b["dst"].view(np.int32)).cuda(),
+                            "elabel": torch.from_numpy(b["elabel"]).cuda(),
+                            "ts": torch.from_numpy(b["ts"]).cuda(),
+                            "del_keys": torch.from_numpy(b["del_keys"].view(np.int64)).cuda()})
+    torch.cuda.synchronize()
+    flags = binding.F_TIMING | (0 if args.count_only else binding.F_EMIT)
+    t0 = time.perf_counter()
+    m = binding.Matcher(case["graph"], case["queries"], flags=flags, out_capacity=args.out_capacity,
+                        stream=stream.cuda_stream, n_elabels=32)
+    torch.cuda.synchronize()
+    log("create (upload + sort + index of %d edges): %.2f s" % (len(case["graph"]["src"]), time.perf_counter() - t0))
+
+    for i in range(args.warmup):
+        m.apply_batch(dev_batches[i])
+        st = m.stats()
+        log("warmup %d: %.2f ms, tuples %s" % (i, st["ms_batch"], st["tuples"]))
+
+    lat = []
+    keys = list(BYTES)
+    tot = {k: 0 for k in keys}
+    enum_ms = 0.0
+    launches = 0
+    tuples = 0
+    edges = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.warmup, n_batches):
+        tb = time.perf_counter()
+        m.apply_batch(dev_batches[i])  # returns once the batch's counts and digests are on the host
+        lat.append((time.perf_counter() - tb) * 1e3)
+        st = m.stats()
+        for p in range(2):
+            if st["seeds"][p] or st["ms_enumerate"][p] > 0:
+                launches += 1
+            enum_ms += st["ms_enumerate"][p]
+            for k in keys:
+                tot[k] += st[k][p]
+        tuples += st["tuples"][0] + st["tuples"][1]
+        edges += len(case["batches"][i]["src"]) + len(case["batches"][i]["del_keys"])
+        log("step %d: %.2f ms (enum %.2f + %.2f ms), seeds %s, tuples %s" % (
+            i, lat[-1], st["ms_enumerate"][0], st["ms_enumerate"][1], st["seeds"], st["tuples"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    m.close()
+
+    if args.count_only:
+        tot["tuple_words"] = 0
+    alg_bytes = sum(BYTES[k] * tot[k] for k in keys)
+    per_launch = alg_bytes / max(launches, 1)
+    avg_ms = enum_ms / max(launches, 1)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = read_traffic()
+    lat_s = sorted(lat)
+
+    def pct(p):
+        return lat_s[min(len(lat_s) - 1, int(np.ceil(p / 100.0 * len(lat_s))) - 1)]
+
+    out = {
+        "metric": METRIC,
+        "value": edges / elapsed,
+        "unit": "matched data edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic (seeded R-MAT stream, stand-in for the paper's NetFlow/LSBench streams)",
+        "config": {
+            "workload": "rmat_s%d_init%d_batch%d_del%d%%_tt_c4_p5_iso_homo" % (
+                args.scale, args.n_init, args.batch, int(round(args.del_frac * 100))),
+            "vertices": 1 << args.scale, "initial_edges": args.n_init, "batch_insertions": args.batch,
+            "batch_deletions": int(args.del_frac * args.batch), "queries": [q["name"] for q in case["queries"]],
+            "emit_tuples": not args.count_only, "seed": args.seed,
+        },
+        "embeddings_per_s": tuples / elapsed,
+        "p50_batch_ms": pct(50),
+        "p99_batch_ms": pct(99),
+        "learned_vs_plain": None,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_enumerate", "alg_bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
+            "launches": launches,
+        },
+    }
+    if not args.no_cpu_baseline:
+        rate, desc, _ = cpu_baseline(case, args.cpu_seconds)
+        out["cpu_baseline"] = {"value": rate, "unit": "matched data edges/s", "cores": 1, "kind": "oracle",
+                               "sample": desc}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
