@@ -19,8 +19,9 @@ same stream).
 
 Prints ONE JSON line. ``value`` = stream edges (insertions + deletions) fully
 processed per second; embeddings/s and p50/p99 batch latency ride along.
-``roofline`` reports the enumerator kernel's algorithmic bytes per launch
-divided by its average launch time (HIP events on the library's stream),
+``roofline`` reports the expansion kernel's (k_expand, the enumerator's
+dominant kernel) algorithmic bytes per launch divided by its average launch
+time (HIP events the library records around each launch on its stream),
 against the 8 TB/s HBM peak. ``cpu_baseline`` times the single-threaded CPU
 oracle on a bounded prefix of the same stream.
 """
@@ -38,15 +39,15 @@ if ROOT not in sys.path:
 METRIC = "matched data edges/sec + new embeddings/sec at 1 GPU; p99 batch latency; learned vs plain"
 HBM_PEAK_GBS = 8000.0
 ENUM_SRC = os.path.join(ROOT, "paper_2206_09983_amd", "csrc", "mn_enum.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_enumerate_traffic_rmat_s20.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_expand_traffic_rmat_s20.txt")
 
-# Algorithmic bytes the enumerator must move, per unit of work it counts:
-#   seed: the 8 B work unit + src, dst (4 B each) and key (8 B) of its slot
-#   candidate: one 8 B adjacency entry; vertex-filter test: one 4 B word
-#   binary-search / closing-run probe: one 4 B word; edge key gathered: 8 B
-#   tuple key written: 8 B
-BYTES = {"seeds": 24, "entries_scanned": 8, "vf_reads": 4, "probe_words": 4, "key_reads": 8,
-         "tuple_words": 8}
+# Algorithmic bytes k_expand must move, per unit of work it counts:
+#   candidate: one 8 B adjacency entry; vertex-filter test: one 4 B word;
+#   closing-edge lookup: one 4 B word per probe (binary search, run walk,
+#   offsets); edge key gathered for a tuple: 8 B; tuple key written: 8 B.
+# Rows of partial embeddings passed between levels are this implementation's
+# choice, not the method's, and are not counted.
+BYTES = {"entries_scanned": 8, "vf_reads": 4, "probe_words": 4, "key_reads": 8, "tuple_words": 8}
 
 
 def log(*a):
@@ -198,8 +199,9 @@ def main():
     lat = []
     keys = list(BYTES)
     tot = {k: 0 for k in keys}
-    enum_ms = 0.0
+    expand_ms = 0.0
     launches = 0
+    rows = 0
     tuples = 0
     edges = 0
     torch.cuda.synchronize()
@@ -210,15 +212,17 @@ def main():
         lat.append((time.perf_counter() - tb) * 1e3)
         st = m.stats()
         for p in range(2):
-            if st["seeds"][p] or st["ms_enumerate"][p] > 0:
-                launches += 1
-            enum_ms += st["ms_enumerate"][p]
+            launches += st["expand_launches"][p]
+            expand_ms += st["ms_expand"][p]
+            rows += st["frontier_rows"][p]
             for k in keys:
                 tot[k] += st[k][p]
         tuples += st["tuples"][0] + st["tuples"][1]
         edges += len(case["batches"][i]["src"]) + len(case["batches"][i]["del_keys"])
-        log("step %d: %.2f ms (enum %.2f + %.2f ms), seeds %s, tuples %s" % (
-            i, lat[-1], st["ms_enumerate"][0], st["ms_enumerate"][1], st["seeds"], st["tuples"]))
+        log("step %d: %.2f ms (enumerate %.2f + %.2f ms, of which k_expand %.2f + %.2f ms in %s launches), "
+            "seeds %s, rows %s, candidates %s, tuples %s" % (
+                i, lat[-1], st["ms_enumerate"][0], st["ms_enumerate"][1], st["ms_expand"][0], st["ms_expand"][1],
+                st["expand_launches"], st["seeds"], st["frontier_rows"], st["entries_scanned"], st["tuples"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     m.close()
@@ -227,7 +231,7 @@ def main():
         tot["tuple_words"] = 0
     alg_bytes = sum(BYTES[k] * tot[k] for k in keys)
     per_launch = alg_bytes / max(launches, 1)
-    avg_ms = enum_ms / max(launches, 1)
+    avg_ms = expand_ms / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = read_traffic()
     lat_s = sorted(lat)
@@ -262,8 +266,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_enumerate", "alg_bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
-            "launches": launches,
+            "kernel": "k_expand", "alg_bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
+            "launches": launches, "frontier_rows_per_launch": rows / max(launches, 1),
         },
     }
     if not args.no_cpu_baseline:

@@ -115,19 +115,38 @@ typedef struct {
     uint32_t n_qe;
 } mnemonic_result;
 
-/* Work and timing of the last successful batch. Per phase p (0 insert,
- * 1 delete): enumeration work units (seeds), adjacency entries scanned,
- * adjacency words read by binary searches, edge keys gathered, tuples
- * emitted, and (with MNEMONIC_F_TIMING) the enumeration kernel time. */
+/* Work and timing of the last successful batch, per phase p (0 insert,
+ * 1 delete). The enumerator runs level by level (see mnemonic_apply_batch):
+ *   seeds              work units (start edge at one query-edge position) that
+ *                      passed edgeMatcher, the vertex filter and the
+ *                      start-level closing edges
+ *   entries_scanned    candidate adjacency entries tested by the expansion kernel
+ *   probe_words        adjacency words the expansion kernel read to find and
+ *                      walk closing-edge instances
+ *   range_probe_words  adjacency words read by the per-level binary searches
+ *                      that delimit each partial embedding's candidates
+ *   key_reads          edge keys gathered for emitted tuples
+ *   tuples             embeddings found; tuple_words = tuples x |E_Q| keys
+ *   vf_reads           vertex-filter words tested
+ *   frontier_rows      partial embeddings passed from one level to the next
+ *   expand_launches    launches of the expansion kernel
+ * With MNEMONIC_F_TIMING: ms_expand = summed device time of the expansion
+ * launches, ms_enumerate = the whole enumeration phase, ms_batch = the whole
+ * snapshot on the device. */
 typedef struct {
     uint64_t n_live_edges;
     uint64_t slot_high_water;
     uint64_t seeds[2];
     uint64_t entries_scanned[2];
     uint64_t probe_words[2];
+    uint64_t range_probe_words[2];
     uint64_t key_reads[2];
     uint64_t tuples[2];
     uint64_t tuple_words[2];
+    uint64_t vf_reads[2];
+    uint64_t frontier_rows[2];
+    uint64_t expand_launches[2];
+    double ms_expand[2];
     double ms_enumerate[2];
     double ms_batch;
 } mnemonic_stats;

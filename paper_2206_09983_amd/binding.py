@@ -62,8 +62,10 @@ class mnemonic_result(C.Structure):
 class mnemonic_stats(C.Structure):
     _fields_ = [("n_live_edges", C.c_uint64), ("slot_high_water", C.c_uint64), ("seeds", C.c_uint64 * 2),
                 ("entries_scanned", C.c_uint64 * 2), ("probe_words", C.c_uint64 * 2),
-                ("key_reads", C.c_uint64 * 2), ("tuples", C.c_uint64 * 2), ("tuple_words", C.c_uint64 * 2),
-                ("ms_enumerate", C.c_double * 2), ("ms_batch", C.c_double)]
+                ("range_probe_words", C.c_uint64 * 2), ("key_reads", C.c_uint64 * 2),
+                ("tuples", C.c_uint64 * 2), ("tuple_words", C.c_uint64 * 2), ("vf_reads", C.c_uint64 * 2),
+                ("frontier_rows", C.c_uint64 * 2), ("expand_launches", C.c_uint64 * 2),
+                ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2), ("ms_batch", C.c_double)]
 
 
 class MnemonicError(RuntimeError):

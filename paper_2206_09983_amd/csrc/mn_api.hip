@@ -94,8 +94,15 @@ struct mnemonic_ctx {
     uint32_t flags = MNEMONIC_F_EMIT;
     uint32_t nV = 0, n_elabels = 256, nbr_bits = 1, hb = 1;
 
+    // vertex classes: distinct label sets in increasing order; internal ids
+    // number the vertices class by class (cls_start[c] = first id of class c)
+    std::vector<uint64_t> cls_mask;
+    std::vector<uint32_t> cls_start;
+    uint32_t* d_ext2int = nullptr;
+
     // queries and their preprocessed tables
     uint32_t n_q = 0;
+    uint32_t n_plans = 0, max_levels = 0, wv = 2, we = 1;
     std::vector<QueryDev> hq;
     std::vector<SeedPlan> hplans;
     std::vector<DebiBit> hdebi;
@@ -143,7 +150,7 @@ struct mnemonic_ctx {
     uint64_t* d_adj2[2] = {nullptr, nullptr};
 
     // batch scratch
-    uint64_t cap_ins = 0, cap_del = 0, cap_seed = 0, cap_touch = 0, cap_sort = 0;
+    uint64_t cap_ins = 0, cap_del = 0, cap_touch = 0, cap_sort = 0;
     uint32_t* d_in_src = nullptr;
     uint32_t* d_in_dst = nullptr;
     uint8_t* d_in_lab = nullptr;
@@ -162,7 +169,26 @@ struct mnemonic_ctx {
     uint32_t hb_pos = 32;  // significant bits of an adjacency position
     uint32_t* d_sort_scratch = nullptr;
     uint64_t cap_sort_scratch = 0;
-    uint64_t* d_seeds[2] = {nullptr, nullptr};
+
+    // level-wise enumeration: rows of partial embeddings per level, their
+    // candidate runs and offsets, scan scratch and small control words
+    struct LevelBuf {
+        uint32_t* rows = nullptr;  // cap x ncol words, column-wise
+        uint32_t* lo = nullptr;
+        uint32_t* cnt = nullptr;
+        uint64_t* off = nullptr;
+        uint64_t cap = 0;
+    };
+    std::vector<LevelBuf> lvb;
+    uint64_t rows_max = 1ull << 22;  // rows per level buffer (bounds each expansion chunk)
+    uint64_t* d_scan64 = nullptr;
+    uint64_t cap_scan64 = 0;
+    uint32_t* d_nrows = nullptr;     // [MN_MAXLV + 1] row counters
+    uint64_t* d_total = nullptr;     // candidate total of the last scan
+    uint64_t* h_ctl = nullptr;       // pinned: readback of counters
+    hipEvent_t ev_x[2] = {nullptr, nullptr};  // around each expansion launch
+    double ms_expand[2] = {0, 0};
+    uint64_t n_expand[2] = {0, 0};
 
     // control block: err, last_ts, zeroed counters
     uint32_t* d_err = nullptr;
@@ -191,19 +217,68 @@ struct mnemonic_ctx {
     uint32_t zr_count(int p) const { return 4u + (uint32_t)p * n_q; }
     uint32_t zr_digest(int p) const { return 4u + 2u * n_q + 2u * (uint32_t)p * n_q; }
     uint32_t zr_stats(int p) const { return 4u + 6u * n_q + 8u * (uint32_t)p; }
+    uint32_t ncol() const { return 1 + wv + we; }
 };
 
 namespace {
 
 // ----------------------------------------------------------------- planning
+// Internal id range [id_lo, id_hi) spanning every vertex class whose label set
+// contains `req`; `exact` when every class in between does too. Returns false
+// when no class qualifies.
+bool class_hull(const mnemonic_ctx* c, uint64_t req, uint32_t& id_lo, uint32_t& id_hi, bool& exact) {
+    int lo = -1, hi = -1;
+    const int n = (int)c->cls_mask.size();
+    for (int i = 0; i < n; i++)
+        if ((req & ~c->cls_mask[i]) == 0) {
+            if (lo < 0) lo = i;
+            hi = i;
+        }
+    if (lo < 0) return false;
+    exact = true;
+    for (int i = lo; i <= hi; i++)
+        if (req & ~c->cls_mask[i]) exact = false;
+    id_lo = c->cls_start[lo];
+    id_hi = c->cls_start[hi + 1];
+    return true;
+}
+
+// Whether every local-filter requirement of query vertex u is met by the one
+// anchor edge that maps it (need <= 1 on a counter that edge increments), in
+// which case testing the vertex-filter bit can prune nothing.
+bool filters_trivial(const mnemonic_ctx* c, const QueryDev& Q, uint32_t u, uint32_t anchor, uint32_t from,
+                     uint32_t dir) {
+    const uint32_t E = c->n_elab_c, Lc = c->n_vlab_c;
+    const uint32_t dw = 1u - dir;  // the anchor is an in-edge of f(u) when it leaves f(from)
+    std::vector<uint16_t> inc;
+    inc.push_back((uint16_t)cnt_index(dw, 0, E, Lc));
+    if (Q.qlab[anchor] >= 0) inc.push_back((uint16_t)cnt_index(dw, 1 + c->elab_idx[Q.qlab[anchor]], E, Lc));
+    for (int b = 0; b < 64; b++)
+        if (((Q.vreq[from] >> b) & 1) && c->vlab_idx[b] >= 0)
+            inc.push_back((uint16_t)cnt_index(dw, 1 + E + c->vlab_idx[b], E, Lc));
+    for (uint32_t r = Q.req_begin[u]; r < Q.req_begin[u + 1]; r++) {
+        const VfReq& q = c->hreq[r];
+        if (q.need == 0) continue;
+        if (q.need > 1 || std::find(inc.begin(), inc.end(), q.cnt) == inc.end()) return false;
+    }
+    return true;
+}
+
 // Static matching order for start edge j (Section VI): the start edge maps
 // both its endpoints; then, repeatedly, the unmapped query vertex with the most
 // edges to mapped vertices (ties: lowest index) is mapped through one of those
 // edges (a labelled one first, then the lowest index), and its other edges to
 // mapped vertices become closing edges checked at that level.
-void build_plan(const QueryDev& Q, uint32_t j, SeedPlan& P) {
+void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t j, SeedPlan& P) {
     memset(&P, 0, sizeof(P));
     const uint32_t nqv = Q.n_qv, nqe = Q.n_qe;
+    P.q = (uint16_t)qi;
+    P.j = (uint8_t)j;
+    P.n_qe = (uint8_t)nqe;
+    P.sem = (uint8_t)Q.sem;
+    P.vf_base = Q.vf_base;
+    P.debi_base = Q.debi_base;
+    for (uint32_t k = 0; k < MN_MAXQE; k++) P.close_idx[k] = 0xFF;
     bool mapped[MN_MAXQV] = {false};
     bool used[MN_MAXQE] = {false};
     uint32_t qa = Q.qsrc[j], qb = Q.qdst[j];
@@ -214,22 +289,24 @@ void build_plan(const QueryDev& Q, uint32_t j, SeedPlan& P) {
     mapped[qa] = mapped[qb] = true;
     used[j] = true;
     uint32_t nc = 0;
-    auto make_close = [&](uint32_t k, uint32_t newv) {
-        CloseDesc c;
+    auto add_close = [&](uint32_t k, uint32_t newv) {
+        if (nc >= MN_MAXCLOSE)
+            throw ApiError{MNEMONIC_E_QUERY, "a query has more than 8 edges beyond a spanning tree"};
+        CloseDesc& cd = P.close[nc];
         uint32_t other = Q.qsrc[k] == newv ? Q.qdst[k] : Q.qsrc[k];
-        c.qe = (uint8_t)k;
-        c.other = (uint8_t)other;
-        c.dir = Q.qsrc[k] == other ? 0 : 1;
-        c.masked = k < j ? 1 : 0;
-        c.label = Q.qlab[k];
-        return c;
+        cd.qe = (uint8_t)k;
+        cd.other = (uint8_t)other;
+        cd.nv = (uint8_t)newv;
+        cd.dir = Q.qsrc[k] == other ? 0 : 1;
+        cd.masked = k < j ? 1 : 0;
+        cd.label = Q.qlab[k];
+        P.close_idx[k] = (uint8_t)nc;
+        used[k] = true;
+        nc++;
     };
     for (uint32_t k = 0; k < nqe; k++) {
         if (used[k]) continue;
-        if ((Q.qsrc[k] == qa && Q.qdst[k] == qb) || (Q.qsrc[k] == qb && Q.qdst[k] == qa)) {
-            P.close[nc++] = make_close(k, qb);
-            used[k] = true;
-        }
+        if ((Q.qsrc[k] == qa && Q.qdst[k] == qb) || (Q.qsrc[k] == qb && Q.qdst[k] == qa)) add_close(k, qb);
     }
     P.c0_end = (uint8_t)nc;
     uint32_t L = 0;
@@ -264,17 +341,28 @@ void build_plan(const QueryDev& Q, uint32_t j, SeedPlan& P) {
         lv.qe = (uint8_t)ak;
         lv.from = (uint8_t)from;
         lv.dir = Q.qsrc[ak] == from ? 0 : 1;
-        lv.label = Q.qlab[ak];
         lv.masked = ak < j ? 1 : 0;
         lv.n_mapped = (uint8_t)(L + 2);
         used[ak] = true;
+        // candidates: the anchor label's run restricted to the classes that
+        // can carry n's labels (or the whole list for a wildcard label)
+        uint32_t id_lo = 0, id_hi = 0;
+        bool exact = false;
+        const bool some = class_hull(c, Q.vreq[n], id_lo, id_hi, exact);
+        lv.whole = Q.qlab[ak] < 0 ? 1 : 0;
+        lv.empty = some ? 0 : 1;
+        bool labels_implied = exact;
+        if (lv.whole) {
+            labels_implied = some && exact && id_lo == 0 && id_hi == c->nV;
+        } else if (some) {
+            lv.key_lo = ((uint32_t)Q.qlab[ak] << c->nbr_bits) | id_lo;
+            lv.key_hi = ((uint32_t)Q.qlab[ak] << c->nbr_bits) | (id_hi - 1);
+        }
+        lv.need_vf = labels_implied ? 0 : 1;  // refined below once the last level is known
         lv.c_begin = (uint8_t)nc;
         for (uint32_t k = 0; k < nqe; k++) {
             if (used[k]) continue;
-            if ((Q.qsrc[k] == n && mapped[Q.qdst[k]]) || (Q.qdst[k] == n && mapped[Q.qsrc[k]])) {
-                P.close[nc++] = make_close(k, n);
-                used[k] = true;
-            }
+            if ((Q.qsrc[k] == n && mapped[Q.qdst[k]]) || (Q.qdst[k] == n && mapped[Q.qsrc[k]])) add_close(k, n);
         }
         lv.c_end = (uint8_t)nc;
         mapped[n] = true;
@@ -282,11 +370,11 @@ void build_plan(const QueryDev& Q, uint32_t j, SeedPlan& P) {
         L++;
     }
     P.n_levels = (uint8_t)L;
-    for (uint32_t k = 0; k < MN_MAXQE; k++) P.last_src[k] = 0xFF;
-    if (L > 0) {
-        const LevelDesc& last = P.lv[L - 1];
-        P.last_src[last.qe] = 0xFE;
-        for (uint32_t c = last.c_begin; c < last.c_end; c++) P.last_src[P.close[c].qe] = (uint8_t)(c - last.c_begin);
+    P.n_close = (uint8_t)nc;
+    // Below the last level the filter bit can also prune by degree.
+    for (uint32_t l = 0; l + 1 < L; l++) {
+        LevelDesc& lv = P.lv[l];
+        if (!lv.need_vf && !filters_trivial(c, Q, lv.vtx, lv.qe, lv.from, lv.dir)) lv.need_vf = 1;
     }
 }
 
@@ -392,16 +480,19 @@ void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
         }
         for (uint32_t j = 0; j < q.n_qe; j++) {
             SeedPlan P;
-            build_plan(Q, j, P);
-            for (uint32_t L = 0; L < P.n_levels; L++)
-                if (P.lv[L].c_end - P.lv[L].c_begin > 8)
-                    throw ApiError{MNEMONIC_E_QUERY, "a query vertex closes more than 8 edges at once"};
+            build_plan(c, Q, i, j, P);
+            c->max_levels = std::max<uint32_t>(c->max_levels, P.n_levels);
             c->hplans.push_back(P);
         }
         vf_base += q.n_qv;
         debi_base += q.n_qe;
         plan_base += q.n_qe;
         c->hq.push_back(Q);
+    }
+    c->n_plans = (uint32_t)c->hplans.size();
+    for (uint32_t i = 0; i < n_q; i++) {
+        c->wv = std::max<uint32_t>(c->wv, qs[i].n_qv);
+        c->we = std::max<uint32_t>(c->we, qs[i].n_qe);
     }
     c->n_vf_bits = vf_base;
     c->n_debi_bits = debi_base;
@@ -445,6 +536,7 @@ GraphView make_view(const mnemonic_ctx* c, bool next) {
     g.vfreq = c->d_req;
     g.elab_idx = c->d_elab_idx;
     g.vlab_idx = c->d_vlab_idx;
+    g.ext2int = c->d_ext2int;
     g.n_elab_c = c->n_elab_c;
     g.n_vlab_c = c->n_vlab_c;
     return g;
@@ -483,7 +575,8 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     }
     uint64_t need_E = c->E - c->n_pending + n_ins;
     c->hb_pos = std::max<uint32_t>(1, ceil_log2(std::max<uint64_t>(c->E, need_E) + 1));
-    if (need_E >= (1ull << 32) - 1) throw ApiError{MNEMONIC_E_LIMIT, "more than 2^32 adjacency entries"};
+    // adjacency positions must stay below 2^31 (bit 31 tags closing-edge runs)
+    if (need_E >= (1ull << 31) - 1) throw ApiError{MNEMONIC_E_LIMIT, "more than 2^31 adjacency entries"};
     for (int d = 0; d < 2; d++) {
         uint64_t t = c->cap_E;
         dev_grow(c->d_adj[d], t, need_E, c->E, s);
@@ -558,15 +651,6 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         dev_alloc(c->d_touched, nc);
         c->cap_touch = nc;
     }
-    uint64_t n_seed = std::max<uint64_t>(n_ins, n_del) * c->total_qe;
-    if (n_seed > c->cap_seed) {
-        uint64_t nc = std::max<uint64_t>(n_seed, c->cap_seed + c->cap_seed / 2);
-        for (int p = 0; p < 2; p++) {
-            dev_free(c->d_seeds[p]);
-            dev_alloc(c->d_seeds[p], nc);
-        }
-        c->cap_seed = nc;
-    }
 }
 
 void grow_outputs(mnemonic_ctx* c, const std::vector<uint64_t>& need) {
@@ -590,8 +674,10 @@ PhaseOut phase_out(mnemonic_ctx* c, int p) {
     PhaseOut po;
     po.count = c->d_zr + c->zr_count(p);
     po.digest = c->d_zr + c->zr_digest(p);
-    po.stats = reinterpret_cast<EnumStats*>(c->d_zr + c->zr_stats(0));
+    po.stats = reinterpret_cast<EnumStats*>(c->d_zr + c->zr_stats(p));
     po.outs = c->d_outs;
+    po.phase = p;
+    po.emit = (c->flags & MNEMONIC_F_EMIT) ? 1 : 0;
     return po;
 }
 
@@ -600,19 +686,119 @@ void reset_phase(mnemonic_ctx* c, int p) {
     // counts, digests, cursor and stats of one phase (err is 0 whenever this runs)
     mn_launch_reset(c->d_err, c->d_zr + c->zr_count(p), c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), 2 * c->n_q, s);
-    mn_launch_reset(c->d_err, c->d_zr + c->zr_cursor(p), 1, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), 8, s);
 }
 
-void enumerate_phase(mnemonic_ctx* c, int p, uint64_t max_seeds) {
-    GraphView g = make_view(c, false);
-    bool emit = (c->flags & MNEMONIC_F_EMIT) != 0;
-    bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
-    if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], c->stream));
-    mn_launch_enumerate(g, c->d_seeds[p], reinterpret_cast<uint32_t*>(c->d_zr + c->zr_nseeds(p)),
-                        (uint32_t)max_seeds, reinterpret_cast<uint32_t*>(c->d_zr + c->zr_cursor(p)),
-                        phase_out(c, p), p, emit ? 1 : 0, c->d_err, c->stream);
-    if (timing) HIPCHK(hipEventRecord(c->ev[2 * p + 1], c->stream));
+// Grows level L's buffers to hold `need` rows (contents are not kept: a
+// level is only grown while it holds no rows).
+void grow_level(mnemonic_ctx* c, uint32_t L, uint64_t need) {
+    auto& B = c->lvb[L];
+    if (need <= B.cap) return;
+    uint64_t nc = std::min<uint64_t>(c->rows_max, std::max<uint64_t>(need, std::max<uint64_t>(B.cap * 2, 4096)));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dev_free(B.rows);
+    dev_free(B.lo);
+    dev_free(B.cnt);
+    dev_free(B.off);
+    B.cap = 0;
+    dev_alloc(B.rows, nc * c->ncol());
+    dev_alloc(B.lo, nc);
+    dev_alloc(B.cnt, nc);
+    dev_alloc(B.off, nc);
+    B.cap = nc;
+    uint64_t sw = mn_scan64_scratch_words((uint32_t)nc);
+    if (sw > c->cap_scan64) {
+        dev_free(c->d_scan64);
+        dev_alloc(c->d_scan64, sw);
+        c->cap_scan64 = sw;
+    }
+}
+
+RowsView rows_view(const mnemonic_ctx* c, uint32_t L) {
+    RowsView R;
+    memset(&R, 0, sizeof(R));
+    R.wv = c->wv;
+    R.we = c->we;
+    if (L < c->lvb.size()) {
+        R.col = c->lvb[L].rows;
+        R.cap = (uint32_t)c->lvb[L].cap;
+    }
+    return R;
+}
+
+uint64_t read_u32(mnemonic_ctx* c, const uint32_t* d) {
+    HIPCHK(hipMemcpyAsync(c->h_ctl, d, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return *reinterpret_cast<uint32_t*>(c->h_ctl);
+}
+
+uint64_t read_u64(mnemonic_ctx* c, const uint64_t* d) {
+    HIPCHK(hipMemcpyAsync(c->h_ctl, d, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return c->h_ctl[0];
+}
+
+// Level L of the search over the n rows of level buffer L: candidate runs,
+// their offsets, then the candidate space in chunks no larger than the next
+// level's row buffer; each chunk's survivors are searched to the end before
+// the next chunk starts (depth first over chunks, breadth first inside one).
+void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint32_t L, uint64_t n) {
+    if (n == 0) return;
+    hipStream_t s = c->stream;
+    auto& B = c->lvb[L];
+    mn_launch_level_range(g, rows_view(c, L), (uint32_t)n, L, B.lo, B.cnt, po.stats, c->d_err, s);
+    mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n, c->d_scan64, c->d_total, s);
+    const uint64_t T = read_u64(c, c->d_total);
+    if (T == 0) return;
+    const bool next = L + 1 < c->max_levels;
+    if (next) grow_level(c, L + 1, T);
+    // chunks bounded by the next level's rows (each candidate yields <= 1 row)
+    const uint64_t K = next ? c->lvb[L + 1].cap : (1ull << 26);
+    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
+    for (uint64_t c0 = 0; c0 < T; c0 += K) {
+        const uint64_t c1 = std::min<uint64_t>(T, c0 + K);
+        uint32_t* n_out = c->d_nrows + L + 1;
+        mn_launch_set_u32(n_out, 0, s);
+        // one event pair serves every launch: the readback below waits for it
+        if (timing) HIPCHK(hipEventRecord(c->ev_x[0], s));
+        mn_launch_expand(g, rows_view(c, L), (uint32_t)n, B.lo, B.off, c0, c1, L, rows_view(c, L + 1), n_out, po,
+                         c->d_err, s);
+        if (timing) HIPCHK(hipEventRecord(c->ev_x[1], s));
+        c->n_expand[po.phase]++;
+        const uint64_t n1 = read_u32(c, n_out);
+        if (timing) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev_x[0], c->ev_x[1]));
+            c->ms_expand[po.phase] += ms;
+        }
+        if (next && n1 > c->lvb[L + 1].cap) throw ApiError{MNEMONIC_E_HIP, "row buffer overflow (internal)"};
+        if (next) process_level(c, g, po, L + 1, n1);
+    }
+}
+
+// One enumeration phase (p = 0: new embeddings of the inserted slots; 1:
+// expired embeddings of the deleted slots) on the current graph view.
+void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_slots) {
+    hipStream_t s = c->stream;
+    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
+    if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], s));
+    if (n_slots && c->n_plans) {
+        GraphView g = make_view(c, false);
+        PhaseOut po = phase_out(c, p);
+        // every (slot, plan) pair may become one start row
+        const uint64_t chunk = std::max<uint64_t>(1, c->rows_max / c->n_plans);
+        for (uint64_t s0 = 0; s0 < n_slots; s0 += chunk) {
+            const uint64_t ns = std::min<uint64_t>(chunk, n_slots - s0);
+            if (c->max_levels) grow_level(c, 0, ns * c->n_plans);  // else every plan emits at once
+            mn_launch_set_u32(c->d_nrows, 0, s);
+            mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_plans, rows_view(c, 0), c->d_nrows, po, c->d_err,
+                                s);
+            if (c->max_levels == 0) continue;
+            const uint64_t n0 = read_u32(c, c->d_nrows);
+            process_level(c, g, po, 0, n0);
+        }
+    }
+    if (timing) HIPCHK(hipEventRecord(c->ev[2 * p + 1], s));
 }
 
 // One snapshot; `enumerate` is false only for the initial load.
@@ -623,6 +809,10 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     if (n_ins + n_del >= (1ull << 31)) throw ApiError{MNEMONIC_E_ARG, "batch too large"};
     ensure_capacity(c, n_ins, n_del);
     const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0 && enumerate;
+    for (int p = 0; p < 2; p++) {
+        c->ms_expand[p] = 0;
+        c->n_expand[p] = 0;
+    }
     if (timing) HIPCHK(hipEventRecord(c->ev[4], s));
 
     const uint32_t* in_src = src;
@@ -723,10 +913,6 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     mn_launch_vf_refresh(g1, c->d_vf_bits, c->n_vf_bits, enumerate ? c->d_touched : nullptr,
                          enumerate ? (uint32_t)(2 * (n_prev + n_ins)) : c->nV, c->d_err, s);
     uint64_t* adjn[2] = {merge ? c->d_adj2[0] : c->d_adj[0], merge ? c->d_adj2[1] : c->d_adj[1]};
-    if (enumerate) {
-        mn_launch_seed(g1, c->d_debi_bits, c->d_ins_slot, (uint32_t)n_ins, c->d_seeds[0],
-                       reinterpret_cast<uint32_t*>(c->d_zr + c->zr_nseeds(0)), c->d_err, s);
-    }
     // the enumerator reads the current view; point it at the merged arrays
     auto swap_in = [&]() {
         if (!merge) return;
@@ -738,15 +924,11 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     swap_in();
     uint32_t err = 0;
     try {
-        if (enumerate) enumerate_phase(c, 0, n_ins * c->total_qe);
+        if (enumerate) enumerate_phase(c, 0, c->d_ins_slot, n_ins);
         for (int d = 0; d < 2; d++) mn_launch_set_flags(adjn[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
         GraphView g2 = make_view(c, false);
         mn_launch_flag_del(g2, adjn[0], adjn[1], b, s);
-        if (enumerate) {
-            mn_launch_seed(g2, c->d_debi_bits, c->d_del_slot[cur], (uint32_t)n_del, c->d_seeds[1],
-                           reinterpret_cast<uint32_t*>(c->d_zr + c->zr_nseeds(1)), c->d_err, s);
-            enumerate_phase(c, 1, n_del * c->total_qe);
-        }
+        if (enumerate) enumerate_phase(c, 1, c->d_del_slot[cur], n_del);
         uint32_t n_free_after = c->n_free - (uint32_t)std::min<uint64_t>(n_ins, c->n_free);
         mn_launch_finalize(b, n_free_after, s);
         if (timing) HIPCHK(hipEventRecord(c->ev[5], s));
@@ -796,7 +978,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                     mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 1, c->d_err, s);
                 }
                 reset_phase(c, 0);
-                enumerate_phase(c, 0, n_ins * c->total_qe);
+                enumerate_phase(c, 0, c->d_ins_slot, n_ins);
                 for (int d = 0; d < 2; d++) {
                     mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
                     mn_launch_set_flags(c->d_adj[d], c->d_delpos[cur][d], (uint32_t)n_del, 1, c->d_err, s);
@@ -804,7 +986,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             }
             if (redo[1]) {
                 reset_phase(c, 1);
-                enumerate_phase(c, 1, n_del * c->total_qe);
+                enumerate_phase(c, 1, c->d_del_slot[cur], n_del);
             }
             HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -818,8 +1000,13 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             st.seeds[p] = z[0];
             st.entries_scanned[p] = z[1];
             st.probe_words[p] = z[2];
-            st.key_reads[p] = z[3];
-            st.tuples[p] = z[4];
+            st.range_probe_words[p] = z[3];
+            st.key_reads[p] = z[4];
+            st.tuples[p] = z[5];
+            st.vf_reads[p] = z[6];
+            st.frontier_rows[p] = z[7];
+            st.expand_launches[p] = c->n_expand[p];
+            st.ms_expand[p] = c->ms_expand[p];
             uint64_t words = 0;
             for (uint32_t q = 0; q < c->n_q; q++) words += c->h_zr[c->zr_count(p) + q] * c->hq[q].n_qe;
             st.tuple_words[p] = words;
@@ -888,7 +1075,6 @@ void free_all(mnemonic_ctx* c) {
         dev_free(c->d_adj2[d]);
         dev_free(c->d_inspos[d]);
         dev_free(c->d_del_slot[d]);
-        dev_free(c->d_seeds[d]);
         for (int k = 0; k < 2; k++) {
             dev_free(c->d_dkey[d][k]);
             dev_free(c->d_dval[d][k]);
@@ -913,6 +1099,20 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_outs);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->ev_x)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& B : c->lvb) {
+        dev_free(B.rows);
+        dev_free(B.lo);
+        dev_free(B.cnt);
+        dev_free(B.off);
+    }
+    dev_free(c->d_scan64);
+    dev_free(c->d_nrows);
+    dev_free(c->d_total);
+    dev_free(c->d_ext2int);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    c->h_ctl = nullptr;
 }
 
 }  // namespace
@@ -941,6 +1141,25 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         c->n_elabels = g->n_elabels ? g->n_elabels : 256;
         c->nbr_bits = std::max<uint32_t>(1, ceil_log2(c->nV));
         c->hb = c->nbr_bits + std::max<uint32_t>(1, ceil_log2(c->n_elabels));
+        // vertex classes (distinct label sets, ascending) and internal ids
+        // assigned class by class, caller's order within a class
+        std::vector<uint32_t> order(c->nV);
+        for (uint32_t v = 0; v < c->nV; v++) order[v] = v;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            return g->vlabel_mask[a] < g->vlabel_mask[b];
+        });
+        std::vector<uint32_t> ext2int(c->nV);
+        std::vector<uint64_t> vmask_int(c->nV);
+        for (uint32_t i = 0; i < c->nV; i++) {
+            const uint64_t m = g->vlabel_mask[order[i]];
+            ext2int[order[i]] = i;
+            vmask_int[i] = m;
+            if (c->cls_mask.empty() || c->cls_mask.back() != m) {
+                c->cls_mask.push_back(m);
+                c->cls_start.push_back(i);
+            }
+        }
+        c->cls_start.push_back(c->nV);
         prepare_queries(c, q, n_q);
         for (uint32_t i = 0; i < n_q; i++)
             for (uint32_t k = 0; k < q[i].n_qe; k++)
@@ -949,7 +1168,14 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         hipStream_t s = c->stream;
         for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
         dev_alloc(c->d_vmask, c->nV);
-        HIPCHK(hipMemcpyAsync(c->d_vmask, g->vlabel_mask, (size_t)c->nV * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->d_vmask, vmask_int.data(), (size_t)c->nV * 8, hipMemcpyHostToDevice, s));
+        dev_alloc(c->d_ext2int, c->nV);
+        HIPCHK(hipMemcpyAsync(c->d_ext2int, ext2int.data(), (size_t)c->nV * 4, hipMemcpyHostToDevice, s));
+        c->lvb.resize(c->max_levels);
+        dev_alloc(c->d_nrows, MN_MAXLV + 2);
+        dev_alloc(c->d_total, 1);
+        HIPCHK(hipHostMalloc((void**)&c->h_ctl, 64, hipHostMallocDefault));
+        for (auto& e : c->ev_x) HIPCHK(hipEventCreate(&e));
         upload(c->d_q, c->hq, s);
         upload(c->d_plans, c->hplans, s);
         upload(c->d_debi_bits, c->hdebi, s);

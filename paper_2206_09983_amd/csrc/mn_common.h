@@ -14,6 +14,10 @@
 //   neighbour lookup is a binary search. The flag marks the edges of the batch
 //   the current phase enumerates (insert phase: the inserted edges; delete
 //   phase: the deleted ones, which stay in the arrays until the next merge).
+//   vertex ids: internally, vertices are numbered in order of their label
+//   set (vertices with equal label sets form a class, a contiguous id range),
+//   so within one edge label a segment is ordered by neighbour class too, and
+//   the neighbours that can satisfy a query vertex's labels are one run.
 //   vertex filter VF[v * vf_words + w]: one bit per (query, query vertex).
 //   counters cnt[v * n_cnt + c]: per-direction degree, per-direction degree of
 //   each edge label the queries use, per-direction count of edges whose far
@@ -42,48 +46,83 @@
 #define MN_ERR_DELETE 6
 #define MN_ERR_INTERNAL 99
 
-// A closing query edge: both endpoints are mapped when it is reached. Its
-// instances are looked up in the adjacency of the already-mapped endpoint
-// `other`: dir 0 = out-list of f(other) (query edge other -> new vertex),
-// dir 1 = in-list of f(other) (query edge new vertex -> other).
+#define MN_SEM_ISO 0  // mnemonic_semantics: MNEMONIC_ISO
+#define MN_MAXCLOSE 8  // closing edges per start edge (the query's cyclomatic number)
+
+// A closing query edge: both of its endpoints are mapped by the time the
+// level that adds it is reached; it only has to exist. `other` was mapped
+// earlier, `nv` by the level itself (for the start level: other = qa,
+// nv = qb). dir 0: the query edge runs other -> nv, so its instances sit in
+// the out-list of f(other) under (label, f(nv)); dir 1: nv -> other, in the
+// in-list of f(other). The same instances also sit in the opposite list of
+// f(nv) under (label, f(other)); the enumerator searches the shorter list.
 struct CloseDesc {
     uint8_t qe;
     uint8_t other;
+    uint8_t nv;
     uint8_t dir;
     uint8_t masked;  // query edge index < start position: batch edges forbidden
+    uint8_t pad[3];
     int32_t label;   // -1 = any label
 };
 
 // One level of the search maps one new query vertex `vtx` through its anchor
-// edge, whose candidates are the label run of f(from)'s out-list (dir 0, query
-// edge from -> vtx) or in-list (dir 1, query edge vtx -> from). Closing edges
-// close[c_begin, c_end) join vtx to vertices mapped earlier.
+// edge: the candidates are the entries of f(from)'s out-list (dir 0, query
+// edge from -> vtx) or in-list (dir 1, query edge vtx -> from) whose high
+// word lies in [key_lo, key_hi] (one label and the id range of the vertex
+// classes that can satisfy vtx's label requirement), or the whole list when
+// the anchor label is a wildcard. Closing edges close[c_begin, c_end) join
+// vtx to vertices mapped earlier.
 struct LevelDesc {
     uint8_t vtx;
     uint8_t qe;
     uint8_t from;
     uint8_t dir;
-    int32_t label;
     uint8_t masked;
     uint8_t c_begin;
     uint8_t c_end;
-    uint8_t n_mapped;  // query vertices mapped before this level (seed pair + earlier levels)
+    uint8_t n_mapped;  // query vertices mapped before this level (start pair + earlier levels)
+    uint8_t whole;     // wildcard anchor label: every entry of the list is a candidate
+    uint8_t empty;     // no vertex class satisfies vtx's labels: no candidates
+    uint8_t need_vf;   // candidates must pass the vertex-filter bit of vtx
+    uint8_t pad;
+    uint32_t key_lo;   // inclusive bounds of the candidates' high words
+    uint32_t key_hi;
 };
 
 // Static matching order for one (query, start position j) pair (Section VI,
-// "matching order computation"): the start edge maps qa -> qb; closing edges
+// matching order computation): the start edge maps qa -> qb; closing edges
 // between qa and qb come first (close[0, c0_end)), then one level per
 // remaining query vertex.
 struct SeedPlan {
+    uint16_t q;        // query index
+    uint8_t j;         // start position
+    uint8_t n_qe;
     uint8_t qa, qb;
     uint8_t n_levels;
     uint8_t c0_end;
-    uint8_t mapped[MN_MAXQV];  // query vertices in mapping order: qa, qb, level vtx...
-    // where the last level finds each query edge's key when it emits:
-    // 0xFF = mapped above (LDS), 0xFE = the last level's anchor, c = its c-th closing edge
-    uint8_t last_src[MN_MAXQE];
+    uint8_t sem;
+    uint8_t n_close;
+    uint8_t pad[2];
+    uint32_t vf_base;    // first vertex-filter bit of the query
+    uint32_t debi_base;  // first edgeMatcher bit of the query
+    uint8_t mapped[MN_MAXQV];     // query vertices in mapping order: qa, qb, level vtx...
+    uint8_t close_idx[MN_MAXQE];  // per query edge: index into close[], or 0xFF for a tree edge
     LevelDesc lv[MN_MAXLV];
-    CloseDesc close[MN_MAXQE];
+    CloseDesc close[MN_MAXCLOSE];
+};
+
+// Partial embeddings between levels, stored column-wise (row r of column c at
+// col[c * cap + r]): column 0 the plan index, 1 + u the data vertex of query
+// vertex u (u < wv), 1 + wv + k the slot of query edge k (tree edges), or for
+// a closing edge the position of its instance run in the adjacency list that
+// was searched, with bit 31 set when that was the list of f(nv).
+struct RowsView {
+    uint32_t* col;
+    uint32_t cap;
+    uint32_t wv;
+    uint32_t we;
+    uint32_t pad;
 };
 
 // One local-filter requirement of a query vertex: counter c must be >= need.
@@ -132,6 +171,7 @@ struct GraphView {
     const VfReq* vfreq;
     const int16_t* elab_idx;   // [256] compact index of an edge label, -1 if unused
     const int16_t* vlab_idx;   // [64] compact index of a vertex label bit, -1 if unused
+    const uint32_t* ext2int;   // [n_vertices] caller's vertex id -> internal id
     uint32_t n_elab_c;         // compact edge labels
     uint32_t n_vlab_c;         // compact vertex labels
 };

@@ -1,31 +1,48 @@
-// Work units and the enumerator (Section VI, "Embedding Enumeration").
+// Work units and the level-wise enumerator (Section VI, "Embedding
+// Enumeration").
 //
-// k_seed: every batch edge whose DEBI word says it satisfies edgeMatcher for
-// query edge q_j, and whose endpoints pass the vertex filter, becomes one work
-// unit (slot, query, j) (Section VI, "work decomposition"). The DEBI word holds
-// a bit for every query edge, tree or not, so a non-tree start edge needs no
-// expansion into tree-edge seeds.
+// A work unit is a batch edge at a start position j of a query: its
+// edgeMatcher bit for q_j is set and both endpoints pass the vertex filter
+// (Section VI, work decomposition; the edgeMatcher word holds a bit for every
+// query edge, tree or not, so a non-tree start edge needs no expansion into
+// tree-edge units). The static order for (query, j) then maps one new query
+// vertex per level through an anchor edge whose candidates are one run of the
+// mapped endpoint's sorted adjacency (getCandidates of Section IV-A),
+// checks each candidate against the duplicate-removal mask (positions k < j
+// may not use batch edges), the vertex filter, injectivity (isomorphism only)
+// and the closing edges (verifyNte), and emits at the last level.
 //
-// k_enumerate: one 64-lane wavefront backtracks one work unit at a time,
-// pulling units from a global counter (the paper's pull-based distribution).
-// The static order for (query, j) maps one new query vertex per level through
-// an anchor edge; the anchor's candidates are a label run of the mapped
-// endpoint's sorted adjacency (getCandidates, Section IV-A), tested 64 at a
-// time, one per lane: duplicate-removal mask (positions k < j may not use
-// batch edges, Section VI), vertex filter bit, injectivity (isomorphism
-// only), and each closing edge (verifyNte) by binary search for the
-// (label, neighbour) run in the already-mapped endpoint's adjacency. Survivors
-// are compacted by ballot into the level's LDS buffer and expanded one at a
-// time; at the last level every surviving lane emits its embeddings directly.
-// Parallel closing edges multiply embeddings (each instance is distinct).
+// The paper gives each work unit to one CPU thread, which backtracks depth
+// first. On the GPU the search runs breadth first instead, one level at a
+// time over all work units of a phase, so that every candidate entry is one
+// lane's work no matter how skewed the subtrees are:
+//   k_seed_rows    one row per work unit (start pair mapped, start-level
+//                  closing edges found); 2-vertex queries emit here
+//   k_level_range  per row, the candidate run [lo, lo + cnt) of the level
+//   scan           u64 offsets of the runs (flattened candidate space)
+//   k_expand       one lane per candidate: filters, closing edges, then a
+//                  new row for the next level or, at the plan's last level,
+//                  the embeddings themselves
+// The host walks the levels depth first over chunks of the candidate space,
+// so each level's row buffer stays bounded whatever the fan-out. Parallel
+// closing-edge instances do not multiply rows: a row keeps the start of each
+// closing edge's instance run, and emission expands every combination of
+// instances (parallel edges are distinct instances, Section I).
 #include "mn_internal.h"
 
 namespace {
 
-constexpr uint32_t EN_WAVES = MN_BLOCK / MN_WAVE;
-constexpr uint32_t MN_MAXCL = 8;  // closing edges per level (checked at creation)
+constexpr uint32_t EX_ITEMS = 2;
+constexpr uint32_t EX_TILE = MN_BLOCK * EX_ITEMS;
+constexpr uint32_t NO_RUN = 0xFFFFFFFFu;
+constexpr uint32_t RUN_SWAP = 0x80000000u;
+constexpr uint8_t TREE_EDGE = 0xFF;
 
 __device__ inline bool failed(const uint32_t* err) { return *(volatile const uint32_t*)err != 0u; }
+
+__device__ inline void set_err(const uint32_t* err, uint32_t code) {
+    atomicCAS(const_cast<uint32_t*>(err), 0u, code);
+}
 
 __device__ inline uint64_t shfl64(uint64_t x, int src) {
     uint32_t lo = __shfl((uint32_t)x, src, MN_WAVE);
@@ -43,15 +60,17 @@ __device__ inline uint64_t wave_sum64(uint64_t x) {
     return x;
 }
 
-__device__ inline uint32_t wave_excl_scan(uint32_t x, uint32_t& total) {
-    uint32_t lane = __lane_id();
-    uint32_t incl = x;
+// Exclusive prefix sum over the wave (all 64 lanes must take part).
+__device__ inline uint64_t wave_excl_scan64(uint64_t x, uint64_t& total) {
+    const uint32_t lane = __lane_id();
+    uint64_t incl = x;
 #pragma unroll
     for (int d = 1; d < MN_WAVE; d <<= 1) {
-        uint32_t y = __shfl_up(incl, d, MN_WAVE);
-        if (lane >= (uint32_t)d) incl += y;
+        uint32_t lo = __shfl_up((uint32_t)incl, d, MN_WAVE);
+        uint32_t hi = __shfl_up((uint32_t)(incl >> 32), d, MN_WAVE);
+        if (lane >= (uint32_t)d) incl += ((uint64_t)hi << 32) | lo;
     }
-    total = __shfl(incl, MN_WAVE - 1, MN_WAVE);
+    total = shfl64(incl, MN_WAVE - 1);
     return incl - x;
 }
 
@@ -59,11 +78,32 @@ __device__ inline bool vf_bit(const GraphView& g, uint32_t v, uint32_t bit) {
     return (g.vf[(size_t)v * g.vf_words + (bit >> 5)] >> (bit & 31)) & 1u;
 }
 
-struct Counters {
-    uint64_t entries, probes, keys, tuples, seeds;
+__device__ inline uint32_t rcol(const RowsView& R, uint32_t c, uint32_t r) {
+    return R.col[(size_t)c * R.cap + r];
+}
+
+__device__ inline void wcol(const RowsView& R, uint32_t c, uint32_t r, uint32_t v) {
+    R.col[(size_t)c * R.cap + r] = v;
+}
+
+struct Cnt {
+    uint64_t seeds, entries, probes, range_probes, keys, tuples, vf, rows;
 };
 
-// Binary searches that also count the adjacency words they read.
+__device__ void flush_stats(const Cnt& K, EnumStats* st) {
+    const uint64_t v[8] = {wave_sum64(K.seeds), wave_sum64(K.entries), wave_sum64(K.probes),
+                           wave_sum64(K.range_probes), wave_sum64(K.keys), wave_sum64(K.tuples),
+                           wave_sum64(K.vf), wave_sum64(K.rows)};
+    if (__lane_id() == 0) {
+        unsigned long long* d = reinterpret_cast<unsigned long long*>(st);
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            if (v[i]) atomicAdd(d + i, (unsigned long long)v[i]);
+    }
+}
+
+// Binary searches over the high words of a sorted segment, counting the
+// words they read.
 __device__ inline uint32_t lower_hi_c(const uint64_t* adj, uint32_t lo, uint32_t hi, uint32_t key,
                                       uint64_t& probes) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(adj);
@@ -92,456 +132,472 @@ __device__ inline uint32_t upper_hi_c(const uint64_t* adj, uint32_t lo, uint32_t
     return lo;
 }
 
-// Range of possible instances of closing edge c whose new endpoint is w.
-// A labelled closing edge is one (label, w) run; an unlabelled one scans the
-// whole segment and filters by neighbour.
-__device__ inline void close_range(const GraphView& g, const CloseDesc& c, uint32_t x, uint32_t w,
-                                   uint32_t& lo, uint32_t& hi, uint64_t& probes) {
-    const uint64_t* adj = g.adj[c.dir];
-    uint32_t s0 = g.off[c.dir][x], s1 = g.off[c.dir][x + 1];
+// Where the images of query vertices come from while a candidate is tested:
+// the row of the partial embedding (or, at the start level, the start edge's
+// endpoints) plus the level's new vertex.
+struct Bind {
+    RowsView R;
+    bool row;  // false at the start level
+    uint32_t r;
+    uint32_t qa, fa, qb, fb;  // start level: f(qa), f(qb)
+    uint32_t sj, sslot;       // start level: start position and its slot
+    uint32_t cv, fw;          // the level's new vertex (0xFF: none) and its image
+
+    __device__ uint32_t f(uint32_t u) const {
+        if (u == cv) return fw;
+        if (!row) return u == qa ? fa : fb;
+        return rcol(R, 1 + u, r);
+    }
+    // slot of a tree edge mapped before the current level
+    __device__ uint32_t tree_slot(uint32_t k) const {
+        if (!row) return sslot;  // at the start level the start edge is the only tree edge
+        return rcol(R, 1 + R.wv + k, r);
+    }
+};
+
+// Instances of closing edge c between f(other) = fo and f(nv) = fn: searches
+// the shorter of the two adjacency lists that hold them. Returns the start of
+// the instance run (labelled edge: the (label, neighbour) run; unlabelled
+// edge: the first accepted entry of the list), with RUN_SWAP set when the
+// list of fn was used, or NO_RUN when no instance passes the mask.
+__device__ uint32_t close_find(const GraphView& g, const CloseDesc& c, uint32_t fo, uint32_t fn,
+                               uint64_t& probes) {
+    const uint32_t d0 = c.dir, d1 = 1u - c.dir;
+    const uint32_t a0 = g.off[d0][fo], a1 = g.off[d0][fo + 1];
+    const uint32_t b0 = g.off[d1][fn], b1 = g.off[d1][fn + 1];
+    probes += 4;
+    const bool sw = (b1 - b0) < (a1 - a0);
+    const uint32_t dir = sw ? d1 : d0;
+    const uint32_t s0 = sw ? b0 : a0, s1 = sw ? b1 : a1, tgt = sw ? fo : fn;
+    const uint64_t* adj = g.adj[dir];
+    const uint32_t flag = sw ? RUN_SWAP : 0u;
     if (c.label >= 0) {
-        uint32_t h = ((uint32_t)c.label << g.nbr_bits) | w;
-        lo = lower_hi_c(adj, s0, s1, h, probes);
-        hi = upper_hi_c(adj, lo, s1, h, probes);
-    } else {
-        lo = s0;
-        hi = s1;
+        const uint32_t key = ((uint32_t)c.label << g.nbr_bits) | tgt;
+        const uint32_t lb = lower_hi_c(adj, s0, s1, key, probes);
+        for (uint32_t p = lb; p < s1; p++) {
+            const uint64_t e = adj[p];
+            probes += 2;
+            if (ent_hi(e) != key) break;
+            if (!(c.masked && (ent_lo(e) & MN_FLAG))) return lb | flag;
+        }
+        return NO_RUN;
     }
+    for (uint32_t p = s0; p < s1; p++) {
+        const uint64_t e = adj[p];
+        probes += 2;
+        if ((ent_hi(e) & g.nbr_mask) == tgt && !(c.masked && (ent_lo(e) & MN_FLAG))) return p | flag;
+    }
+    return NO_RUN;
 }
 
-__device__ inline bool close_accept(const GraphView& g, const CloseDesc& c, uint32_t p, uint32_t w) {
-    uint64_t e = g.adj[c.dir][p];
-    if (c.label < 0 && (ent_hi(e) & g.nbr_mask) != w) return false;
-    if (c.masked && (ent_lo(e) & MN_FLAG)) return false;
-    return true;
-}
-
-__device__ inline uint32_t close_count(const GraphView& g, const CloseDesc& c, uint32_t lo, uint32_t hi,
-                                       uint32_t w, uint64_t& probes) {
-    uint32_t n = 0;
-    for (uint32_t p = lo; p < hi; p++) n += close_accept(g, c, p, w);
-    probes += hi - lo;
-    return n;
-}
-
-// Position of the first acceptable instance at or after p, or hi.
-__device__ inline uint32_t close_next(const GraphView& g, const CloseDesc& c, uint32_t p, uint32_t hi,
-                                      uint32_t w) {
-    while (p < hi && !close_accept(g, c, p, w)) p++;
-    return p;
-}
-
-struct WaveLds {
-    uint64_t ekey[MN_MAXQE];  // key of each query edge mapped above the current level
-    uint32_t map[MN_MAXQV];   // data vertex of each mapped query vertex
-    uint32_t cur[MN_MAXLV], end[MN_MAXLV];
-    uint32_t bn[MN_MAXLV], bi[MN_MAXLV], has[MN_MAXLV];
-    uint32_t od_pos[MN_MAXQE], od_hi[MN_MAXQE], od_lo[MN_MAXQE];
-    uint32_t buf[MN_MAXLV][MN_WAVE];
+// Iterator over the accepted instances of a closing edge from its run start.
+struct RunIt {
+    const uint64_t* adj;
+    uint32_t p, end, key, tgt, nbr_mask;
+    bool lab, masked;
 };
 
-struct Ctx {
-    const GraphView* g;
-    const QueryDev* Q;
-    const SeedPlan* P;
-    WaveLds* S;
-    uint32_t q;
-    uint32_t lane;
-};
-
-// Odometer over the closing edges [cb, ce) of a level whose new vertex is the
-// (wave-uniform) data vertex w: first combination / next combination. Every
-// lane computes the same values; lane 0 stores them.
-__device__ bool od_first(Ctx& C, uint32_t cb, uint32_t ce, uint32_t w, Counters& K) {
-    const GraphView& g = *C.g;
-    for (uint32_t c = cb; c < ce; c++) {
-        const CloseDesc cd = C.P->close[c];
-        uint32_t x = C.S->map[cd.other];
-        uint32_t lo, hi;
-        close_range(g, cd, x, w, lo, hi, K.probes);
-        uint32_t p = close_next(g, cd, lo, hi, w);
-        if (p >= hi) return false;
-        uint32_t slot = ent_lo(g.adj[cd.dir][p]) & MN_SLOTMASK;
-        uint64_t key = g.s_key[slot];
-        K.keys++;
-        if (C.lane == 0) {
-            C.S->od_lo[c] = lo;
-            C.S->od_hi[c] = hi;
-            C.S->od_pos[c] = p;
-            C.S->ekey[cd.qe] = key;
-        }
-    }
-    wave_lds_sync();
-    return true;
+__device__ inline RunIt run_open(const GraphView& g, const CloseDesc& c, uint32_t st, uint32_t fo,
+                                 uint32_t fn) {
+    RunIt it;
+    const bool sw = (st & RUN_SWAP) != 0;
+    const uint32_t dir = sw ? 1u - c.dir : (uint32_t)c.dir;
+    const uint32_t x = sw ? fn : fo;
+    it.adj = g.adj[dir];
+    it.p = st & ~RUN_SWAP;
+    it.end = g.off[dir][x + 1];
+    it.tgt = sw ? fo : fn;
+    it.lab = c.label >= 0;
+    it.key = it.lab ? (((uint32_t)c.label << g.nbr_bits) | it.tgt) : 0u;
+    it.nbr_mask = g.nbr_mask;
+    it.masked = c.masked != 0;
+    return it;
 }
 
-__device__ bool od_next(Ctx& C, uint32_t cb, uint32_t ce, uint32_t w, Counters& K) {
-    const GraphView& g = *C.g;
-    for (uint32_t cc = ce; cc > cb; cc--) {
-        uint32_t c = cc - 1;
-        const CloseDesc cd = C.P->close[c];
-        uint32_t hi = uniform_u32(C.S->od_hi[c]);
-        uint32_t p = close_next(g, cd, uniform_u32(C.S->od_pos[c]) + 1, hi, w);
-        K.probes++;
-        if (p < hi) {
-            uint32_t slot = ent_lo(g.adj[cd.dir][p]) & MN_SLOTMASK;
-            uint64_t key = g.s_key[slot];
-            K.keys++;
-            if (C.lane == 0) {
-                C.S->od_pos[c] = p;
-                C.S->ekey[cd.qe] = key;
-            }
-            // reset the later closing edges to their first instance
-            for (uint32_t c2 = c + 1; c2 < ce; c2++) {
-                const CloseDesc d2 = C.P->close[c2];
-                uint32_t lo2 = uniform_u32(C.S->od_lo[c2]), hi2 = uniform_u32(C.S->od_hi[c2]);
-                uint32_t p2 = close_next(g, d2, lo2, hi2, w);
-                if (p2 >= hi2) p2 = lo2;  // never expected: the first instance existed before
-                uint32_t s2 = ent_lo(g.adj[d2.dir][p2]) & MN_SLOTMASK;
-                uint64_t k2 = g.s_key[s2];
-                K.keys++;
-                if (C.lane == 0) {
-                    C.S->od_pos[c2] = p2;
-                    C.S->ekey[d2.qe] = k2;
-                }
-            }
-            wave_lds_sync();
-            return true;
+// First accepted instance at or after p, or it.end.
+__device__ inline uint32_t run_next(const RunIt& it, uint32_t p, uint64_t& probes) {
+    for (; p < it.end; p++) {
+        const uint64_t e = it.adj[p];
+        probes += 2;
+        if (it.lab) {
+            if (ent_hi(e) != it.key) return it.end;
+        } else if ((ent_hi(e) & it.nbr_mask) != it.tgt) {
+            continue;
         }
+        if (it.masked && (ent_lo(e) & MN_FLAG)) continue;
+        return p;
     }
-    return false;
+    return it.end;
 }
 
-// Tests the anchor entry at position p for level L. Returns the number of
-// closing-edge instance combinations (0 = rejected) and, for the last level,
-// the per-closing ranges and counts.
-__device__ inline uint32_t filter_candidate(Ctx& C, const LevelDesc& lv, uint32_t p, uint32_t& w_out,
-                                            uint32_t& slot_out, uint32_t* clo, uint32_t* chi,
-                                            uint32_t* ccnt, Counters& K) {
-    const GraphView& g = *C.g;
-    uint64_t e = g.adj[lv.dir][p];
-    K.entries++;
-    uint32_t w = ent_hi(e) & g.nbr_mask;
-    w_out = w;
-    slot_out = ent_lo(e) & MN_SLOTMASK;
-    if (lv.masked && (ent_lo(e) & MN_FLAG)) return 0;
-    if (!vf_bit(g, w, C.Q->vf_base + lv.vtx)) return 0;
-    if (C.Q->sem == 0) {
-        for (uint32_t t = 0; t < lv.n_mapped; t++)
-            if (C.S->map[C.P->mapped[t]] == w) return 0;
-    }
-    uint32_t mult = 1;
-    uint32_t ncl = lv.c_end - lv.c_begin;
-#pragma unroll
-    for (uint32_t i = 0; i < MN_MAXCL; i++) {
-        if (i < ncl) {
-            const CloseDesc cd = C.P->close[lv.c_begin + i];
-            uint32_t x = C.S->map[cd.other];
-            uint32_t lo, hi;
-            close_range(g, cd, x, w, lo, hi, K.probes);
-            uint32_t n = close_count(g, cd, lo, hi, w, K.probes);
-            clo[i] = lo;
-            chi[i] = hi;
-            ccnt[i] = n;
-            mult *= n;
-            if (!n) return 0;
-        }
-    }
-    return mult;
-}
-
-// Emits the mult embeddings of one lane at the last level (or of the seed
-// level when the query has two vertices). pos is this lane's first output row.
-__device__ void emit_lane(Ctx& C, const LevelDesc* lv, uint32_t mult, uint32_t slot, const uint32_t* clo,
-                          const uint32_t* chi, const uint32_t* ccnt, uint32_t w, uint64_t pos,
-                          uint64_t* out, uint64_t cap, int emit, uint64_t& dA, uint64_t& dB,
-                          Counters& K) {
-    const GraphView& g = *C.g;
-    const uint32_t nqe = C.Q->n_qe;
-    uint64_t akey = 0;
-    if (lv) {
-        akey = g.s_key[slot];
-        K.keys++;
-    }
-    uint32_t ncl = lv ? (uint32_t)(lv->c_end - lv->c_begin) : 0u;
-    const uint64_t s0A = mn_mix64(MN_SEED_A ^ (uint64_t)C.q);
-    const uint64_t s0B = mn_mix64(MN_SEED_B ^ (uint64_t)C.q);
-    for (uint32_t t = 0; t < mult; t++) {
-        uint64_t ckey[MN_MAXCL];
-        uint32_t rem = t;
-#pragma unroll
-        for (uint32_t i = 0; i < MN_MAXCL; i++) {
-            ckey[i] = 0;
-            if (i < ncl) {
-                const CloseDesc cd = C.P->close[lv->c_begin + i];
-                uint32_t dig = rem % ccnt[i];
-                rem /= ccnt[i];
-                uint32_t p = close_next(g, cd, clo[i], chi[i], w);
-                for (uint32_t k = 0; k < dig && p < chi[i]; k++) p = close_next(g, cd, p + 1, chi[i], w);
-                if (p < chi[i]) {  // always true: the instances were counted
-                    uint32_t s = ent_lo(g.adj[cd.dir][p]) & MN_SLOTMASK;
-                    ckey[i] = g.s_key[s];
-                    K.keys++;
-                }
-            }
-        }
-        uint64_t hA = s0A, hB = s0B;
-        bool write = emit && (pos + t) < cap;
-        uint64_t* row = out + (pos + t) * nqe;
-        for (uint32_t k = 0; k < nqe; k++) {
-            uint32_t src = C.P->last_src[k];
-            uint64_t key;
-            if (src == 0xFF)
-                key = C.S->ekey[k];
-            else if (src == 0xFE)
-                key = akey;
-            else {
-                key = 0;
-#pragma unroll
-                for (uint32_t i = 0; i < MN_MAXCL; i++)
-                    if (i == src) key = ckey[i];
-            }
-            hA = mn_mix64(hA + key);
-            hB = mn_mix64(hB + key);
-            if (write) row[k] = key;
-        }
-        dA += hA;
-        dB += hB;
-        K.tuples++;
-    }
-}
-
-// Processes the candidates of the last level in chunks of 64 and emits.
-__device__ void run_last_level(Ctx& C, uint32_t L, const PhaseOut& po, int phase, int emit,
-                               uint64_t& dA, uint64_t& dB, Counters& K) {
-    const LevelDesc lv = C.P->lv[L];
-    uint64_t* out = po.outs[C.Q->out_index].keys[phase];
-    uint64_t cap = po.outs[C.Q->out_index].cap[phase];
-    uint32_t cur = uniform_u32(C.S->cur[L]);
-    const uint32_t end = uniform_u32(C.S->end[L]);
-    for (; cur < end; cur += MN_WAVE) {
-        uint32_t p = cur + C.lane;
-        uint32_t clo[MN_MAXCL], chi[MN_MAXCL], ccnt[MN_MAXCL];
-        uint32_t mult = 0, w = 0, slot = 0;
-        if (p < end) mult = filter_candidate(C, lv, p, w, slot, clo, chi, ccnt, K);
-        uint32_t total;
-        uint32_t excl = wave_excl_scan(mult, total);
-        total = uniform_u32(total);
-        if (!total) continue;
+// Lanes with `active` set reserve v consecutive places in the per-query
+// counters[q]; lanes with the same q share one atomic. All lanes of the wave
+// must call this together. Returns the lane's first place.
+__device__ uint64_t grouped_reserve(bool active, uint32_t q, uint64_t v, unsigned long long* counters) {
+    uint64_t pending = __ballot(active);
+    const uint32_t lane = __lane_id();
+    uint64_t mine = 0;
+    while (pending) {
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)pending) - 1;
+        const uint32_t k = __shfl(q, leader, MN_WAVE);
+        const uint64_t grp = __ballot(active && q == k) & pending;
+        const bool in = (grp >> lane) & 1ull;
+        uint64_t tot;
+        const uint64_t ex = wave_excl_scan64(in ? v : 0ull, tot);
         unsigned long long base = 0;
-        if (C.lane == 0) base = atomicAdd(&po.count[C.q], (unsigned long long)total);
-        base = shfl64(base, 0);
-        if (mult) emit_lane(C, &lv, mult, slot, clo, chi, ccnt, w, base + excl, out, cap, emit, dA, dB, K);
+        if (lane == leader) base = atomicAdd(&counters[k], (unsigned long long)tot);
+        base = shfl64(base, leader);
+        if (in) mine = base + ex;
+        pending &= ~grp;
+    }
+    return mine;
+}
+
+// Adds (a, b) of the active lanes to digest[2q], digest[2q + 1], one atomic
+// pair per distinct q in the wave. All lanes must call this together.
+__device__ void grouped_digest(bool active, uint32_t q, uint64_t a, uint64_t b, unsigned long long* digest) {
+    uint64_t pending = __ballot(active);
+    const uint32_t lane = __lane_id();
+    while (pending) {
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)pending) - 1;
+        const uint32_t k = __shfl(q, leader, MN_WAVE);
+        const uint64_t grp = __ballot(active && q == k) & pending;
+        const bool in = (grp >> lane) & 1ull;
+        const uint64_t sa = wave_sum64(in ? a : 0ull), sb = wave_sum64(in ? b : 0ull);
+        if (lane == leader) {
+            atomicAdd(&digest[2 * k], (unsigned long long)sa);
+            atomicAdd(&digest[2 * k + 1], (unsigned long long)sb);
+        }
+        pending &= ~grp;
     }
 }
 
-// Sets up level L's anchor range from the mapped endpoint's sorted adjacency.
-__device__ void setup_level(Ctx& C, uint32_t L, Counters& K) {
-    const GraphView& g = *C.g;
-    const LevelDesc lv = C.P->lv[L];
-    uint32_t x = uniform_u32(C.S->map[lv.from]);
-    const uint64_t* adj = g.adj[lv.dir];
-    uint32_t lo = g.off[lv.dir][x], hi = g.off[lv.dir][x + 1];
-    if (lv.label >= 0) {
-        uint32_t l = (uint32_t)lv.label << g.nbr_bits;
-        lo = lower_hi_c(adj, lo, hi, l, K.probes);
-        hi = upper_hi_c(adj, lo, hi, l | g.nbr_mask, K.probes);
-    }
-    if (C.lane == 0) {
-        C.S->cur[L] = lo;
-        C.S->end[L] = hi;
-        C.S->bn[L] = 0;
-        C.S->bi[L] = 0;
-        C.S->has[L] = 0;
-    }
-    wave_lds_sync();
-}
-
-// Moves level L (not the last) to its next mapping; false when exhausted.
-__device__ bool advance_level(Ctx& C, uint32_t L, Counters& K) {
-    const GraphView& g = *C.g;
-    const LevelDesc lv = C.P->lv[L];
-    if (uniform_u32(C.S->has[L])) {
-        uint32_t w = uniform_u32(C.S->map[lv.vtx]);
-        if (od_next(C, lv.c_begin, lv.c_end, w, K)) return true;
-        if (C.lane == 0) C.S->has[L] = 0;
-        wave_lds_sync();
-    }
-    while (true) {
-        uint32_t bi = uniform_u32(C.S->bi[L]);
-        uint32_t bn = uniform_u32(C.S->bn[L]);
-        if (bi < bn) {
-            uint32_t p = uniform_u32(C.S->buf[L][bi]);
-            uint64_t e = g.adj[lv.dir][p];
-            uint32_t w = ent_hi(e) & g.nbr_mask;
-            uint32_t slot = ent_lo(e) & MN_SLOTMASK;
-            uint64_t key = g.s_key[slot];
-            K.keys++;
-            if (C.lane == 0) {
-                C.S->bi[L] = bi + 1;
-                C.S->map[lv.vtx] = w;
-                C.S->ekey[lv.qe] = key;
-            }
-            wave_lds_sync();
-            if (!od_first(C, lv.c_begin, lv.c_end, w, K)) continue;
-            if (C.lane == 0) C.S->has[L] = 1;
-            wave_lds_sync();
-            return true;
-        }
-        uint32_t cur = uniform_u32(C.S->cur[L]);
-        uint32_t end = uniform_u32(C.S->end[L]);
-        if (cur >= end) return false;
-        uint32_t p = cur + C.lane;
-        uint32_t clo[MN_MAXCL], chi[MN_MAXCL], ccnt[MN_MAXCL];
-        uint32_t w, slot, mult = 0;
-        if (p < end) mult = filter_candidate(C, lv, p, w, slot, clo, chi, ccnt, K);
-        uint64_t bal = __ballot(mult != 0);
-        if (mult) C.S->buf[L][__popcll(bal & lanemask_lt())] = p;
-        if (C.lane == 0) {
-            C.S->bn[L] = (uint32_t)__popcll(bal);
-            C.S->bi[L] = 0;
-            C.S->cur[L] = cur + MN_WAVE;
-        }
-        wave_lds_sync();
-    }
-}
-
-__global__ __launch_bounds__(MN_BLOCK) void k_enumerate(GraphView g, const uint64_t* __restrict__ seeds,
-                                                        const uint32_t* n_seeds_p, uint32_t* cursor,
-                                                        PhaseOut po, int phase, int emit,
-                                                        const uint32_t* err) {
-    __shared__ WaveLds lds[EN_WAVES];
-    if (failed(err)) return;
-    Ctx C;
-    C.g = &g;
-    C.S = &lds[threadIdx.x / MN_WAVE];
-    C.lane = __lane_id();
-    const uint32_t n_seeds = *n_seeds_p;
-    Counters K = {0, 0, 0, 0, 0};
-    while (true) {
-        uint32_t sidx = 0;
-        if (C.lane == 0) sidx = atomicAdd(cursor, 1u);
-        sidx = uniform_u32(__shfl(sidx, 0, MN_WAVE));
-        if (sidx >= n_seeds) break;
-        const uint64_t sd = seeds[sidx];
-        const uint32_t slot = (uint32_t)sd;
-        const uint32_t q = (uint32_t)(sd >> 32) & 0xFFFFu;
-        const uint32_t j = (uint32_t)(sd >> 48);
-        C.q = q;
-        C.Q = &g.queries[q];
-        C.P = &g.plans[C.Q->plan_base + j];
-        if (C.lane == 0) K.seeds++;
-        const uint32_t qa = C.P->qa, qb = C.P->qb;
-        const uint32_t vs = g.s_src[slot], vd = g.s_dst[slot];
-        const uint64_t skey = g.s_key[slot];
-        if (C.lane == 0) {
-            C.S->map[qa] = vs;
-            C.S->map[qb] = vd;
-            C.S->ekey[j] = skey;
-        }
-        wave_lds_sync();
-        uint64_t dA = 0, dB = 0;
-        const uint32_t nl = C.P->n_levels;
-        if (od_first(C, 0, C.P->c0_end, vd, K)) {
-            do {
-                if (nl == 0) {
-                    uint64_t* out = po.outs[C.Q->out_index].keys[phase];
-                    uint64_t cap = po.outs[C.Q->out_index].cap[phase];
-                    if (C.lane == 0) {
-                        unsigned long long base = atomicAdd(&po.count[q], 1ull);
-                        emit_lane(C, nullptr, 1, 0, nullptr, nullptr, nullptr, 0, base, out, cap, emit,
-                                  dA, dB, K);
-                    }
-                    continue;
-                }
-                uint32_t L = 0;
-                setup_level(C, 0, K);
-                while (true) {
-                    if (L == nl - 1) {
-                        run_last_level(C, L, po, phase, emit, dA, dB, K);
-                        if (L == 0) break;
-                        L--;
-                        continue;
-                    }
-                    if (advance_level(C, L, K)) {
-                        L++;
-                        setup_level(C, L, K);
-                    } else {
-                        if (L == 0) break;
-                        L--;
-                    }
-                }
-            } while (od_next(C, 0, C.P->c0_end, vd, K));
-        }
-        uint64_t sA = wave_sum64(dA), sB = wave_sum64(dB);
-        if (C.lane == 0 && (sA | sB)) {
-            atomicAdd(&po.digest[2 * q], (unsigned long long)sA);
-            atomicAdd(&po.digest[2 * q + 1], (unsigned long long)sB);
-        }
-    }
-    uint64_t e = wave_sum64(K.entries), p = wave_sum64(K.probes), k = wave_sum64(K.keys);
-    uint64_t t = wave_sum64(K.tuples), s = wave_sum64(K.seeds);
-    if (C.lane == 0) {
-        EnumStats* st = po.stats + phase;
-        atomicAdd(&st->seeds, (unsigned long long)s);
-        atomicAdd(&st->entries, (unsigned long long)e);
-        atomicAdd(&st->probe_words, (unsigned long long)p);
-        atomicAdd(&st->key_reads, (unsigned long long)k);
-        atomicAdd(&st->tuples, (unsigned long long)t);
-    }
-}
-
-__global__ __launch_bounds__(MN_BLOCK) void k_seed(GraphView g, const uint32_t* __restrict__ slots,
-                                                   uint32_t n, uint64_t* __restrict__ seeds,
-                                                   uint32_t* n_seeds, const uint32_t* err) {
-    if (failed(err)) return;
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = i < n;
-    uint32_t slot = valid ? slots[i] : 0;
-    uint32_t s = valid ? g.s_src[slot] : 0, d = valid ? g.s_dst[slot] : 0;
-    uint32_t c = 0;
-    for (int pass = 0; pass < 2; pass++) {
-        uint32_t base_l = 0;
-        if (pass == 1) {
-            uint32_t total;
-            uint32_t excl = wave_excl_scan(c, total);
-            uint32_t base = 0;
-            if (__lane_id() == 0 && total) base = atomicAdd(n_seeds, total);
-            base = __shfl(base, 0, MN_WAVE);
-            base_l = base + excl;
-        }
-        uint32_t k = 0;
-        if (valid) {
-            for (uint32_t q = 0; q < g.n_queries; q++) {
-                const QueryDev& Q = g.queries[q];
-                for (uint32_t j = 0; j < Q.n_qe; j++) {
-                    uint32_t bit = Q.debi_base + j;
-                    if (!((g.s_debi[(size_t)slot * g.debi_words + (bit >> 5)] >> (bit & 31)) & 1u)) continue;
-                    if (Q.sem == 0 && s == d) continue;
-                    if (!vf_bit(g, s, Q.vf_base + Q.qsrc[j]) || !vf_bit(g, d, Q.vf_base + Q.qdst[j])) continue;
-                    if (pass == 1)
-                        seeds[base_l + k] = (uint64_t)slot | ((uint64_t)q << 32) | ((uint64_t)j << 48);
-                    k++;
-                }
+// Emits every embedding of a complete vertex mapping: the product of the
+// closing edges' accepted instances. st[i] is the run start of close[i];
+// the anchor query edge aqe (0xFF: none) maps to slot aslot. Each tuple is
+// written in query-edge order and folded into the query's two digests:
+// h_s = mix(...mix(mix(s ^ q) + k_0)... + k_{m-1}), mix = SplitMix64's
+// finaliser. All lanes of the wave must call this together.
+__device__ void emit_complete(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                              uint32_t aqe, uint32_t aslot, bool active, const PhaseOut& po, Cnt& K) {
+    uint32_t cnt[MN_MAXCLOSE];
+    uint64_t mult = active ? 1u : 0u;
+    if (active) {
+#pragma unroll
+        for (uint32_t i = 0; i < MN_MAXCLOSE; i++) {
+            cnt[i] = 1;
+            if (i < P.n_close) {
+                const CloseDesc c = P.close[i];
+                const RunIt it = run_open(g, c, st[i], B.f(c.other), B.f(c.nv));
+                uint32_t n = 0;
+                for (uint32_t p = run_next(it, it.p, K.probes); p < it.end; p = run_next(it, p + 1, K.probes)) n++;
+                cnt[i] = n;
+                mult *= n;
             }
         }
-        c = k;
     }
+    const uint32_t q = P.q;
+    const uint64_t pos = grouped_reserve(mult != 0, q, mult, po.count);
+    uint64_t dA = 0, dB = 0;
+    if (mult) {
+        const OutView& ov = po.outs[q];
+        uint64_t* out = ov.keys[po.phase];
+        const uint64_t cap = ov.cap[po.phase];
+        const uint32_t nqe = P.n_qe;
+        const uint64_t s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
+        const uint64_t s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
+        for (uint64_t t = 0; t < mult; t++) {
+            uint32_t dig[MN_MAXCLOSE];
+            uint64_t rem = t;
+#pragma unroll
+            for (uint32_t i = 0; i < MN_MAXCLOSE; i++) {
+                dig[i] = 0;
+                if (rem) {  // t = 0 (the only tuple when every run holds one instance) has all digits 0
+                    dig[i] = (uint32_t)(rem % cnt[i]);
+                    rem /= cnt[i];
+                }
+            }
+            uint64_t hA = s0A, hB = s0B;
+            const bool write = po.emit && (pos + t) < cap;
+            uint64_t* row = out + (pos + t) * nqe;
+            for (uint32_t k = 0; k < nqe; k++) {
+                uint32_t slot;
+                const uint32_t ci = P.close_idx[k];
+                if (k == aqe) {
+                    slot = aslot;
+                } else if (ci == TREE_EDGE) {
+                    slot = B.tree_slot(k);
+                } else {
+                    uint32_t s_st = 0, s_dig = 0;
+#pragma unroll
+                    for (uint32_t i = 0; i < MN_MAXCLOSE; i++)
+                        if (i == ci) {
+                            s_st = st[i];
+                            s_dig = dig[i];
+                        }
+                    const CloseDesc c = P.close[ci];
+                    const RunIt it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
+                    uint32_t p = run_next(it, it.p, K.probes);
+                    for (uint32_t n = 0; n < s_dig; n++) p = run_next(it, p + 1, K.probes);
+                    slot = p < it.end ? (ent_lo(it.adj[p]) & MN_SLOTMASK) : 0u;  // p < end: counted above
+                }
+                const uint64_t key = g.s_key[slot];
+                K.keys++;
+                hA = mn_mix64(hA + key);
+                hB = mn_mix64(hB + key);
+                if (write) row[k] = key;
+            }
+            dA += hA;
+            dB += hB;
+            K.tuples++;
+        }
+    }
+    grouped_digest(mult != 0, q, dA, dB, po.digest);
 }
+
+// Block b of nb -> tile index, so that consecutive tiles run on one XCD
+// (workgroups are dealt to the 8 XCDs round robin; each XCD has its own L2).
+__device__ inline uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+    const uint32_t x = b & 7u, i = b >> 3;
+    const uint32_t q = nb >> 3, rmd = nb & 7u;
+    return x * q + min(x, rmd) + i;
+}
+
+// Largest r in [a, b) with off[r] <= t (off[a] <= t is required).
+__device__ inline uint32_t row_of(const uint64_t* off, uint32_t a, uint32_t b, uint64_t t) {
+    while (a + 1 < b) {
+        const uint32_t m = (a + b) >> 1;
+        if (off[m] <= t)
+            a = m;
+        else
+            b = m;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint32_t* __restrict__ slots,
+                                                        uint32_t n, RowsView R, uint32_t* n_rows,
+                                                        PhaseOut po, const uint32_t* err) {
+    if (failed(err)) return;
+    const SeedPlan& P = g.plans[blockIdx.y];
+    const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
+    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool ok = i < n;
+    uint32_t slot = 0, s = 0, d = 0;
+    if (ok) {
+        slot = slots[i];
+        const uint32_t bit = P.debi_base + P.j;
+        ok = (g.s_debi[(size_t)slot * g.debi_words + (bit >> 5)] >> (bit & 31)) & 1u;
+    }
+    if (ok) {
+        s = g.s_src[slot];
+        d = g.s_dst[slot];
+        K.vf += 2;
+        ok = !(P.sem == MN_SEM_ISO && s == d) && vf_bit(g, s, P.vf_base + P.qa) &&
+             vf_bit(g, d, P.vf_base + P.qb);
+    }
+    Bind B;
+    B.R = R;
+    B.row = false;
+    B.r = 0;
+    B.qa = P.qa;
+    B.fa = s;
+    B.qb = P.qb;
+    B.fb = d;
+    B.sj = P.j;
+    B.sslot = slot;
+    B.cv = 0xFF;
+    B.fw = 0;
+    uint32_t st[MN_MAXCLOSE];
+#pragma unroll
+    for (uint32_t c = 0; c < MN_MAXCLOSE; c++) {
+        st[c] = 0;
+        if (ok && c < P.c0_end) {
+            const CloseDesc cd = P.close[c];
+            st[c] = close_find(g, cd, B.f(cd.other), B.f(cd.nv), K.probes);
+            if (st[c] == NO_RUN) ok = false;
+        }
+    }
+    if (ok) K.seeds++;
+    if (P.n_levels == 0) {  // block-uniform: every lane takes this branch or none
+        emit_complete(g, P, B, st, 0xFF, 0, ok, po, K);
+    } else {
+        const uint64_t bal = __ballot(ok);
+        uint32_t base = 0;
+        if (__lane_id() == 0 && bal) base = atomicAdd(n_rows, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0, MN_WAVE);
+        if (ok) {
+            const uint32_t r = base + (uint32_t)__popcll(bal & lanemask_lt());
+            if (r < R.cap) {
+                wcol(R, 0, r, blockIdx.y);
+                wcol(R, 1 + P.qa, r, s);
+                wcol(R, 1 + P.qb, r, d);
+                wcol(R, 1 + R.wv + P.j, r, slot);
+                for (uint32_t c = 0; c < P.c0_end; c++) {
+                    uint32_t v = 0;
+#pragma unroll
+                    for (uint32_t x = 0; x < MN_MAXCLOSE; x++)
+                        if (x == c) v = st[x];
+                    wcol(R, 1 + R.wv + P.close[c].qe, r, v);
+                }
+                K.rows++;
+            } else {
+                set_err(err, MN_ERR_INTERNAL);  // the host sizes R for every possible row
+            }
+        }
+    }
+    flush_stats(K, po.stats);
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView R, uint32_t n, uint32_t L,
+                                                          uint32_t* __restrict__ lo, uint32_t* __restrict__ cnt,
+                                                          EnumStats* stats, const uint32_t* err) {
+    if (failed(err)) return;
+    const uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x;
+    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (r < n) {
+        const LevelDesc& lv = g.plans[rcol(R, 0, r)].lv[L];
+        uint32_t a = 0, b = 0;
+        if (!lv.empty) {
+            const uint32_t x = rcol(R, 1 + lv.from, r);
+            const uint32_t s0 = g.off[lv.dir][x], s1 = g.off[lv.dir][x + 1];
+            K.range_probes += 2;
+            if (lv.whole) {
+                a = s0;
+                b = s1;
+            } else {
+                a = lower_hi_c(g.adj[lv.dir], s0, s1, lv.key_lo, K.range_probes);
+                b = upper_hi_c(g.adj[lv.dir], a, s1, lv.key_hi, K.range_probes);
+            }
+        }
+        lo[r] = a;
+        cnt[r] = b - a;
+    }
+    flush_stats(K, stats);
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, uint32_t n_in,
+                                                     const uint32_t* __restrict__ lo,
+                                                     const uint64_t* __restrict__ off, uint64_t c0,
+                                                     uint64_t c1, uint32_t L, RowsView out,
+                                                     uint32_t* n_out, PhaseOut po, const uint32_t* err) {
+    __shared__ uint32_t s_rows[2];
+    __shared__ uint32_t s_dead;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint64_t t0 = c0 + (uint64_t)tile * EX_TILE;
+    const uint64_t t1 = min(t0 + (uint64_t)EX_TILE, c1);
+    if (threadIdx.x == 0) {
+        s_dead = failed(err) ? 1u : 0u;  // one read per block: every wave leaves together
+        s_rows[0] = row_of(off, 0, n_in, t0);
+    }
+    if (threadIdx.x == 1) s_rows[1] = row_of(off, 0, n_in, t1 - 1);
+    __syncthreads();
+    if (s_dead) return;
+    const uint32_t rlo = s_rows[0], rhi = s_rows[1] + 1;
+    const uint32_t ncol = 1 + in.wv + in.we;
+    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t it = 0; it < EX_ITEMS; it++) {
+        const uint64_t t = t0 + (uint64_t)it * MN_BLOCK + threadIdx.x;
+        bool ok = t < t1;
+        uint32_t r = 0, w = 0, slot = 0, plan = 0;
+        LevelDesc lv = {};
+        lv.vtx = 0xFF;
+        lv.qe = 0xFF;
+        uint32_t st[MN_MAXCLOSE];
+#pragma unroll
+        for (uint32_t c = 0; c < MN_MAXCLOSE; c++) st[c] = 0;
+        const SeedPlan* P = g.plans;
+        if (ok) {
+            r = row_of(off, rlo, rhi, t);
+            plan = rcol(in, 0, r);
+            P = &g.plans[plan];
+            lv = P->lv[L];
+            const uint32_t p = lo[r] + (uint32_t)(t - off[r]);
+            const uint64_t e = g.adj[lv.dir][p];
+            K.entries++;
+            w = ent_hi(e) & g.nbr_mask;
+            slot = ent_lo(e) & MN_SLOTMASK;
+            if (lv.masked && (ent_lo(e) & MN_FLAG)) ok = false;
+            if (ok && lv.need_vf) {
+                K.vf++;
+                ok = vf_bit(g, w, P->vf_base + lv.vtx);
+            }
+            if (ok && P->sem == MN_SEM_ISO) {
+                for (uint32_t m = 0; m < lv.n_mapped; m++)
+                    if (rcol(in, 1 + P->mapped[m], r) == w) {
+                        ok = false;
+                        break;
+                    }
+            }
+#pragma unroll
+            for (uint32_t c = 0; c < MN_MAXCLOSE; c++) {
+                if (ok && c >= lv.c_begin && c < lv.c_end) {
+                    const CloseDesc cd = P->close[c];
+                    st[c] = close_find(g, cd, rcol(in, 1 + cd.other, r), w, K.probes);
+                    if (st[c] == NO_RUN) ok = false;
+                }
+            }
+        }
+        const bool last = ok && (L + 1 == P->n_levels);
+        const bool to_row = ok && !last;
+        // survivors with levels to go: one new row each
+        const uint64_t bal = __ballot(to_row);
+        uint32_t base = 0;
+        if (__lane_id() == 0 && bal) base = atomicAdd(n_out, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0, MN_WAVE);
+        if (to_row) {
+            const uint32_t dst = base + (uint32_t)__popcll(bal & lanemask_lt());
+            if (dst < out.cap) {
+                for (uint32_t c = 0; c < ncol; c++) wcol(out, c, dst, rcol(in, c, r));
+                wcol(out, 1 + lv.vtx, dst, w);
+                wcol(out, 1 + out.wv + lv.qe, dst, slot);
+#pragma unroll
+                for (uint32_t c = 0; c < MN_MAXCLOSE; c++)
+                    if (c >= lv.c_begin && c < lv.c_end) wcol(out, 1 + out.wv + P->close[c].qe, dst, st[c]);
+                K.rows++;
+            } else {
+                set_err(err, MN_ERR_INTERNAL);  // the host bounds every chunk by the row capacity
+            }
+        }
+        // survivors at their plan's last level: the embeddings themselves
+        Bind B;
+        B.R = in;
+        B.row = true;
+        B.r = r;
+        B.qa = B.fa = B.qb = B.fb = B.sj = B.sslot = 0;
+        B.cv = lv.vtx;
+        B.fw = w;
+        if (last) {
+#pragma unroll
+            for (uint32_t c = 0; c < MN_MAXCLOSE; c++)
+                if (c < P->n_close && !(c >= lv.c_begin && c < lv.c_end))
+                    st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
+        }
+        emit_complete(g, *P, B, st, lv.qe, slot, last, po, K);
+    }
+    flush_stats(K, po.stats);
+}
+
+inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK); }
 
 }  // namespace
 
-void mn_launch_seed(const GraphView& g, const DebiBit*, const uint32_t* slots, uint32_t n,
-                    uint64_t* seeds, uint32_t* n_seeds, const uint32_t* err, hipStream_t s) {
-    if (n) k_seed<<<(n + MN_BLOCK - 1) / MN_BLOCK, MN_BLOCK, 0, s>>>(g, slots, n, seeds, n_seeds, err);
+void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans,
+                         RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s) {
+    if (!n || !n_plans) return;
+    dim3 grid(nblocks(n), n_plans);
+    k_seed_rows<<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err);
 }
 
-void mn_launch_enumerate(const GraphView& g, const uint64_t* seeds, const uint32_t* n_seeds,
-                         uint32_t max_seeds, uint32_t* cursor, PhaseOut po, int phase, int emit,
-                         const uint32_t* err, hipStream_t s) {
-    if (!max_seeds) return;
-    uint32_t waves = max_seeds;
-    uint32_t blocks = (waves + EN_WAVES - 1) / EN_WAVES;
-    if (blocks > 2048) blocks = 2048;
-    k_enumerate<<<blocks, MN_BLOCK, 0, s>>>(g, seeds, n_seeds, cursor, po, phase, emit, err);
+void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32_t L, uint32_t* lo,
+                           uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s) {
+    if (n) k_level_range<<<nblocks(n), MN_BLOCK, 0, s>>>(g, rows, n, L, lo, cnt, st, err);
+}
+
+void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo, const uint64_t* off,
+                      uint64_t c0, uint64_t c1, uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po,
+                      const uint32_t* err, hipStream_t s) {
+    if (c1 <= c0 || !n_in) return;
+    const uint64_t tiles = (c1 - c0 + EX_TILE - 1) / EX_TILE;
+    k_expand<<<(uint32_t)tiles, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, c0, c1, L, out, n_out, po, err);
 }

@@ -94,7 +94,8 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n_ins || failed(b.err)) return;
     uint32_t slot = i < b.n_free ? b.free_stack[b.n_free - 1 - i] : b.fresh + (i - b.n_free);
-    uint32_t s = b.in_src[i], d = b.in_dst[i], l = b.in_lab[i];
+    // caller's vertex ids (validated above) -> internal ids
+    uint32_t s = g.ext2int[b.in_src[i]], d = g.ext2int[b.in_dst[i]], l = b.in_lab[i];
     uint64_t key = b.next_key + i;
     g.s_src[slot] = s;
     g.s_dst[slot] = d;
@@ -298,6 +299,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_init_vertices(uint32_t* vf, uint32
     if (i < (size_t)nv * n_cnt) cnt[i] = 0;
 }
 
+__global__ void k_set_u32(uint32_t* p, uint32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 __global__ __launch_bounds__(MN_BLOCK) void k_widen(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
                                                     uint32_t n, const uint32_t* err) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -307,6 +312,8 @@ __global__ __launch_bounds__(MN_BLOCK) void k_widen(const uint32_t* __restrict__
 inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK); }
 
 }  // namespace
+
+void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) { k_set_u32<<<1, 64, 0, s>>>(p, v); }
 
 void mn_launch_widen(const uint32_t* in, uint64_t* out, uint32_t n, const uint32_t* err, hipStream_t s) {
     if (n) k_widen<<<nblocks(n), MN_BLOCK, 0, s>>>(in, out, n, err);

@@ -13,6 +13,12 @@ size_t mn_scan_scratch_words(uint32_t n);
 void mn_scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* scratch,
                        hipStream_t s);
 
+// Exclusive prefix sum of n u32 values into u64 offsets; *total receives the
+// sum. `scratch` must hold mn_scan64_scratch_words(n) u64 words.
+size_t mn_scan64_scratch_words(uint32_t n);
+void mn_scan_exclusive64(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* scratch,
+                         uint64_t* total, hipStream_t s);
+
 // Stable LSD radix sort of (u64 key, u32 value) pairs on bits [0, nbits).
 // Ping-pongs between (keys, vals) and (ktmp, vtmp); on return keys/vals point
 // at the sorted arrays (the pointers may have been swapped).
@@ -93,27 +99,43 @@ struct OutView {
     uint64_t cap[2];              // tuples
 };
 
-struct EnumStats {  // per phase, accumulated by the enumerator
-    unsigned long long seeds;
-    unsigned long long entries;
-    unsigned long long probe_words;
-    unsigned long long key_reads;
+struct EnumStats {  // per phase, accumulated by the enumeration kernels
+    unsigned long long seeds;         // start rows (work units) that passed the filters
+    unsigned long long entries;       // candidate entries tested by k_expand
+    unsigned long long probes;        // adjacency words read by closing-edge lookups in k_expand
+    unsigned long long range_probes;  // adjacency words read by the candidate-range searches
+    unsigned long long keys;          // edge keys gathered for emission
     unsigned long long tuples;
-    unsigned long long pad[3];
+    unsigned long long vf_reads;
+    unsigned long long rows;          // partial embeddings written between levels
 };
 
 struct PhaseOut {
     unsigned long long* count;    // [n_queries]
     unsigned long long* digest;   // [n_queries][2]
-    EnumStats* stats;
+    EnumStats* stats;             // this phase's figures
     const OutView* outs;          // [n_queries]
+    int phase;                    // 0 new, 1 expired: which buffer of outs[q]
+    int emit;                     // write tuples (else counts and digests only)
 };
 
-void mn_launch_seed(const GraphView& g, const DebiBit* bits, const uint32_t* slots, uint32_t n,
-                    uint64_t* seeds, uint32_t* n_seeds, const uint32_t* err, hipStream_t s);
-void mn_launch_enumerate(const GraphView& g, const uint64_t* seeds, const uint32_t* n_seeds,
-                         uint32_t max_seeds, uint32_t* cursor, PhaseOut po, int phase, int emit,
-                         const uint32_t* err, hipStream_t s);
+// Start rows: one per (batch slot, start position) whose edgeMatcher bit and
+// endpoint filters pass and whose start-level closing edges exist. Plans with
+// no further level emit their embeddings directly.
+void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans,
+                         RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s);
+// Candidate range of every row at level L: lo[r] and cnt[r].
+void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32_t L, uint32_t* lo,
+                           uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s);
+// Tests the candidates [c0, c1) of level L (flattened over rows by the
+// offsets `off`); survivors become rows of `out` or, at a plan's last level,
+// emitted embeddings.
+void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo,
+                      const uint64_t* off, uint64_t c0, uint64_t c1, uint32_t L, RowsView out,
+                      uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s);
+
+// Stores v into *p (a device word) in stream order.
+void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 
 // Widens n u32 values into u64 (sort keys).
 void mn_launch_widen(const uint32_t* in, uint64_t* out, uint32_t n, const uint32_t* err, hipStream_t s);

@@ -24,8 +24,8 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-__global__ __launch_bounds__(MN_BLOCK) void k_scan_local(const uint32_t* __restrict__ in,
-                                                         uint32_t* __restrict__ out,
+// in and out may be the same array (the block sums are scanned in place).
+__global__ __launch_bounds__(MN_BLOCK) void k_scan_local(const uint32_t* in, uint32_t* out,
                                                          uint32_t* __restrict__ sums, uint32_t n) {
     __shared__ uint32_t wsum[RS_WAVES];
     uint32_t tid = threadIdx.x;
@@ -131,9 +131,92 @@ __global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter(const uint64_t* __restr
     }
 }
 
+__device__ inline uint64_t wave_incl_scan64(uint64_t x) {
+    uint32_t lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < MN_WAVE; d <<= 1) {
+        uint32_t lo = __shfl_up((uint32_t)x, d, MN_WAVE);
+        uint32_t hi = __shfl_up((uint32_t)(x >> 32), d, MN_WAVE);
+        if (lane >= (uint32_t)d) x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Block-local exclusive scan into u64 (input u32 counts or u64 block sums).
+template <typename TI>
+__global__ __launch_bounds__(MN_BLOCK) void k_scan64_local(const TI* in, uint64_t* out,
+                                                           uint64_t* __restrict__ sums, uint32_t n) {
+    __shared__ uint64_t wsum[RS_WAVES];
+    uint32_t tid = threadIdx.x;
+    size_t base = (size_t)blockIdx.x * SC_TILE + (size_t)tid * SC_ITEMS;
+    uint64_t v[SC_ITEMS];
+    uint64_t tsum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < SC_ITEMS; i++) {
+        size_t idx = base + i;
+        v[i] = idx < n ? (uint64_t)in[idx] : 0ull;
+        tsum += v[i];
+    }
+    uint64_t incl = wave_incl_scan64(tsum);
+    uint32_t wave = tid / MN_WAVE;
+    if (__lane_id() == MN_WAVE - 1) wsum[wave] = incl;
+    __syncthreads();
+    uint64_t wpre = 0;
+    for (uint32_t w = 0; w < wave; w++) wpre += wsum[w];
+    uint64_t run = wpre + incl - tsum;
+#pragma unroll
+    for (uint32_t i = 0; i < SC_ITEMS; i++) {
+        size_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    if (tid == MN_BLOCK - 1) sums[blockIdx.x] = wpre + incl;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_scan64_add(uint64_t* __restrict__ out,
+                                                         const uint64_t* __restrict__ sums, uint32_t n) {
+    uint64_t add = sums[blockIdx.x];
+    size_t base = (size_t)blockIdx.x * SC_TILE;
+    for (uint32_t i = threadIdx.x; i < SC_TILE; i += MN_BLOCK) {
+        size_t idx = base + i;
+        if (idx < n) out[idx] += add;
+    }
+}
+
+__global__ void k_scan64_total(const uint32_t* __restrict__ in, const uint64_t* __restrict__ out,
+                               uint32_t n, uint64_t* total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *total = n ? out[n - 1] + in[n - 1] : 0ull;
+}
+
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+template <typename TI>
+void scan64_rec(const TI* in, uint64_t* out, uint32_t n, uint64_t* scratch, hipStream_t s) {
+    uint32_t nb = ceil_div(n, SC_TILE);
+    uint64_t* sums = scratch;
+    k_scan64_local<TI><<<nb, MN_BLOCK, 0, s>>>(in, out, sums, n);
+    if (nb == 1) return;
+    scan64_rec<uint64_t>(sums, sums, nb, scratch + nb + 1, s);
+    k_scan64_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n);
+}
+
 }  // namespace
+
+size_t mn_scan64_scratch_words(uint32_t n) {
+    size_t words = 4;
+    uint64_t m = n;
+    while (m > 1) {
+        m = (m + SC_TILE - 1) / SC_TILE;
+        words += m + 1;
+    }
+    return words;
+}
+
+void mn_scan_exclusive64(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* scratch,
+                         uint64_t* total, hipStream_t s) {
+    if (n) scan64_rec<uint32_t>(in, out, n, scratch, s);
+    k_scan64_total<<<1, 64, 0, s>>>(in, out, n, total);
+}
 
 size_t mn_scan_scratch_words(uint32_t n) {
     size_t words = 4;
