@@ -102,7 +102,9 @@ struct mnemonic_ctx {
 
     // queries and their preprocessed tables
     uint32_t n_q = 0;
-    uint32_t n_plans = 0, max_levels = 0, wv = 2, we = 1;
+    uint32_t n_plans = 0, max_levels = 0, wv = 2, we = 1, max_close = 0;
+    uint8_t level_rows[MN_MAXLV] = {0};  // some plan continues past level L
+    uint8_t level_emit[MN_MAXLV] = {0};  // some plan ends at level L
     std::vector<QueryDev> hq;
     std::vector<SeedPlan> hplans;
     std::vector<DebiBit> hdebi;
@@ -148,6 +150,8 @@ struct mnemonic_ctx {
     uint32_t* d_off2[2] = {nullptr, nullptr};
     uint64_t* d_adj[2] = {nullptr, nullptr};
     uint64_t* d_adj2[2] = {nullptr, nullptr};
+    uint64_t* d_adjk[2] = {nullptr, nullptr};   // key of the edge at each adjacency position
+    uint64_t* d_adjk2[2] = {nullptr, nullptr};
 
     // batch scratch
     uint64_t cap_ins = 0, cap_del = 0, cap_touch = 0, cap_sort = 0;
@@ -174,6 +178,7 @@ struct mnemonic_ctx {
     // candidate runs and offsets, scan scratch and small control words
     struct LevelBuf {
         uint32_t* rows = nullptr;  // cap x ncol words, column-wise
+        uint64_t* keys = nullptr;  // cap x we tree-edge keys, column-wise
         uint32_t* lo = nullptr;
         uint32_t* cnt = nullptr;
         uint64_t* off = nullptr;
@@ -183,6 +188,8 @@ struct mnemonic_ctx {
     uint64_t rows_max = 1ull << 22;  // rows per level buffer (bounds each expansion chunk)
     uint64_t* d_scan64 = nullptr;
     uint64_t cap_scan64 = 0;
+    uint32_t* d_tiles = nullptr;     // first row of every expansion tile
+    uint64_t cap_tiles = 0;
     uint32_t* d_nrows = nullptr;     // [MN_MAXLV + 1] row counters
     uint64_t* d_total = nullptr;     // candidate total of the last scan
     uint64_t* h_ctl = nullptr;       // pinned: readback of counters
@@ -215,8 +222,26 @@ struct mnemonic_ctx {
     uint32_t zr_nseeds(int p) const { return (uint32_t)p; }
     uint32_t zr_cursor(int p) const { return 2u + (uint32_t)p; }
     uint32_t zr_count(int p) const { return 4u + (uint32_t)p * n_q; }
-    uint32_t zr_digest(int p) const { return 4u + 2u * n_q + 2u * (uint32_t)p * n_q; }
-    uint32_t zr_stats(int p) const { return 4u + 6u * n_q + 8u * (uint32_t)p; }
+    uint32_t zr_digest(int p) const { return 4u + 2u * n_q + (uint32_t)p * MN_SHARDS * 2u * n_q; }
+    uint32_t zr_stats(int p) const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + (uint32_t)p * MN_SHARDS * 8u; }
+    uint32_t zr_words() const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS; }
+    // shard sums of the last readback: digests [p][q][2], tallies [p][8]
+    std::vector<uint64_t> sum_dig;
+    uint64_t sum_st[2][8] = {{0}};
+    void summarize() {
+        sum_dig.assign(4 * (size_t)n_q, 0);
+        for (int p = 0; p < 2; p++) {
+            for (uint32_t sh = 0; sh < MN_SHARDS; sh++) {
+                const unsigned long long* d = h_zr.data() + zr_digest(p) + (size_t)sh * 2 * n_q;
+                for (uint32_t i = 0; i < 2 * n_q; i++) sum_dig[(size_t)p * 2 * n_q + i] += d[i];
+            }
+            for (int i = 0; i < 8; i++) {
+                uint64_t v = 0;
+                for (uint32_t sh = 0; sh < MN_SHARDS; sh++) v += h_zr[zr_stats(p) + sh * 8 + i];
+                sum_st[p][i] = v;
+            }
+        }
+    }
     uint32_t ncol() const { return 1 + wv + we; }
 };
 
@@ -482,6 +507,13 @@ void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
             SeedPlan P;
             build_plan(c, Q, i, j, P);
             c->max_levels = std::max<uint32_t>(c->max_levels, P.n_levels);
+            c->max_close = std::max<uint32_t>(c->max_close, P.n_close);
+            for (uint32_t L = 0; L < P.n_levels; L++) {
+                if (L + 1 == P.n_levels)
+                    c->level_emit[L] = 1;
+                else
+                    c->level_rows[L] = 1;
+            }
             c->hplans.push_back(P);
         }
         vf_base += q.n_qv;
@@ -522,6 +554,7 @@ GraphView make_view(const mnemonic_ctx* c, bool next) {
     for (int d = 0; d < 2; d++) {
         g.off[d] = next ? c->d_off2[d] : c->d_off[d];
         g.adj[d] = next ? c->d_adj2[d] : c->d_adj[d];
+        g.adjk[d] = next ? c->d_adjk2[d] : c->d_adjk[d];
     }
     g.vf = c->d_vf;
     g.cnt = c->d_cnt;
@@ -580,6 +613,10 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     for (int d = 0; d < 2; d++) {
         uint64_t t = c->cap_E;
         dev_grow(c->d_adj[d], t, need_E, c->E, s);
+        t = c->cap_E;
+        dev_grow(c->d_adjk[d], t, need_E, c->E, s);
+        t = c->cap_E;
+        dev_grow(c->d_adjk2[d], t, need_E, 0, s);
         t = c->cap_E;
         dev_grow(c->d_adj2[d], t, need_E, 0, s);
         if (d == 1) c->cap_E = t;
@@ -675,6 +712,7 @@ PhaseOut phase_out(mnemonic_ctx* c, int p) {
     po.count = c->d_zr + c->zr_count(p);
     po.digest = c->d_zr + c->zr_digest(p);
     po.stats = reinterpret_cast<EnumStats*>(c->d_zr + c->zr_stats(p));
+    po.n_q = c->n_q;
     po.outs = c->d_outs;
     po.phase = p;
     po.emit = (c->flags & MNEMONIC_F_EMIT) ? 1 : 0;
@@ -685,8 +723,8 @@ void reset_phase(mnemonic_ctx* c, int p) {
     hipStream_t s = c->stream;
     // counts, digests, cursor and stats of one phase (err is 0 whenever this runs)
     mn_launch_reset(c->d_err, c->d_zr + c->zr_count(p), c->n_q, s);
-    mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), 2 * c->n_q, s);
-    mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), 8, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), MN_SHARDS * 2 * c->n_q, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), MN_SHARDS * 8, s);
 }
 
 // Grows level L's buffers to hold `need` rows (contents are not kept: a
@@ -697,11 +735,13 @@ void grow_level(mnemonic_ctx* c, uint32_t L, uint64_t need) {
     uint64_t nc = std::min<uint64_t>(c->rows_max, std::max<uint64_t>(need, std::max<uint64_t>(B.cap * 2, 4096)));
     HIPCHK(hipStreamSynchronize(c->stream));
     dev_free(B.rows);
+    dev_free(B.keys);
     dev_free(B.lo);
     dev_free(B.cnt);
     dev_free(B.off);
     B.cap = 0;
     dev_alloc(B.rows, nc * c->ncol());
+    dev_alloc(B.keys, nc * c->we);
     dev_alloc(B.lo, nc);
     dev_alloc(B.cnt, nc);
     dev_alloc(B.off, nc);
@@ -721,6 +761,7 @@ RowsView rows_view(const mnemonic_ctx* c, uint32_t L) {
     R.we = c->we;
     if (L < c->lvb.size()) {
         R.col = c->lvb[L].rows;
+        R.kcol = c->lvb[L].keys;
         R.cap = (uint32_t)c->lvb[L].cap;
     }
     return R;
@@ -759,10 +800,18 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         const uint64_t c1 = std::min<uint64_t>(T, c0 + K);
         uint32_t* n_out = c->d_nrows + L + 1;
         mn_launch_set_u32(n_out, 0, s);
+        const uint64_t need_tiles = mn_expand_tiles(c0, c1) + 1;
+        if (need_tiles > c->cap_tiles) {
+            HIPCHK(hipStreamSynchronize(s));
+            dev_free(c->d_tiles);
+            c->cap_tiles = 0;
+            dev_alloc(c->d_tiles, need_tiles);
+            c->cap_tiles = need_tiles;
+        }
         // one event pair serves every launch: the readback below waits for it
         if (timing) HIPCHK(hipEventRecord(c->ev_x[0], s));
-        mn_launch_expand(g, rows_view(c, L), (uint32_t)n, B.lo, B.off, c0, c1, L, rows_view(c, L + 1), n_out, po,
-                         c->d_err, s);
+        mn_launch_expand(g, rows_view(c, L), (uint32_t)n, B.lo, B.off, c->d_tiles, c0, c1, L, c->max_close,
+                         c->level_rows[L] != 0, c->level_emit[L] != 0, rows_view(c, L + 1), n_out, po, c->d_err, s);
         if (timing) HIPCHK(hipEventRecord(c->ev_x[1], s));
         c->n_expand[po.phase]++;
         const uint64_t n1 = read_u32(c, n_out);
@@ -791,8 +840,8 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
             const uint64_t ns = std::min<uint64_t>(chunk, n_slots - s0);
             if (c->max_levels) grow_level(c, 0, ns * c->n_plans);  // else every plan emits at once
             mn_launch_set_u32(c->d_nrows, 0, s);
-            mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_plans, rows_view(c, 0), c->d_nrows, po, c->d_err,
-                                s);
+            mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_plans, c->max_close, rows_view(c, 0), c->d_nrows,
+                                po, c->d_err, s);
             if (c->max_levels == 0) continue;
             const uint64_t n0 = read_u32(c, c->d_nrows);
             process_level(c, g, po, 0, n0);
@@ -903,9 +952,9 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         for (int d = 0; d < 2; d++) {
             mn_launch_vertex_meta(c->d_off[d], c->nV, (uint32_t)c->E, b.skey[d], (uint32_t)n_ins, dpos[d],
                                   n_prev, c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
-            mn_launch_merge(c->d_off[d], c->d_adj[d], c->nV, (uint32_t)c->E, c->d_off2[d], c->d_meta[d],
-                            b.skey[d], b.sval[d], (uint32_t)n_ins, dpos[d], c->hb, c->d_adj2[d],
-                            c->d_inspos[d], (uint32_t)E_new, c->d_err, s);
+            mn_launch_merge(c->d_off[d], c->d_adj[d], c->d_adjk[d], c->nV, (uint32_t)c->E, c->d_off2[d],
+                            c->d_meta[d], b.skey[d], b.sval[d], c->d_key, (uint32_t)n_ins, dpos[d], c->hb,
+                            c->d_adj2[d], c->d_adjk2[d], c->d_inspos[d], (uint32_t)E_new, c->d_err, s);
         }
     }
     // from here on the kernels work on the merged adjacency
@@ -918,6 +967,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         if (!merge) return;
         for (int d = 0; d < 2; d++) {
             std::swap(c->d_adj[d], c->d_adj2[d]);
+            std::swap(c->d_adjk[d], c->d_adjk2[d]);
             std::swap(c->d_off[d], c->d_off2[d]);
         }
     };
@@ -935,6 +985,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         HIPCHK(hipMemcpyAsync(&err, c->d_err, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        c->summarize();
     } catch (...) {
         swap_in();  // a swap is its own inverse: back to the pre-batch arrays
         throw;
@@ -990,13 +1041,14 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             }
             HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            c->summarize();
         }
         // stats
         mnemonic_stats& st = c->stats;
         st.n_live_edges = c->n_live;
         st.slot_high_water = c->fresh;
         for (int p = 0; p < 2; p++) {
-            const unsigned long long* z = c->h_zr.data() + c->zr_stats(p);
+            const uint64_t* z = c->sum_st[p];
             st.seeds[p] = z[0];
             st.entries_scanned[p] = z[1];
             st.probe_words[p] = z[2];
@@ -1073,6 +1125,8 @@ void free_all(mnemonic_ctx* c) {
         dev_free(c->d_off2[d]);
         dev_free(c->d_adj[d]);
         dev_free(c->d_adj2[d]);
+        dev_free(c->d_adjk[d]);
+        dev_free(c->d_adjk2[d]);
         dev_free(c->d_inspos[d]);
         dev_free(c->d_del_slot[d]);
         for (int k = 0; k < 2; k++) {
@@ -1101,7 +1155,9 @@ void free_all(mnemonic_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->ev_x)
         if (e) (void)hipEventDestroy(e);
+    dev_free(c->d_tiles);
     for (auto& B : c->lvb) {
+        dev_free(B.keys);
         dev_free(B.rows);
         dev_free(B.lo);
         dev_free(B.cnt);
@@ -1199,7 +1255,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         dev_alloc(c->d_last_ts, 1);
         int64_t mn = INT64_MIN;
         HIPCHK(hipMemcpyAsync(c->d_last_ts, &mn, 8, hipMemcpyHostToDevice, s));
-        c->n_zr = 4 + 6 * n_q + 16;
+        c->n_zr = c->zr_words();
         c->h_zr.assign(c->n_zr, 0);
         dev_alloc(c->d_zr, c->n_zr);
         // output buffers
@@ -1249,10 +1305,12 @@ int mnemonic_get_result(mnemonic_ctx* ctx, uint32_t query, mnemonic_result* out)
     if (!ctx->have_result) return MNEMONIC_OK;
     out->n_new = ctx->h_zr[ctx->zr_count(0) + query];
     out->n_expired = ctx->h_zr[ctx->zr_count(1) + query];
-    out->dig_new[0] = ctx->h_zr[ctx->zr_digest(0) + 2 * query];
-    out->dig_new[1] = ctx->h_zr[ctx->zr_digest(0) + 2 * query + 1];
-    out->dig_expired[0] = ctx->h_zr[ctx->zr_digest(1) + 2 * query];
-    out->dig_expired[1] = ctx->h_zr[ctx->zr_digest(1) + 2 * query + 1];
+    const uint64_t* d = ctx->sum_dig.data();
+    const uint32_t nq = ctx->n_q;
+    out->dig_new[0] = d[2 * query];
+    out->dig_new[1] = d[2 * query + 1];
+    out->dig_expired[0] = d[2 * nq + 2 * query];
+    out->dig_expired[1] = d[2 * nq + 2 * query + 1];
     if (ctx->flags & MNEMONIC_F_EMIT) {
         out->new_keys = ctx->houts[query].keys[0];
         out->expired_keys = ctx->houts[query].keys[1];

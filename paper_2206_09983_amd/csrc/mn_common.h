@@ -9,6 +9,8 @@
 //   arrays, direction 0 = out-edges, 1 = in-edges. An entry is one u64:
 //     high 32 bits  (label << nbr_bits) | neighbour
 //     low  32 bits  flag << 31 | slot
+//   A parallel array adjk[dir][p] holds the key of the edge at position p, so
+//   the enumerator reads an emitted edge's key next to its entry.
 //   Each vertex's segment is sorted by the high word, so a label's edges form
 //   one run, parallel edges to one neighbour form a contiguous sub-run, and a
 //   neighbour lookup is a binary search. The flag marks the edges of the batch
@@ -47,6 +49,7 @@
 #define MN_ERR_INTERNAL 99
 
 #define MN_SEM_ISO 0  // mnemonic_semantics: MNEMONIC_ISO
+#define MN_SHARDS 32  // copies of the per-phase digests and work tallies (summed on the host)
 #define MN_MAXCLOSE 8  // closing edges per start edge (the query's cyclomatic number)
 
 // A closing query edge: both of its endpoints are mapped by the time the
@@ -114,11 +117,12 @@ struct SeedPlan {
 
 // Partial embeddings between levels, stored column-wise (row r of column c at
 // col[c * cap + r]): column 0 the plan index, 1 + u the data vertex of query
-// vertex u (u < wv), 1 + wv + k the slot of query edge k (tree edges), or for
-// a closing edge the position of its instance run in the adjacency list that
-// was searched, with bit 31 set when that was the list of f(nv).
+// vertex u (u < wv), 1 + wv + k for a closing edge k the position of its
+// instance run in the adjacency list that was searched (bit 31 set when that
+// was the list of f(nv)); kcol[k * cap + r] the key of tree edge k.
 struct RowsView {
     uint32_t* col;
+    uint64_t* kcol;
     uint32_t cap;
     uint32_t wv;
     uint32_t we;
@@ -158,6 +162,7 @@ struct GraphView {
     const uint64_t* vmask;
     const uint32_t* off[2];
     const uint64_t* adj[2];
+    const uint64_t* adjk[2];   // key of the edge at each adjacency position
     uint32_t* vf;
     uint32_t* cnt;
     uint32_t* s_src;

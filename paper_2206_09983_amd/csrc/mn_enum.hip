@@ -86,26 +86,67 @@ __device__ inline void wcol(const RowsView& R, uint32_t c, uint32_t r, uint32_t 
     R.col[(size_t)c * R.cap + r] = v;
 }
 
+__device__ inline uint64_t rkey(const RowsView& R, uint32_t k, uint32_t r) { return R.kcol[(size_t)k * R.cap + r]; }
+
+__device__ inline void wkey(const RowsView& R, uint32_t k, uint32_t r, uint64_t v) {
+    R.kcol[(size_t)k * R.cap + r] = v;
+}
+
+// Per-lane work tallies of one launch (32 bits suffice per lane and launch).
 struct Cnt {
-    uint64_t seeds, entries, probes, range_probes, keys, tuples, vf, rows;
+    uint32_t seeds, entries, probes, range_probes, keys, tuples, vf, rows;
 };
 
-__device__ void flush_stats(const Cnt& K, EnumStats* st) {
+constexpr uint32_t MAXQ = 256;
+
+// Per-block accumulators in LDS: work tallies and per-query digests are
+// summed here and reach global memory once per block, into shard
+// b % MN_SHARDS, so that no address sees more than a few atomics per launch.
+struct BlockAcc {
+    unsigned long long st[8];
+    unsigned long long dig[2 * MAXQ];
+    uint32_t dead;  // the error word was set before this block started
+};
+
+__device__ inline uint32_t block_linear() { return blockIdx.x + blockIdx.y * gridDim.x; }
+
+// Zeroes the accumulators and reads the error word once for the whole block.
+__device__ void acc_init(BlockAcc& A, uint32_t n_dig, const uint32_t* err) {
+    for (uint32_t i = threadIdx.x; i < 8 + n_dig; i += MN_BLOCK) {
+        if (i < 8)
+            A.st[i] = 0;
+        else
+            A.dig[i - 8] = 0;
+    }
+    if (threadIdx.x == 0) A.dead = failed(err) ? 1u : 0u;
+    __syncthreads();
+}
+
+// Adds the lanes' tallies and the block's digests to this block's shard.
+// Every thread of the block must call it.
+__device__ void acc_flush(BlockAcc& A, const Cnt& K, uint32_t n_dig, EnumStats* stats,
+                          unsigned long long* digest) {
     const uint64_t v[8] = {wave_sum64(K.seeds), wave_sum64(K.entries), wave_sum64(K.probes),
                            wave_sum64(K.range_probes), wave_sum64(K.keys), wave_sum64(K.tuples),
                            wave_sum64(K.vf), wave_sum64(K.rows)};
     if (__lane_id() == 0) {
-        unsigned long long* d = reinterpret_cast<unsigned long long*>(st);
 #pragma unroll
         for (int i = 0; i < 8; i++)
-            if (v[i]) atomicAdd(d + i, (unsigned long long)v[i]);
+            if (v[i]) atomicAdd(&A.st[i], (unsigned long long)v[i]);
     }
+    __syncthreads();
+    const uint32_t shard = block_linear() % MN_SHARDS;
+    unsigned long long* gst = reinterpret_cast<unsigned long long*>(stats + shard);
+    unsigned long long* gdig = digest ? digest + (size_t)shard * n_dig : nullptr;
+    if (threadIdx.x < 8 && A.st[threadIdx.x]) atomicAdd(&gst[threadIdx.x], A.st[threadIdx.x]);
+    for (uint32_t i = threadIdx.x; i < n_dig; i += MN_BLOCK)
+        if (A.dig[i]) atomicAdd(&gdig[i], A.dig[i]);
 }
 
 // Binary searches over the high words of a sorted segment, counting the
 // words they read.
 __device__ inline uint32_t lower_hi_c(const uint64_t* adj, uint32_t lo, uint32_t hi, uint32_t key,
-                                      uint64_t& probes) {
+                                      uint32_t& probes) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(adj);
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
@@ -119,7 +160,7 @@ __device__ inline uint32_t lower_hi_c(const uint64_t* adj, uint32_t lo, uint32_t
 }
 
 __device__ inline uint32_t upper_hi_c(const uint64_t* adj, uint32_t lo, uint32_t hi, uint32_t key,
-                                      uint64_t& probes) {
+                                      uint32_t& probes) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(adj);
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
@@ -140,7 +181,7 @@ struct Bind {
     bool row;  // false at the start level
     uint32_t r;
     uint32_t qa, fa, qb, fb;  // start level: f(qa), f(qb)
-    uint32_t sj, sslot;       // start level: start position and its slot
+    uint64_t skey;            // start level: key of the start edge
     uint32_t cv, fw;          // the level's new vertex (0xFF: none) and its image
 
     __device__ uint32_t f(uint32_t u) const {
@@ -148,10 +189,10 @@ struct Bind {
         if (!row) return u == qa ? fa : fb;
         return rcol(R, 1 + u, r);
     }
-    // slot of a tree edge mapped before the current level
-    __device__ uint32_t tree_slot(uint32_t k) const {
-        if (!row) return sslot;  // at the start level the start edge is the only tree edge
-        return rcol(R, 1 + R.wv + k, r);
+    // key of a tree edge mapped before the current level
+    __device__ uint64_t tree_key(uint32_t k) const {
+        if (!row) return skey;  // at the start level the start edge is the only tree edge
+        return rkey(R, k, r);
     }
 };
 
@@ -161,7 +202,7 @@ struct Bind {
 // edge: the first accepted entry of the list), with RUN_SWAP set when the
 // list of fn was used, or NO_RUN when no instance passes the mask.
 __device__ uint32_t close_find(const GraphView& g, const CloseDesc& c, uint32_t fo, uint32_t fn,
-                               uint64_t& probes) {
+                               uint32_t& probes) {
     const uint32_t d0 = c.dir, d1 = 1u - c.dir;
     const uint32_t a0 = g.off[d0][fo], a1 = g.off[d0][fo + 1];
     const uint32_t b0 = g.off[d1][fn], b1 = g.off[d1][fn + 1];
@@ -193,6 +234,7 @@ __device__ uint32_t close_find(const GraphView& g, const CloseDesc& c, uint32_t 
 // Iterator over the accepted instances of a closing edge from its run start.
 struct RunIt {
     const uint64_t* adj;
+    const uint64_t* adjk;
     uint32_t p, end, key, tgt, nbr_mask;
     bool lab, masked;
 };
@@ -204,6 +246,7 @@ __device__ inline RunIt run_open(const GraphView& g, const CloseDesc& c, uint32_
     const uint32_t dir = sw ? 1u - c.dir : (uint32_t)c.dir;
     const uint32_t x = sw ? fn : fo;
     it.adj = g.adj[dir];
+    it.adjk = g.adjk[dir];
     it.p = st & ~RUN_SWAP;
     it.end = g.off[dir][x + 1];
     it.tgt = sw ? fo : fn;
@@ -215,7 +258,7 @@ __device__ inline RunIt run_open(const GraphView& g, const CloseDesc& c, uint32_
 }
 
 // First accepted instance at or after p, or it.end.
-__device__ inline uint32_t run_next(const RunIt& it, uint32_t p, uint64_t& probes) {
+__device__ inline uint32_t run_next(const RunIt& it, uint32_t p, uint32_t& probes) {
     for (; p < it.end; p++) {
         const uint64_t e = it.adj[p];
         probes += 2;
@@ -253,8 +296,9 @@ __device__ uint64_t grouped_reserve(bool active, uint32_t q, uint64_t v, unsigne
     return mine;
 }
 
-// Adds (a, b) of the active lanes to digest[2q], digest[2q + 1], one atomic
-// pair per distinct q in the wave. All lanes must call this together.
+// Adds (a, b) of the active lanes to the block's LDS digests dig[2q],
+// dig[2q + 1], one atomic pair per distinct q in the wave. All lanes must call
+// this together.
 __device__ void grouped_digest(bool active, uint32_t q, uint64_t a, uint64_t b, unsigned long long* digest) {
     uint64_t pending = __ballot(active);
     const uint32_t lane = __lane_id();
@@ -272,87 +316,109 @@ __device__ void grouped_digest(bool active, uint32_t q, uint64_t a, uint64_t b, 
     }
 }
 
-// Emits every embedding of a complete vertex mapping: the product of the
-// closing edges' accepted instances. st[i] is the run start of close[i];
-// the anchor query edge aqe (0xFF: none) maps to slot aslot. Each tuple is
-// written in query-edge order and folded into the query's two digests:
-// h_s = mix(...mix(mix(s ^ q) + k_0)... + k_{m-1}), mix = SplitMix64's
-// finaliser. All lanes of the wave must call this together.
-__device__ void emit_complete(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                              uint32_t aqe, uint32_t aslot, bool active, const PhaseOut& po, Cnt& K) {
-    uint32_t cnt[MN_MAXCLOSE];
-    uint64_t mult = active ? 1u : 0u;
-    if (active) {
+// Number of embeddings of a complete vertex mapping: the product over the
+// closing edges of their accepted instances (st[i] is the run start of
+// close[i]); cnt[i] receives each factor.
+template <int NC>
+__device__ uint64_t close_mult(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                               uint32_t* cnt, uint32_t& probes) {
+    constexpr int NA = NC > 0 ? NC : 1;
+    uint64_t mult = 1;
 #pragma unroll
-        for (uint32_t i = 0; i < MN_MAXCLOSE; i++) {
-            cnt[i] = 1;
-            if (i < P.n_close) {
-                const CloseDesc c = P.close[i];
-                const RunIt it = run_open(g, c, st[i], B.f(c.other), B.f(c.nv));
-                uint32_t n = 0;
-                for (uint32_t p = run_next(it, it.p, K.probes); p < it.end; p = run_next(it, p + 1, K.probes)) n++;
-                cnt[i] = n;
-                mult *= n;
-            }
+    for (uint32_t i = 0; i < NA; i++) {
+        cnt[i] = 1;
+        if (i < (uint32_t)NC && i < P.n_close) {
+            const CloseDesc c = P.close[i];
+            const RunIt it = run_open(g, c, st[i], B.f(c.other), B.f(c.nv));
+            uint32_t n = 0;
+            for (uint32_t p = run_next(it, it.p, probes); p < it.end; p = run_next(it, p + 1, probes)) n++;
+            cnt[i] = n;
+            mult *= n;
         }
     }
+    return mult;
+}
+
+// Writes the mult embeddings of one complete mapping at rows pos.. of the
+// query's output (when emitting) and returns their digest sums: each tuple
+// lists its edges' keys in query-edge order, the anchor query edge aqe
+// (0xFF: none) mapping to the edge with key akey, and is folded as
+// h_s = mix(...mix(mix(s ^ q) + k_0)... + k_{m-1}), mix = SplitMix64's
+// finaliser.
+template <int NC>
+__device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                            const uint32_t* cnt, uint64_t mult, uint32_t aqe, uint64_t akey, uint64_t pos,
+                            const PhaseOut& po, Cnt& K, uint64_t& dA, uint64_t& dB) {
+    constexpr int NA = NC > 0 ? NC : 1;
+    const uint32_t q = P.q;
+    const OutView& ov = po.outs[q];
+    uint64_t* out = ov.keys[po.phase];
+    const uint64_t cap = ov.cap[po.phase];
+    const uint32_t nqe = P.n_qe;
+    const uint64_t s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
+    const uint64_t s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
+    uint32_t unused = 0;
+    for (uint64_t t = 0; t < mult; t++) {
+        uint32_t dig[NA];
+        uint64_t rem = t;
+#pragma unroll
+        for (uint32_t i = 0; i < NA; i++) {
+            dig[i] = 0;
+            if (rem) {  // t = 0 (the only tuple when every run holds one instance) has all digits 0
+                dig[i] = (uint32_t)(rem % cnt[i]);
+                rem /= cnt[i];
+            }
+        }
+        uint64_t hA = s0A, hB = s0B;
+        const bool write = po.emit && (pos + t) < cap;
+        uint64_t* row = out + (pos + t) * nqe;
+        for (uint32_t k = 0; k < nqe; k++) {
+            uint64_t key;
+            const uint32_t ci = P.close_idx[k];
+            if (k == aqe) {
+                key = akey;
+            } else if (ci == TREE_EDGE) {
+                key = B.tree_key(k);
+            } else {
+                uint32_t s_st = 0, s_dig = 0;
+#pragma unroll
+                for (uint32_t i = 0; i < NA; i++)
+                    if (i == ci) {
+                        s_st = st[i];
+                        s_dig = dig[i];
+                    }
+                const CloseDesc c = P.close[ci];
+                const RunIt it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
+                uint32_t p = run_next(it, it.p, unused);  // walks runs counted by close_mult
+                for (uint32_t n = 0; n < s_dig; n++) p = run_next(it, p + 1, unused);
+                key = p < it.end ? it.adjk[p] : 0ull;  // p < end: the instances were counted
+            }
+            K.keys++;
+            hA = mn_mix64(hA + key);
+            hB = mn_mix64(hB + key);
+            if (write) row[k] = key;
+        }
+        dA += hA;
+        dB += hB;
+        K.tuples++;
+    }
+}
+
+// Emits every embedding of a complete vertex mapping, reserving its places
+// with one global atomic per query and wave. All lanes of the wave must call
+// this together (used where complete mappings are rare: 2-vertex queries).
+template <int NC>
+__device__ void emit_complete(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                              uint32_t aqe, uint64_t akey, bool active, const PhaseOut& po, BlockAcc& A,
+                              Cnt& K) {
+    constexpr int NA = NC > 0 ? NC : 1;
+    uint32_t cnt[NA];
+    const uint64_t mult = active ? close_mult<NC>(g, P, B, st, cnt, K.probes) : 0u;
     const uint32_t q = P.q;
     const uint64_t pos = grouped_reserve(mult != 0, q, mult, po.count);
     uint64_t dA = 0, dB = 0;
-    if (mult) {
-        const OutView& ov = po.outs[q];
-        uint64_t* out = ov.keys[po.phase];
-        const uint64_t cap = ov.cap[po.phase];
-        const uint32_t nqe = P.n_qe;
-        const uint64_t s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
-        const uint64_t s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
-        for (uint64_t t = 0; t < mult; t++) {
-            uint32_t dig[MN_MAXCLOSE];
-            uint64_t rem = t;
-#pragma unroll
-            for (uint32_t i = 0; i < MN_MAXCLOSE; i++) {
-                dig[i] = 0;
-                if (rem) {  // t = 0 (the only tuple when every run holds one instance) has all digits 0
-                    dig[i] = (uint32_t)(rem % cnt[i]);
-                    rem /= cnt[i];
-                }
-            }
-            uint64_t hA = s0A, hB = s0B;
-            const bool write = po.emit && (pos + t) < cap;
-            uint64_t* row = out + (pos + t) * nqe;
-            for (uint32_t k = 0; k < nqe; k++) {
-                uint32_t slot;
-                const uint32_t ci = P.close_idx[k];
-                if (k == aqe) {
-                    slot = aslot;
-                } else if (ci == TREE_EDGE) {
-                    slot = B.tree_slot(k);
-                } else {
-                    uint32_t s_st = 0, s_dig = 0;
-#pragma unroll
-                    for (uint32_t i = 0; i < MN_MAXCLOSE; i++)
-                        if (i == ci) {
-                            s_st = st[i];
-                            s_dig = dig[i];
-                        }
-                    const CloseDesc c = P.close[ci];
-                    const RunIt it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
-                    uint32_t p = run_next(it, it.p, K.probes);
-                    for (uint32_t n = 0; n < s_dig; n++) p = run_next(it, p + 1, K.probes);
-                    slot = p < it.end ? (ent_lo(it.adj[p]) & MN_SLOTMASK) : 0u;  // p < end: counted above
-                }
-                const uint64_t key = g.s_key[slot];
-                K.keys++;
-                hA = mn_mix64(hA + key);
-                hB = mn_mix64(hB + key);
-                if (write) row[k] = key;
-            }
-            dA += hA;
-            dB += hB;
-            K.tuples++;
-        }
-    }
-    grouped_digest(mult != 0, q, dA, dB, po.digest);
+    if (mult) emit_tuples<NC>(g, P, B, st, cnt, mult, aqe, akey, pos, po, K, dA, dB);
+    grouped_digest(mult != 0, q, dA, dB, A.dig);
 }
 
 // Block b of nb -> tile index, so that consecutive tiles run on one XCD
@@ -375,14 +441,16 @@ __device__ inline uint32_t row_of(const uint64_t* off, uint32_t a, uint32_t b, u
     return a;
 }
 
+template <int NC>
 __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint32_t* __restrict__ slots,
                                                         uint32_t n, RowsView R, uint32_t* n_rows,
                                                         PhaseOut po, const uint32_t* err) {
-    if (failed(err)) return;
+    __shared__ BlockAcc A;
+    acc_init(A, 2 * po.n_q, err);
     const SeedPlan& P = g.plans[blockIdx.y];
     const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
     Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
-    bool ok = i < n;
+    bool ok = i < n && !A.dead;
     uint32_t slot = 0, s = 0, d = 0;
     if (ok) {
         slot = slots[i];
@@ -404,15 +472,15 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
     B.fa = s;
     B.qb = P.qb;
     B.fb = d;
-    B.sj = P.j;
-    B.sslot = slot;
+    B.skey = ok ? g.s_key[slot] : 0ull;
     B.cv = 0xFF;
     B.fw = 0;
-    uint32_t st[MN_MAXCLOSE];
+    constexpr int NA = NC > 0 ? NC : 1;
+    uint32_t st[NA];
 #pragma unroll
-    for (uint32_t c = 0; c < MN_MAXCLOSE; c++) {
+    for (uint32_t c = 0; c < NA; c++) {
         st[c] = 0;
-        if (ok && c < P.c0_end) {
+        if (ok && c < (uint32_t)NC && c < P.c0_end) {
             const CloseDesc cd = P.close[c];
             st[c] = close_find(g, cd, B.f(cd.other), B.f(cd.nv), K.probes);
             if (st[c] == NO_RUN) ok = false;
@@ -420,7 +488,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
     }
     if (ok) K.seeds++;
     if (P.n_levels == 0) {  // block-uniform: every lane takes this branch or none
-        emit_complete(g, P, B, st, 0xFF, 0, ok, po, K);
+        emit_complete<NC>(g, P, B, st, 0xFF, 0ull, ok, po, A, K);
     } else {
         const uint64_t bal = __ballot(ok);
         uint32_t base = 0;
@@ -432,30 +500,27 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
                 wcol(R, 0, r, blockIdx.y);
                 wcol(R, 1 + P.qa, r, s);
                 wcol(R, 1 + P.qb, r, d);
-                wcol(R, 1 + R.wv + P.j, r, slot);
-                for (uint32_t c = 0; c < P.c0_end; c++) {
-                    uint32_t v = 0;
+                wkey(R, P.j, r, B.skey);
 #pragma unroll
-                    for (uint32_t x = 0; x < MN_MAXCLOSE; x++)
-                        if (x == c) v = st[x];
-                    wcol(R, 1 + R.wv + P.close[c].qe, r, v);
-                }
+                for (uint32_t c = 0; c < NA; c++)
+                    if (c < (uint32_t)NC && c < P.c0_end) wcol(R, 1 + R.wv + P.close[c].qe, r, st[c]);
                 K.rows++;
             } else {
                 set_err(err, MN_ERR_INTERNAL);  // the host sizes R for every possible row
             }
         }
     }
-    flush_stats(K, po.stats);
+    acc_flush(A, K, 2 * po.n_q, po.stats, po.digest);
 }
 
 __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView R, uint32_t n, uint32_t L,
                                                           uint32_t* __restrict__ lo, uint32_t* __restrict__ cnt,
                                                           EnumStats* stats, const uint32_t* err) {
-    if (failed(err)) return;
+    __shared__ BlockAcc A;
+    acc_init(A, 0, err);
     const uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x;
     Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (r < n) {
+    if (r < n && !A.dead) {
         const LevelDesc& lv = g.plans[rcol(R, 0, r)].lv[L];
         uint32_t a = 0, b = 0;
         if (!lv.empty) {
@@ -473,50 +538,92 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
         lo[r] = a;
         cnt[r] = b - a;
     }
-    flush_stats(K, stats);
+    acc_flush(A, K, 0, stats, nullptr);
 }
 
+// First row of every expansion tile: tile_row[i] = row of candidate
+// c0 + i * EX_TILE for i < nt, tile_row[nt] = row of candidate c1 - 1.
+__global__ __launch_bounds__(MN_BLOCK) void k_partition(const uint64_t* __restrict__ off, uint32_t n,
+                                                        uint64_t c0, uint64_t c1, uint32_t nt,
+                                                        uint32_t* __restrict__ tile_row) {
+    const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
+    if (i > nt) return;
+    const uint64_t t = i < nt ? c0 + (uint64_t)i * EX_TILE : c1 - 1;
+    tile_row[i] = row_of(off, 0, n, t);
+}
+
+constexpr uint32_t EX_LDS_ROWS = EX_TILE + 1;
+constexpr uint32_t NO_LOC = 0xFFFFFFFFu;
+
+// One block tests a tile of EX_TILE candidates in two passes. Pass 1 runs the
+// filters and gives every survivor a place inside the block (LDS counters per
+// query for embeddings, one for new rows); one global atomic per query and
+// block then reserves the block's places; pass 2 writes rows and embeddings.
+// Contended device-scope atomics (they serialise across the XCDs) drop from
+// one per wave and item to one per block.
+template <int NC, bool ROWS, bool EMIT>
 __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, uint32_t n_in,
                                                      const uint32_t* __restrict__ lo,
-                                                     const uint64_t* __restrict__ off, uint64_t c0,
+                                                     const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ tile_row, uint64_t c0,
                                                      uint64_t c1, uint32_t L, RowsView out,
                                                      uint32_t* n_out, PhaseOut po, const uint32_t* err) {
-    __shared__ uint32_t s_rows[2];
-    __shared__ uint32_t s_dead;
+    constexpr int NA = NC > 0 ? NC : 1;
+    __shared__ uint64_t s_off[EX_LDS_ROWS];
+    __shared__ BlockAcc A;
+    __shared__ uint32_t s_r[EX_TILE], s_p[EX_TILE], s_loc[EX_TILE];
+    __shared__ uint32_t s_st[NA][EX_TILE];
+    __shared__ unsigned long long s_qn[MAXQ];  // places per query: counts, then global bases
+    __shared__ uint32_t s_nrows, s_rbase;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint64_t t0 = c0 + (uint64_t)tile * EX_TILE;
     const uint64_t t1 = min(t0 + (uint64_t)EX_TILE, c1);
-    if (threadIdx.x == 0) {
-        s_dead = failed(err) ? 1u : 0u;  // one read per block: every wave leaves together
-        s_rows[0] = row_of(off, 0, n_in, t0);
-    }
-    if (threadIdx.x == 1) s_rows[1] = row_of(off, 0, n_in, t1 - 1);
-    __syncthreads();
-    if (s_dead) return;
-    const uint32_t rlo = s_rows[0], rhi = s_rows[1] + 1;
+    const uint32_t rlo = tile_row[tile], rhi = tile_row[tile + 1] + 1;  // rows of this tile lie in [rlo, rhi)
+    const uint32_t span = rhi - rlo;
+    const bool staged = span <= EX_LDS_ROWS;
+    if (staged)
+        for (uint32_t x = threadIdx.x; x < span; x += MN_BLOCK) s_off[x] = off[rlo + x];
+    if (EMIT)
+        for (uint32_t x = threadIdx.x; x < po.n_q; x += MN_BLOCK) s_qn[x] = 0;
+    if (threadIdx.x == 0) s_nrows = 0;
+    acc_init(A, EMIT ? 2 * po.n_q : 0, err);  // its barrier also publishes the above
     const uint32_t ncol = 1 + in.wv + in.we;
     Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    // ---- pass 1: filters and places inside the block
     for (uint32_t it = 0; it < EX_ITEMS; it++) {
-        const uint64_t t = t0 + (uint64_t)it * MN_BLOCK + threadIdx.x;
-        bool ok = t < t1;
-        uint32_t r = 0, w = 0, slot = 0, plan = 0;
+        const uint32_t idx = it * MN_BLOCK + threadIdx.x;
+        const uint64_t t = t0 + idx;
+        bool ok = t < t1 && !A.dead;
+        uint32_t r = 0, w = 0, p = 0;
         LevelDesc lv = {};
-        lv.vtx = 0xFF;
-        lv.qe = 0xFF;
-        uint32_t st[MN_MAXCLOSE];
+        uint32_t st[NA];
 #pragma unroll
-        for (uint32_t c = 0; c < MN_MAXCLOSE; c++) st[c] = 0;
+        for (uint32_t c = 0; c < NA; c++) st[c] = 0;
         const SeedPlan* P = g.plans;
         if (ok) {
-            r = row_of(off, rlo, rhi, t);
-            plan = rcol(in, 0, r);
-            P = &g.plans[plan];
+            uint64_t o;
+            if (staged) {  // largest r with off[r] <= t, searched in LDS
+                uint32_t a = 0, b = span;
+                while (a + 1 < b) {
+                    const uint32_t m = (a + b) >> 1;
+                    if (s_off[m] <= t)
+                        a = m;
+                    else
+                        b = m;
+                }
+                r = rlo + a;
+                o = s_off[a];
+            } else {
+                r = row_of(off, rlo, rhi, t);
+                o = off[r];
+            }
+            P = &g.plans[rcol(in, 0, r)];
             lv = P->lv[L];
-            const uint32_t p = lo[r] + (uint32_t)(t - off[r]);
+            p = lo[r] + (uint32_t)(t - o);
             const uint64_t e = g.adj[lv.dir][p];
             K.entries++;
             w = ent_hi(e) & g.nbr_mask;
-            slot = ent_lo(e) & MN_SLOTMASK;
             if (lv.masked && (ent_lo(e) & MN_FLAG)) ok = false;
             if (ok && lv.need_vf) {
                 K.vf++;
@@ -530,8 +637,8 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                     }
             }
 #pragma unroll
-            for (uint32_t c = 0; c < MN_MAXCLOSE; c++) {
-                if (ok && c >= lv.c_begin && c < lv.c_end) {
+            for (uint32_t c = 0; c < NA; c++) {
+                if (ok && c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
                     const CloseDesc cd = P->close[c];
                     st[c] = close_find(g, cd, rcol(in, 1 + cd.other, r), w, K.probes);
                     if (st[c] == NO_RUN) ok = false;
@@ -540,53 +647,140 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
         }
         const bool last = ok && (L + 1 == P->n_levels);
         const bool to_row = ok && !last;
-        // survivors with levels to go: one new row each
-        const uint64_t bal = __ballot(to_row);
-        uint32_t base = 0;
-        if (__lane_id() == 0 && bal) base = atomicAdd(n_out, (uint32_t)__popcll(bal));
-        base = __shfl(base, 0, MN_WAVE);
-        if (to_row) {
-            const uint32_t dst = base + (uint32_t)__popcll(bal & lanemask_lt());
+        uint32_t loc = NO_LOC;
+        if (ROWS) {
+            const uint64_t bal = __ballot(to_row);
+            uint32_t base = 0;
+            if (__lane_id() == 0 && bal) base = atomicAdd(&s_nrows, (uint32_t)__popcll(bal));
+            base = __shfl(base, 0, MN_WAVE);
+            if (to_row) loc = base + (uint32_t)__popcll(bal & lanemask_lt());
+        } else if (to_row) {
+            set_err(err, MN_ERR_INTERNAL);  // the host launches ROWS wherever a plan continues
+        }
+        if (EMIT) {
+            uint64_t mult = 0;
+            if (last) {
+                Bind B;
+                B.R = in;
+                B.row = true;
+                B.r = r;
+                B.qa = B.fa = B.qb = B.fb = 0;
+                B.skey = 0;
+                B.cv = lv.vtx;
+                B.fw = w;
+#pragma unroll
+                for (uint32_t c = 0; c < NA; c++)
+                    if (c < (uint32_t)NC && c < P->n_close && !(c >= lv.c_begin && c < lv.c_end))
+                        st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
+                uint32_t cnt[NA];
+                mult = close_mult<NC>(g, *P, B, st, cnt, K.probes);
+            }
+            const uint64_t lpos = grouped_reserve(mult != 0, P->q, mult, s_qn);
+            if (mult) loc = (uint32_t)lpos;
+        } else if (last) {
+            set_err(err, MN_ERR_INTERNAL);  // the host launches EMIT wherever a plan ends
+        }
+        if (t < t1) {
+            s_loc[idx] = loc;
+            s_r[idx] = r;
+            s_p[idx] = p;
+#pragma unroll
+            for (uint32_t c = 0; c < NA; c++) s_st[c][idx] = st[c];
+        }
+    }
+    __syncthreads();
+    // ---- one global reservation per query (and one for rows) per block
+    if (ROWS && threadIdx.x == 0 && s_nrows) s_rbase = atomicAdd(n_out, s_nrows);
+    if (EMIT)
+        for (uint32_t x = threadIdx.x; x < po.n_q; x += MN_BLOCK)
+            if (s_qn[x]) s_qn[x] = atomicAdd(&po.count[x], s_qn[x]);
+    __syncthreads();
+
+    // ---- pass 2: write rows and embeddings at their places
+    for (uint32_t it = 0; it < EX_ITEMS; it++) {
+        const uint32_t idx = it * MN_BLOCK + threadIdx.x;
+        const uint64_t t = t0 + idx;
+        const uint32_t loc = t < t1 ? s_loc[idx] : NO_LOC;
+        const bool active = loc != NO_LOC;
+        uint32_t r = 0, w = 0;
+        uint64_t akey = 0;
+        LevelDesc lv = {};
+        lv.vtx = 0xFF;
+        lv.qe = 0xFF;
+        uint32_t st[NA];
+#pragma unroll
+        for (uint32_t c = 0; c < NA; c++) st[c] = active ? s_st[c][idx] : 0u;
+        const SeedPlan* P = g.plans;
+        if (active) {
+            r = s_r[idx];
+            P = &g.plans[rcol(in, 0, r)];
+            lv = P->lv[L];
+            const uint32_t p = s_p[idx];
+            w = ent_hi(g.adj[lv.dir][p]) & g.nbr_mask;
+            akey = g.adjk[lv.dir][p];
+        }
+        const bool last = active && (L + 1 == P->n_levels);
+        if (ROWS && active && !last) {
+            const uint32_t dst = s_rbase + loc;
             if (dst < out.cap) {
                 for (uint32_t c = 0; c < ncol; c++) wcol(out, c, dst, rcol(in, c, r));
+                for (uint32_t k = 0; k < in.we; k++) wkey(out, k, dst, rkey(in, k, r));
                 wcol(out, 1 + lv.vtx, dst, w);
-                wcol(out, 1 + out.wv + lv.qe, dst, slot);
+                wkey(out, lv.qe, dst, akey);
+                K.keys++;
 #pragma unroll
-                for (uint32_t c = 0; c < MN_MAXCLOSE; c++)
-                    if (c >= lv.c_begin && c < lv.c_end) wcol(out, 1 + out.wv + P->close[c].qe, dst, st[c]);
+                for (uint32_t c = 0; c < NA; c++)
+                    if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end)
+                        wcol(out, 1 + out.wv + P->close[c].qe, dst, st[c]);
                 K.rows++;
             } else {
                 set_err(err, MN_ERR_INTERNAL);  // the host bounds every chunk by the row capacity
             }
         }
-        // survivors at their plan's last level: the embeddings themselves
-        Bind B;
-        B.R = in;
-        B.row = true;
-        B.r = r;
-        B.qa = B.fa = B.qb = B.fb = B.sj = B.sslot = 0;
-        B.cv = lv.vtx;
-        B.fw = w;
-        if (last) {
+        if (EMIT) {
+            uint64_t dA = 0, dB = 0;
+            if (last) {
+                Bind B;
+                B.R = in;
+                B.row = true;
+                B.r = r;
+                B.qa = B.fa = B.qb = B.fb = 0;
+                B.skey = 0;
+                B.cv = lv.vtx;
+                B.fw = w;
 #pragma unroll
-            for (uint32_t c = 0; c < MN_MAXCLOSE; c++)
-                if (c < P->n_close && !(c >= lv.c_begin && c < lv.c_end))
-                    st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
+                for (uint32_t c = 0; c < NA; c++)
+                    if (c < (uint32_t)NC && c < P->n_close && !(c >= lv.c_begin && c < lv.c_end))
+                        st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
+                uint32_t cnt[NA];
+                uint32_t unused = 0;
+                const uint64_t mult = close_mult<NC>(g, *P, B, st, cnt, unused);
+                emit_tuples<NC>(g, *P, B, st, cnt, mult, lv.qe, akey, s_qn[P->q] + loc, po, K, dA, dB);
+            }
+            grouped_digest(last, P->q, dA, dB, A.dig);
         }
-        emit_complete(g, *P, B, st, lv.qe, slot, last, po, K);
     }
-    flush_stats(K, po.stats);
+    acc_flush(A, K, EMIT ? 2 * po.n_q : 0, po.stats, po.digest);
 }
 
 inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK); }
 
 }  // namespace
 
-void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans,
+// Closing-edge arrays sized to the context's largest plan: 0, 1, 2, 4 or 8.
+inline int nc_bucket(uint32_t nc) { return nc == 0 ? 0 : nc == 1 ? 1 : nc == 2 ? 2 : nc <= 4 ? 4 : 8; }
+
+void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans, uint32_t max_close,
                          RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s) {
     if (!n || !n_plans) return;
     dim3 grid(nblocks(n), n_plans);
-    k_seed_rows<<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err);
+    switch (nc_bucket(max_close)) {
+        case 0: k_seed_rows<0><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
+        case 1: k_seed_rows<1><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
+        case 2: k_seed_rows<2><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
+        case 4: k_seed_rows<4><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
+        default: k_seed_rows<8><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
+    }
 }
 
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32_t L, uint32_t* lo,
@@ -594,10 +788,32 @@ void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32
     if (n) k_level_range<<<nblocks(n), MN_BLOCK, 0, s>>>(g, rows, n, L, lo, cnt, st, err);
 }
 
+uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return c1 > c0 ? (c1 - c0 + EX_TILE - 1) / EX_TILE : 0; }
+
+template <int NC>
+void launch_expand_nc(bool rows, bool emit, dim3 grid, hipStream_t s, const GraphView& g, RowsView in,
+                      uint32_t n_in, const uint32_t* lo, const uint64_t* off, const uint32_t* tile_row, uint64_t c0,
+                      uint64_t c1, uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err) {
+    if (rows && emit)
+        k_expand<NC, true, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err);
+    else if (rows)
+        k_expand<NC, true, false><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err);
+    else
+        k_expand<NC, false, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err);
+}
+
 void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo, const uint64_t* off,
-                      uint64_t c0, uint64_t c1, uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po,
-                      const uint32_t* err, hipStream_t s) {
+                      uint32_t* tile_row, uint64_t c0, uint64_t c1, uint32_t L, uint32_t max_close, bool rows,
+                      bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s) {
     if (c1 <= c0 || !n_in) return;
-    const uint64_t tiles = (c1 - c0 + EX_TILE - 1) / EX_TILE;
-    k_expand<<<(uint32_t)tiles, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, c0, c1, L, out, n_out, po, err);
+    const uint64_t tiles = mn_expand_tiles(c0, c1);
+    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, c0, c1, (uint32_t)tiles, tile_row);
+    const dim3 grid((uint32_t)tiles);
+    switch (nc_bucket(max_close)) {
+        case 0: launch_expand_nc<0>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
+        case 1: launch_expand_nc<1>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
+        case 2: launch_expand_nc<2>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
+        case 4: launch_expand_nc<4>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
+        default: launch_expand_nc<8>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
+    }
 }

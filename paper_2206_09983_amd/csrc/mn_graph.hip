@@ -158,10 +158,10 @@ constexpr uint32_t MG_TILE = MN_BLOCK * MG_ITEMS;
 // Old entries: each block takes a tile of the old flat array; the tile's
 // vertex range is found once, then each entry finds its vertex inside it.
 __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
-    const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj, uint32_t nv, uint32_t e_old,
-    const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
+    const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj, const uint64_t* __restrict__ adjk,
+    uint32_t nv, uint32_t e_old, const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
     const uint64_t* __restrict__ bk, const uint64_t* __restrict__ dpos, uint32_t hb,
-    uint64_t* __restrict__ adj_new, uint32_t e_new, uint32_t* err) {
+    uint64_t* __restrict__ adj_new, uint64_t* __restrict__ adjk_new, uint32_t e_new, uint32_t* err) {
     __shared__ uint32_t s_v[2];
     if (failed(err)) return;
     uint32_t p0 = blockIdx.x * MG_TILE;
@@ -187,6 +187,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
             continue;
         }
         adj_new[dst] = e;
+        adjk_new[dst] = adjk[p];
     }
 }
 
@@ -194,9 +195,9 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
 __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
     const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj,
     const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
-    const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, uint32_t n_b,
-    const uint64_t* __restrict__ dpos, uint32_t hb, uint64_t* __restrict__ adj_new,
-    uint32_t* __restrict__ inspos, uint32_t e_new, uint32_t* err) {
+    const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, const uint64_t* __restrict__ s_key,
+    uint32_t n_b, const uint64_t* __restrict__ dpos, uint32_t hb, uint64_t* __restrict__ adj_new,
+    uint64_t* __restrict__ adjk_new, uint32_t* __restrict__ inspos, uint32_t e_new, uint32_t* err) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_b || failed(err)) return;
     uint64_t key = bk[r];
@@ -214,6 +215,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
         return;
     }
     adj_new[out] = ((uint64_t)h << 32) | MN_FLAG | bv[r];
+    adjk_new[out] = s_key[bv[r]];
     inspos[r] = out;
 }
 
@@ -344,16 +346,17 @@ void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_
                                                            n_d, hb, newoff, meta, err);
 }
 
-void mn_launch_merge(const uint32_t* off, const uint64_t* adj, uint32_t n_vertices, uint32_t e_old,
-                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
-                     const uint32_t* bvals, uint32_t n_b, const uint64_t* dpos, uint32_t hb,
-                     uint64_t* adj_new, uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s) {
+void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t n_vertices,
+                     uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
+                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
+                     uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new, uint32_t* inspos, uint32_t e_new,
+                     uint32_t* err, hipStream_t s) {
     if (e_old)
         k_merge_old<<<(e_old + MG_TILE - 1) / MG_TILE, MN_BLOCK, 0, s>>>(
-            off, adj, n_vertices, e_old, newoff, meta, bkeys, dpos, hb, adj_new, e_new, err);
+            off, adj, adjk, n_vertices, e_old, newoff, meta, bkeys, dpos, hb, adj_new, adjk_new, e_new, err);
     if (n_b)
-        k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, bvals, n_b, dpos,
-                                                      hb, adj_new, inspos, e_new, err);
+        k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, bvals, s_key, n_b, dpos,
+                                                      hb, adj_new, adjk_new, inspos, e_new, err);
 }
 
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,

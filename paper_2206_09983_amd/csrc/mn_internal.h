@@ -79,10 +79,11 @@ void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_
                            const uint64_t* bkeys, uint32_t n_b, const uint64_t* dpos, uint32_t n_d,
                            uint32_t hb, uint32_t* newoff, uint4* meta, const uint32_t* err,
                            hipStream_t s);
-void mn_launch_merge(const uint32_t* off, const uint64_t* adj, uint32_t n_vertices, uint32_t e_old,
-                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
-                     const uint32_t* bvals, uint32_t n_b, const uint64_t* dpos, uint32_t hb,
-                     uint64_t* adj_new, uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s);
+void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t n_vertices,
+                     uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
+                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
+                     uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new, uint32_t* inspos, uint32_t e_new,
+                     uint32_t* err, hipStream_t s);
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
 void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
@@ -110,10 +111,14 @@ struct EnumStats {  // per phase, accumulated by the enumeration kernels
     unsigned long long rows;          // partial embeddings written between levels
 };
 
+// Per-phase outputs. Digests and tallies have MN_SHARDS copies so that
+// blocks spread their atomics over many addresses: block b adds into copy
+// b % MN_SHARDS, the host sums the copies.
 struct PhaseOut {
     unsigned long long* count;    // [n_queries]
-    unsigned long long* digest;   // [n_queries][2]
-    EnumStats* stats;             // this phase's figures
+    unsigned long long* digest;   // [MN_SHARDS][n_queries][2]
+    EnumStats* stats;             // [MN_SHARDS]
+    uint32_t n_q;
     const OutView* outs;          // [n_queries]
     int phase;                    // 0 new, 1 expired: which buffer of outs[q]
     int emit;                     // write tuples (else counts and digests only)
@@ -122,7 +127,8 @@ struct PhaseOut {
 // Start rows: one per (batch slot, start position) whose edgeMatcher bit and
 // endpoint filters pass and whose start-level closing edges exist. Plans with
 // no further level emit their embeddings directly.
-void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans,
+// max_close: the most closing edges any plan has (sizes the kernels' arrays).
+void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans, uint32_t max_close,
                          RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s);
 // Candidate range of every row at level L: lo[r] and cnt[r].
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32_t L, uint32_t* lo,
@@ -130,9 +136,13 @@ void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32
 // Tests the candidates [c0, c1) of level L (flattened over rows by the
 // offsets `off`); survivors become rows of `out` or, at a plan's last level,
 // emitted embeddings.
+// tile_row must hold mn_expand_tiles(c0, c1) + 1 words.
+uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1);
+// rows: some plan continues past level L; emit: some plan ends at level L.
 void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo,
-                      const uint64_t* off, uint64_t c0, uint64_t c1, uint32_t L, RowsView out,
-                      uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s);
+                      const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, uint32_t L,
+                      uint32_t max_close, bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po,
+                      const uint32_t* err, hipStream_t s);
 
 // Stores v into *p (a device word) in stream order.
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
