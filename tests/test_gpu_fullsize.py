@@ -1,0 +1,199 @@
+"""GPU parity at the benchmark's full size, in the configuration bench.py times.
+
+The R-MAT stream (2^20 vertices, 2^24 initial edges, batches of 65,536
+insertions + 6,553 oldest-key deletions, six queries) is too large for the
+single-thread oracle to recompute whole result lists per batch, so this test
+checks what holds at any size plus outputs the oracle can compute one by one:
+
+  * every emitted tuple is an embedding of the post-insert graph (live edges,
+    consistent vertex map, labels, injectivity under isomorphism), tuples are
+    distinct, and each uses a batch edge (insertions: new; deletions: expired);
+  * work units (batch edge at start position j, Section VI) are recovered
+    from the tuples (the smallest position holding a batch edge) and sampled
+    units, including the heaviest the oracle handles quickly, are compared
+    bit-exact with the oracle's per-unit enumeration;
+  * the homomorphic 5-path counts equal the closed form (chains of sparse
+    matrix-vector products) on the graphs before and after each phase.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle.closed_form import hom_count_tree
+from oracle.core import Oracle
+from paper_2206_09983_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+N_BATCHES = 2
+SAMPLE_UNITS = 6       # random units per (query, phase), plus the heaviest manageable one
+HEAVY_LIMIT = 20000    # largest unit (in tuples) handed to the oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def canon(rows):
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    if len(rows) == 0:
+        return rows
+    return rows[np.lexsort(rows.T[::-1])]
+
+
+class LiveGraph:
+    """Key-indexed edge arrays of the stream, with a live mask."""
+
+    def __init__(self, graph, batches):
+        self.nv = graph["n_vertices"]
+        self.vmask = graph["vlabel_mask"]
+        src = [graph["src"]] + [b["src"] for b in batches]
+        dst = [graph["dst"]] + [b["dst"] for b in batches]
+        lab = [graph["elabel"]] + [b["elabel"] for b in batches]
+        self.src = np.concatenate(src).astype(np.int64)
+        self.dst = np.concatenate(dst).astype(np.int64)
+        self.lab = np.concatenate(lab).astype(np.int64)
+        self.live = np.zeros(len(self.src), dtype=bool)
+        self.live[:len(graph["src"])] = True
+
+    def hom_count(self, q):
+        k = np.nonzero(self.live)[0]
+        exact, estimate = hom_count_tree(self.nv, self.vmask, self.src[k], self.dst[k], self.lab[k], q)
+        return exact
+
+
+def distinct_rows(rows):
+    """True when no two rows are equal: rows with distinct 64-bit hashes are
+    distinct; rows whose hashes collide are compared exactly."""
+    h = np.zeros(len(rows), dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        for k in range(rows.shape[1]):
+            h = (h ^ rows[:, k].astype(np.uint64)) * np.uint64(0x9E3779B97F4A7C15)
+            h ^= h >> np.uint64(29)
+    order = np.argsort(h, kind="stable")
+    hs = h[order]
+    dup = np.nonzero(hs[1:] == hs[:-1])[0]
+    if len(dup) == 0:
+        return True
+    idx = np.unique(np.concatenate([order[dup], order[dup + 1]]))
+    sub = rows[idx]
+    return len(np.unique(sub, axis=0)) == len(sub)
+
+
+def check_embeddings(G, q, rows, in_batch):
+    """Every row is an embedding of the live graph using >= 1 batch edge."""
+    if len(rows) == 0:
+        return
+    rows = rows.astype(np.int64)
+    assert G.live[rows].all(), "tuple uses a dead edge"
+    qs, qd, ql = q["qsrc"], q["qdst"], q["qlabel"]
+    nqv = int(q["n_qv"])
+    f = np.full((len(rows), nqv), -1, dtype=np.int64)
+    for k in range(len(qs)):
+        s, d = G.src[rows[:, k]], G.dst[rows[:, k]]
+        for u, img in ((int(qs[k]), s), (int(qd[k]), d)):
+            seen = f[:, u] >= 0
+            assert (f[seen, u] == img[seen]).all(), "inconsistent vertex map"
+            f[:, u] = img
+        if ql[k] >= 0:
+            assert (G.lab[rows[:, k]] == ql[k]).all(), "edge label"
+    for u in range(nqv):
+        req = np.uint64(int(q["vreq"][u]))
+        assert ((G.vmask[f[:, u]] & req) == req).all(), "vertex labels"
+    if int(q["sem"]) == synth.ISO:
+        fs = np.sort(f, axis=1)
+        assert (fs[:, 1:] != fs[:, :-1]).all(), "isomorphism needs an injective vertex map"
+    assert in_batch.any(axis=1).all(), "tuple uses no batch edge"
+    assert distinct_rows(rows), "duplicate tuples"
+
+
+def units_of(rows, in_batch):
+    """(key, position) of the unit producing each tuple: smallest batch position."""
+    j = np.argmax(in_batch, axis=1)
+    return rows[np.arange(len(rows)), j], j
+
+
+def compare_units(o, qi, q, rows, in_batch, mode, batch_keys, rng):
+    keys, js = units_of(rows, in_batch)
+    code = keys.astype(np.uint64) * np.uint64(64) + js.astype(np.uint64)
+    uniq, counts = np.unique(code, return_counts=True)
+    picks = []
+    ok = np.nonzero(counts <= HEAVY_LIMIT)[0]
+    if len(ok):
+        picks.append(int(uniq[ok[np.argmax(counts[ok])]]))
+    if len(uniq):
+        picks += [int(x) for x in rng.choice(uniq, size=min(SAMPLE_UNITS, len(uniq)), replace=False)]
+    # units the GPU produced nothing for: batch edges at random positions
+    for _ in range(3):
+        picks.append(int(rng.choice(batch_keys)) * 64 + int(rng.integers(0, len(q["qsrc"]))))
+    checked = 0
+    for c in sorted(set(picks)):
+        key, j = c // 64, c % 64
+        ref, ovf = o.seed(qi, key, j, mode)
+        assert ovf == 0
+        sel = (keys == key) & (js == j)
+        got = canon(rows[sel])
+        np.testing.assert_array_equal(got, ref, err_msg="unit key %d position %d" % (key, j))
+        checked += len(ref)
+    return checked
+
+
+def test_full_size_rmat_stream(request):
+    torch = pytest.importorskip("torch")
+    from paper_2206_09983_amd import binding as B
+    B.load()
+    t0 = time.time()
+    case = synth.rmat_case()  # the whole stream, as bench.py draws it
+    batches = case["batches"][:N_BATCHES]
+    qs = case["queries"]
+    say("full-size case %s: %d initial edges, %d batches checked (%.1f s)" % (
+        case["name"], len(case["graph"]["src"]), N_BATCHES, time.time() - t0))
+    G = LiveGraph(case["graph"], batches)
+    o = Oracle(case["graph"], qs)
+    stream = torch.cuda.current_stream()
+    m = B.Matcher(case["graph"], qs, flags=B.F_EMIT | B.F_TIMING, out_capacity=1 << 22,
+                  stream=stream.cuda_stream, n_elabels=32)
+    rng = np.random.default_rng(11)
+    p5h = [i for i, q in enumerate(qs) if q["name"] == "p5_homo"][0]
+    try:
+        for bi, b in enumerate(batches):
+            db = {"src": torch.from_numpy(b["src"].view(np.int32)).cuda(),
+                  "dst": torch.from_numpy(b["dst"].view(np.int32)).cuda(),
+                  "elabel": torch.from_numpy(b["elabel"]).cuda(),
+                  "ts": torch.from_numpy(b["ts"]).cuda(),
+                  "del_keys": torch.from_numpy(b["del_keys"].view(np.int64)).cuda()}
+            torch.cuda.synchronize()
+            hom_before = G.hom_count(qs[p5h])
+            first = m.apply_batch(db)
+            ins_keys = np.arange(first, first + len(b["src"]), dtype=np.int64)
+            del_keys = b["del_keys"].astype(np.int64)
+            G.live[ins_keys] = True
+            o.insert(b, enumerate=False)
+            hom_mid = G.hom_count(qs[p5h])
+            total = 0
+            for qi, q in enumerate(qs):
+                rows = m.keys(qi).astype(np.int64)
+                inb = rows >= first
+                check_embeddings(G, q, rows, inb)
+                total += compare_units(o, qi, q, rows, inb, 1, ins_keys, rng)
+            assert m.result(p5h)["n_new"] == (hom_mid - hom_before) % (1 << 64)
+            o.mark(del_keys)
+            for qi, q in enumerate(qs):
+                rows = m.keys(qi, expired=True).astype(np.int64)
+                inb = np.isin(rows, del_keys)
+                check_embeddings(G, q, rows, inb)
+                total += compare_units(o, qi, q, rows, inb, 2, del_keys, rng)
+            o.unmark(del_keys)
+            o.delete(del_keys, enumerate=False)
+            G.live[del_keys] = False
+            hom_after = G.hom_count(qs[p5h])
+            assert m.result(p5h)["n_expired"] == (hom_mid - hom_after) % (1 << 64)
+            say("batch %d: %s new, %s expired; %d tuples of sampled units matched the oracle (%.1f s)" % (
+                bi, [m.result(i)["n_new"] for i in range(len(qs))],
+                [m.result(i)["n_expired"] for i in range(len(qs))], total, time.time() - t0))
+    finally:
+        m.close()
+        o.close()
