@@ -161,15 +161,17 @@ struct mnemonic_ctx {
     int64_t* d_in_ts = nullptr;
     uint64_t* d_del_keys = nullptr;
     uint32_t* d_ins_slot = nullptr;
-    uint64_t* d_skey[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    uint32_t* d_sval[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // batch sort keys of both directions in one array (direction bit on top),
+    // ping-pong pair
+    uint64_t* d_skey[2] = {nullptr, nullptr};
+    uint32_t* d_sval[2] = {nullptr, nullptr};
     uint32_t* d_inspos[2] = {nullptr, nullptr};
     uint32_t* d_touched = nullptr;
     uint32_t* d_del_slot[2] = {nullptr, nullptr};        // [buffer]
     uint32_t* d_delpos[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buffer][dir]
     uint64_t cap_delbuf[2] = {0, 0};
-    uint64_t* d_dkey[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [dir][ping-pong]
-    uint32_t* d_dval[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    uint64_t* d_dkey[2] = {nullptr, nullptr};  // deleted positions of both directions, ping-pong
+    uint32_t* d_dval[2] = {nullptr, nullptr};
     uint32_t hb_pos = 32;  // significant bits of an adjacency position
     uint32_t* d_sort_scratch = nullptr;
     uint64_t cap_sort_scratch = 0;
@@ -633,13 +635,13 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         dev_alloc(c->d_in_lab, nc);
         dev_alloc(c->d_in_ts, nc);
         dev_alloc(c->d_ins_slot, nc);
+        for (int k = 0; k < 2; k++) {
+            dev_free(c->d_skey[k]);
+            dev_free(c->d_sval[k]);
+            dev_alloc(c->d_skey[k], 2 * nc);
+            dev_alloc(c->d_sval[k], 2 * nc);
+        }
         for (int d = 0; d < 2; d++) {
-            for (int k = 0; k < 2; k++) {
-                dev_free(c->d_skey[d][k]);
-                dev_free(c->d_sval[d][k]);
-                dev_alloc(c->d_skey[d][k], nc);
-                dev_alloc(c->d_sval[d][k], nc);
-            }
             dev_free(c->d_inspos[d]);
             dev_alloc(c->d_inspos[d], nc);
         }
@@ -666,16 +668,15 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     uint64_t n_sort = std::max<uint64_t>(n_ins, c->n_pending);
     if (n_sort > c->cap_sort) {
         uint64_t nc = std::max<uint64_t>(n_sort, c->cap_sort + c->cap_sort / 2);
-        for (int d = 0; d < 2; d++)
-            for (int k = 0; k < 2; k++) {
-                dev_free(c->d_dkey[d][k]);
-                dev_free(c->d_dval[d][k]);
-                dev_alloc(c->d_dkey[d][k], nc);
-                dev_alloc(c->d_dval[d][k], nc);
-            }
+        for (int k = 0; k < 2; k++) {
+            dev_free(c->d_dkey[k]);
+            dev_free(c->d_dval[k]);
+            dev_alloc(c->d_dkey[k], 2 * nc);
+            dev_alloc(c->d_dval[k], 2 * nc);
+        }
         c->cap_sort = nc;
     }
-    uint64_t ssw = mn_sort_scratch_words((uint32_t)std::max<uint64_t>(n_sort, 1));
+    uint64_t ssw = mn_sort_scratch_words((uint32_t)std::max<uint64_t>(2 * n_sort, 1));
     if (ssw > c->cap_sort_scratch) {
         dev_free(c->d_sort_scratch);
         dev_alloc(c->d_sort_scratch, ssw);
@@ -893,6 +894,8 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     b.n_free = c->n_free;
     b.fresh = c->fresh;
     b.hb = c->hb;
+    const uint64_t dirbit = 1ull << (c->hb + c->nbr_bits);  // direction bit of the batch sort keys
+    b.dirbit = dirbit;
     b.next_key = c->next_key;
     b.n_elabels = c->n_elabels;
     b.n_debi_bits = c->n_debi_bits;
@@ -909,8 +912,8 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     b.last_ts = c->d_last_ts;
     b.ins_slot = c->d_ins_slot;
     for (int d = 0; d < 2; d++) {
-        b.skey[d] = c->d_skey[d][0];
-        b.sval[d] = c->d_sval[d][0];
+        b.skey[d] = c->d_skey[0] + d * n_ins;
+        b.sval[d] = c->d_sval[0] + d * n_ins;
         b.delpos[d] = c->d_delpos[cur][d];
     }
     b.touched = c->d_touched;
@@ -928,33 +931,33 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     const bool merge = n_ins > 0 || n_prev > 0;
     const uint64_t E_new = c->E - n_prev + n_ins;
     if (merge) {
-        // sort the pending deletion positions and the batch entries per direction
-        uint64_t* dpos[2] = {nullptr, nullptr};
-        for (int d = 0; d < 2; d++) {
-            uint64_t* bk = c->d_skey[d][0];
-            uint32_t* bv = c->d_sval[d][0];
-            uint64_t* tk = c->d_skey[d][1];
-            uint32_t* tv = c->d_sval[d][1];
-            mn_radix_sort(bk, bv, tk, tv, (uint32_t)n_ins, c->hb + c->nbr_bits, c->d_sort_scratch, s);
-            b.skey[d] = bk;
-            b.sval[d] = bv;
-        }
-        // positions of the previous snapshot's deletions, sorted per direction
-        for (int d = 0; d < 2 && n_prev; d++) {
-            uint64_t* k0 = c->d_dkey[d][0];
-            uint32_t* v0 = c->d_dval[d][0];
-            uint64_t* k1 = c->d_dkey[d][1];
-            uint32_t* v1 = c->d_dval[d][1];
-            mn_launch_widen(c->d_delpos[pend][d], k0, n_prev, c->d_err, s);
-            mn_radix_sort(k0, v0, k1, v1, n_prev, c->hb_pos, c->d_sort_scratch, s);
-            dpos[d] = k0;
+        // one sort of the batch entries of both directions (the direction bit
+        // on top keeps them apart) and one of the pending deletion positions
+        uint64_t* bk = c->d_skey[0];
+        uint32_t* bv = c->d_sval[0];
+        uint64_t* tk = c->d_skey[1];
+        uint32_t* tv = c->d_sval[1];
+        mn_radix_sort(bk, bv, tk, tv, (uint32_t)(2 * n_ins), c->hb + c->nbr_bits + 1, c->d_sort_scratch, s);
+        const uint64_t dbit = 1ull << c->hb_pos;
+        uint64_t* dk = c->d_dkey[0];
+        if (n_prev) {
+            uint32_t* v0 = c->d_dval[0];
+            uint64_t* k1 = c->d_dkey[1];
+            uint32_t* v1 = c->d_dval[1];
+            mn_launch_widen(c->d_delpos[pend][0], dk, 0, n_prev, c->d_err, s);
+            mn_launch_widen(c->d_delpos[pend][1], dk + n_prev, dbit, n_prev, c->d_err, s);
+            mn_radix_sort(dk, v0, k1, v1, 2 * n_prev, c->hb_pos + 1, c->d_sort_scratch, s);
         }
         for (int d = 0; d < 2; d++) {
-            mn_launch_vertex_meta(c->d_off[d], c->nV, (uint32_t)c->E, b.skey[d], (uint32_t)n_ins, dpos[d],
-                                  n_prev, c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
+            const uint64_t kb = d ? dirbit : 0, db = d ? dbit : 0;
+            const uint64_t* bkd = bk + d * n_ins;
+            const uint32_t* bvd = bv + d * n_ins;
+            const uint64_t* dpd = n_prev ? dk + d * n_prev : nullptr;
+            mn_launch_vertex_meta(c->d_off[d], c->nV, (uint32_t)c->E, bkd, kb, (uint32_t)n_ins, dpd, db, n_prev,
+                                  c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
             mn_launch_merge(c->d_off[d], c->d_adj[d], c->d_adjk[d], c->nV, (uint32_t)c->E, c->d_off2[d],
-                            c->d_meta[d], b.skey[d], b.sval[d], c->d_key, (uint32_t)n_ins, dpos[d], c->hb,
-                            c->d_adj2[d], c->d_adjk2[d], c->d_inspos[d], (uint32_t)E_new, c->d_err, s);
+                            c->d_meta[d], bkd, kb, bvd, c->d_key, (uint32_t)n_ins, dpd, db, c->hb, c->d_adj2[d],
+                            c->d_adjk2[d], c->d_inspos[d], (uint32_t)E_new, c->d_err, s);
         }
     }
     // from here on the kernels work on the merged adjacency
@@ -1120,6 +1123,12 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_free);
     dev_free(c->d_key2slot);
     dev_free(c->d_delbits);
+    for (int k = 0; k < 2; k++) {
+        dev_free(c->d_skey[k]);
+        dev_free(c->d_sval[k]);
+        dev_free(c->d_dkey[k]);
+        dev_free(c->d_dval[k]);
+    }
     for (int d = 0; d < 2; d++) {
         dev_free(c->d_off[d]);
         dev_free(c->d_off2[d]);
@@ -1129,13 +1138,7 @@ void free_all(mnemonic_ctx* c) {
         dev_free(c->d_adjk2[d]);
         dev_free(c->d_inspos[d]);
         dev_free(c->d_del_slot[d]);
-        for (int k = 0; k < 2; k++) {
-            dev_free(c->d_dkey[d][k]);
-            dev_free(c->d_dval[d][k]);
-            dev_free(c->d_skey[d][k]);
-            dev_free(c->d_sval[d][k]);
-            dev_free(c->d_delpos[d][k]);
-        }
+        for (int k = 0; k < 2; k++) dev_free(c->d_delpos[d][k]);
     }
     dev_free(c->d_in_src);
     dev_free(c->d_in_dst);

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
     uint64_t hs = ((uint64_t)l << g.nbr_bits) | d;  // out-entry high word
     uint64_t hd = ((uint64_t)l << g.nbr_bits) | s;  // in-entry high word
     b.skey[0][i] = ((uint64_t)s << b.hb) | hs;
-    b.skey[1][i] = ((uint64_t)d << b.hb) | hd;
+    b.skey[1][i] = b.dirbit | ((uint64_t)d << b.hb) | hd;
     b.sval[0][i] = slot;
     b.sval[1][i] = slot;
     b.ins_slot[i] = slot;
@@ -131,7 +131,8 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
 
 __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __restrict__ off, uint32_t nv,
                                                           uint32_t e_old, const uint64_t* __restrict__ bk,
-                                                          uint32_t n_b, const uint64_t* __restrict__ dpos,
+                                                          uint64_t kbase, uint32_t n_b,
+                                                          const uint64_t* __restrict__ dpos, uint64_t dbase,
                                                           uint32_t n_d, uint32_t hb,
                                                           uint32_t* __restrict__ newoff,
                                                           uint4* __restrict__ meta, const uint32_t* err) {
@@ -139,13 +140,13 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __rest
     if (v >= nv || failed(err)) return;
     uint32_t bs = 0, be = 0, ds = 0, de = 0;
     if (n_b) {
-        bs = lower_bound_dev<uint64_t>(bk, 0, n_b, (uint64_t)v << hb);
-        be = lower_bound_dev<uint64_t>(bk, bs, n_b, (uint64_t)(v + 1) << hb);
+        bs = lower_bound_dev<uint64_t>(bk, 0, n_b, kbase + ((uint64_t)v << hb));
+        be = lower_bound_dev<uint64_t>(bk, bs, n_b, kbase + ((uint64_t)(v + 1) << hb));
     }
     uint32_t o0 = off[v], o1 = off[v + 1];
     if (n_d) {
-        ds = lower_bound_dev<uint64_t>(dpos, 0, n_d, (uint64_t)o0);
-        de = lower_bound_dev<uint64_t>(dpos, ds, n_d, (uint64_t)o1);
+        ds = lower_bound_dev<uint64_t>(dpos, 0, n_d, dbase + o0);
+        de = lower_bound_dev<uint64_t>(dpos, ds, n_d, dbase + o1);
     }
     newoff[v] = o0 - ds + bs;
     meta[v] = make_uint4(bs, be - bs, ds, de - ds);
@@ -160,8 +161,8 @@ constexpr uint32_t MG_TILE = MN_BLOCK * MG_ITEMS;
 __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
     const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj, const uint64_t* __restrict__ adjk,
     uint32_t nv, uint32_t e_old, const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
-    const uint64_t* __restrict__ bk, const uint64_t* __restrict__ dpos, uint32_t hb,
-    uint64_t* __restrict__ adj_new, uint64_t* __restrict__ adjk_new, uint32_t e_new, uint32_t* err) {
+    const uint64_t* __restrict__ bk, uint64_t kbase, const uint64_t* __restrict__ dpos, uint64_t dbase,
+    uint32_t hb, uint64_t* __restrict__ adj_new, uint64_t* __restrict__ adjk_new, uint32_t e_new, uint32_t* err) {
     __shared__ uint32_t s_v[2];
     if (failed(err)) return;
     uint32_t p0 = blockIdx.x * MG_TILE;
@@ -178,9 +179,9 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
         uint32_t v = upper_bound_dev<uint32_t>(off, vlo, vhi + 1, p) - 1;
         uint4 m = meta[v];
         uint32_t kept = p - off[v];
-        if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, (uint64_t)p) - m.z;
+        if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, dbase + p) - m.z;
         uint32_t ins = 0;
-        if (m.y) ins = lower_bound_dev<uint64_t>(bk, m.x, m.x + m.y, ((uint64_t)v << hb) | ent_hi(e)) - m.x;
+        if (m.y) ins = lower_bound_dev<uint64_t>(bk, m.x, m.x + m.y, kbase + (((uint64_t)v << hb) | ent_hi(e))) - m.x;
         uint32_t dst = newoff[v] + kept + ins;
         if (dst >= e_new) {  // never expected; refuse rather than write out of bounds
             set_err(err, MN_ERR_INTERNAL);
@@ -195,19 +196,20 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
 __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
     const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj,
     const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
-    const uint64_t* __restrict__ bk, const uint32_t* __restrict__ bv, const uint64_t* __restrict__ s_key,
-    uint32_t n_b, const uint64_t* __restrict__ dpos, uint32_t hb, uint64_t* __restrict__ adj_new,
-    uint64_t* __restrict__ adjk_new, uint32_t* __restrict__ inspos, uint32_t e_new, uint32_t* err) {
+    const uint64_t* __restrict__ bk, uint64_t kbase, const uint32_t* __restrict__ bv,
+    const uint64_t* __restrict__ s_key, uint32_t n_b, const uint64_t* __restrict__ dpos, uint64_t dbase,
+    uint32_t hb, uint64_t* __restrict__ adj_new, uint64_t* __restrict__ adjk_new, uint32_t* __restrict__ inspos,
+    uint32_t e_new, uint32_t* err) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_b || failed(err)) return;
-    uint64_t key = bk[r];
+    uint64_t key = bk[r] - kbase;
     uint32_t v = (uint32_t)(key >> hb);
     uint32_t h = (uint32_t)(key & ((1ull << hb) - 1));
     uint32_t o0 = off[v], o1 = off[v + 1];
     uint32_t ub = upper_hi(adj, o0, o1, h);
     uint4 m = meta[v];
     uint32_t kept = ub - o0;
-    if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, (uint64_t)ub) - m.z;
+    if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, dbase + ub) - m.z;
     uint32_t out = newoff[v] + kept + (r - m.x);
     if (out >= e_new) {  // never expected; refuse rather than write out of bounds
         set_err(err, MN_ERR_INTERNAL);
@@ -306,9 +308,9 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v) {
 }
 
 __global__ __launch_bounds__(MN_BLOCK) void k_widen(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
-                                                    uint32_t n, const uint32_t* err) {
+                                                    uint64_t add, uint32_t n, const uint32_t* err) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && !failed(err)) out[i] = in[i];
+    if (i < n && !failed(err)) out[i] = add + in[i];
 }
 
 inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK); }
@@ -317,8 +319,9 @@ inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_
 
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) { k_set_u32<<<1, 64, 0, s>>>(p, v); }
 
-void mn_launch_widen(const uint32_t* in, uint64_t* out, uint32_t n, const uint32_t* err, hipStream_t s) {
-    if (n) k_widen<<<nblocks(n), MN_BLOCK, 0, s>>>(in, out, n, err);
+void mn_launch_widen(const uint32_t* in, uint64_t* out, uint64_t add, uint32_t n, const uint32_t* err,
+                     hipStream_t s) {
+    if (n) k_widen<<<nblocks(n), MN_BLOCK, 0, s>>>(in, out, add, n, err);
 }
 
 void mn_launch_reset(uint32_t* err, unsigned long long* zero_a, uint32_t n_a, hipStream_t s) {
@@ -339,24 +342,25 @@ void mn_launch_ingest(const GraphView& g, const BatchView& b, hipStream_t s) {
 }
 
 void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_old,
-                           const uint64_t* bkeys, uint32_t n_b, const uint64_t* dpos, uint32_t n_d,
-                           uint32_t hb, uint32_t* newoff, uint4* meta, const uint32_t* err,
-                           hipStream_t s) {
-    k_vertex_meta<<<nblocks(n_vertices), MN_BLOCK, 0, s>>>(off, n_vertices, e_old, bkeys, n_b, dpos,
-                                                           n_d, hb, newoff, meta, err);
+                           const uint64_t* bkeys, uint64_t kbase, uint32_t n_b, const uint64_t* dpos,
+                           uint64_t dbase, uint32_t n_d, uint32_t hb, uint32_t* newoff, uint4* meta,
+                           const uint32_t* err, hipStream_t s) {
+    k_vertex_meta<<<nblocks(n_vertices), MN_BLOCK, 0, s>>>(off, n_vertices, e_old, bkeys, kbase, n_b, dpos,
+                                                           dbase, n_d, hb, newoff, meta, err);
 }
 
 void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t n_vertices,
                      uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
-                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
-                     uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new, uint32_t* inspos, uint32_t e_new,
-                     uint32_t* err, hipStream_t s) {
+                     uint64_t kbase, const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b,
+                     const uint64_t* dpos, uint64_t dbase, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
+                     uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s) {
     if (e_old)
-        k_merge_old<<<(e_old + MG_TILE - 1) / MG_TILE, MN_BLOCK, 0, s>>>(
-            off, adj, adjk, n_vertices, e_old, newoff, meta, bkeys, dpos, hb, adj_new, adjk_new, e_new, err);
+        k_merge_old<<<(e_old + MG_TILE - 1) / MG_TILE, MN_BLOCK, 0, s>>>(off, adj, adjk, n_vertices, e_old, newoff,
+                                                                       meta, bkeys, kbase, dpos, dbase, hb, adj_new,
+                                                                       adjk_new, e_new, err);
     if (n_b)
-        k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, bvals, s_key, n_b, dpos,
-                                                      hb, adj_new, adjk_new, inspos, e_new, err);
+        k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, kbase, bvals, s_key, n_b, dpos,
+                                                      dbase, hb, adj_new, adjk_new, inspos, e_new, err);
 }
 
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,

@@ -45,6 +45,7 @@ struct BatchView {
     uint32_t n_free;        // free-slot stack height before this batch
     uint32_t fresh;         // first never-used slot
     uint32_t hb;            // composite sort key = (vertex << hb) | high word
+    uint64_t dirbit;        // direction bit of in-list sort keys (above every vertex/high-word bit)
     uint64_t next_key;      // key of the first inserted edge
     uint32_t n_elabels;
     uint32_t n_debi_bits;
@@ -75,15 +76,17 @@ void mn_launch_reset(uint32_t* err, unsigned long long* zero_a, uint32_t n_a, hi
 void mn_launch_validate(const GraphView& g, const BatchView& b, hipStream_t s);
 void mn_launch_prev_del(const GraphView& g, const BatchView& b, hipStream_t s);
 void mn_launch_ingest(const GraphView& g, const BatchView& b, hipStream_t s);
+// bkeys (n_b) and dpos (n_d) are sorted and carry the constant kbase / dbase
+// (the direction bit of the combined sort) on top of every value.
 void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_old,
-                           const uint64_t* bkeys, uint32_t n_b, const uint64_t* dpos, uint32_t n_d,
-                           uint32_t hb, uint32_t* newoff, uint4* meta, const uint32_t* err,
-                           hipStream_t s);
+                           const uint64_t* bkeys, uint64_t kbase, uint32_t n_b, const uint64_t* dpos,
+                           uint64_t dbase, uint32_t n_d, uint32_t hb, uint32_t* newoff, uint4* meta,
+                           const uint32_t* err, hipStream_t s);
 void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t n_vertices,
                      uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
-                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
-                     uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new, uint32_t* inspos, uint32_t e_new,
-                     uint32_t* err, hipStream_t s);
+                     uint64_t kbase, const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b,
+                     const uint64_t* dpos, uint64_t dbase, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
+                     uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s);
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
 void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
@@ -147,5 +150,6 @@ void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint
 // Stores v into *p (a device word) in stream order.
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 
-// Widens n u32 values into u64 (sort keys).
-void mn_launch_widen(const uint32_t* in, uint64_t* out, uint32_t n, const uint32_t* err, hipStream_t s);
+// out[i] = add + in[i] as u64 (sort keys).
+void mn_launch_widen(const uint32_t* in, uint64_t* out, uint64_t add, uint32_t n, const uint32_t* err,
+                     hipStream_t s);

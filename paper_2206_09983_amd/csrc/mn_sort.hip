@@ -13,6 +13,7 @@ constexpr uint32_t SC_TILE = MN_BLOCK * SC_ITEMS;  // 2048
 constexpr uint32_t RS_ROUNDS = 16;
 constexpr uint32_t RS_TILE = MN_BLOCK * RS_ROUNDS;  // 4096
 constexpr uint32_t RS_WAVES = MN_BLOCK / MN_WAVE;
+constexpr uint32_t RS_FUSE_BLOCKS = 64;  // inputs up to 64 tiles scan their histograms in the scatter
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x) {
     uint32_t lane = __lane_id();
@@ -80,18 +81,12 @@ __global__ __launch_bounds__(MN_BLOCK) void k_rs_hist(const uint64_t* __restrict
     hist[(size_t)tid * nblk + blockIdx.x] = h[tid];
 }
 
-__global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                         const uint32_t* __restrict__ vin,
-                                                         uint64_t* __restrict__ kout,
-                                                         uint32_t* __restrict__ vout, uint32_t n,
-                                                         uint32_t shift,
-                                                         const uint32_t* __restrict__ hist,
-                                                         uint32_t nblk) {
-    __shared__ uint32_t base_off[256];
-    __shared__ uint32_t wcnt[RS_WAVES][256];
+// Stable scatter of one tile by digit, starting at base_off[digit] (LDS).
+__device__ void rs_scatter_tile(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
+                                uint32_t shift, uint32_t* base_off, uint32_t (*wcnt)[256]) {
     uint32_t tid = threadIdx.x;
     uint32_t wave = tid / MN_WAVE;
-    base_off[tid] = hist[(size_t)tid * nblk + blockIdx.x];
     for (uint32_t w = 0; w < RS_WAVES; w++) wcnt[w][tid] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
@@ -129,6 +124,49 @@ __global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter(const uint64_t* __restr
         base_off[tid] += tot;
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint64_t* __restrict__ kout,
+                                                         uint32_t* __restrict__ vout, uint32_t n,
+                                                         uint32_t shift,
+                                                         const uint32_t* __restrict__ hist,
+                                                         uint32_t nblk) {
+    __shared__ uint32_t base_off[256];
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    base_off[threadIdx.x] = hist[(size_t)threadIdx.x * nblk + blockIdx.x];
+    rs_scatter_tile(kin, vin, kout, vout, n, shift, base_off, wcnt);
+}
+
+// Scatter for small inputs (nblk <= RS_FUSE_BLOCKS): each block derives its
+// digit offsets from the unscanned per-block histograms itself (column sums
+// scanned over digits, plus the counts of earlier blocks), saving the
+// device-wide scan launches.
+__global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter_fused(const uint64_t* __restrict__ kin,
+                                                               const uint32_t* __restrict__ vin,
+                                                               uint64_t* __restrict__ kout,
+                                                               uint32_t* __restrict__ vout, uint32_t n,
+                                                               uint32_t shift,
+                                                               const uint32_t* __restrict__ hist,
+                                                               uint32_t nblk) {
+    __shared__ uint32_t base_off[256];
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    __shared__ uint32_t wsum[RS_WAVES];
+    const uint32_t d = threadIdx.x;
+    uint32_t col = 0, before = 0;
+    for (uint32_t b = 0; b < nblk; b++) {
+        const uint32_t h = hist[(size_t)d * nblk + b];
+        col += h;
+        if (b < blockIdx.x) before += h;
+    }
+    const uint32_t incl = wave_incl_scan(col);
+    if (__lane_id() == MN_WAVE - 1) wsum[d / MN_WAVE] = incl;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (uint32_t w = 0; w < d / MN_WAVE; w++) wpre += wsum[w];
+    base_off[d] = wpre + incl - col + before;
+    rs_scatter_tile(kin, vin, kout, vout, n, shift, base_off, wcnt);
 }
 
 __device__ inline uint64_t wave_incl_scan64(uint64_t x) {
@@ -253,8 +291,12 @@ void mn_radix_sort(uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*&
     uint32_t* sscr = scratch + (size_t)256 * nblk;
     for (uint32_t shift = 0; shift < nbits; shift += 8) {
         k_rs_hist<<<nblk, MN_BLOCK, 0, s>>>(keys, n, shift, hist, nblk);
-        mn_scan_exclusive(hist, hist, 256 * nblk, sscr, s);
-        k_rs_scatter<<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
+        if (nblk <= RS_FUSE_BLOCKS) {
+            k_rs_scatter_fused<<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
+        } else {
+            mn_scan_exclusive(hist, hist, 256 * nblk, sscr, s);
+            k_rs_scatter<<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
+        }
         uint64_t* tk = keys;
         keys = ktmp;
         ktmp = tk;
