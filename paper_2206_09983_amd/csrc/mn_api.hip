@@ -192,6 +192,8 @@ struct mnemonic_ctx {
     uint64_t cap_scan64 = 0;
     uint32_t* d_tiles = nullptr;     // first row of every expansion tile
     uint64_t cap_tiles = 0;
+    uint32_t* d_mtiles = nullptr;    // first vertex of every merge tile
+    uint64_t cap_mtiles = 0;
     uint32_t* d_nrows = nullptr;     // [MN_MAXLV + 1] row counters
     uint64_t* d_total = nullptr;     // candidate total of the last scan
     uint64_t* h_ctl = nullptr;       // pinned: readback of counters
@@ -939,6 +941,14 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         uint32_t* tv = c->d_sval[1];
         mn_radix_sort(bk, bv, tk, tv, (uint32_t)(2 * n_ins), c->hb + c->nbr_bits + 1, c->d_sort_scratch, s);
         const uint64_t dbit = 1ull << c->hb_pos;
+        const uint64_t need_mt = (uint64_t)mn_merge_tiles((uint32_t)c->E) + 1;
+        if (need_mt > c->cap_mtiles) {
+            HIPCHK(hipStreamSynchronize(s));
+            dev_free(c->d_mtiles);
+            c->cap_mtiles = 0;
+            dev_alloc(c->d_mtiles, need_mt + need_mt / 2);
+            c->cap_mtiles = need_mt + need_mt / 2;
+        }
         uint64_t* dk = c->d_dkey[0];
         if (n_prev) {
             uint32_t* v0 = c->d_dval[0];
@@ -957,7 +967,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                                   c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
             mn_launch_merge(c->d_off[d], c->d_adj[d], c->d_adjk[d], c->nV, (uint32_t)c->E, c->d_off2[d],
                             c->d_meta[d], bkd, kb, bvd, c->d_key, (uint32_t)n_ins, dpd, db, c->hb, c->d_adj2[d],
-                            c->d_adjk2[d], c->d_inspos[d], (uint32_t)E_new, c->d_err, s);
+                            c->d_adjk2[d], c->d_inspos[d], (uint32_t)E_new, c->d_mtiles, c->d_err, s);
         }
     }
     // from here on the kernels work on the merged adjacency
@@ -1159,6 +1169,7 @@ void free_all(mnemonic_ctx* c) {
     for (auto& e : c->ev_x)
         if (e) (void)hipEventDestroy(e);
     dev_free(c->d_tiles);
+    dev_free(c->d_mtiles);
     for (auto& B : c->lvb) {
         dev_free(B.keys);
         dev_free(B.rows);

@@ -156,33 +156,79 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __rest
 constexpr uint32_t MG_ITEMS = 8;
 constexpr uint32_t MG_TILE = MN_BLOCK * MG_ITEMS;
 
-// Old entries: each block takes a tile of the old flat array; the tile's
-// vertex range is found once, then each entry finds its vertex inside it.
+constexpr uint32_t MG_LDS = MG_TILE + 1;
+
+// First vertex of every merge tile: tile_v[i] = vertex holding old entry
+// i * MG_TILE for i < nt, tile_v[nt] = vertex holding the last old entry.
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_partition(const uint32_t* __restrict__ off, uint32_t nv,
+                                                              uint32_t e_old, uint32_t nt,
+                                                              uint32_t* __restrict__ tile_v) {
+    const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
+    if (i > nt) return;
+    const uint32_t p = i < nt ? i * MG_TILE : e_old - 1;
+    tile_v[i] = upper_bound_dev<uint32_t>(off, 0, nv + 1, p) - 1;
+}
+
+// Old entries: each block takes a tile of the old flat array. The tile's
+// vertices (offsets, shift to the new offsets, touched or not) are staged in
+// LDS; an entry of a vertex the batch leaves alone moves by its vertex's
+// shift, others also count the deleted entries before them and the batch
+// entries that sort before them.
 __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
     const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj, const uint64_t* __restrict__ adjk,
-    uint32_t nv, uint32_t e_old, const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
-    const uint64_t* __restrict__ bk, uint64_t kbase, const uint64_t* __restrict__ dpos, uint64_t dbase,
-    uint32_t hb, uint64_t* __restrict__ adj_new, uint64_t* __restrict__ adjk_new, uint32_t e_new, uint32_t* err) {
-    __shared__ uint32_t s_v[2];
-    if (failed(err)) return;
-    uint32_t p0 = blockIdx.x * MG_TILE;
-    uint32_t p1 = min(p0 + MG_TILE, e_old);
-    if (threadIdx.x == 0) s_v[0] = upper_bound_dev<uint32_t>(off, 0, nv + 1, p0) - 1;
-    if (threadIdx.x == 1) s_v[1] = upper_bound_dev<uint32_t>(off, 0, nv + 1, p1 - 1) - 1;
+    const uint32_t* __restrict__ tile_v, uint32_t e_old, const uint32_t* __restrict__ newoff,
+    const uint4* __restrict__ meta, const uint64_t* __restrict__ bk, uint64_t kbase,
+    const uint64_t* __restrict__ dpos, uint64_t dbase, uint32_t hb, uint64_t* __restrict__ adj_new,
+    uint64_t* __restrict__ adjk_new, uint32_t e_new, uint32_t* err) {
+    __shared__ uint32_t s_off[MG_LDS + 1];
+    __shared__ uint32_t s_shift[MG_LDS];  // newoff[v] - off[v] (mod 2^32), or MN_INVALID when touched
+    __shared__ uint32_t s_dead;
+    const uint32_t p0 = blockIdx.x * MG_TILE;
+    const uint32_t p1 = min(p0 + MG_TILE, e_old);
+    const uint32_t vlo = tile_v[blockIdx.x], vhi = tile_v[blockIdx.x + 1];
+    const uint32_t span = vhi - vlo + 1;
+    const bool staged = span <= MG_LDS;
+    if (threadIdx.x == 0) s_dead = failed(err) ? 1u : 0u;
+    if (staged) {
+        for (uint32_t x = threadIdx.x; x <= span; x += MN_BLOCK) s_off[x] = off[vlo + x];
+        for (uint32_t x = threadIdx.x; x < span; x += MN_BLOCK) {
+            const uint4 m = meta[vlo + x];
+            s_shift[x] = (m.y | m.w) ? MN_INVALID : newoff[vlo + x] - off[vlo + x];
+        }
+    }
     __syncthreads();
-    uint32_t vlo = s_v[0], vhi = s_v[1];
+    if (s_dead) return;
     for (uint32_t k = 0; k < MG_ITEMS; k++) {
-        uint32_t p = p0 + k * MN_BLOCK + threadIdx.x;
+        const uint32_t p = p0 + k * MN_BLOCK + threadIdx.x;
         if (p >= p1) break;
-        uint64_t e = adj[p];
+        const uint64_t e = adj[p];
         if (ent_lo(e) & MN_FLAG) continue;  // deleted by the previous snapshot
-        uint32_t v = upper_bound_dev<uint32_t>(off, vlo, vhi + 1, p) - 1;
-        uint4 m = meta[v];
-        uint32_t kept = p - off[v];
-        if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, dbase + p) - m.z;
-        uint32_t ins = 0;
-        if (m.y) ins = lower_bound_dev<uint64_t>(bk, m.x, m.x + m.y, kbase + (((uint64_t)v << hb) | ent_hi(e))) - m.x;
-        uint32_t dst = newoff[v] + kept + ins;
+        uint32_t v, shift = MN_INVALID;
+        if (staged) {
+            uint32_t a = 0, b = span;  // largest x with s_off[x] <= p
+            while (a + 1 < b) {
+                const uint32_t mid = (a + b) >> 1;
+                if (s_off[mid] <= p)
+                    a = mid;
+                else
+                    b = mid;
+            }
+            v = vlo + a;
+            shift = s_shift[a];
+        } else {
+            v = upper_bound_dev<uint32_t>(off, vlo, vhi + 1, p) - 1;
+        }
+        uint32_t dst;
+        if (shift != MN_INVALID) {
+            dst = p + shift;
+        } else {
+            const uint4 m = meta[v];
+            uint32_t kept = p - off[v];
+            if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, dbase + p) - m.z;
+            uint32_t ins = 0;
+            if (m.y) ins = lower_bound_dev<uint64_t>(bk, m.x, m.x + m.y, kbase + (((uint64_t)v << hb) | ent_hi(e))) - m.x;
+            dst = newoff[v] + kept + ins;
+        }
         if (dst >= e_new) {  // never expected; refuse rather than write out of bounds
             set_err(err, MN_ERR_INTERNAL);
             continue;
@@ -317,6 +363,8 @@ inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_
 
 }  // namespace
 
+uint32_t mn_merge_tiles(uint32_t e_old) { return (e_old + MG_TILE - 1) / MG_TILE; }
+
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) { k_set_u32<<<1, 64, 0, s>>>(p, v); }
 
 void mn_launch_widen(const uint32_t* in, uint64_t* out, uint64_t add, uint32_t n, const uint32_t* err,
@@ -353,11 +401,13 @@ void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* a
                      uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
                      uint64_t kbase, const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b,
                      const uint64_t* dpos, uint64_t dbase, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s) {
-    if (e_old)
-        k_merge_old<<<(e_old + MG_TILE - 1) / MG_TILE, MN_BLOCK, 0, s>>>(off, adj, adjk, n_vertices, e_old, newoff,
-                                                                       meta, bkeys, kbase, dpos, dbase, hb, adj_new,
-                                                                       adjk_new, e_new, err);
+                     uint32_t* inspos, uint32_t e_new, uint32_t* tile_v, uint32_t* err, hipStream_t s) {
+    if (e_old) {
+        const uint32_t nt = (e_old + MG_TILE - 1) / MG_TILE;
+        k_merge_partition<<<nblocks(nt + 1), MN_BLOCK, 0, s>>>(off, n_vertices, e_old, nt, tile_v);
+        k_merge_old<<<nt, MN_BLOCK, 0, s>>>(off, adj, adjk, tile_v, e_old, newoff, meta, bkeys, kbase, dpos, dbase,
+                                            hb, adj_new, adjk_new, e_new, err);
+    }
     if (n_b)
         k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, kbase, bvals, s_key, n_b, dpos,
                                                       dbase, hb, adj_new, adjk_new, inspos, e_new, err);

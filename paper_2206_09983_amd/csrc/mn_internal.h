@@ -86,7 +86,9 @@ void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* a
                      uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
                      uint64_t kbase, const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b,
                      const uint64_t* dpos, uint64_t dbase, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t e_new, uint32_t* err, hipStream_t s);
+                     uint32_t* inspos, uint32_t e_new, uint32_t* tile_v, uint32_t* err, hipStream_t s);
+// Words tile_v needs for a merge of e_old old entries, minus one.
+uint32_t mn_merge_tiles(uint32_t e_old);
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
 void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
