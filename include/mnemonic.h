@@ -94,8 +94,11 @@ typedef struct {
 #define MNEMONIC_F_TIMING 2u /* record HIP events around the enumeration kernels */
 
 typedef struct {
-    uint32_t flags;        /* MNEMONIC_F_* */
-    uint64_t out_capacity; /* initial tuples per (query, new/expired) buffer; 0 = 2^20 */
+    uint32_t flags;          /* MNEMONIC_F_* */
+    uint64_t out_capacity;   /* initial tuples per (query, new/expired) buffer; 0 = 2^20 */
+    uint64_t rows_per_level; /* partial embeddings one search level may hold (bounds the
+                                enumerator's memory; larger fan-outs are processed in
+                                chunks); 0 = 2^22, minimum 1024 */
 } mnemonic_options;
 
 /* Result of the last successful mnemonic_apply_batch for one query.

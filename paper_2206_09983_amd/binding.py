@@ -50,7 +50,7 @@ class mnemonic_edges(C.Structure):
 
 
 class mnemonic_options(C.Structure):
-    _fields_ = [("flags", C.c_uint32), ("out_capacity", C.c_uint64)]
+    _fields_ = [("flags", C.c_uint32), ("out_capacity", C.c_uint64), ("rows_per_level", C.c_uint64)]
 
 
 class mnemonic_result(C.Structure):
@@ -130,7 +130,7 @@ def _check(rc, ctx):
 
 
 # ------------------------------------------------------------------- ABI calls
-def mnemonic_create(graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n_elabels=0):
+def mnemonic_create(graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n_elabels=0, rows_per_level=0):
     """graph/queries: dicts as produced by paper_2206_09983_amd.synth. Returns the context."""
     L = load()
     keep = []
@@ -158,7 +158,7 @@ def mnemonic_create(graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n
         qs[i].qdst = _ptr(arr(q["qdst"], np.uint32), C.c_uint32)
         qs[i].qelabel = _ptr(arr(q["qlabel"], np.int32), C.c_int32)
         qs[i].sem = int(q["sem"])
-    opt = mnemonic_options(int(flags), int(out_capacity))
+    opt = mnemonic_options(int(flags), int(out_capacity), int(rows_per_level))
     ctx = C.c_void_p()
     rc = L.mnemonic_create(C.byref(g), qs, len(queries), C.byref(opt),
                            C.c_void_p(stream) if stream else None, C.byref(ctx))
@@ -234,9 +234,9 @@ def mnemonic_destroy(ctx):
 class Matcher:
     """Owns one context: create on construction, destroy on close."""
 
-    def __init__(self, graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n_elabels=0):
+    def __init__(self, graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n_elabels=0, rows_per_level=0):
         self.n_q = len(queries)
-        self.ctx = mnemonic_create(graph, queries, flags, out_capacity, stream, n_elabels)
+        self.ctx = mnemonic_create(graph, queries, flags, out_capacity, stream, n_elabels, rows_per_level)
 
     def apply_batch(self, batch):
         return mnemonic_apply_batch(self.ctx, batch)

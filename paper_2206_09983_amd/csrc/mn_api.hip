@@ -197,7 +197,13 @@ struct mnemonic_ctx {
     uint32_t* d_nrows = nullptr;     // [MN_MAXLV + 1] row counters
     uint64_t* d_total = nullptr;     // candidate total of the last scan
     uint64_t* h_ctl = nullptr;       // pinned: readback of counters
-    hipEvent_t ev_x[2] = {nullptr, nullptr};  // around each expansion launch
+    hipEvent_t ev_x[2] = {nullptr, nullptr};  // around each host-sized expansion launch
+    // device-sized launches: event pairs resolved after the batch's final sync
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_phase;
+    uint32_t ev_used = 0;
+    uint64_t last_k = 1ull << 24;  // candidates one last-level expansion may take (sizes d_tiles)
+    uint64_t expect[2][MN_MAXLV];  // candidate totals of the last batch, per phase and level (grid sizes)
     double ms_expand[2] = {0, 0};
     uint64_t n_expand[2] = {0, 0};
 
@@ -228,7 +234,9 @@ struct mnemonic_ctx {
     uint32_t zr_count(int p) const { return 4u + (uint32_t)p * n_q; }
     uint32_t zr_digest(int p) const { return 4u + 2u * n_q + (uint32_t)p * MN_SHARDS * 2u * n_q; }
     uint32_t zr_stats(int p) const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + (uint32_t)p * MN_SHARDS * 8u; }
-    uint32_t zr_words() const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS; }
+    // per phase and level: [candidates exceeded the next buffer, largest candidate total]
+    uint32_t zr_note(int p) const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS + (uint32_t)p * 2u * MN_MAXLV; }
+    uint32_t zr_words() const { return zr_note(2); }
     // shard sums of the last readback: digests [p][q][2], tallies [p][8]
     std::vector<uint64_t> sum_dig;
     uint64_t sum_st[2][8] = {{0}};
@@ -728,6 +736,7 @@ void reset_phase(mnemonic_ctx* c, int p) {
     mn_launch_reset(c->d_err, c->d_zr + c->zr_count(p), c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), MN_SHARDS * 2 * c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), MN_SHARDS * 8, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_note(p), 2 * MN_MAXLV, s);
 }
 
 // Grows level L's buffers to hold `need` rows (contents are not kept: a
@@ -790,7 +799,7 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
     if (n == 0) return;
     hipStream_t s = c->stream;
     auto& B = c->lvb[L];
-    mn_launch_level_range(g, rows_view(c, L), (uint32_t)n, L, B.lo, B.cnt, po.stats, c->d_err, s);
+    mn_launch_level_range(g, rows_view(c, L), (uint32_t)n, nullptr, L, B.lo, B.cnt, po.stats, c->d_err, s);
     mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n, c->d_scan64, c->d_total, s);
     const uint64_t T = read_u64(c, c->d_total);
     if (T == 0) return;
@@ -813,8 +822,9 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         }
         // one event pair serves every launch: the readback below waits for it
         if (timing) HIPCHK(hipEventRecord(c->ev_x[0], s));
-        mn_launch_expand(g, rows_view(c, L), (uint32_t)n, B.lo, B.off, c->d_tiles, c0, c1, L, c->max_close,
-                         c->level_rows[L] != 0, c->level_emit[L] != 0, rows_view(c, L + 1), n_out, po, c->d_err, s);
+        mn_launch_expand(g, rows_view(c, L), (uint32_t)n, nullptr, B.lo, B.off, c->d_tiles, c0, c1, nullptr, nullptr, 0,
+                         L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0, rows_view(c, L + 1), n_out, po,
+                         c->d_err, s);
         if (timing) HIPCHK(hipEventRecord(c->ev_x[1], s));
         c->n_expand[po.phase]++;
         const uint64_t n1 = read_u32(c, n_out);
@@ -828,9 +838,79 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
     }
 }
 
+// Event pair i of the batch (created on first use).
+std::pair<hipEvent_t, hipEvent_t> event_pair(mnemonic_ctx* c, int phase) {
+    const uint32_t i = c->ev_used++;
+    while (c->ev_pool.size() < 2 * (size_t)(i + 1)) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    if (c->ev_phase.size() < i + 1) c->ev_phase.resize(i + 1);
+    c->ev_phase[i] = phase;
+    return {c->ev_pool[2 * i], c->ev_pool[2 * i + 1]};
+}
+
+// Adds the durations of the recorded device-sized expansions (after a sync).
+void resolve_events(mnemonic_ctx* c) {
+    for (uint32_t i = 0; i < c->ev_used; i++) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+        c->ms_expand[c->ev_phase[i]] += ms;
+    }
+    c->ev_used = 0;
+}
+
+// All levels of one chunk of start rows with no host round trip: every
+// launch reads its row count and candidate total from device memory and
+// each level takes at most as many candidates as the next level's buffer
+// holds. A level with more sets its note; the host then grows the buffers
+// and runs the phase again.
+void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint64_t n0_max) {
+    hipStream_t s = c->stream;
+    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
+    // every level takes some candidates, so that an overflow always leaves a note
+    for (uint32_t L = 1; L < c->max_levels; L++) grow_level(c, L, 1ull << 16);
+    uint64_t kmax = c->last_k;
+    for (uint32_t L = 1; L < c->max_levels; L++) kmax = std::max<uint64_t>(kmax, c->lvb[L].cap);
+    const uint64_t need_tiles = mn_expand_tiles(0, kmax) + 1;
+    if (need_tiles > c->cap_tiles) {
+        HIPCHK(hipStreamSynchronize(s));
+        dev_free(c->d_tiles);
+        c->cap_tiles = 0;
+        dev_alloc(c->d_tiles, need_tiles);
+        c->cap_tiles = need_tiles;
+    }
+    uint64_t n_max = std::min<uint64_t>(n0_max, c->lvb[0].cap);
+    for (uint32_t L = 0; L < c->max_levels; L++) {
+        auto& B = c->lvb[L];
+        const uint32_t* n_dev = c->d_nrows + L;
+        mn_launch_level_range(g, rows_view(c, L), (uint32_t)n_max, n_dev, L, B.lo, B.cnt, po.stats, c->d_err, s);
+        mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n_max, c->d_scan64, c->d_total, s, n_dev);
+        const bool next = L + 1 < c->max_levels;
+        const uint64_t K = next ? c->lvb[L + 1].cap : c->last_k;
+        uint32_t* n_out = c->d_nrows + L + 1;
+        if (next) mn_launch_set_u32(n_out, 0, s);
+        unsigned long long* note = c->d_zr + c->zr_note(po.phase) + 2 * L;
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (timing) {
+            ev = event_pair(c, po.phase);
+            HIPCHK(hipEventRecord(ev.first, s));
+        }
+        mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, c->d_tiles, 0, K, c->d_total, note,
+                         c->expect[po.phase][L], L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
+                         rows_view(c, L + 1), n_out, po, c->d_err, s);
+        if (timing) HIPCHK(hipEventRecord(ev.second, s));
+        c->n_expand[po.phase]++;
+        n_max = K;
+    }
+}
+
 // One enumeration phase (p = 0: new embeddings of the inserted slots; 1:
-// expired embeddings of the deleted slots) on the current graph view.
-void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_slots) {
+// expired embeddings of the deleted slots) on the current graph view. With
+// host_chunks the levels are walked with host round trips and chunked to any
+// size; otherwise they run device-sized (device_levels).
+void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_slots, bool host_chunks = false) {
     hipStream_t s = c->stream;
     const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
     if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], s));
@@ -846,11 +926,42 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
             mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_plans, c->max_close, rows_view(c, 0), c->d_nrows,
                                 po, c->d_err, s);
             if (c->max_levels == 0) continue;
-            const uint64_t n0 = read_u32(c, c->d_nrows);
-            process_level(c, g, po, 0, n0);
+            if (host_chunks) {
+                const uint64_t n0 = read_u32(c, c->d_nrows);
+                process_level(c, g, po, 0, n0);
+            } else {
+                device_levels(c, g, po, ns * c->n_plans);
+            }
         }
     }
     if (timing) HIPCHK(hipEventRecord(c->ev[2 * p + 1], s));
+}
+
+// After a device-sized phase: grows what its notes say was too small.
+// Returns true when the phase must run again; host_chunks is set when a level
+// needs more rows than one buffer may hold.
+bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks) {
+    const unsigned long long* note = c->h_zr.data() + c->zr_note(p);
+    bool again = false;
+    for (uint32_t L = 0; L < c->max_levels; L++) {
+        if (!note[2 * L]) continue;
+        again = true;
+        // the level had more candidates than its grid or the next level's
+        // rows cover. Levels after a truncated one saw truncated input, so
+        // their totals are lower bounds: grow at least geometrically and let
+        // the next attempt reveal the rest.
+        const uint64_t T = note[2 * L + 1];
+        c->expect[p][L] = std::max<uint64_t>(c->expect[p][L] == (~0ull >> 8) ? 0 : c->expect[p][L], T);
+        if (L + 1 < c->max_levels) {
+            if (T > c->rows_max)
+                host_chunks = true;
+            else if (T > c->lvb[L + 1].cap)
+                grow_level(c, L + 1, std::max<uint64_t>(T + T / 4, 2 * c->lvb[L + 1].cap));
+        } else if (T > c->last_k) {
+            c->last_k = std::max<uint64_t>(T + T / 4, 2 * c->last_k);
+        }
+    }
+    return again;
 }
 
 // One snapshot; `enumerate` is false only for the initial load.
@@ -865,6 +976,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         c->ms_expand[p] = 0;
         c->n_expand[p] = 0;
     }
+    c->ev_used = 0;
     if (timing) HIPCHK(hipEventRecord(c->ev[4], s));
 
     const uint32_t* in_src = src;
@@ -1025,16 +1137,23 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     c->pend = cur;
 
     if (enumerate) {
-        // outputs too small: grow and enumerate again on the same state
+        // outputs too small, or a level's buffers too small: grow and
+        // enumerate the phase again on the same state (the flags of the
+        // phase being re-run are restored first)
         bool emit = (c->flags & MNEMONIC_F_EMIT) != 0;
-        std::vector<uint64_t> need(2 * c->n_q, 0);
-        bool redo[2] = {false, false};
-        for (uint32_t q = 0; q < c->n_q; q++)
-            for (int p = 0; p < 2; p++) {
-                need[2 * q + p] = c->h_zr[c->zr_count(p) + q];
-                if (emit && need[2 * q + p] > c->houts[q].cap[p]) redo[p] = true;
-            }
-        if (redo[0] || redo[1]) {
+        bool host_chunks[2] = {false, false};
+        const int max_attempts = 2 * (int)c->max_levels + 4;
+        for (int attempt = 0; attempt < max_attempts; attempt++) {
+            std::vector<uint64_t> need(2 * c->n_q, 0);
+            bool redo[2] = {false, false};
+            for (int p = 0; p < 2; p++) redo[p] = absorb_notes(c, p, host_chunks[p]);
+            for (uint32_t q = 0; q < c->n_q; q++)
+                for (int p = 0; p < 2; p++) {
+                    need[2 * q + p] = c->h_zr[c->zr_count(p) + q];
+                    if (emit && need[2 * q + p] > c->houts[q].cap[p]) redo[p] = true;
+                }
+            if (!redo[0] && !redo[1]) break;
+            if (attempt == max_attempts - 1) throw ApiError{MNEMONIC_E_HIP, "enumeration did not settle (internal)"};
             grow_outputs(c, need);
             if (redo[0]) {
                 for (int d = 0; d < 2; d++) {
@@ -1042,7 +1161,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                     mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 1, c->d_err, s);
                 }
                 reset_phase(c, 0);
-                enumerate_phase(c, 0, c->d_ins_slot, n_ins);
+                enumerate_phase(c, 0, c->d_ins_slot, n_ins, host_chunks[0]);
                 for (int d = 0; d < 2; d++) {
                     mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
                     mn_launch_set_flags(c->d_adj[d], c->d_delpos[cur][d], (uint32_t)n_del, 1, c->d_err, s);
@@ -1050,12 +1169,18 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             }
             if (redo[1]) {
                 reset_phase(c, 1);
-                enumerate_phase(c, 1, c->d_del_slot[cur], n_del);
+                enumerate_phase(c, 1, c->d_del_slot[cur], n_del, host_chunks[1]);
             }
             HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             c->summarize();
         }
+        if (timing) resolve_events(c);
+        for (int p = 0; p < 2; p++)
+            for (uint32_t L = 0; L < c->max_levels; L++) {
+                const uint64_t T = c->h_zr[c->zr_note(p) + 2 * L + 1];
+                if (T) c->expect[p][L] = T;
+            }
         // stats
         mnemonic_stats& st = c->stats;
         st.n_live_edges = c->n_live;
@@ -1168,6 +1293,8 @@ void free_all(mnemonic_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->ev_x)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->ev_pool)
+        if (e) (void)hipEventDestroy(e);
     dev_free(c->d_tiles);
     dev_free(c->d_mtiles);
     for (auto& B : c->lvb) {
@@ -1207,6 +1334,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         HIPCHK(hipGetDevice(&c->device));
         c->stream = static_cast<hipStream_t>(hip_stream);
         if (opt) c->flags = opt->flags;
+        if (opt && opt->rows_per_level) c->rows_max = std::max<uint64_t>(1024, opt->rows_per_level);
         c->nV = g->n_vertices;
         c->n_elabels = g->n_elabels ? g->n_elabels : 256;
         c->nbr_bits = std::max<uint32_t>(1, ceil_log2(c->nV));
@@ -1242,6 +1370,8 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         dev_alloc(c->d_ext2int, c->nV);
         HIPCHK(hipMemcpyAsync(c->d_ext2int, ext2int.data(), (size_t)c->nV * 4, hipMemcpyHostToDevice, s));
         c->lvb.resize(c->max_levels);
+        for (int p = 0; p < 2; p++)
+            for (int L = 0; L < MN_MAXLV; L++) c->expect[p][L] = ~0ull >> 8;  // unknown: size grids by capacity
         dev_alloc(c->d_nrows, MN_MAXLV + 2);
         dev_alloc(c->d_total, 1);
         HIPCHK(hipHostMalloc((void**)&c->h_ctl, 64, hipHostMallocDefault));

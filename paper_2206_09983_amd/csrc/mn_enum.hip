@@ -33,6 +33,7 @@
 namespace {
 
 constexpr uint32_t EX_ITEMS = 2;
+constexpr uint64_t EX_MAX_BLOCKS = 1u << 20;  // grid cap when the candidate total is only known on the device
 constexpr uint32_t EX_TILE = MN_BLOCK * EX_ITEMS;
 constexpr uint32_t NO_RUN = 0xFFFFFFFFu;
 constexpr uint32_t RUN_SWAP = 0x80000000u;
@@ -513,11 +514,13 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
     acc_flush(A, K, 2 * po.n_q, po.stats, po.digest);
 }
 
-__global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView R, uint32_t n, uint32_t L,
+__global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView R, uint32_t n,
+                                                          const uint32_t* n_dev, uint32_t L,
                                                           uint32_t* __restrict__ lo, uint32_t* __restrict__ cnt,
                                                           EnumStats* stats, const uint32_t* err) {
     __shared__ BlockAcc A;
     acc_init(A, 0, err);
+    if (n_dev) n = min(n, *n_dev);
     const uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x;
     Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
     if (r < n && !A.dead) {
@@ -541,14 +544,34 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
     acc_flush(A, K, 0, stats, nullptr);
 }
 
+// Candidates [c0, cend) of one expansion, cend = min(c1, *T_dev) when the
+// total is on the device, and the number of tiles that cover them.
+__device__ inline uint64_t expand_end(uint64_t c1, const uint64_t* T_dev) { return T_dev ? min(c1, *T_dev) : c1; }
+
+__device__ inline uint32_t expand_tiles(uint64_t c0, uint64_t cend) {
+    return cend > c0 ? (uint32_t)((cend - c0 + EX_TILE - 1) / EX_TILE) : 0u;
+}
+
 // First row of every expansion tile: tile_row[i] = row of candidate
-// c0 + i * EX_TILE for i < nt, tile_row[nt] = row of candidate c1 - 1.
+// c0 + i * EX_TILE for i < nt, tile_row[nt] = row of candidate cend - 1.
+// With the total on the device, thread 0 also records it in `note`
+// (note[0] = 1 when it exceeds c1, the candidates the next level's rows can
+// take; note[1] = the largest total seen), so the host can grow and re-run.
 __global__ __launch_bounds__(MN_BLOCK) void k_partition(const uint64_t* __restrict__ off, uint32_t n,
-                                                        uint64_t c0, uint64_t c1, uint32_t nt,
-                                                        uint32_t* __restrict__ tile_row) {
+                                                        const uint32_t* n_dev, uint64_t c0, uint64_t c1,
+                                                        const uint64_t* T_dev, uint32_t* __restrict__ tile_row,
+                                                        unsigned long long* note) {
+    if (n_dev) n = min(n, *n_dev);
+    const uint64_t cend = expand_end(c1, T_dev);
+    const uint32_t nt = expand_tiles(c0, cend);
     const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
-    if (i > nt) return;
-    const uint64_t t = i < nt ? c0 + (uint64_t)i * EX_TILE : c1 - 1;
+    if (i == 0 && T_dev && note) {
+        const unsigned long long T = *T_dev;
+        if (T > c1) note[0] = 1ull;
+        atomicMax(note + 1, T);
+    }
+    if (nt == 0 || i > nt) return;
+    const uint64_t t = i < nt ? c0 + (uint64_t)i * EX_TILE : cend - 1;
     tile_row[i] = row_of(off, 0, n, t);
 }
 
@@ -566,8 +589,9 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                                                      const uint32_t* __restrict__ lo,
                                                      const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ tile_row, uint64_t c0,
-                                                     uint64_t c1, uint32_t L, RowsView out,
-                                                     uint32_t* n_out, PhaseOut po, const uint32_t* err) {
+                                                     uint64_t c1, const uint64_t* T_dev, uint32_t L,
+                                                     RowsView out, uint32_t* n_out, PhaseOut po,
+                                                     const uint32_t* err) {
     constexpr int NA = NC > 0 ? NC : 1;
     __shared__ uint64_t s_off[EX_LDS_ROWS];
     __shared__ BlockAcc A;
@@ -575,9 +599,19 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     __shared__ uint32_t s_st[NA][EX_TILE];
     __shared__ unsigned long long s_qn[MAXQ];  // places per query: counts, then global bases
     __shared__ uint32_t s_nrows, s_rbase;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // one tile per block; the grid covers [c0, c1) (the host sizes c1 to the
+    // grid), and blocks past the candidates present leave at once
+    const uint64_t cend = expand_end(c1, T_dev);
+    const uint32_t nt = expand_tiles(c0, cend);
+    if (blockIdx.x >= nt) return;  // the same for every thread of the block
+    acc_init(A, EMIT ? 2 * po.n_q : 0, err);
+    // the first nt blocks are dealt to the XCDs round robin; consecutive tiles
+    // go to blocks of one XCD
+    const uint32_t tile = xcd_tile(blockIdx.x, nt);
+    const uint32_t ncol = 1 + in.wv + in.we;
+    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint64_t t0 = c0 + (uint64_t)tile * EX_TILE;
-    const uint64_t t1 = min(t0 + (uint64_t)EX_TILE, c1);
+    const uint64_t t1 = min(t0 + (uint64_t)EX_TILE, cend);
     const uint32_t rlo = tile_row[tile], rhi = tile_row[tile + 1] + 1;  // rows of this tile lie in [rlo, rhi)
     const uint32_t span = rhi - rlo;
     const bool staged = span <= EX_LDS_ROWS;
@@ -586,9 +620,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     if (EMIT)
         for (uint32_t x = threadIdx.x; x < po.n_q; x += MN_BLOCK) s_qn[x] = 0;
     if (threadIdx.x == 0) s_nrows = 0;
-    acc_init(A, EMIT ? 2 * po.n_q : 0, err);  // its barrier also publishes the above
-    const uint32_t ncol = 1 + in.wv + in.we;
-    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    __syncthreads();
 
     // ---- pass 1: filters and places inside the block
     for (uint32_t it = 0; it < EX_ITEMS; it++) {
@@ -783,9 +815,9 @@ void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, 
     }
 }
 
-void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32_t L, uint32_t* lo,
-                           uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s) {
-    if (n) k_level_range<<<nblocks(n), MN_BLOCK, 0, s>>>(g, rows, n, L, lo, cnt, st, err);
+void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
+                           uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s) {
+    if (n) k_level_range<<<nblocks(n), MN_BLOCK, 0, s>>>(g, rows, n, n_dev, L, lo, cnt, st, err);
 }
 
 uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return c1 > c0 ? (c1 - c0 + EX_TILE - 1) / EX_TILE : 0; }
@@ -793,27 +825,39 @@ uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return c1 > c0 ? (c1 - c0 +
 template <int NC>
 void launch_expand_nc(bool rows, bool emit, dim3 grid, hipStream_t s, const GraphView& g, RowsView in,
                       uint32_t n_in, const uint32_t* lo, const uint64_t* off, const uint32_t* tile_row, uint64_t c0,
-                      uint64_t c1, uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err) {
+                      uint64_t c1, const uint64_t* T_dev, uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po,
+                      const uint32_t* err) {
     if (rows && emit)
-        k_expand<NC, true, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err);
+        k_expand<NC, true, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
+                                                           n_out, po, err);
     else if (rows)
-        k_expand<NC, true, false><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err);
+        k_expand<NC, true, false><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
+                                                            n_out, po, err);
     else
-        k_expand<NC, false, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err);
+        k_expand<NC, false, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
+                                                            n_out, po, err);
 }
 
-void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo, const uint64_t* off,
-                      uint32_t* tile_row, uint64_t c0, uint64_t c1, uint32_t L, uint32_t max_close, bool rows,
-                      bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s) {
+void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
+                      const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
+                      unsigned long long* note, uint64_t expect, uint32_t L, uint32_t max_close, bool rows, bool emit,
+                      RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s) {
     if (c1 <= c0 || !n_in) return;
+    // With the total on the device, the grid follows the expected candidate
+    // count with a margin, and the candidates it can cover bound c1: a larger
+    // total leaves a note and the host runs the phase again with more blocks.
+    if (T_dev) {
+        const uint64_t want = mn_expand_tiles(0, expect + expect / 2) + 64;
+        c1 = std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, EX_MAX_BLOCKS) * EX_TILE);
+    }
     const uint64_t tiles = mn_expand_tiles(c0, c1);
-    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, c0, c1, (uint32_t)tiles, tile_row);
+    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, n_dev, c0, c1, T_dev, tile_row, note);
     const dim3 grid((uint32_t)tiles);
     switch (nc_bucket(max_close)) {
-        case 0: launch_expand_nc<0>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
-        case 1: launch_expand_nc<1>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
-        case 2: launch_expand_nc<2>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
-        case 4: launch_expand_nc<4>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
-        default: launch_expand_nc<8>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, L, out, n_out, po, err); break;
+        case 0: launch_expand_nc<0>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        case 1: launch_expand_nc<1>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        case 2: launch_expand_nc<2>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        case 4: launch_expand_nc<4>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        default: launch_expand_nc<8>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
     }
 }

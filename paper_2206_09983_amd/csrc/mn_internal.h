@@ -14,10 +14,11 @@ void mn_scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* 
                        hipStream_t s);
 
 // Exclusive prefix sum of n u32 values into u64 offsets; *total receives the
-// sum. `scratch` must hold mn_scan64_scratch_words(n) u64 words.
+// sum. `scratch` must hold mn_scan64_scratch_words(n) u64 words. With n_dev,
+// the count is min(n, *n_dev), read on the device (n sizes the launch).
 size_t mn_scan64_scratch_words(uint32_t n);
 void mn_scan_exclusive64(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* scratch,
-                         uint64_t* total, hipStream_t s);
+                         uint64_t* total, hipStream_t s, const uint32_t* n_dev = nullptr);
 
 // Stable LSD radix sort of (u64 key, u32 value) pairs on bits [0, nbits).
 // Ping-pongs between (keys, vals) and (ktmp, vtmp); on return keys/vals point
@@ -135,19 +136,25 @@ struct PhaseOut {
 // max_close: the most closing edges any plan has (sizes the kernels' arrays).
 void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans, uint32_t max_close,
                          RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s);
-// Candidate range of every row at level L: lo[r] and cnt[r].
-void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, uint32_t L, uint32_t* lo,
-                           uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s);
+// Candidate range of every row at level L: lo[r] and cnt[r]. With n_dev the
+// row count is min(n, *n_dev), read on the device (n sizes the launch).
+void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
+                           uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s);
 // Tests the candidates [c0, c1) of level L (flattened over rows by the
 // offsets `off`); survivors become rows of `out` or, at a plan's last level,
 // emitted embeddings.
 // tile_row must hold mn_expand_tiles(c0, c1) + 1 words.
 uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1);
 // rows: some plan continues past level L; emit: some plan ends at level L.
-void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo,
-                      const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, uint32_t L,
-                      uint32_t max_close, bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po,
-                      const uint32_t* err, hipStream_t s);
+// Host-sized form: n_dev = T_dev = note = NULL, candidates exactly [c0, c1).
+// Device-sized form: the row count is min(n_in, *n_dev) and the candidates
+// are [c0, min(c1, *T_dev)); note[0] is set when *T_dev > c1 and note[1]
+// keeps the largest *T_dev (the host grows buffers and re-runs); `expect`,
+// the candidates the host expects, only sizes the grid.
+void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
+                      const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
+                      unsigned long long* note, uint64_t expect, uint32_t L, uint32_t max_close, bool rows, bool emit,
+                      RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s);
 
 // Stores v into *p (a device word) in stream order.
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);

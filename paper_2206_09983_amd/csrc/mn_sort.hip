@@ -181,10 +181,13 @@ __device__ inline uint64_t wave_incl_scan64(uint64_t x) {
 }
 
 // Block-local exclusive scan into u64 (input u32 counts or u64 block sums).
+// n_dev (optional) holds the element count on the device; the grid covers n.
 template <typename TI>
 __global__ __launch_bounds__(MN_BLOCK) void k_scan64_local(const TI* in, uint64_t* out,
-                                                           uint64_t* __restrict__ sums, uint32_t n) {
+                                                           uint64_t* __restrict__ sums, uint32_t n,
+                                                           const uint32_t* n_dev) {
     __shared__ uint64_t wsum[RS_WAVES];
+    if (n_dev) n = min(n, *n_dev);
     uint32_t tid = threadIdx.x;
     size_t base = (size_t)blockIdx.x * SC_TILE + (size_t)tid * SC_ITEMS;
     uint64_t v[SC_ITEMS];
@@ -222,20 +225,22 @@ __global__ __launch_bounds__(MN_BLOCK) void k_scan64_add(uint64_t* __restrict__ 
 }
 
 __global__ void k_scan64_total(const uint32_t* __restrict__ in, const uint64_t* __restrict__ out,
-                               uint32_t n, uint64_t* total) {
+                               uint32_t n, const uint32_t* n_dev, uint64_t* total) {
+    if (n_dev) n = min(n, *n_dev);
     if (threadIdx.x == 0 && blockIdx.x == 0) *total = n ? out[n - 1] + in[n - 1] : 0ull;
 }
 
 inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 template <typename TI>
-void scan64_rec(const TI* in, uint64_t* out, uint32_t n, uint64_t* scratch, hipStream_t s) {
+void scan64_rec(const TI* in, uint64_t* out, uint32_t n, const uint32_t* n_dev, uint64_t* scratch,
+                hipStream_t s) {
     uint32_t nb = ceil_div(n, SC_TILE);
     uint64_t* sums = scratch;
-    k_scan64_local<TI><<<nb, MN_BLOCK, 0, s>>>(in, out, sums, n);
+    k_scan64_local<TI><<<nb, MN_BLOCK, 0, s>>>(in, out, sums, n, n_dev);
     if (nb == 1) return;
-    scan64_rec<uint64_t>(sums, sums, nb, scratch + nb + 1, s);
-    k_scan64_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n);
+    scan64_rec<uint64_t>(sums, sums, nb, nullptr, scratch + nb + 1, s);
+    k_scan64_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n);  // past the device count it adds into unused slots
 }
 
 }  // namespace
@@ -251,9 +256,9 @@ size_t mn_scan64_scratch_words(uint32_t n) {
 }
 
 void mn_scan_exclusive64(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* scratch,
-                         uint64_t* total, hipStream_t s) {
-    if (n) scan64_rec<uint32_t>(in, out, n, scratch, s);
-    k_scan64_total<<<1, 64, 0, s>>>(in, out, n, total);
+                         uint64_t* total, hipStream_t s, const uint32_t* n_dev) {
+    if (n) scan64_rec<uint32_t>(in, out, n, n_dev, scratch, s);
+    k_scan64_total<<<1, 64, 0, s>>>(in, out, n, n_dev, total);
 }
 
 size_t mn_scan_scratch_words(uint32_t n) {

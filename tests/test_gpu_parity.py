@@ -40,13 +40,14 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_parity(B, case, batches=None, flags=None, out_capacity=0, n_elabels=0, check_lists=True):
+def run_parity(B, case, batches=None, flags=None, out_capacity=0, n_elabels=0, check_lists=True, rows_per_level=0):
     batches = case["batches"] if batches is None else batches
     flags = B.F_EMIT if flags is None else flags
     qs = case["queries"]
     say("parity case", case["name"], "queries", len(qs), "batches", len(batches))
     o = Oracle(case["graph"], qs)
-    m = B.Matcher(case["graph"], qs, flags=flags, out_capacity=out_capacity, n_elabels=n_elabels)
+    m = B.Matcher(case["graph"], qs, flags=flags, out_capacity=out_capacity, n_elabels=n_elabels,
+                  rows_per_level=rows_per_level)
     total = 0
     try:
         for bi, b in enumerate(batches):
@@ -150,6 +151,13 @@ def test_rmat_ragged_batches_and_wide_labels(B):
 def test_output_overflow_regrows_and_reruns(B):
     case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
     assert run_parity(B, case, out_capacity=1) > 0
+
+
+def test_small_level_buffers_force_chunked_levels(B):
+    # 1024 rows per level: the device-sized levels overflow, the buffers
+    # cannot grow past the limit and the phase is re-run in host-walked chunks
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
+    assert run_parity(B, case, rows_per_level=1024) > 0
 
 
 def test_count_only_mode_gives_same_counts_and_digests(B):
