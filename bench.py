@@ -17,6 +17,13 @@ deletion of the 6,553 oldest live edges; queries triangle-with-tail, 4-cycle
 and 5-path, each under isomorphism and homomorphism (six query runs over the
 same stream).
 
+With --workload multiquery the same stream is cut into log-uniform batches
+(1,000..262,144 insertions, 10% oldest-key deletions each) and matched
+against 64 random trees, cycles and 4-clique cores (tests/golden/
+multiquery_queries.json lists them and how they were drawn), all in the
+same per-level launches; --autotune lets the library pick its expansion
+tile on the warm-up batches.
+
 Prints ONE JSON line. ``value`` = stream edges (insertions + deletions) fully
 processed per second; embeddings/s and p50/p99 batch latency ride along.
 ``roofline`` reports the expansion kernel's (k_expand, the enumerator's
@@ -68,6 +75,8 @@ def parse():
     ap.add_argument("--out-capacity", type=int, default=1 << 22, help="initial tuples per result buffer")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU-oracle sample")
+    ap.add_argument("--workload", choices=("rmat", "multiquery"), default="rmat")
+    ap.add_argument("--autotune", action="store_true", help="let the library choose its expansion tile")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -171,8 +180,14 @@ def main():
     t0 = time.perf_counter()
     # the whole 2^23-insertion stream is always drawn, so the graph and every
     # batch are the same whatever --steps and --warmup say
-    case = synth.rmat_case(scale=args.scale, n_init=args.n_init, n_stream=max(1 << 23, n_batches * args.batch),
-                           batch=args.batch, del_frac=args.del_frac, seed=args.seed, query_seed=7)
+    if args.workload == "multiquery":
+        with open(os.path.join(ROOT, "tests", "golden", "multiquery_queries.json")) as f:
+            qdoc = json.load(f)
+        case = synth.multiquery_case(scale=args.scale, n_init=args.n_init, del_frac=args.del_frac, seed=args.seed,
+                                     queries=synth.queries_from_json(qdoc["queries"]))
+    else:
+        case = synth.rmat_case(scale=args.scale, n_init=args.n_init, n_stream=max(1 << 23, n_batches * args.batch),
+                               batch=args.batch, del_frac=args.del_frac, seed=args.seed, query_seed=7)
     log("generated %s: %d initial edges, %d batches in %.1f s" % (case["name"], len(case["graph"]["src"]),
                                                                    len(case["batches"]), time.perf_counter() - t0))
     stream = torch.cuda.current_stream()
@@ -184,7 +199,9 @@ def main():
                             "ts": torch.from_numpy(b["ts"]).cuda(),
                             "del_keys": torch.from_numpy(b["del_keys"].view(np.int64)).cuda()})
     torch.cuda.synchronize()
-    flags = binding.F_TIMING | (0 if args.count_only else binding.F_EMIT)
+    flags = binding.F_TIMING | (0 if args.count_only else binding.F_EMIT) | (binding.F_AUTOTUNE if args.autotune else 0)
+    if args.workload == "multiquery":
+        args.out_capacity = min(args.out_capacity, 1 << 16)  # 64 queries: buffers grow on demand
     t0 = time.perf_counter()
     m = binding.Matcher(case["graph"], case["queries"], flags=flags, out_capacity=args.out_capacity,
                         stream=stream.cuda_stream, n_elabels=32)
@@ -194,7 +211,8 @@ def main():
     for i in range(args.warmup):
         m.apply_batch(dev_batches[i])
         st = m.stats()
-        log("warmup %d: %.2f ms, tuples %s" % (i, st["ms_batch"], st["tuples"]))
+        log("warmup %d: %d insertions, %.2f ms, tuples %s, tile %d" % (
+            i, len(case["batches"][i]["src"]), st["ms_batch"], st["tuples"], st["expand_tile"]))
 
     lat = []
     keys = list(BYTES)
@@ -225,6 +243,7 @@ def main():
                 st["expand_launches"], st["seeds"], st["frontier_rows"], st["entries_scanned"], st["tuples"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    m_tile = m.stats()["expand_tile"]
     m.close()
 
     if args.count_only:
@@ -252,13 +271,20 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic (seeded R-MAT stream, stand-in for the paper's NetFlow/LSBench streams)",
-        "config": {
+        "config": ({
             "workload": "rmat_s%d_init%d_batch%d_del%d%%_tt_c4_p5_iso_homo" % (
                 args.scale, args.n_init, args.batch, int(round(args.del_frac * 100))),
             "vertices": 1 << args.scale, "initial_edges": args.n_init, "batch_insertions": args.batch,
             "batch_deletions": int(args.del_frac * args.batch), "queries": [q["name"] for q in case["queries"]],
             "emit_tuples": not args.count_only, "seed": args.seed,
-        },
+        } if args.workload == "rmat" else {
+            "workload": "rmat_s%d_init%d_logbatch1000-262144_del%d%%_64q" % (
+                args.scale, args.n_init, int(round(args.del_frac * 100))),
+            "vertices": 1 << args.scale, "initial_edges": args.n_init,
+            "batch_insertions": [len(case["batches"][i]["src"]) for i in range(args.warmup, n_batches)],
+            "queries": len(case["queries"]), "emit_tuples": not args.count_only, "seed": args.seed,
+            "autotune": bool(args.autotune), "expand_tile": m_tile,
+        }),
         "embeddings_per_s": tuples / elapsed,
         "p50_batch_ms": pct(50),
         "p99_batch_ms": pct(99),

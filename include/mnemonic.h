@@ -92,13 +92,17 @@ typedef struct {
 
 #define MNEMONIC_F_EMIT 1u   /* write the embedding tuples (else counts and digests only) */
 #define MNEMONIC_F_TIMING 2u /* record HIP events around the enumeration kernels */
+#define MNEMONIC_F_AUTOTUNE 4u /* the first batches try each expansion tile size (256, 512,
+                                  1024 candidates per block) twice and keep the fastest per
+                                  candidate; results do not depend on the choice */
 
 typedef struct {
     uint32_t flags;          /* MNEMONIC_F_* */
     uint64_t out_capacity;   /* initial tuples per (query, new/expired) buffer; 0 = 2^20 */
     uint64_t rows_per_level; /* partial embeddings one search level may hold (bounds the
                                 enumerator's memory; larger fan-outs are processed in
-                                chunks); 0 = 2^22, minimum 1024 */
+                                chunks; buffers grow on demand up to it); 0 = 2^25,
+                                minimum 1024 */
 } mnemonic_options;
 
 /* Result of the last successful mnemonic_apply_batch for one query.
@@ -133,6 +137,8 @@ typedef struct {
  *   vf_reads           vertex-filter words tested
  *   frontier_rows      partial embeddings passed from one level to the next
  *   expand_launches    launches of the expansion kernel
+ *   expand_tile        candidates per expansion block in use (autotuned with
+ *                      MNEMONIC_F_AUTOTUNE, else 512)
  * With MNEMONIC_F_TIMING: ms_expand = summed device time of the expansion
  * launches, ms_enumerate = the whole enumeration phase, ms_batch = the whole
  * snapshot on the device. */
@@ -149,6 +155,7 @@ typedef struct {
     uint64_t vf_reads[2];
     uint64_t frontier_rows[2];
     uint64_t expand_launches[2];
+    uint64_t expand_tile;
     double ms_expand[2];
     double ms_enumerate[2];
     double ms_batch;

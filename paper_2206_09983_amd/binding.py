@@ -18,6 +18,7 @@ ISO = 0
 HOMO = 1
 F_EMIT = 1
 F_TIMING = 2
+F_AUTOTUNE = 4
 
 ERRORS = {
     -1: "MNEMONIC_E_ARG", -2: "MNEMONIC_E_QUERY", -3: "MNEMONIC_E_VERTEX", -4: "MNEMONIC_E_LABEL",
@@ -65,7 +66,7 @@ class mnemonic_stats(C.Structure):
                 ("range_probe_words", C.c_uint64 * 2), ("key_reads", C.c_uint64 * 2),
                 ("tuples", C.c_uint64 * 2), ("tuple_words", C.c_uint64 * 2), ("vf_reads", C.c_uint64 * 2),
                 ("frontier_rows", C.c_uint64 * 2), ("expand_launches", C.c_uint64 * 2),
-                ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2), ("ms_batch", C.c_double)]
+                ("expand_tile", C.c_uint64), ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2), ("ms_batch", C.c_double)]
 
 
 class MnemonicError(RuntimeError):

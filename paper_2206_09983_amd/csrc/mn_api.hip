@@ -187,7 +187,7 @@ struct mnemonic_ctx {
         uint64_t cap = 0;
     };
     std::vector<LevelBuf> lvb;
-    uint64_t rows_max = 1ull << 22;  // rows per level buffer (bounds each expansion chunk)
+    uint64_t rows_max = 1ull << 25;  // rows per level buffer, grown on demand (bounds each expansion chunk)
     uint64_t* d_scan64 = nullptr;
     uint64_t cap_scan64 = 0;
     uint32_t* d_tiles = nullptr;     // first row of every expansion tile
@@ -203,7 +203,18 @@ struct mnemonic_ctx {
     std::vector<int> ev_phase;
     uint32_t ev_used = 0;
     uint64_t last_k = 1ull << 24;  // candidates one last-level expansion may take (sizes d_tiles)
-    uint64_t expect[2][MN_MAXLV];  // candidate totals of the last batch, per phase and level (grid sizes)
+    // observed rates per inserted/deleted slot of the last batches: start rows
+    // (index MN_MAXLV) and candidates per level; negative = not seen yet. They
+    // size grids and buffers for the next batch, whatever its size.
+    double rate[2][MN_MAXLV + 1];
+    uint64_t chunk_ns[2] = {1, 1};  // slots of the largest start chunk of the last run of each phase
+    uint32_t tile_items = 2;       // expansion tile = 256 x tile_items candidates
+    // autotuning of tile_items: trial batches per setting, time and candidates
+    static constexpr uint32_t TUNE_TRIALS = 2;
+    uint32_t tune_batch = 0;
+    double tune_ms[3] = {0, 0, 0};
+    double tune_cand[3] = {0, 0, 0};
+    bool tuning() const { return (flags & MNEMONIC_F_AUTOTUNE) && tune_batch < 3 * TUNE_TRIALS; }
     double ms_expand[2] = {0, 0};
     uint64_t n_expand[2] = {0, 0};
 
@@ -234,8 +245,11 @@ struct mnemonic_ctx {
     uint32_t zr_count(int p) const { return 4u + (uint32_t)p * n_q; }
     uint32_t zr_digest(int p) const { return 4u + 2u * n_q + (uint32_t)p * MN_SHARDS * 2u * n_q; }
     uint32_t zr_stats(int p) const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + (uint32_t)p * MN_SHARDS * 8u; }
-    // per phase and level: [candidates exceeded the next buffer, largest candidate total]
-    uint32_t zr_note(int p) const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS + (uint32_t)p * 2u * MN_MAXLV; }
+    // per phase and level: [candidates exceeded the next buffer, largest
+    // candidate total]; slot MN_MAXLV: [start rows exceeded their buffer, largest count]
+    uint32_t zr_note(int p) const {
+        return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS + (uint32_t)p * 2u * (MN_MAXLV + 1);
+    }
     uint32_t zr_words() const { return zr_note(2); }
     // shard sums of the last readback: digests [p][q][2], tallies [p][8]
     std::vector<uint64_t> sum_dig;
@@ -736,7 +750,7 @@ void reset_phase(mnemonic_ctx* c, int p) {
     mn_launch_reset(c->d_err, c->d_zr + c->zr_count(p), c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), MN_SHARDS * 2 * c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), MN_SHARDS * 8, s);
-    mn_launch_reset(c->d_err, c->d_zr + c->zr_note(p), 2 * MN_MAXLV, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_note(p), 2 * (MN_MAXLV + 1), s);
 }
 
 // Grows level L's buffers to hold `need` rows (contents are not kept: a
@@ -807,7 +821,7 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
     if (next) grow_level(c, L + 1, T);
     // chunks bounded by the next level's rows (each candidate yields <= 1 row)
     const uint64_t K = next ? c->lvb[L + 1].cap : (1ull << 26);
-    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
     for (uint64_t c0 = 0; c0 < T; c0 += K) {
         const uint64_t c1 = std::min<uint64_t>(T, c0 + K);
         uint32_t* n_out = c->d_nrows + L + 1;
@@ -823,8 +837,8 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         // one event pair serves every launch: the readback below waits for it
         if (timing) HIPCHK(hipEventRecord(c->ev_x[0], s));
         mn_launch_expand(g, rows_view(c, L), (uint32_t)n, nullptr, B.lo, B.off, c->d_tiles, c0, c1, nullptr, nullptr, 0,
-                         L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0, rows_view(c, L + 1), n_out, po,
-                         c->d_err, s);
+                         c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
+                         rows_view(c, L + 1), n_out, po, c->d_err, s);
         if (timing) HIPCHK(hipEventRecord(c->ev_x[1], s));
         c->n_expand[po.phase]++;
         const uint64_t n1 = read_u32(c, n_out);
@@ -866,9 +880,9 @@ void resolve_events(mnemonic_ctx* c) {
 // each level takes at most as many candidates as the next level's buffer
 // holds. A level with more sets its note; the host then grows the buffers
 // and runs the phase again.
-void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint64_t n0_max) {
+void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint64_t n0_max, uint64_t ns) {
     hipStream_t s = c->stream;
-    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
     // every level takes some candidates, so that an overflow always leaves a note
     for (uint32_t L = 1; L < c->max_levels; L++) grow_level(c, L, 1ull << 16);
     uint64_t kmax = c->last_k;
@@ -897,8 +911,10 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
             ev = event_pair(c, po.phase);
             HIPCHK(hipEventRecord(ev.first, s));
         }
+        const double rt = c->rate[po.phase][L];
+        const uint64_t expect = rt < 0 ? (~0ull >> 8) : (uint64_t)(rt * (double)ns) + 1;
         mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, c->d_tiles, 0, K, c->d_total, note,
-                         c->expect[po.phase][L], L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
+                         expect, c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
                          rows_view(c, L + 1), n_out, po, c->d_err, s);
         if (timing) HIPCHK(hipEventRecord(ev.second, s));
         c->n_expand[po.phase]++;
@@ -912,25 +928,33 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
 // size; otherwise they run device-sized (device_levels).
 void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_slots, bool host_chunks = false) {
     hipStream_t s = c->stream;
-    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0;
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
     if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], s));
     if (n_slots && c->n_plans) {
         GraphView g = make_view(c, false);
         PhaseOut po = phase_out(c, p);
-        // every (slot, plan) pair may become one start row
-        const uint64_t chunk = std::max<uint64_t>(1, c->rows_max / c->n_plans);
+        // Start rows per slot: the last batches' rate with a margin when known
+        // (the seed kernel counts past the buffer and the phase is re-run if
+        // that was short), else every (slot, plan) pair; host-walked levels
+        // keep the worst case.
+        const double r0 = c->rate[p][MN_MAXLV];
+        const double per_slot = (host_chunks || r0 < 0) ? (double)c->n_plans : std::min<double>(c->n_plans, 1.5 * r0 + 0.01);
+        const uint64_t chunk = std::max<uint64_t>(1, (uint64_t)((double)c->rows_max / per_slot));
+        c->chunk_ns[p] = std::min<uint64_t>(chunk, n_slots);
         for (uint64_t s0 = 0; s0 < n_slots; s0 += chunk) {
             const uint64_t ns = std::min<uint64_t>(chunk, n_slots - s0);
-            if (c->max_levels) grow_level(c, 0, ns * c->n_plans);  // else every plan emits at once
+            if (c->max_levels)  // else every plan emits at once
+                grow_level(c, 0, std::min<uint64_t>(c->rows_max, (uint64_t)(per_slot * (double)ns) + 1024));
             mn_launch_set_u32(c->d_nrows, 0, s);
             mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_plans, c->max_close, rows_view(c, 0), c->d_nrows,
                                 po, c->d_err, s);
             if (c->max_levels == 0) continue;
+            mn_launch_note_count(c->d_nrows, c->lvb[0].cap, c->d_zr + c->zr_note(p) + 2 * MN_MAXLV, s);
             if (host_chunks) {
                 const uint64_t n0 = read_u32(c, c->d_nrows);
                 process_level(c, g, po, 0, n0);
             } else {
-                device_levels(c, g, po, ns * c->n_plans);
+                device_levels(c, g, po, ns * c->n_plans, ns);
             }
         }
     }
@@ -943,6 +967,13 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
 bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks) {
     const unsigned long long* note = c->h_zr.data() + c->zr_note(p);
     bool again = false;
+    const double ns = (double)std::max<uint64_t>(1, c->chunk_ns[p]);
+    if (note[2 * MN_MAXLV]) {  // start rows past their buffer
+        again = true;
+        const uint64_t n0 = note[2 * MN_MAXLV + 1];
+        c->rate[p][MN_MAXLV] = std::max<double>(c->rate[p][MN_MAXLV], (double)n0 / ns);
+        if (n0 > c->rows_max) host_chunks = true;
+    }
     for (uint32_t L = 0; L < c->max_levels; L++) {
         if (!note[2 * L]) continue;
         again = true;
@@ -951,7 +982,7 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks) {
         // their totals are lower bounds: grow at least geometrically and let
         // the next attempt reveal the rest.
         const uint64_t T = note[2 * L + 1];
-        c->expect[p][L] = std::max<uint64_t>(c->expect[p][L] == (~0ull >> 8) ? 0 : c->expect[p][L], T);
+        c->rate[p][L] = std::max<double>(c->rate[p][L], (double)T / ns);
         if (L + 1 < c->max_levels) {
             if (T > c->rows_max)
                 host_chunks = true;
@@ -971,7 +1002,10 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     hipStream_t s = c->stream;
     if (n_ins + n_del >= (1ull << 31)) throw ApiError{MNEMONIC_E_ARG, "batch too large"};
     ensure_capacity(c, n_ins, n_del);
-    const bool timing = (c->flags & MNEMONIC_F_TIMING) != 0 && enumerate;
+    static const uint32_t kItems[3] = {1, 2, 4};
+    const bool tune = enumerate && c->tuning();
+    if (tune) c->tile_items = kItems[c->tune_batch % 3];
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0 && enumerate;
     for (int p = 0; p < 2; p++) {
         c->ms_expand[p] = 0;
         c->n_expand[p] = 0;
@@ -1176,11 +1210,32 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             c->summarize();
         }
         if (timing) resolve_events(c);
-        for (int p = 0; p < 2; p++)
-            for (uint32_t L = 0; L < c->max_levels; L++) {
-                const uint64_t T = c->h_zr[c->zr_note(p) + 2 * L + 1];
-                if (T) c->expect[p][L] = T;
+        if (tune) {
+            const uint32_t k = c->tune_batch % 3;
+            c->tune_ms[k] += c->ms_expand[0] + c->ms_expand[1];
+            c->tune_cand[k] += (double)(c->sum_st[0][1] + c->sum_st[1][1]);
+            if (++c->tune_batch == 3 * mnemonic_ctx::TUNE_TRIALS) {
+                int best = 1;
+                double best_cost = 1e300;
+                for (int i = 0; i < 3; i++) {
+                    const double cost = c->tune_cand[i] > 0 ? c->tune_ms[i] / c->tune_cand[i] : 1e300;
+                    if (cost < best_cost) {
+                        best_cost = cost;
+                        best = i;
+                    }
+                }
+                c->tile_items = kItems[best];
             }
+        }
+        // rates of this batch for the next one (levels that saw candidates)
+        for (int p = 0; p < 2; p++) {
+            const double ns = (double)std::max<uint64_t>(1, c->chunk_ns[p]);
+            for (uint32_t L = 0; L <= MN_MAXLV; L++) {
+                if (L < MN_MAXLV && L >= c->max_levels) continue;
+                const uint64_t T = c->h_zr[c->zr_note(p) + 2 * L + 1];
+                if (T) c->rate[p][L] = (double)T / ns;
+            }
+        }
         // stats
         mnemonic_stats& st = c->stats;
         st.n_live_edges = c->n_live;
@@ -1196,6 +1251,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             st.vf_reads[p] = z[6];
             st.frontier_rows[p] = z[7];
             st.expand_launches[p] = c->n_expand[p];
+            st.expand_tile = (uint64_t)MN_BLOCK * c->tile_items;
             st.ms_expand[p] = c->ms_expand[p];
             uint64_t words = 0;
             for (uint32_t q = 0; q < c->n_q; q++) words += c->h_zr[c->zr_count(p) + q] * c->hq[q].n_qe;
@@ -1371,7 +1427,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         HIPCHK(hipMemcpyAsync(c->d_ext2int, ext2int.data(), (size_t)c->nV * 4, hipMemcpyHostToDevice, s));
         c->lvb.resize(c->max_levels);
         for (int p = 0; p < 2; p++)
-            for (int L = 0; L < MN_MAXLV; L++) c->expect[p][L] = ~0ull >> 8;  // unknown: size grids by capacity
+            for (int L = 0; L <= MN_MAXLV; L++) c->rate[p][L] = -1.0;  // unknown: size by capacity
         dev_alloc(c->d_nrows, MN_MAXLV + 2);
         dev_alloc(c->d_total, 1);
         HIPCHK(hipHostMalloc((void**)&c->h_ctl, 64, hipHostMallocDefault));

@@ -32,9 +32,9 @@
 
 namespace {
 
-constexpr uint32_t EX_ITEMS = 2;
+// candidates per lane in one expansion tile (tile = 256 x items): 1, 2 or 4
 constexpr uint64_t EX_MAX_BLOCKS = 1u << 20;  // grid cap when the candidate total is only known on the device
-constexpr uint32_t EX_TILE = MN_BLOCK * EX_ITEMS;
+constexpr uint32_t EX_TILE_MIN = MN_BLOCK;  // the smallest tile sizes the tile_row buffer
 constexpr uint32_t NO_RUN = 0xFFFFFFFFu;
 constexpr uint32_t RUN_SWAP = 0x80000000u;
 constexpr uint8_t TREE_EDGE = 0xFF;
@@ -506,9 +506,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
                 for (uint32_t c = 0; c < NA; c++)
                     if (c < (uint32_t)NC && c < P.c0_end) wcol(R, 1 + R.wv + P.close[c].qe, r, st[c]);
                 K.rows++;
-            } else {
-                set_err(err, MN_ERR_INTERNAL);  // the host sizes R for every possible row
-            }
+            }  // rows past the buffer are counted, not written: the host grows it and runs again
         }
     }
     acc_flush(A, K, 2 * po.n_q, po.stats, po.digest);
@@ -544,26 +542,36 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
     acc_flush(A, K, 0, stats, nullptr);
 }
 
+// Records a device count against a capacity: note[0] = 1 when *count > cap,
+// note[1] = the largest count seen.
+__global__ void k_note_count(const uint32_t* count, uint64_t cap, unsigned long long* note) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const unsigned long long n = *count;
+        if (n > cap) note[0] = 1ull;
+        atomicMax(note + 1, n);
+    }
+}
+
 // Candidates [c0, cend) of one expansion, cend = min(c1, *T_dev) when the
 // total is on the device, and the number of tiles that cover them.
 __device__ inline uint64_t expand_end(uint64_t c1, const uint64_t* T_dev) { return T_dev ? min(c1, *T_dev) : c1; }
 
-__device__ inline uint32_t expand_tiles(uint64_t c0, uint64_t cend) {
-    return cend > c0 ? (uint32_t)((cend - c0 + EX_TILE - 1) / EX_TILE) : 0u;
+__host__ __device__ inline uint32_t expand_tiles(uint64_t c0, uint64_t cend, uint32_t tile) {
+    return cend > c0 ? (uint32_t)((cend - c0 + tile - 1) / tile) : 0u;
 }
 
 // First row of every expansion tile: tile_row[i] = row of candidate
-// c0 + i * EX_TILE for i < nt, tile_row[nt] = row of candidate cend - 1.
+// c0 + i * tile for i < nt, tile_row[nt] = row of candidate cend - 1.
 // With the total on the device, thread 0 also records it in `note`
 // (note[0] = 1 when it exceeds c1, the candidates the next level's rows can
 // take; note[1] = the largest total seen), so the host can grow and re-run.
 __global__ __launch_bounds__(MN_BLOCK) void k_partition(const uint64_t* __restrict__ off, uint32_t n,
                                                         const uint32_t* n_dev, uint64_t c0, uint64_t c1,
-                                                        const uint64_t* T_dev, uint32_t* __restrict__ tile_row,
-                                                        unsigned long long* note) {
+                                                        const uint64_t* T_dev, uint32_t tile,
+                                                        uint32_t* __restrict__ tile_row, unsigned long long* note) {
     if (n_dev) n = min(n, *n_dev);
     const uint64_t cend = expand_end(c1, T_dev);
-    const uint32_t nt = expand_tiles(c0, cend);
+    const uint32_t nt = expand_tiles(c0, cend, tile);
     const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
     if (i == 0 && T_dev && note) {
         const unsigned long long T = *T_dev;
@@ -571,20 +579,19 @@ __global__ __launch_bounds__(MN_BLOCK) void k_partition(const uint64_t* __restri
         atomicMax(note + 1, T);
     }
     if (nt == 0 || i > nt) return;
-    const uint64_t t = i < nt ? c0 + (uint64_t)i * EX_TILE : cend - 1;
+    const uint64_t t = i < nt ? c0 + (uint64_t)i * tile : cend - 1;
     tile_row[i] = row_of(off, 0, n, t);
 }
 
-constexpr uint32_t EX_LDS_ROWS = EX_TILE + 1;
 constexpr uint32_t NO_LOC = 0xFFFFFFFFu;
 
-// One block tests a tile of EX_TILE candidates in two passes. Pass 1 runs the
+// One block tests a tile of 256 x ITEMS candidates in two passes. Pass 1 runs the
 // filters and gives every survivor a place inside the block (LDS counters per
 // query for embeddings, one for new rows); one global atomic per query and
 // block then reserves the block's places; pass 2 writes rows and embeddings.
 // Contended device-scope atomics (they serialise across the XCDs) drop from
 // one per wave and item to one per block.
-template <int NC, bool ROWS, bool EMIT>
+template <int NC, bool ROWS, bool EMIT, uint32_t ITEMS>
 __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, uint32_t n_in,
                                                      const uint32_t* __restrict__ lo,
                                                      const uint64_t* __restrict__ off,
@@ -593,6 +600,8 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                                                      RowsView out, uint32_t* n_out, PhaseOut po,
                                                      const uint32_t* err) {
     constexpr int NA = NC > 0 ? NC : 1;
+    constexpr uint32_t EX_TILE = MN_BLOCK * ITEMS;
+    constexpr uint32_t EX_LDS_ROWS = EX_TILE + 1;
     __shared__ uint64_t s_off[EX_LDS_ROWS];
     __shared__ BlockAcc A;
     __shared__ uint32_t s_r[EX_TILE], s_p[EX_TILE], s_loc[EX_TILE];
@@ -602,7 +611,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     // one tile per block; the grid covers [c0, c1) (the host sizes c1 to the
     // grid), and blocks past the candidates present leave at once
     const uint64_t cend = expand_end(c1, T_dev);
-    const uint32_t nt = expand_tiles(c0, cend);
+    const uint32_t nt = expand_tiles(c0, cend, EX_TILE);
     if (blockIdx.x >= nt) return;  // the same for every thread of the block
     acc_init(A, EMIT ? 2 * po.n_q : 0, err);
     // the first nt blocks are dealt to the XCDs round robin; consecutive tiles
@@ -623,7 +632,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     __syncthreads();
 
     // ---- pass 1: filters and places inside the block
-    for (uint32_t it = 0; it < EX_ITEMS; it++) {
+    for (uint32_t it = 0; it < ITEMS; it++) {
         const uint32_t idx = it * MN_BLOCK + threadIdx.x;
         const uint64_t t = t0 + idx;
         bool ok = t < t1 && !A.dead;
@@ -729,7 +738,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     __syncthreads();
 
     // ---- pass 2: write rows and embeddings at their places
-    for (uint32_t it = 0; it < EX_ITEMS; it++) {
+    for (uint32_t it = 0; it < ITEMS; it++) {
         const uint32_t idx = it * MN_BLOCK + threadIdx.x;
         const uint64_t t = t0 + idx;
         const uint32_t loc = t < t1 ? s_loc[idx] : NO_LOC;
@@ -815,49 +824,69 @@ void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, 
     }
 }
 
+void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long long* note, hipStream_t s) {
+    k_note_count<<<1, 64, 0, s>>>(count, cap, note);
+}
+
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
                            uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s) {
     if (n) k_level_range<<<nblocks(n), MN_BLOCK, 0, s>>>(g, rows, n, n_dev, L, lo, cnt, st, err);
 }
 
-uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return c1 > c0 ? (c1 - c0 + EX_TILE - 1) / EX_TILE : 0; }
+uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return expand_tiles(c0, c1, EX_TILE_MIN); }
 
-template <int NC>
+template <int NC, uint32_t ITEMS>
 void launch_expand_nc(bool rows, bool emit, dim3 grid, hipStream_t s, const GraphView& g, RowsView in,
                       uint32_t n_in, const uint32_t* lo, const uint64_t* off, const uint32_t* tile_row, uint64_t c0,
                       uint64_t c1, const uint64_t* T_dev, uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po,
                       const uint32_t* err) {
     if (rows && emit)
-        k_expand<NC, true, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
-                                                           n_out, po, err);
+        k_expand<NC, true, true, ITEMS><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
+                                                                  n_out, po, err);
     else if (rows)
-        k_expand<NC, true, false><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
-                                                            n_out, po, err);
+        k_expand<NC, true, false, ITEMS><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L,
+                                                                   out, n_out, po, err);
     else
-        k_expand<NC, false, true><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
-                                                            n_out, po, err);
+        k_expand<NC, false, true, ITEMS><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L,
+                                                                   out, n_out, po, err);
+}
+
+template <uint32_t ITEMS>
+void launch_expand_items(uint32_t max_close, bool rows, bool emit, dim3 grid, hipStream_t s, const GraphView& g,
+                         RowsView in, uint32_t n_in, const uint32_t* lo, const uint64_t* off, const uint32_t* tile_row,
+                         uint64_t c0, uint64_t c1, const uint64_t* T_dev, uint32_t L, RowsView out, uint32_t* n_out,
+                         PhaseOut po, const uint32_t* err) {
+    switch (nc_bucket(max_close)) {
+        case 0: launch_expand_nc<0, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        case 1: launch_expand_nc<1, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        case 2: launch_expand_nc<2, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        case 4: launch_expand_nc<4, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        default: launch_expand_nc<8, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+    }
 }
 
 void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
                       const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
-                      unsigned long long* note, uint64_t expect, uint32_t L, uint32_t max_close, bool rows, bool emit,
-                      RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s) {
+                      unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
+                      bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
+                      hipStream_t s) {
     if (c1 <= c0 || !n_in) return;
+    if (items != 1 && items != 4) items = 2;
+    const uint32_t tile = MN_BLOCK * items;
     // With the total on the device, the grid follows the expected candidate
     // count with a margin, and the candidates it can cover bound c1: a larger
     // total leaves a note and the host runs the phase again with more blocks.
     if (T_dev) {
-        const uint64_t want = mn_expand_tiles(0, expect + expect / 2) + 64;
-        c1 = std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, EX_MAX_BLOCKS) * EX_TILE);
+        const uint64_t want = expand_tiles(0, expect + expect / 2, tile) + 64;
+        c1 = std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, EX_MAX_BLOCKS) * tile);
     }
-    const uint64_t tiles = mn_expand_tiles(c0, c1);
-    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, n_dev, c0, c1, T_dev, tile_row, note);
+    const uint64_t tiles = expand_tiles(c0, c1, tile);
+    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, n_dev, c0, c1, T_dev, tile, tile_row, note);
     const dim3 grid((uint32_t)tiles);
-    switch (nc_bucket(max_close)) {
-        case 0: launch_expand_nc<0>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        case 1: launch_expand_nc<1>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        case 2: launch_expand_nc<2>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        case 4: launch_expand_nc<4>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        default: launch_expand_nc<8>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-    }
+    if (items == 1)
+        launch_expand_items<1>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
+    else if (items == 4)
+        launch_expand_items<4>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
+    else
+        launch_expand_items<2>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
 }

@@ -132,10 +132,14 @@ struct PhaseOut {
 
 // Start rows: one per (batch slot, start position) whose edgeMatcher bit and
 // endpoint filters pass and whose start-level closing edges exist. Plans with
-// no further level emit their embeddings directly.
+// no further level emit their embeddings directly. *n_rows counts every row,
+// also those past rows.cap, which are not written.
 // max_close: the most closing edges any plan has (sizes the kernels' arrays).
 void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans, uint32_t max_close,
                          RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s);
+// note[0] = 1 when *count > cap; note[1] = max(note[1], *count).
+void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long long* note, hipStream_t s);
+
 // Candidate range of every row at level L: lo[r] and cnt[r]. With n_dev the
 // row count is min(n, *n_dev), read on the device (n sizes the launch).
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
@@ -143,18 +147,20 @@ void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const 
 // Tests the candidates [c0, c1) of level L (flattened over rows by the
 // offsets `off`); survivors become rows of `out` or, at a plan's last level,
 // emitted embeddings.
-// tile_row must hold mn_expand_tiles(c0, c1) + 1 words.
+// tile_row must hold mn_expand_tiles(c0, c1) + 1 words (enough for any tile size).
 uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1);
 // rows: some plan continues past level L; emit: some plan ends at level L.
 // Host-sized form: n_dev = T_dev = note = NULL, candidates exactly [c0, c1).
 // Device-sized form: the row count is min(n_in, *n_dev) and the candidates
 // are [c0, min(c1, *T_dev)); note[0] is set when *T_dev > c1 and note[1]
 // keeps the largest *T_dev (the host grows buffers and re-runs); `expect`,
-// the candidates the host expects, only sizes the grid.
+// the candidates the host expects, only sizes the grid. items (1, 2 or 4)
+// sets the tile: 256 x items candidates per block.
 void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
                       const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
-                      unsigned long long* note, uint64_t expect, uint32_t L, uint32_t max_close, bool rows, bool emit,
-                      RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err, hipStream_t s);
+                      unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
+                      bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
+                      hipStream_t s);
 
 // Stores v into *p (a device word) in stream order.
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);

@@ -12,6 +12,10 @@ Workloads (stand-ins for the paper's NetFlow / LSBench streams, Section VII):
     followed by deletion of the oldest 10% live keys; queries triangle-with-tail,
     4-cycle and 5-path under isomorphism and homomorphism.  The full size is
     2^20 vertices, 2^24 initial edges and 2^23 stream edges in batches of 65,536.
+  * ``multiquery_case`` - the R-MAT stream re-batched with log-uniform batch
+    sizes in [1,000, 262,144] (10% oldest-key deletions each) and 64 random
+    connected queries of 3-8 vertices (trees, cycles, a 4-clique core with
+    tree attachments), labels from the data Zipfs, isomorphism.
   * ``tiny_case``      - small multigraphs with self-loops and parallel edges,
     for brute-force checks.
 
@@ -345,3 +349,82 @@ def tiny_case(seed, max_v=6, max_init=10, n_batches=3, max_ins=4, max_del=3,
     qh = dict(q)
     qh["sem"] = HOMO
     return {"name": "tiny%d" % seed, "graph": graph, "batches": batches, "queries": [q, qh]}
+
+
+# --------------------------------------------------------------------------
+# many queries over one stream
+# --------------------------------------------------------------------------
+def random_shape_query(rng, n_vlabels, n_elabels, s, sem, min_v=3, max_v=8):
+    """One query: shape uniform over {tree, cycle, 4-clique core + tree
+    attachments}, 3..8 vertices (>= 4 with the clique), edge directions
+    uniform, vertex and edge labels drawn from the data Zipfs."""
+    kind = int(rng.integers(0, 3))
+    lo = 4 if kind == 2 else min_v
+    nv = int(rng.integers(lo, max_v + 1))
+    pairs = []
+    if kind == 1:  # cycle
+        pairs = [(i, (i + 1) % nv) for i in range(nv)]
+        start = nv
+    elif kind == 2:  # 4-clique core
+        pairs = [(a, b) for a in range(4) for b in range(a + 1, 4)]
+        start = 4
+    else:  # tree
+        start = 1
+    for v in range(start, nv):
+        pairs.append((int(rng.integers(0, v)), v))
+    edges = [(a, b) if rng.random() < 0.5 else (b, a) for a, b in pairs]
+    order = rng.permutation(len(edges))
+    edges = [edges[i] for i in order]
+    vl = zipf_draw(rng, n_vlabels, s, nv)
+    el = zipf_draw(rng, n_elabels, s, len(edges))
+    vreq = (np.uint64(1) << vl.astype(np.uint64)).astype(np.uint64)
+    name = ("tree", "cycle", "k4")[kind] + str(nv)
+    return make_query(nv, vreq, [(a, b, int(l)) for (a, b), l in zip(edges, el)], sem, name)
+
+
+def random_queries(n, seed=7, n_vlabels=16, n_elabels=32, s=1.2, sem=ISO):
+    rng = _rng(seed + 1000)
+    return [random_shape_query(rng, n_vlabels, n_elabels, s, sem) for _ in range(n)]
+
+
+def log_uniform_sizes(rng, total, lo=1000, hi=262144):
+    """Batch sizes floor(exp U(ln lo, ln hi)) until `total` edges are used."""
+    sizes = []
+    used = 0
+    while used < total:
+        b = int(np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        b = min(b, total - used)
+        sizes.append(b)
+        used += b
+    return sizes
+
+
+def queries_from_json(entries, sem=ISO):
+    """Query dicts from a list of {"name", "n_qv", "vreq", "edges": [[src, dst, label], ...]}."""
+    return [make_query(e["n_qv"], e["vreq"], e["edges"], sem, e.get("name", "")) for e in entries]
+
+
+def multiquery_case(scale=20, n_init=1 << 24, n_stream=1 << 23, n_queries=64, del_frac=0.10, seed=7,
+                    n_vlabels=16, n_elabels=32, s=1.2, multi_p=0.10, lo=1000, hi=262144, max_batches=None,
+                    queries=None):
+    """The R-MAT stream of ``rmat_case`` (same seed, same edges) cut into
+    log-uniform batches, with ``n_queries`` random queries (or the given
+    ``queries``)."""
+    base = rmat_case(scale=scale, n_init=n_init, n_stream=n_stream, batch=min(65536, n_stream),
+                     del_frac=0.0, seed=seed, n_vlabels=n_vlabels, n_elabels=n_elabels, s=s,
+                     multi_p=multi_p, sems=(ISO,))
+    g = base["graph"]
+    src = np.concatenate([g["src"]] + [b["src"] for b in base["batches"]])
+    dst = np.concatenate([g["dst"]] + [b["dst"] for b in base["batches"]])
+    lab = np.concatenate([g["elabel"]] + [b["elabel"] for b in base["batches"]])
+    rng = _rng(seed + 2000)
+    sizes = log_uniform_sizes(rng, len(src) - n_init, lo, hi)
+    if max_batches is not None:
+        sizes = sizes[:max_batches]
+    graph, batches = split_stream(g["n_vertices"], g["vlabel_mask"], src, dst, lab, n_init, sizes,
+                                  del_frac=del_frac)
+    if queries is None:
+        queries = random_queries(n_queries, seed, n_vlabels, n_elabels, s, ISO)
+    return {"name": "rmat_s%d_m%d_logbatch_%dq" % (scale, n_init, len(queries)), "graph": graph,
+            "batches": batches, "queries": queries}
+

@@ -148,6 +148,14 @@ def test_rmat_ragged_batches_and_wide_labels(B):
     assert run_parity(B, case) > 0
 
 
+def test_multiquery_random_shapes(B):
+    # 64 random trees, cycles and 4-clique cores of 3..8 vertices over one
+    # stream cut into log-uniform batches: every query's rows share the same
+    # level launches
+    case = synth.multiquery_case(scale=11, n_init=20000, n_stream=24000, n_queries=64, lo=100, hi=8000)
+    assert run_parity(B, case, out_capacity=1 << 12) > 0
+
+
 def test_output_overflow_regrows_and_reruns(B):
     case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
     assert run_parity(B, case, out_capacity=1) > 0
