@@ -202,12 +202,13 @@ struct mnemonic_ctx {
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_phase;
     uint32_t ev_used = 0;
-    uint64_t last_k = 1ull << 24;  // candidates one last-level expansion may take (sizes d_tiles)
+    uint64_t cand_k = 1ull << 24;  // candidates one device-sized expansion may take (sizes d_tiles)
     // observed rates per inserted/deleted slot of the last batches: start rows
     // (index MN_MAXLV) and candidates per level; negative = not seen yet. They
     // size grids and buffers for the next batch, whatever its size.
     double rate[2][MN_MAXLV + 1];
     uint64_t chunk_ns[2] = {1, 1};  // slots of the largest start chunk of the last run of each phase
+    uint64_t cover[2][MN_MAXLV];    // candidates each level's launch covered in the last device-sized run
     uint32_t tile_items = 2;       // expansion tile = 256 x tile_items candidates
     // autotuning of tile_items: trial batches per setting, time and candidates
     static constexpr uint32_t TUNE_TRIALS = 2;
@@ -245,11 +246,16 @@ struct mnemonic_ctx {
     uint32_t zr_count(int p) const { return 4u + (uint32_t)p * n_q; }
     uint32_t zr_digest(int p) const { return 4u + 2u * n_q + (uint32_t)p * MN_SHARDS * 2u * n_q; }
     uint32_t zr_stats(int p) const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + (uint32_t)p * MN_SHARDS * 8u; }
-    // per phase and level: [candidates exceeded the next buffer, largest
-    // candidate total]; slot MN_MAXLV: [start rows exceeded their buffer, largest count]
+    // Overflow notes of the device-sized levels, per phase, four words per
+    // level L: [candidates exceeded the launch, largest candidate total, rows
+    // of level L + 1 exceeded their buffer, largest row count]; after the
+    // levels: [start rows exceeded their buffer, largest count, -, -].
     uint32_t zr_note(int p) const {
-        return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS + (uint32_t)p * 2u * (MN_MAXLV + 1);
+        return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS + (uint32_t)p * 4u * (MN_MAXLV + 1);
     }
+    uint32_t note_cand(int p, uint32_t L) const { return zr_note(p) + 4u * L; }
+    uint32_t note_rows(int p, uint32_t L) const { return zr_note(p) + 4u * L + 2u; }
+    uint32_t note_seed(int p) const { return zr_note(p) + 4u * MN_MAXLV; }
     uint32_t zr_words() const { return zr_note(2); }
     // shard sums of the last readback: digests [p][q][2], tallies [p][8]
     std::vector<uint64_t> sum_dig;
@@ -750,7 +756,7 @@ void reset_phase(mnemonic_ctx* c, int p) {
     mn_launch_reset(c->d_err, c->d_zr + c->zr_count(p), c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), MN_SHARDS * 2 * c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), MN_SHARDS * 8, s);
-    mn_launch_reset(c->d_err, c->d_zr + c->zr_note(p), 2 * (MN_MAXLV + 1), s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_note(p), 4 * (MN_MAXLV + 1), s);
 }
 
 // Grows level L's buffers to hold `need` rows (contents are not kept: a
@@ -885,9 +891,7 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
     const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
     // every level takes some candidates, so that an overflow always leaves a note
     for (uint32_t L = 1; L < c->max_levels; L++) grow_level(c, L, 1ull << 16);
-    uint64_t kmax = c->last_k;
-    for (uint32_t L = 1; L < c->max_levels; L++) kmax = std::max<uint64_t>(kmax, c->lvb[L].cap);
-    const uint64_t need_tiles = mn_expand_tiles(0, kmax) + 1;
+    const uint64_t need_tiles = mn_expand_tiles(0, c->cand_k) + 1;
     if (need_tiles > c->cap_tiles) {
         HIPCHK(hipStreamSynchronize(s));
         dev_free(c->d_tiles);
@@ -902,10 +906,12 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         mn_launch_level_range(g, rows_view(c, L), (uint32_t)n_max, n_dev, L, B.lo, B.cnt, po.stats, c->d_err, s);
         mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n_max, c->d_scan64, c->d_total, s, n_dev);
         const bool next = L + 1 < c->max_levels;
-        const uint64_t K = next ? c->lvb[L + 1].cap : c->last_k;
+        // candidates are bounded by the tile buffer and the grid only; rows
+        // past the next level's buffer are counted and noted
+        const uint64_t K = c->cand_k;
         uint32_t* n_out = c->d_nrows + L + 1;
         if (next) mn_launch_set_u32(n_out, 0, s);
-        unsigned long long* note = c->d_zr + c->zr_note(po.phase) + 2 * L;
+        unsigned long long* note = c->d_zr + c->note_cand(po.phase, L);
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (timing) {
             ev = event_pair(c, po.phase);
@@ -913,12 +919,16 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         }
         const double rt = c->rate[po.phase][L];
         const uint64_t expect = rt < 0 ? (~0ull >> 8) : (uint64_t)(rt * (double)ns) + 1;
-        mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, c->d_tiles, 0, K, c->d_total, note,
-                         expect, c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
-                         rows_view(c, L + 1), n_out, po, c->d_err, s);
+        c->cover[po.phase][L] =
+            mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, c->d_tiles, 0, K, c->d_total, note,
+                             expect, c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
+                             rows_view(c, L + 1), n_out, po, c->d_err, s);
         if (timing) HIPCHK(hipEventRecord(ev.second, s));
         c->n_expand[po.phase]++;
-        n_max = K;
+        if (next) {
+            mn_launch_note_count(n_out, c->lvb[L + 1].cap, c->d_zr + c->note_rows(po.phase, L), s);
+            n_max = c->lvb[L + 1].cap;
+        }
     }
 }
 
@@ -949,7 +959,7 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
             mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_plans, c->max_close, rows_view(c, 0), c->d_nrows,
                                 po, c->d_err, s);
             if (c->max_levels == 0) continue;
-            mn_launch_note_count(c->d_nrows, c->lvb[0].cap, c->d_zr + c->zr_note(p) + 2 * MN_MAXLV, s);
+            mn_launch_note_count(c->d_nrows, c->lvb[0].cap, c->d_zr + c->note_seed(p), s);
             if (host_chunks) {
                 const uint64_t n0 = read_u32(c, c->d_nrows);
                 process_level(c, g, po, 0, n0);
@@ -965,31 +975,44 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
 // Returns true when the phase must run again; host_chunks is set when a level
 // needs more rows than one buffer may hold.
 bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks) {
-    const unsigned long long* note = c->h_zr.data() + c->zr_note(p);
+    const unsigned long long* z = c->h_zr.data();
     bool again = false;
     const double ns = (double)std::max<uint64_t>(1, c->chunk_ns[p]);
-    if (note[2 * MN_MAXLV]) {  // start rows past their buffer
+    // A stage that was cut short fed only part of its output to the levels
+    // below: their totals are scaled by the parts left out (cut), so that one
+    // re-run sizes every level.
+    double cut = 1.0;
+    auto grow_rows = [&](uint32_t L, uint64_t need) {  // rows of level L
+        if (need > c->rows_max)
+            host_chunks = true;
+        else if (need > c->lvb[L].cap)
+            grow_level(c, L, std::max<uint64_t>(need + need / 4, 2 * c->lvb[L].cap));
+    };
+    const unsigned long long* ns0 = z + c->note_seed(p);
+    if (ns0[0]) {  // start rows past their buffer
         again = true;
-        const uint64_t n0 = note[2 * MN_MAXLV + 1];
-        c->rate[p][MN_MAXLV] = std::max<double>(c->rate[p][MN_MAXLV], (double)n0 / ns);
-        if (n0 > c->rows_max) host_chunks = true;
+        c->rate[p][MN_MAXLV] = std::max<double>(c->rate[p][MN_MAXLV], (double)ns0[1] / ns);
+        if (c->max_levels && c->lvb[0].cap) cut = std::max<double>(1.0, (double)ns0[1] / (double)c->lvb[0].cap);
+        grow_rows(0, ns0[1]);
     }
     for (uint32_t L = 0; L < c->max_levels; L++) {
-        if (!note[2 * L]) continue;
-        again = true;
-        // the level had more candidates than its grid or the next level's
-        // rows cover. Levels after a truncated one saw truncated input, so
-        // their totals are lower bounds: grow at least geometrically and let
-        // the next attempt reveal the rest.
-        const uint64_t T = note[2 * L + 1];
-        c->rate[p][L] = std::max<double>(c->rate[p][L], (double)T / ns);
-        if (L + 1 < c->max_levels) {
-            if (T > c->rows_max)
-                host_chunks = true;
-            else if (T > c->lvb[L + 1].cap)
-                grow_level(c, L + 1, std::max<uint64_t>(T + T / 4, 2 * c->lvb[L + 1].cap));
-        } else if (T > c->last_k) {
-            c->last_k = std::max<uint64_t>(T + T / 4, 2 * c->last_k);
+        const unsigned long long* nc = z + c->note_cand(p, L);
+        const unsigned long long* nr = z + c->note_rows(p, L);
+        if (!nc[1]) continue;
+        const double T_est = (double)nc[1] * cut;
+        if (nc[0] || cut > 1.0) c->rate[p][L] = std::max<double>(c->rate[p][L], T_est / ns);
+        if (nc[0]) {  // more candidates than the launch covered
+            again = true;
+            if (c->cover[p][L] > 0) cut *= std::max<double>(1.0, (double)nc[1] / (double)c->cover[p][L]);
+            if ((uint64_t)T_est > c->cand_k) c->cand_k = std::max<uint64_t>((uint64_t)T_est + (uint64_t)T_est / 4, 2 * c->cand_k);
+        }
+        if (L + 1 < c->max_levels && nr[1]) {
+            const double R_est = (double)nr[1] * cut;
+            if (nr[0] || cut > 1.0) grow_rows(L + 1, (uint64_t)R_est);
+            if (nr[0]) {  // rows past the next level's buffer
+                again = true;
+                cut *= std::max<double>(1.0, (double)nr[1] / (double)std::max<uint64_t>(1, c->lvb[L + 1].cap));
+            }
         }
     }
     return again;
@@ -1232,8 +1255,11 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             const double ns = (double)std::max<uint64_t>(1, c->chunk_ns[p]);
             for (uint32_t L = 0; L <= MN_MAXLV; L++) {
                 if (L < MN_MAXLV && L >= c->max_levels) continue;
-                const uint64_t T = c->h_zr[c->zr_note(p) + 2 * L + 1];
-                if (T) c->rate[p][L] = (double)T / ns;
+                // the largest rate seen: batch sizes and hub hits vary, an
+                // estimate that falls short costs a re-run of the phase, and a
+                // generous one only idle blocks
+                const uint64_t T = c->h_zr[L < MN_MAXLV ? c->note_cand(p, L) + 1 : c->note_seed(p) + 1];
+                if (T) c->rate[p][L] = std::max<double>((double)T / ns, c->rate[p][L]);
             }
         }
         // stats

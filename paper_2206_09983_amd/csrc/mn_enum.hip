@@ -774,9 +774,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                     if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end)
                         wcol(out, 1 + out.wv + P->close[c].qe, dst, st[c]);
                 K.rows++;
-            } else {
-                set_err(err, MN_ERR_INTERNAL);  // the host bounds every chunk by the row capacity
-            }
+            }  // rows past the buffer are counted, not written: the host grows it and runs again
         }
         if (EMIT) {
             uint64_t dA = 0, dB = 0;
@@ -865,12 +863,12 @@ void launch_expand_items(uint32_t max_close, bool rows, bool emit, dim3 grid, hi
     }
 }
 
-void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
-                      const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
-                      unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
-                      bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
-                      hipStream_t s) {
-    if (c1 <= c0 || !n_in) return;
+uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
+                          const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
+                          unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
+                          bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
+                          hipStream_t s) {
+    if (c1 <= c0 || !n_in) return c1;
     if (items != 1 && items != 4) items = 2;
     const uint32_t tile = MN_BLOCK * items;
     // With the total on the device, the grid follows the expected candidate
@@ -889,4 +887,5 @@ void mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint
         launch_expand_items<4>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
     else
         launch_expand_items<2>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
+    return c1;
 }
