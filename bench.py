@@ -26,6 +26,11 @@ tile on the warm-up batches.
 
 Prints ONE JSON line. ``value`` = stream edges (insertions + deletions) fully
 processed per second; embeddings/s and p50/p99 batch latency ride along.
+With the committed order-cost network present, the same batches are also
+timed under the learned scheduler (a fresh context; every start row takes
+the matching order the network predicts cheapest) and ``learned_vs_plain``
+is its throughput over the static order's, after checking that both give
+identical counts and digests for every batch and query.
 ``roofline`` reports the expansion kernel's (k_expand, the enumerator's
 dominant kernel) algorithmic bytes per launch divided by its average launch
 time (HIP events the library records around each launch on its stream),
@@ -79,6 +84,10 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="let the library choose its expansion tile")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
+    ap.add_argument("--scheduler", choices=("both", "static", "learned"), default="both",
+                    help="both: the line reports the static order and times the learned scheduler on the same "
+                         "batches for learned_vs_plain; static or learned: time that one only")
+    ap.add_argument("--weights", default=None, help="order-cost network (default: the committed weights)")
     return ap.parse_args()
 
 
@@ -202,53 +211,81 @@ def main():
     flags = binding.F_TIMING | (0 if args.count_only else binding.F_EMIT) | (binding.F_AUTOTUNE if args.autotune else 0)
     if args.workload == "multiquery":
         args.out_capacity = min(args.out_capacity, 1 << 16)  # 64 queries: buffers grow on demand
-    t0 = time.perf_counter()
-    m = binding.Matcher(case["graph"], case["queries"], flags=flags, out_capacity=args.out_capacity,
-                        stream=stream.cuda_stream, n_elabels=32)
-    torch.cuda.synchronize()
-    log("create (upload + sort + index of %d edges): %.2f s" % (len(case["graph"]["src"]), time.perf_counter() - t0))
+    weights = None
+    if args.scheduler != "static":
+        from paper_2206_09983_amd import sched
+        try:
+            weights = sched.load_weights(args.weights)
+        except FileNotFoundError:
+            if args.scheduler == "learned":
+                raise
+            log("no order-cost network weights found: timing the static order only")
+            args.scheduler = "static"
 
-    for i in range(args.warmup):
-        m.apply_batch(dev_batches[i])
-        st = m.stats()
-        log("warmup %d: %d insertions, %.2f ms, tuples %s, tile %d" % (
-            i, len(case["batches"][i]["src"]), st["ms_batch"], st["tuples"], st["expand_tile"]))
+    def run(mode, tag):
+        """Warm-up, then the timed steps, under one scheduler mode."""
+        t0 = time.perf_counter()
+        m = binding.Matcher(case["graph"], case["queries"], flags=flags, out_capacity=args.out_capacity,
+                            stream=stream.cuda_stream, n_elabels=32)
+        m.set_scheduler(mode, weights if mode == binding.SCHED_LEARNED else None)
+        torch.cuda.synchronize()
+        log("[%s] create (upload + sort + index of %d edges): %.2f s" % (
+            tag, len(case["graph"]["src"]), time.perf_counter() - t0))
+        for i in range(args.warmup):
+            m.apply_batch(dev_batches[i])
+            st = m.stats()
+            log("[%s] warmup %d: %d insertions, %.2f ms, tuples %s, tile %d" % (
+                tag, i, len(case["batches"][i]["src"]), st["ms_batch"], st["tuples"], st["expand_tile"]))
+        r = {"lat": [], "tot": {k: 0 for k in BYTES}, "expand_ms": 0.0, "launches": 0, "rows": 0, "tuples": 0,
+             "edges": 0, "results": []}
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for i in range(args.warmup, n_batches):
+            tb = time.perf_counter()
+            m.apply_batch(dev_batches[i])  # returns once the batch's counts and digests are on the host
+            r["lat"].append((time.perf_counter() - tb) * 1e3)
+            st = m.stats()
+            for p in range(2):
+                r["launches"] += st["expand_launches"][p]
+                r["expand_ms"] += st["ms_expand"][p]
+                r["rows"] += st["frontier_rows"][p]
+                for k in BYTES:
+                    r["tot"][k] += st[k][p]
+            r["tuples"] += st["tuples"][0] + st["tuples"][1]
+            r["edges"] += len(case["batches"][i]["src"]) + len(case["batches"][i]["del_keys"])
+            res = [m.result(q) for q in range(len(case["queries"]))]
+            r["results"].append([(x["n_new"], x["dig_new"], x["n_expired"], x["dig_expired"]) for x in res])
+            log("[%s] step %d: %.2f ms (enumerate %.2f + %.2f ms, of which k_expand %.2f + %.2f ms in %s launches), "
+                "seeds %s, rows %s, candidates %s, tuples %s" % (
+                    tag, i, r["lat"][-1], st["ms_enumerate"][0], st["ms_enumerate"][1], st["ms_expand"][0],
+                    st["ms_expand"][1], st["expand_launches"], st["seeds"], st["frontier_rows"],
+                    st["entries_scanned"], st["tuples"]))
+        torch.cuda.synchronize()
+        r["elapsed"] = time.perf_counter() - t_start
+        r["tile"] = m.stats()["expand_tile"]
+        m.close()
+        return r
 
-    lat = []
-    keys = list(BYTES)
-    tot = {k: 0 for k in keys}
-    expand_ms = 0.0
-    launches = 0
-    rows = 0
-    tuples = 0
-    edges = 0
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.warmup, n_batches):
-        tb = time.perf_counter()
-        m.apply_batch(dev_batches[i])  # returns once the batch's counts and digests are on the host
-        lat.append((time.perf_counter() - tb) * 1e3)
-        st = m.stats()
-        for p in range(2):
-            launches += st["expand_launches"][p]
-            expand_ms += st["ms_expand"][p]
-            rows += st["frontier_rows"][p]
-            for k in keys:
-                tot[k] += st[k][p]
-        tuples += st["tuples"][0] + st["tuples"][1]
-        edges += len(case["batches"][i]["src"]) + len(case["batches"][i]["del_keys"])
-        log("step %d: %.2f ms (enumerate %.2f + %.2f ms, of which k_expand %.2f + %.2f ms in %s launches), "
-            "seeds %s, rows %s, candidates %s, tuples %s" % (
-                i, lat[-1], st["ms_enumerate"][0], st["ms_enumerate"][1], st["ms_expand"][0], st["ms_expand"][1],
-                st["expand_launches"], st["seeds"], st["frontier_rows"], st["entries_scanned"], st["tuples"]))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    m_tile = m.stats()["expand_tile"]
-    m.close()
+    main_mode = binding.SCHED_LEARNED if args.scheduler == "learned" else binding.SCHED_STATIC
+    R = run(main_mode, args.scheduler if args.scheduler != "both" else "static")
+    lat, tot, expand_ms, launches = R["lat"], R["tot"], R["expand_ms"], R["launches"]
+    rows, tuples, edges, elapsed, m_tile = R["rows"], R["tuples"], R["edges"], R["elapsed"], R["tile"]
+    learned = None
+    if args.scheduler == "both":
+        L = run(binding.SCHED_LEARNED, "learned")
+        learned = {"value": L["edges"] / L["elapsed"], "ms_per_step": L["elapsed"] * 1e3 / args.steps,
+                   "ratio": (L["edges"] / L["elapsed"]) / (edges / elapsed),
+                   "identical_results": L["results"] == R["results"],
+                   "candidates": L["tot"]["entries_scanned"], "candidates_static": tot["entries_scanned"],
+                   "p99_batch_ms": sorted(L["lat"])[min(len(L["lat"]) - 1, int(np.ceil(0.99 * len(L["lat"]))) - 1)]}
+        log("learned scheduler: %.3f ms per step vs %.3f (x%.3f), identical results: %s" % (
+            learned["ms_per_step"], elapsed * 1e3 / args.steps, learned["ratio"], learned["identical_results"]))
+        if not learned["identical_results"]:
+            raise SystemExit("the learned scheduler changed the results")
 
     if args.count_only:
         tot["tuple_words"] = 0
-    alg_bytes = sum(BYTES[k] * tot[k] for k in keys)
+    alg_bytes = sum(BYTES[k] * tot[k] for k in BYTES)
     per_launch = alg_bytes / max(launches, 1)
     avg_ms = expand_ms / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -288,7 +325,9 @@ def main():
         "embeddings_per_s": tuples / elapsed,
         "p50_batch_ms": pct(50),
         "p99_batch_ms": pct(99),
-        "learned_vs_plain": None,
+        "scheduler": args.scheduler if args.scheduler != "both" else "static",
+        "learned_vs_plain": learned["ratio"] if learned else None,
+        "learned": learned,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

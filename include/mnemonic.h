@@ -216,6 +216,77 @@ int mnemonic_get_stats(mnemonic_ctx *ctx, mnemonic_stats *out);
  * a failed mnemonic_create on this thread. */
 const char *mnemonic_last_error(const mnemonic_ctx *ctx);
 
+/* ------------------------------------------------------------- scheduler
+ * Matching orders. Section VI computes one matching order per start position
+ * of a query (the order in which the remaining query vertices are bound). The
+ * library keeps up to four orders per (query, start position): the static one
+ * (most connections to the bound vertices first, lowest index on ties,
+ * labelled anchor edges first) and the distinct ones among three variants
+ * (highest index on ties and/or the highest-index anchor edge). Every order
+ * finds the same embeddings; they differ in the work done. The scheduler picks
+ * one order per start row (one batch edge at one start position): */
+#define MNEMONIC_SCHED_STATIC 0  /* always the static order (the default) */
+#define MNEMONIC_SCHED_LEARNED 1 /* the order the cost network predicts cheapest */
+#define MNEMONIC_SCHED_FIXED 2   /* MNEMONIC_SCHED_FIXED + v: always order v (v < 4; the static
+                                    order where a pair has fewer orders) */
+
+/* Order-cost network: 24 features -> 64 -> 64 -> 1 with ReLU, predicting
+ * log2(1 + search work below a start row) under one order. Weights are 5,825
+ * fp32 values: W1[24][64], b1[64], W2[64][64], b2[64], W3[64], b3 (row-major,
+ * y = relu(relu(x W1 + b1) W2 + b2) W3 + b3). */
+#define MNEMONIC_MLP_IN 24
+#define MNEMONIC_MLP_HIDDEN 64
+#define MNEMONIC_MLP_WEIGHTS 5825
+#define MNEMONIC_MAX_ORDERS 4
+
+/* Sets the scheduler mode for the following batches. weights: host array of
+ * MNEMONIC_MLP_WEIGHTS fp32, required for MNEMONIC_SCHED_LEARNED (copied and
+ * rounded to bf16 on the device; the caller keeps ownership), ignored
+ * otherwise (NULL allowed). Errors: ARG (bad ctx or mode, or LEARNED without
+ * weights), OOM, HIP. */
+int mnemonic_set_scheduler(mnemonic_ctx *ctx, int mode, const float *weights);
+
+/* Number of orders (1..4) of start position j of query `query`.
+ * Errors: ARG. */
+int mnemonic_query_orders(mnemonic_ctx *ctx, uint32_t query, uint32_t j, uint32_t *n_orders);
+
+/* Start-row traces. capacity > 0 makes the following batches record, per
+ * phase, up to `capacity` start rows that continue past the start level:
+ * their identity, the features of each order of their pair, and the search
+ * work below them under the order they took (1 + candidates examined at all
+ * levels). capacity = 0 turns tracing off. Tracing adds one column to the
+ * rows between levels and costs time; results are unchanged.
+ * Errors: ARG, OOM, HIP. */
+int mnemonic_set_trace(mnemonic_ctx *ctx, uint64_t capacity);
+
+/* Copies the last batch's trace of one phase (0 new, 1 expired) to host
+ * memory. *n receives the number of entries recorded (min(rows, capacity));
+ * codes[i] = phase << 62 | order << 56 | static plan << 32 | index of the
+ * start edge in the phase's edge list (insertions: batch order; deletions:
+ * del_keys order); x[i][v][f]: feature f of order v (zeros past the pair's
+ * orders), MNEMONIC_MAX_ORDERS x MNEMONIC_MLP_IN floats per entry;
+ * work[i]: the search work. Entries come in no particular order. Any of
+ * codes, x, work may be NULL; cap bounds the entries copied.
+ * Errors: ARG (bad ctx or phase, tracing off), HIP. */
+int mnemonic_get_trace(mnemonic_ctx *ctx, int phase, uint64_t *n, uint64_t *codes, float *x, uint64_t *work,
+                       uint64_t cap);
+
+/* Training and inference kernels of the order-cost network, on caller-owned
+ * device memory (fp32), on hip_stream (NULL: default stream). No context.
+ *   predict: y[i] = net(x[i]) for n samples of MNEMONIC_MLP_IN floats; bf16 != 0
+ *     rounds weights and inputs to bfloat16 first (sums stay fp32).
+ *   grad: adds to grad[MNEMONIC_MLP_WEIGHTS] the gradient of
+ *     L = mean over t < m of (net(x[k]) - target[k])^2, k = idx[off + t]
+ *     (idx NULL: k = off + t), and adds L to *loss. grad and loss accumulate.
+ *   adam: one Adam step (Kingma and Ba, 2015; beta1 0.9, beta2 0.999,
+ *     eps 1e-8, step >= 1 for bias correction) on w with moments m1, m2, then
+ *     zeroes grad.
+ * Launches are asynchronous; errors of the launch itself return HIP. */
+int mnemonic_mlp_predict(const float *w, const float *x, uint64_t n, int bf16, float *y, void *hip_stream);
+int mnemonic_mlp_grad(const float *w, const float *x, const float *target, const uint32_t *idx, uint64_t off,
+                      uint64_t m, float *grad, float *loss, void *hip_stream);
+int mnemonic_mlp_adam(float *w, float *m1, float *m2, float *grad, float lr, uint32_t step, void *hip_stream);
+
 /* Frees every device and host buffer of the context. NULL is ignored. */
 void mnemonic_destroy(mnemonic_ctx *ctx);
 

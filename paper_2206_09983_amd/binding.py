@@ -19,6 +19,13 @@ HOMO = 1
 F_EMIT = 1
 F_TIMING = 2
 F_AUTOTUNE = 4
+SCHED_STATIC = 0
+SCHED_LEARNED = 1
+SCHED_FIXED = 2
+MLP_IN = 24
+MLP_HIDDEN = 64
+MLP_WEIGHTS = 5825
+MAX_ORDERS = 4
 
 ERRORS = {
     -1: "MNEMONIC_E_ARG", -2: "MNEMONIC_E_QUERY", -3: "MNEMONIC_E_VERTEX", -4: "MNEMONIC_E_LABEL",
@@ -26,7 +33,9 @@ ERRORS = {
     -8: "MNEMONIC_E_CAPACITY", -9: "MNEMONIC_E_HIP", -10: "MNEMONIC_E_LIMIT",
 }
 EXPORTS = ["mnemonic_create", "mnemonic_apply_batch", "mnemonic_get_result", "mnemonic_copy_keys",
-           "mnemonic_get_stats", "mnemonic_last_error", "mnemonic_destroy"]
+           "mnemonic_get_stats", "mnemonic_last_error", "mnemonic_destroy", "mnemonic_set_scheduler",
+           "mnemonic_query_orders", "mnemonic_set_trace", "mnemonic_get_trace", "mnemonic_mlp_predict",
+           "mnemonic_mlp_grad", "mnemonic_mlp_adam"]
 
 _u8p = C.POINTER(C.c_uint8)
 _u32p = C.POINTER(C.c_uint32)
@@ -112,6 +121,21 @@ def load():
     L.mnemonic_last_error.argtypes = [vp]
     L.mnemonic_destroy.restype = None
     L.mnemonic_destroy.argtypes = [vp]
+    fp = C.POINTER(C.c_float)
+    L.mnemonic_set_scheduler.restype = C.c_int
+    L.mnemonic_set_scheduler.argtypes = [vp, C.c_int, fp]
+    L.mnemonic_query_orders.restype = C.c_int
+    L.mnemonic_query_orders.argtypes = [vp, C.c_uint32, C.c_uint32, _u32p]
+    L.mnemonic_set_trace.restype = C.c_int
+    L.mnemonic_set_trace.argtypes = [vp, C.c_uint64]
+    L.mnemonic_get_trace.restype = C.c_int
+    L.mnemonic_get_trace.argtypes = [vp, C.c_int, _u64p, _u64p, fp, _u64p, C.c_uint64]
+    L.mnemonic_mlp_predict.restype = C.c_int
+    L.mnemonic_mlp_predict.argtypes = [vp, vp, C.c_uint64, C.c_int, vp, vp]
+    L.mnemonic_mlp_grad.restype = C.c_int
+    L.mnemonic_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_uint64, C.c_uint64, vp, vp, vp]
+    L.mnemonic_mlp_adam.restype = C.c_int
+    L.mnemonic_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_float, C.c_uint32, vp]
     _LIB = L
     return L
 
@@ -232,6 +256,67 @@ def mnemonic_destroy(ctx):
         load().mnemonic_destroy(ctx)
 
 
+def mnemonic_set_scheduler(ctx, mode, weights=None):
+    """mode: SCHED_STATIC, SCHED_LEARNED (weights: 5,825 floats) or SCHED_FIXED + v."""
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    if w is not None and w.size != MLP_WEIGHTS:
+        raise ValueError("the network has %d weights" % MLP_WEIGHTS)
+    _check(load().mnemonic_set_scheduler(ctx, int(mode), _ptr(w, C.c_float)), ctx)
+
+
+def mnemonic_query_orders(ctx, query, j):
+    n = C.c_uint32(0)
+    _check(load().mnemonic_query_orders(ctx, int(query), int(j), C.byref(n)), ctx)
+    return int(n.value)
+
+
+def mnemonic_set_trace(ctx, capacity):
+    _check(load().mnemonic_set_trace(ctx, int(capacity)), ctx)
+
+
+def mnemonic_get_trace(ctx, phase, with_x=True):
+    """Last batch's trace of one phase: codes (n,), x (n, 4, 24) float32 (None
+    unless with_x), work (n,)."""
+    L = load()
+    n = C.c_uint64(0)
+    _check(L.mnemonic_get_trace(ctx, int(phase), C.byref(n), None, None, None, 0), ctx)
+    m = int(n.value)
+    codes = np.zeros(m, dtype=np.uint64)
+    x = np.zeros((m, MAX_ORDERS, MLP_IN), dtype=np.float32) if with_x else None
+    work = np.zeros(m, dtype=np.uint64)
+    _check(L.mnemonic_get_trace(ctx, int(phase), C.byref(n), _ptr(codes, C.c_uint64), _ptr(x, C.c_float),
+                                _ptr(work, C.c_uint64), m), ctx)
+    return {"codes": codes, "x": x, "work": work}
+
+
+def _dev(t):
+    """Device address of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _mlp_check(rc, what):
+    if rc != 0:
+        raise MnemonicError(rc, what + " launch failed")
+
+
+def mnemonic_mlp_predict(w, x, y, bf16=False, stream=None):
+    """Device tensors: w (5825,), x (n, 24), y (n,) float32."""
+    _mlp_check(load().mnemonic_mlp_predict(_dev(w), _dev(x), int(x.shape[0]), 1 if bf16 else 0, _dev(y), stream),
+               "mnemonic_mlp_predict")
+
+
+def mnemonic_mlp_grad(w, x, target, grad, loss, idx=None, off=0, m=None, stream=None):
+    """Adds the MSE gradient over samples idx[off:off+m] (or off:off+m) to grad and the loss to loss[0]."""
+    m = int(x.shape[0] if m is None else m)
+    _mlp_check(load().mnemonic_mlp_grad(_dev(w), _dev(x), _dev(target), _dev(idx), int(off), m, _dev(grad),
+                                        _dev(loss), stream), "mnemonic_mlp_grad")
+
+
+def mnemonic_mlp_adam(w, m1, m2, grad, lr, step, stream=None):
+    _mlp_check(load().mnemonic_mlp_adam(_dev(w), _dev(m1), _dev(m2), _dev(grad), float(lr), int(step), stream),
+               "mnemonic_mlp_adam")
+
+
 class Matcher:
     """Owns one context: create on construction, destroy on close."""
 
@@ -250,6 +335,18 @@ class Matcher:
 
     def stats(self):
         return mnemonic_get_stats(self.ctx)
+
+    def set_scheduler(self, mode, weights=None):
+        mnemonic_set_scheduler(self.ctx, mode, weights)
+
+    def orders(self, q, j):
+        return mnemonic_query_orders(self.ctx, q, j)
+
+    def set_trace(self, capacity):
+        mnemonic_set_trace(self.ctx, capacity)
+
+    def trace(self, phase, with_x=True):
+        return mnemonic_get_trace(self.ctx, phase, with_x)
 
     def close(self):
         if self.ctx:

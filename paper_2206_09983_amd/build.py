@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmnemonic.so")
-SOURCES = ["mn_sort.hip", "mn_graph.hip", "mn_enum.hip", "mn_api.hip"]
+SOURCES = ["mn_sort.hip", "mn_graph.hip", "mn_enum.hip", "mn_mlp.hip", "mn_api.hip"]
 ARCH = os.environ.get("MNEMONIC_ARCH", "gfx950")
 FLAGS = [
     "--offload-arch=" + ARCH,
@@ -17,7 +17,7 @@ FLAGS = [
     "-fPIC",
     "-Wall",
     "-Wno-unused-function",
-    # packed fp32 instructions stay off (the library has no float math anyway)
+    # no packed fp32 instructions (the order network is plain fp32 code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

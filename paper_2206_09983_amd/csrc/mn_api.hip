@@ -18,6 +18,7 @@
 // superset), and an enumeration can be re-run on exactly the same state when
 // an output buffer was too small.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -98,11 +99,13 @@ struct mnemonic_ctx {
     // number the vertices class by class (cls_start[c] = first id of class c)
     std::vector<uint64_t> cls_mask;
     std::vector<uint32_t> cls_start;
+    // edges per vertex of each edge label in the initial graph ([256]: all labels)
+    std::vector<double> lab_deg;
     uint32_t* d_ext2int = nullptr;
 
     // queries and their preprocessed tables
     uint32_t n_q = 0;
-    uint32_t n_plans = 0, max_levels = 0, wv = 2, we = 1, max_close = 0;
+    uint32_t n_plans = 0, n_static = 0, max_levels = 0, wv = 2, we = 1, max_close = 0;
     uint8_t level_rows[MN_MAXLV] = {0};  // some plan continues past level L
     uint8_t level_emit[MN_MAXLV] = {0};  // some plan ends at level L
     std::vector<QueryDev> hq;
@@ -219,6 +222,22 @@ struct mnemonic_ctx {
     double ms_expand[2] = {0, 0};
     uint64_t n_expand[2] = {0, 0};
 
+    // scheduler: matching-order choice (MN_SCHED_*) and the network's bf16 weights
+    uint32_t sched_mode = MN_SCHED_STATIC;
+    uint16_t* d_sched_w = nullptr;
+    float* d_sched_f32 = nullptr;
+    // start rows whose order the decision kernel settles
+    uint64_t* d_dec = nullptr;
+    uint64_t cap_dec = 0;
+    uint32_t* d_dec_n = nullptr;
+    bool deciding() const { return sched_mode == MN_SCHED_LEARNED || tr_cap != 0; }
+    // traces of the start rows (tr_cap entries per phase, 0: off)
+    uint32_t tr_cap = 0;
+    uint32_t* d_tr_n = nullptr;
+    uint64_t* d_tr_code = nullptr;
+    float* d_tr_x = nullptr;
+    unsigned long long* d_tr_work = nullptr;
+
     // control block: err, last_ts, zeroed counters
     uint32_t* d_err = nullptr;
     int64_t* d_last_ts = nullptr;
@@ -274,7 +293,7 @@ struct mnemonic_ctx {
             }
         }
     }
-    uint32_t ncol() const { return 1 + wv + we; }
+    uint32_t ncol() const { return 1 + wv + we + (tr_cap ? 1 : 0); }
 };
 
 namespace {
@@ -326,7 +345,12 @@ bool filters_trivial(const mnemonic_ctx* c, const QueryDev& Q, uint32_t u, uint3
 // edges to mapped vertices (ties: lowest index) is mapped through one of those
 // edges (a labelled one first, then the lowest index), and its other edges to
 // mapped vertices become closing edges checked at that level.
-void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t j, SeedPlan& P) {
+// variant bit 0: among the vertices with the most connections to the mapped
+// ones, take the highest index instead of the lowest; bit 1: anchor a level
+// at its highest-index connecting edge instead of the lowest (labelled edges
+// first either way). Variant 0 is the static order.
+void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t j, SeedPlan& P, uint32_t variant = 0) {
+    const bool rev_vtx = (variant & 1u) != 0, rev_anchor = (variant & 2u) != 0;
     memset(&P, 0, sizeof(P));
     const uint32_t nqv = Q.n_qv, nqe = Q.n_qe;
     P.q = (uint16_t)qi;
@@ -375,7 +399,7 @@ void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t 
             for (uint32_t k = 0; k < nqe; k++)
                 if (!used[k] && ((Q.qsrc[k] == u && mapped[Q.qdst[k]]) || (Q.qdst[k] == u && mapped[Q.qsrc[k]])))
                     conn++;
-            if (conn > best_conn) {
+            if (conn > best_conn || (rev_vtx && conn == best_conn)) {
                 best_conn = conn;
                 best = (int)u;
             }
@@ -383,7 +407,8 @@ void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t 
         uint32_t n = (uint32_t)best;
         int anchor = -1;
         for (int pass = 0; pass < 2 && anchor < 0; pass++)
-            for (uint32_t k = 0; k < nqe; k++) {
+            for (uint32_t t = 0; t < nqe; t++) {
+                const uint32_t k = rev_anchor ? nqe - 1 - t : t;
                 if (used[k]) continue;
                 bool touches = (Q.qsrc[k] == n && mapped[Q.qdst[k]]) || (Q.qdst[k] == n && mapped[Q.qsrc[k]]);
                 if (touches && (pass == 1 || Q.qlab[k] >= 0)) {
@@ -416,6 +441,11 @@ void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t 
             lv.key_hi = ((uint32_t)Q.qlab[ak] << c->nbr_bits) | (id_hi - 1);
         }
         lv.need_vf = labels_implied ? 0 : 1;  // refined below once the last level is known
+        {  // expected candidates per row: the label's mean degree times the share of the class range
+            const double deg = c->lab_deg.empty() ? 0.0 : c->lab_deg[Q.qlab[ak] >= 0 ? Q.qlab[ak] : 256];
+            const double share = some ? (double)(id_hi - id_lo) / (double)std::max<uint32_t>(1, c->nV) : 0.0;
+            P.lv_est[L] = (float)std::log2(1.0 + deg * share);
+        }
         lv.c_begin = (uint8_t)nc;
         for (uint32_t k = 0; k < nqe; k++) {
             if (used[k]) continue;
@@ -476,6 +506,7 @@ void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
     const uint32_t E = c->n_elab_c, Lc = c->n_vlab_c;
     c->n_cnt = 2 * (1 + E + Lc);
     uint32_t vf_base = 0, debi_base = 0, plan_base = 0;
+    std::vector<std::vector<SeedPlan>> alts;  // per static plan: all of its orders
     for (uint32_t i = 0; i < n_q; i++) {
         const mnemonic_query& q = qs[i];
         QueryDev Q;
@@ -536,22 +567,54 @@ void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
             c->hdebi.push_back(db);
         }
         for (uint32_t j = 0; j < q.n_qe; j++) {
+            // the static order, then the distinct alternatives (kept aside:
+            // they follow every static plan)
             SeedPlan P;
-            build_plan(c, Q, i, j, P);
-            c->max_levels = std::max<uint32_t>(c->max_levels, P.n_levels);
-            c->max_close = std::max<uint32_t>(c->max_close, P.n_close);
-            for (uint32_t L = 0; L < P.n_levels; L++) {
-                if (L + 1 == P.n_levels)
-                    c->level_emit[L] = 1;
-                else
-                    c->level_rows[L] = 1;
+            build_plan(c, Q, i, j, P, 0);
+            P.n_var = 1;
+            P.variant = 0;
+            std::vector<SeedPlan> vs(1, P);
+            for (uint32_t v : {3u, 1u, 2u}) {
+                SeedPlan V;
+                build_plan(c, Q, i, j, V, v);
+                bool dup = false;
+                for (const SeedPlan& W : vs)
+                    dup = dup || (memcmp(W.mapped, V.mapped, sizeof(V.mapped)) == 0 &&
+                                  memcmp(W.lv, V.lv, sizeof(V.lv)) == 0 && memcmp(W.close, V.close, sizeof(V.close)) == 0);
+                if (!dup && vs.size() < MN_NVAR) vs.push_back(V);
             }
-            c->hplans.push_back(P);
+            for (uint32_t v = 0; v < vs.size(); v++) {
+                SeedPlan& V = vs[v];
+                c->max_levels = std::max<uint32_t>(c->max_levels, V.n_levels);
+                c->max_close = std::max<uint32_t>(c->max_close, V.n_close);
+                for (uint32_t L = 0; L < V.n_levels; L++) {
+                    if (L + 1 == V.n_levels)
+                        c->level_emit[L] = 1;
+                    else
+                        c->level_rows[L] = 1;
+                }
+                V.n_var = (uint8_t)vs.size();
+                V.variant = (uint8_t)v;
+            }
+            c->hplans.push_back(vs[0]);
+            alts.push_back(vs);
         }
         vf_base += q.n_qv;
         debi_base += q.n_qe;
         plan_base += q.n_qe;
         c->hq.push_back(Q);
+    }
+    // alternatives after the static plans; every order of a pair lists all of them
+    c->n_static = (uint32_t)c->hplans.size();
+    for (uint32_t sp = 0; sp < c->n_static; sp++) {
+        std::vector<SeedPlan>& vs = alts[sp];
+        uint16_t idx[MN_NVAR] = {0, 0, 0, 0};
+        idx[0] = (uint16_t)sp;
+        for (uint32_t v = 1; v < vs.size(); v++) idx[v] = (uint16_t)(c->hplans.size() + v - 1);
+        if (c->hplans.size() + vs.size() > 65535) throw ApiError{MNEMONIC_E_LIMIT, "too many matching orders"};
+        for (uint32_t v = 0; v < vs.size(); v++) memcpy(vs[v].vars, idx, sizeof(idx));
+        c->hplans[sp] = vs[0];
+        for (uint32_t v = 1; v < vs.size(); v++) c->hplans.push_back(vs[v]);
     }
     c->n_plans = (uint32_t)c->hplans.size();
     for (uint32_t i = 0; i < n_q; i++) {
@@ -604,6 +667,16 @@ GraphView make_view(const mnemonic_ctx* c, bool next) {
     g.ext2int = c->d_ext2int;
     g.n_elab_c = c->n_elab_c;
     g.n_vlab_c = c->n_vlab_c;
+    g.n_static = c->n_static;
+    g.sched_mode = c->sched_mode;
+    g.sched_w = c->d_sched_w;
+    g.dec = c->deciding() ? c->d_dec : nullptr;
+    g.dec_n = c->d_dec_n;
+    g.tr_cap = c->tr_cap;
+    g.tr_n = c->d_tr_n;
+    g.tr_code = c->d_tr_code;
+    g.tr_x = c->d_tr_x;
+    g.tr_work = c->d_tr_work;
     return g;
 }
 
@@ -757,6 +830,7 @@ void reset_phase(mnemonic_ctx* c, int p) {
     mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), MN_SHARDS * 2 * c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), MN_SHARDS * 8, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_note(p), 4 * (MN_MAXLV + 1), s);
+    if (c->tr_cap) mn_launch_set_u32(c->d_tr_n + p, 0, s);
 }
 
 // Grows level L's buffers to hold `need` rows (contents are not kept: a
@@ -791,6 +865,7 @@ RowsView rows_view(const mnemonic_ctx* c, uint32_t L) {
     memset(&R, 0, sizeof(R));
     R.wv = c->wv;
     R.we = c->we;
+    R.trace = c->tr_cap ? 1u : 0u;
     if (L < c->lvb.size()) {
         R.col = c->lvb[L].rows;
         R.kcol = c->lvb[L].keys;
@@ -940,7 +1015,7 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
     hipStream_t s = c->stream;
     const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
     if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], s));
-    if (n_slots && c->n_plans) {
+    if (n_slots && c->n_static) {
         GraphView g = make_view(c, false);
         PhaseOut po = phase_out(c, p);
         // Start rows per slot: the last batches' rate with a margin when known
@@ -948,23 +1023,39 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
         // that was short), else every (slot, plan) pair; host-walked levels
         // keep the worst case.
         const double r0 = c->rate[p][MN_MAXLV];
-        const double per_slot = (host_chunks || r0 < 0) ? (double)c->n_plans : std::min<double>(c->n_plans, 1.5 * r0 + 0.01);
+        const double per_slot = (host_chunks || r0 < 0) ? (double)c->n_static : std::min<double>(c->n_static, 1.5 * r0 + 0.01);
         const uint64_t chunk = std::max<uint64_t>(1, (uint64_t)((double)c->rows_max / per_slot));
         c->chunk_ns[p] = std::min<uint64_t>(chunk, n_slots);
         for (uint64_t s0 = 0; s0 < n_slots; s0 += chunk) {
             const uint64_t ns = std::min<uint64_t>(chunk, n_slots - s0);
             if (c->max_levels)  // else every plan emits at once
                 grow_level(c, 0, std::min<uint64_t>(c->rows_max, (uint64_t)(per_slot * (double)ns) + 1024));
+            const bool decide = c->max_levels && c->deciding();
+            if (decide) {
+                if (c->cap_dec < c->lvb[0].cap) {
+                    HIPCHK(hipStreamSynchronize(s));
+                    dev_free(c->d_dec);
+                    c->cap_dec = 0;
+                    dev_alloc(c->d_dec, c->lvb[0].cap);
+                    c->cap_dec = c->lvb[0].cap;
+                }
+                mn_launch_set_u32(c->d_dec_n, 0, s);
+                g.dec = c->d_dec;
+            }
             mn_launch_set_u32(c->d_nrows, 0, s);
-            mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_plans, c->max_close, rows_view(c, 0), c->d_nrows,
+            g.tr_base = (uint32_t)s0;
+            mn_launch_seed_rows(g, slots + s0, (uint32_t)ns, c->n_static, c->max_close, rows_view(c, 0), c->d_nrows,
                                 po, c->d_err, s);
             if (c->max_levels == 0) continue;
+            if (decide)
+                mn_launch_decide(g, rows_view(c, 0), slots + s0, (uint32_t)c->cap_dec,
+                                 (uint32_t)std::min<double>((double)c->cap_dec, per_slot * (double)ns + 1.0), p, s);
             mn_launch_note_count(c->d_nrows, c->lvb[0].cap, c->d_zr + c->note_seed(p), s);
             if (host_chunks) {
                 const uint64_t n0 = read_u32(c, c->d_nrows);
                 process_level(c, g, po, 0, n0);
             } else {
-                device_levels(c, g, po, ns * c->n_plans, ns);
+                device_levels(c, g, po, ns * c->n_static, ns);
             }
         }
     }
@@ -974,9 +1065,16 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
 // After a device-sized phase: grows what its notes say was too small.
 // Returns true when the phase must run again; host_chunks is set when a level
 // needs more rows than one buffer may hold.
-bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks) {
+bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = nullptr) {
     const unsigned long long* z = c->h_zr.data();
     bool again = false;
+    auto say = [&](const char* what, uint32_t L, uint64_t got, uint64_t room) {
+        if (!why) return;
+        char buf[160];
+        snprintf(buf, sizeof(buf), " [phase %d level %u: %s %llu > %llu]", p, L, what, (unsigned long long)got,
+                 (unsigned long long)room);
+        *why += buf;
+    };
     const double ns = (double)std::max<uint64_t>(1, c->chunk_ns[p]);
     // A stage that was cut short fed only part of its output to the levels
     // below: their totals are scaled by the parts left out (cut), so that one
@@ -991,6 +1089,7 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks) {
     const unsigned long long* ns0 = z + c->note_seed(p);
     if (ns0[0]) {  // start rows past their buffer
         again = true;
+        say("start rows", 0, ns0[1], c->max_levels ? c->lvb[0].cap : 0);
         c->rate[p][MN_MAXLV] = std::max<double>(c->rate[p][MN_MAXLV], (double)ns0[1] / ns);
         if (c->max_levels && c->lvb[0].cap) cut = std::max<double>(1.0, (double)ns0[1] / (double)c->lvb[0].cap);
         grow_rows(0, ns0[1]);
@@ -1003,14 +1102,21 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks) {
         if (nc[0] || cut > 1.0) c->rate[p][L] = std::max<double>(c->rate[p][L], T_est / ns);
         if (nc[0]) {  // more candidates than the launch covered
             again = true;
+            say("candidates", L, nc[1], c->cover[p][L]);
             if (c->cover[p][L] > 0) cut *= std::max<double>(1.0, (double)nc[1] / (double)c->cover[p][L]);
-            if ((uint64_t)T_est > c->cand_k) c->cand_k = std::max<uint64_t>((uint64_t)T_est + (uint64_t)T_est / 4, 2 * c->cand_k);
+            // past what one device-sized launch can cover, the levels are walked in host chunks
+            const uint64_t most = MN_EXPAND_MAX_BLOCKS * MN_BLOCK * c->tile_items;
+            if ((uint64_t)T_est > most / 2)
+                host_chunks = true;
+            else if ((uint64_t)T_est > c->cand_k)
+                c->cand_k = std::min<uint64_t>(most, std::max<uint64_t>((uint64_t)T_est + (uint64_t)T_est / 4, 2 * c->cand_k));
         }
         if (L + 1 < c->max_levels && nr[1]) {
             const double R_est = (double)nr[1] * cut;
             if (nr[0] || cut > 1.0) grow_rows(L + 1, (uint64_t)R_est);
             if (nr[0]) {  // rows past the next level's buffer
                 again = true;
+                say("rows", L + 1, nr[1], c->lvb[L + 1].cap);
                 cut *= std::max<double>(1.0, (double)nr[1] / (double)std::max<uint64_t>(1, c->lvb[L + 1].cap));
             }
         }
@@ -1095,6 +1201,10 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
 
     GraphView g0 = make_view(c, false);
     mn_launch_reset(c->d_err, c->d_zr, c->n_zr, s);
+    if (c->tr_cap) {  // the trace holds this batch's start rows only
+        mn_launch_set_u32(c->d_tr_n, 0, s);
+        mn_launch_set_u32(c->d_tr_n + 1, 0, s);
+    }
     mn_launch_validate(g0, b, s);
     mn_launch_prev_del(g0, b, s);
     mn_launch_ingest(g0, b, s);
@@ -1199,18 +1309,33 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         // phase being re-run are restored first)
         bool emit = (c->flags & MNEMONIC_F_EMIT) != 0;
         bool host_chunks[2] = {false, false};
-        const int max_attempts = 2 * (int)c->max_levels + 4;
+        // A device-sized run that overflows leaves notes that size the next
+        // one; which rows a truncated level kept depends on atomic order, so
+        // the estimates converge in a few runs but without a fixed bound.
+        // After DEVICE_RUNS of them a phase is walked in host-sized chunks,
+        // which completes in one run; one more run may follow to grow
+        // outputs to the exact counts.
+        constexpr int DEVICE_RUNS = 3;
+        const int max_attempts = DEVICE_RUNS + 3;
         for (int attempt = 0; attempt < max_attempts; attempt++) {
             std::vector<uint64_t> need(2 * c->n_q, 0);
             bool redo[2] = {false, false};
-            for (int p = 0; p < 2; p++) redo[p] = absorb_notes(c, p, host_chunks[p]);
+            std::string why;
+            const bool last = attempt == max_attempts - 1;
+            for (int p = 0; p < 2; p++) {
+                redo[p] = absorb_notes(c, p, host_chunks[p], last ? &why : nullptr);
+                if (redo[p] && attempt + 1 >= DEVICE_RUNS) host_chunks[p] = true;
+            }
             for (uint32_t q = 0; q < c->n_q; q++)
                 for (int p = 0; p < 2; p++) {
                     need[2 * q + p] = c->h_zr[c->zr_count(p) + q];
-                    if (emit && need[2 * q + p] > c->houts[q].cap[p]) redo[p] = true;
+                    if (emit && need[2 * q + p] > c->houts[q].cap[p]) {
+                        redo[p] = true;
+                        if (last) why += " [query " + std::to_string(q) + " output " + std::to_string(need[2 * q + p]) + "]";
+                    }
                 }
             if (!redo[0] && !redo[1]) break;
-            if (attempt == max_attempts - 1) throw ApiError{MNEMONIC_E_HIP, "enumeration did not settle (internal)"};
+            if (last) throw ApiError{MNEMONIC_E_HIP, "enumeration did not settle (internal)" + why};
             grow_outputs(c, need);
             if (redo[0]) {
                 for (int d = 0; d < 2; d++) {
@@ -1390,6 +1515,14 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_nrows);
     dev_free(c->d_total);
     dev_free(c->d_ext2int);
+    dev_free(c->d_sched_w);
+    dev_free(c->d_sched_f32);
+    dev_free(c->d_tr_n);
+    dev_free(c->d_tr_code);
+    dev_free(c->d_tr_x);
+    dev_free(c->d_tr_work);
+    dev_free(c->d_dec);
+    dev_free(c->d_dec_n);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     c->h_ctl = nullptr;
 }
@@ -1440,6 +1573,10 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
             }
         }
         c->cls_start.push_back(c->nV);
+        c->lab_deg.assign(257, 0.0);
+        for (uint64_t e = 0; e < g->n_edges; e++) c->lab_deg[g->elabel[e]] += 1.0;
+        c->lab_deg[256] = (double)g->n_edges;
+        for (double& d : c->lab_deg) d /= (double)c->nV;
         prepare_queries(c, q, n_q);
         for (uint32_t i = 0; i < n_q; i++)
             for (uint32_t k = 0; k < q[i].n_qe; k++)
@@ -1455,6 +1592,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         for (int p = 0; p < 2; p++)
             for (int L = 0; L <= MN_MAXLV; L++) c->rate[p][L] = -1.0;  // unknown: size by capacity
         dev_alloc(c->d_nrows, MN_MAXLV + 2);
+        dev_alloc(c->d_dec_n, 1);
         dev_alloc(c->d_total, 1);
         HIPCHK(hipHostMalloc((void**)&c->h_ctl, 64, hipHostMallocDefault));
         for (auto& e : c->ev_x) HIPCHK(hipEventCreate(&e));
@@ -1574,6 +1712,109 @@ int mnemonic_get_stats(mnemonic_ctx* ctx, mnemonic_stats* out) {
 const char* mnemonic_last_error(const mnemonic_ctx* ctx) {
     if (!ctx) return g_create_error.c_str();
     return ctx->err.c_str();
+}
+
+int mnemonic_set_scheduler(mnemonic_ctx* ctx, int mode, const float* weights) {
+    if (!ctx) return MNEMONIC_E_ARG;
+    return guarded(ctx, [&]() -> int {
+        if (mode < 0 || mode >= MN_SCHED_FIXED + MN_NVAR) throw ApiError{MNEMONIC_E_ARG, "bad scheduler mode"};
+        if (mode == MN_SCHED_LEARNED) {
+            if (!weights) throw ApiError{MNEMONIC_E_ARG, "the learned scheduler needs weights"};
+            if (!ctx->d_sched_w) {
+                dev_alloc(ctx->d_sched_f32, MN_MLP_WEIGHTS);
+                dev_alloc(ctx->d_sched_w, MN_MLP_WEIGHTS);
+            }
+            HIPCHK(hipMemcpyAsync(ctx->d_sched_f32, weights, MN_MLP_WEIGHTS * sizeof(float), hipMemcpyHostToDevice,
+                                  ctx->stream));
+            mn_to_bf16(ctx->d_sched_f32, ctx->d_sched_w, MN_MLP_WEIGHTS, ctx->stream);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        }
+        ctx->sched_mode = (uint32_t)mode;
+        return MNEMONIC_OK;
+    });
+}
+
+int mnemonic_query_orders(mnemonic_ctx* ctx, uint32_t query, uint32_t j, uint32_t* n_orders) {
+    if (!ctx || !n_orders || query >= ctx->n_q || j >= ctx->hq[query].n_qe) return MNEMONIC_E_ARG;
+    *n_orders = ctx->hplans[ctx->hq[query].plan_base + j].n_var;
+    return MNEMONIC_OK;
+}
+
+int mnemonic_set_trace(mnemonic_ctx* ctx, uint64_t capacity) {
+    if (!ctx) return MNEMONIC_E_ARG;
+    return guarded(ctx, [&]() -> int {
+        if (capacity > (1u << 28)) throw ApiError{MNEMONIC_E_ARG, "trace capacity > 2^28"};
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        // the rows between levels gain or lose the trace column: reallocated on demand
+        for (auto& B : ctx->lvb) {
+            dev_free(B.keys);
+            dev_free(B.rows);
+            dev_free(B.lo);
+            dev_free(B.cnt);
+            dev_free(B.off);
+            B.cap = 0;
+        }
+        dev_free(ctx->d_tr_n);
+        dev_free(ctx->d_tr_code);
+        dev_free(ctx->d_tr_x);
+        dev_free(ctx->d_tr_work);
+        ctx->tr_cap = 0;
+        if (capacity) {
+            dev_alloc(ctx->d_tr_n, 2);
+            dev_alloc(ctx->d_tr_code, 2 * capacity);
+            dev_alloc(ctx->d_tr_x, 2 * capacity * MN_NVAR * MN_MLP_IN);
+            dev_alloc(ctx->d_tr_work, 2 * capacity);
+            mn_launch_set_u32(ctx->d_tr_n, 0, ctx->stream);
+            mn_launch_set_u32(ctx->d_tr_n + 1, 0, ctx->stream);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            ctx->tr_cap = (uint32_t)capacity;
+        }
+        return MNEMONIC_OK;
+    });
+}
+
+int mnemonic_get_trace(mnemonic_ctx* ctx, int phase, uint64_t* n, uint64_t* codes, float* x, uint64_t* work,
+                       uint64_t cap) {
+    if (!ctx || (phase != 0 && phase != 1) || !n) return MNEMONIC_E_ARG;
+    return guarded(ctx, [&]() -> int {
+        if (!ctx->tr_cap) throw ApiError{MNEMONIC_E_ARG, "tracing is off"};
+        uint32_t cnt[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(cnt, ctx->d_tr_n, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        const uint64_t m = std::min<uint64_t>(cnt[phase], ctx->tr_cap);
+        *n = m;
+        const uint64_t k = std::min<uint64_t>(m, cap);
+        const size_t base = (size_t)phase * ctx->tr_cap;
+        if (k && codes)
+            HIPCHK(hipMemcpyAsync(codes, ctx->d_tr_code + base, k * 8, hipMemcpyDeviceToHost, ctx->stream));
+        if (k && x)
+            HIPCHK(hipMemcpyAsync(x, ctx->d_tr_x + base * MN_NVAR * MN_MLP_IN, k * MN_NVAR * MN_MLP_IN * 4,
+                                  hipMemcpyDeviceToHost, ctx->stream));
+        if (k && work) HIPCHK(hipMemcpyAsync(work, ctx->d_tr_work + base, k * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return MNEMONIC_OK;
+    });
+}
+
+int mnemonic_mlp_predict(const float* w, const float* x, uint64_t n, int bf16, float* y, void* hip_stream) {
+    if (n && (!w || !x || !y)) return MNEMONIC_E_ARG;
+    mn_mlp_predict(w, x, n, bf16, y, static_cast<hipStream_t>(hip_stream));
+    return hipGetLastError() == hipSuccess ? MNEMONIC_OK : MNEMONIC_E_HIP;
+}
+
+int mnemonic_mlp_grad(const float* w, const float* x, const float* target, const uint32_t* idx, uint64_t off,
+                      uint64_t m, float* grad, float* loss, void* hip_stream) {
+    if (m && (!w || !x || !target || !grad || !loss)) return MNEMONIC_E_ARG;
+    mn_mlp_grad(w, x, target, idx, off, m, grad, loss, static_cast<hipStream_t>(hip_stream));
+    return hipGetLastError() == hipSuccess ? MNEMONIC_OK : MNEMONIC_E_HIP;
+}
+
+int mnemonic_mlp_adam(float* w, float* m1, float* m2, float* grad, float lr, uint32_t step, void* hip_stream) {
+    if (!w || !m1 || !m2 || !grad || step == 0) return MNEMONIC_E_ARG;
+    mn_mlp_adam(w, m1, m2, grad, lr, step, static_cast<hipStream_t>(hip_stream));
+    return hipGetLastError() == hipSuccess ? MNEMONIC_OK : MNEMONIC_E_HIP;
 }
 
 void mnemonic_destroy(mnemonic_ctx* ctx) {

@@ -51,6 +51,19 @@
 #define MN_SEM_ISO 0  // mnemonic_semantics: MNEMONIC_ISO
 #define MN_SHARDS 32  // copies of the per-phase digests and work tallies (summed on the host)
 #define MN_MAXCLOSE 8  // closing edges per start edge (the query's cyclomatic number)
+#define MN_NVAR 4      // matching orders per (query, start position): the static one and alternatives
+
+// Order-cost network of the scheduler: 24 features -> 64 -> 64 -> 1 (ReLU),
+// weights W1[24][64], b1[64], W2[64][64], b2[64], W3[64], b3 in this order.
+#define MN_MLP_IN 24
+#define MN_MLP_HIDDEN 64
+#define MN_MLP_WEIGHTS (MN_MLP_IN * MN_MLP_HIDDEN + MN_MLP_HIDDEN + MN_MLP_HIDDEN * MN_MLP_HIDDEN + 2 * MN_MLP_HIDDEN + 1)
+
+// Scheduler modes (same values as the ABI): the static order, the order the
+// network predicts cheapest, or always variant v (MN_SCHED_FIXED + v).
+#define MN_SCHED_STATIC 0
+#define MN_SCHED_LEARNED 1
+#define MN_SCHED_FIXED 2
 
 // A closing query edge: both of its endpoints are mapped by the time the
 // level that adds it is reached; it only has to exist. `other` was mapped
@@ -93,10 +106,14 @@ struct LevelDesc {
     uint32_t key_hi;
 };
 
-// Static matching order for one (query, start position j) pair (Section VI,
+// Matching order for one (query, start position j) pair (Section VI,
 // matching order computation): the start edge maps qa -> qb; closing edges
 // between qa and qb come first (close[0, c0_end)), then one level per
-// remaining query vertex.
+// remaining query vertex. Plans [0, n_static) hold the static order of each
+// pair; the alternative orders of a pair follow them, and vars[] of every
+// plan of the pair lists its n_var distinct orders (vars[0]: the static one).
+// All orders of a pair share the start-level closing edges, so a start row
+// may take any of them.
 struct SeedPlan {
     uint16_t q;        // query index
     uint8_t j;         // start position
@@ -106,27 +123,32 @@ struct SeedPlan {
     uint8_t c0_end;
     uint8_t sem;
     uint8_t n_close;
-    uint8_t pad[2];
+    uint8_t n_var;       // distinct matching orders of this (query, j) pair
+    uint8_t variant;     // which of them this plan is
     uint32_t vf_base;    // first vertex-filter bit of the query
     uint32_t debi_base;  // first edgeMatcher bit of the query
     uint8_t mapped[MN_MAXQV];     // query vertices in mapping order: qa, qb, level vtx...
     uint8_t close_idx[MN_MAXQE];  // per query edge: index into close[], or 0xFF for a tree edge
     LevelDesc lv[MN_MAXLV];
     CloseDesc close[MN_MAXCLOSE];
+    uint16_t vars[MN_NVAR];       // plan index of each order of the pair
+    float lv_est[MN_MAXLV];       // log2(1 + expected candidates per row) of each level, from the
+                                  // initial graph's label degrees and the level's class range
 };
 
 // Partial embeddings between levels, stored column-wise (row r of column c at
 // col[c * cap + r]): column 0 the plan index, 1 + u the data vertex of query
 // vertex u (u < wv), 1 + wv + k for a closing edge k the position of its
 // instance run in the adjacency list that was searched (bit 31 set when that
-// was the list of f(nv)); kcol[k * cap + r] the key of tree edge k.
+// was the list of f(nv)); kcol[k * cap + r] the key of tree edge k. When
+// tracing, column 1 + wv + we holds the trace entry of the row's start row.
 struct RowsView {
     uint32_t* col;
     uint64_t* kcol;
     uint32_t cap;
     uint32_t wv;
     uint32_t we;
-    uint32_t pad;
+    uint32_t trace;  // 1: the trace column is present
 };
 
 // One local-filter requirement of a query vertex: counter c must be >= need.
@@ -179,6 +201,20 @@ struct GraphView {
     const uint32_t* ext2int;   // [n_vertices] caller's vertex id -> internal id
     uint32_t n_elab_c;         // compact edge labels
     uint32_t n_vlab_c;         // compact vertex labels
+    uint32_t n_static;         // plans holding the static orders
+    // scheduler: which matching order each start row takes
+    uint32_t sched_mode;       // MN_SCHED_*
+    const uint16_t* sched_w;   // bf16 weights of the order-cost network (learned mode)
+    // traces (tr_cap = 0: off): per phase, one entry per start row with the
+    // features of every order of its pair and the search work below it
+    uint64_t* dec;             // start rows whose order the decision kernel settles (NULL: none)
+    uint32_t* dec_n;           // their count
+    uint32_t tr_cap;           // entries per phase
+    uint32_t tr_base;          // index of the launch's first slot in the phase's slot list
+    uint32_t* tr_n;            // [2] entries taken per phase (may exceed tr_cap)
+    uint64_t* tr_code;         // [2][tr_cap] phase << 62 | variant << 56 | static plan << 32 | slot index
+    float* tr_x;               // [2][tr_cap][MN_NVAR][MN_MLP_IN]
+    unsigned long long* tr_work;  // [2][tr_cap] 1 + candidates examined below the start row
 };
 
 // Counter layout of one vertex: [dir][0] degree, [dir][1 + e] edge label e,

@@ -29,15 +29,18 @@
 // closing edge's instance run, and emission expands every combination of
 // instances (parallel edges are distinct instances, Section I).
 #include "mn_internal.h"
+#include "mn_sched.h"
 
 namespace {
 
 // candidates per lane in one expansion tile (tile = 256 x items): 1, 2 or 4
-constexpr uint64_t EX_MAX_BLOCKS = 1u << 20;  // grid cap when the candidate total is only known on the device
 constexpr uint32_t EX_TILE_MIN = MN_BLOCK;  // the smallest tile sizes the tile_row buffer
 constexpr uint32_t NO_RUN = 0xFFFFFFFFu;
 constexpr uint32_t RUN_SWAP = 0x80000000u;
 constexpr uint8_t TREE_EDGE = 0xFF;
+// The learned choice leaves the static order only for a predicted saving of
+// more than this many log2 units of work (0.25: about 16% less work).
+constexpr float SCHED_MARGIN = 0.25f;
 
 __device__ inline bool failed(const uint32_t* err) { return *(volatile const uint32_t*)err != 0u; }
 
@@ -442,6 +445,9 @@ __device__ inline uint32_t row_of(const uint64_t* off, uint32_t a, uint32_t b, u
     return a;
 }
 
+// Start rows. Each row takes the static order, or the fixed variant; rows
+// whose order the decision kernel settles (learned choice, traces) are
+// listed in g.dec as (row << 32 | index into slots).
 template <int NC>
 __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint32_t* __restrict__ slots,
                                                         uint32_t n, RowsView R, uint32_t* n_rows,
@@ -491,25 +497,127 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
     if (P.n_levels == 0) {  // block-uniform: every lane takes this branch or none
         emit_complete<NC>(g, P, B, st, 0xFF, 0ull, ok, po, A, K);
     } else {
+        // block-uniform: does the decision kernel settle this pair's rows?
+        const bool decide = g.dec && (g.tr_cap || (g.sched_mode == MN_SCHED_LEARNED && P.n_var > 1));
+        uint32_t var = 0;
+        if (!decide && g.sched_mode >= MN_SCHED_FIXED && g.sched_mode - MN_SCHED_FIXED < P.n_var)
+            var = g.sched_mode - MN_SCHED_FIXED;
         const uint64_t bal = __ballot(ok);
         uint32_t base = 0;
         if (__lane_id() == 0 && bal) base = atomicAdd(n_rows, (uint32_t)__popcll(bal));
         base = __shfl(base, 0, MN_WAVE);
+        uint32_t r = MN_INVALID;
         if (ok) {
-            const uint32_t r = base + (uint32_t)__popcll(bal & lanemask_lt());
+            r = base + (uint32_t)__popcll(bal & lanemask_lt());
             if (r < R.cap) {
-                wcol(R, 0, r, blockIdx.y);
+                wcol(R, 0, r, P.vars[var]);
                 wcol(R, 1 + P.qa, r, s);
                 wcol(R, 1 + P.qb, r, d);
                 wkey(R, P.j, r, B.skey);
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
                     if (c < (uint32_t)NC && c < P.c0_end) wcol(R, 1 + R.wv + P.close[c].qe, r, st[c]);
+                if (R.trace) wcol(R, 1 + R.wv + R.we, r, MN_INVALID);
                 K.rows++;
-            }  // rows past the buffer are counted, not written: the host grows it and runs again
+            } else {
+                r = MN_INVALID;  // rows past the buffer are counted, not written: the host grows it and runs again
+            }
+        }
+        if (decide) {
+            const bool listed = r != MN_INVALID;
+            const uint64_t lb = __ballot(listed);
+            uint32_t lbase = 0;
+            if (__lane_id() == 0 && lb) lbase = atomicAdd(g.dec_n, (uint32_t)__popcll(lb));
+            lbase = __shfl(lbase, 0, MN_WAVE);
+            if (listed) g.dec[lbase + (uint32_t)__popcll(lb & lanemask_lt())] = ((uint64_t)r << 32) | i;
         }
     }
     acc_flush(A, K, 2 * po.n_q, po.stats, po.digest);
+}
+
+// Settles the order of the listed start rows (four lanes per row, lane v for
+// order v): features of each order, the network's prediction in learned
+// mode, the trace entry when tracing. Rows hold their static plan on entry.
+// The grid strides over min(*dec_n, cap) rows.
+template <bool LEARN>
+__global__ __launch_bounds__(MN_BLOCK) void k_decide(GraphView g, RowsView R, const uint32_t* __restrict__ slots,
+                                                     uint32_t cap, int phase) {
+    __shared__ sched::NetLds N;
+    if (LEARN) {
+        sched::load_net(N, g.sched_w);
+        __syncthreads();
+    }
+    const uint32_t total = min(*g.dec_n, cap);
+    constexpr uint32_t RPB = MN_BLOCK / MN_NVAR;  // rows per block and pass
+    const uint32_t v = threadIdx.x % MN_NVAR;
+    for (uint32_t k0 = blockIdx.x * RPB; k0 < total; k0 += gridDim.x * RPB) {  // uniform per block
+        const uint32_t k = k0 + threadIdx.x / MN_NVAR;
+        const bool on = k < total;
+        uint32_t r = 0, i = 0;
+        const SeedPlan* P = g.plans;
+        if (on) {
+            const uint64_t e = g.dec[k];
+            r = (uint32_t)(e >> 32);
+            i = (uint32_t)e;
+            P = &g.plans[rcol(R, 0, r)];
+        }
+        const bool has = on && v < P->n_var;
+        float x[MN_MLP_IN];
+#pragma unroll
+        for (int f = 0; f < MN_MLP_IN; f++) x[f] = 0.0f;
+        if (has) {
+            const uint32_t slot = slots[i];
+            sched::features(g, g.plans[P->vars[v]], rcol(R, 1 + P->qa, r), rcol(R, 1 + P->qb, r), g.s_lab[slot], x);
+        }
+        float y = has ? 0.0f : 3.4e38f;
+        if (LEARN && has) y = sched::eval(N, x);
+        // the order of the row: smallest prediction (lowest order on ties),
+        // or the fixed variant, or the static order
+        uint32_t best = v;
+        float by = y;
+#pragma unroll
+        for (int m = 1; m < MN_NVAR; m <<= 1) {
+            const float oy = __shfl_xor(by, m, MN_NVAR);
+            const uint32_t ob = __shfl_xor(best, m, MN_NVAR);
+            if (oy < by || (oy == by && ob < best)) {
+                by = oy;
+                best = ob;
+            }
+        }
+        uint32_t var = 0;
+        if (LEARN) {  // another order must promise clearly less work than the static one
+            const float y0 = __shfl(y, (int)(__lane_id() & ~(MN_NVAR - 1u)), MN_WAVE);
+            var = by < y0 - SCHED_MARGIN ? best : 0u;
+        }
+        else if (g.sched_mode >= MN_SCHED_FIXED && on && g.sched_mode - MN_SCHED_FIXED < P->n_var)
+            var = g.sched_mode - MN_SCHED_FIXED;
+        // trace entry: one per row, taken by its lane 0
+        uint32_t te = MN_INVALID;
+        if (g.tr_cap) {
+            const bool lead = on && v == 0;
+            const uint64_t tb = __ballot(lead);
+            uint32_t tbase = 0;
+            if (__lane_id() == 0 && tb) tbase = atomicAdd(g.tr_n + phase, (uint32_t)__popcll(tb));
+            tbase = __shfl(tbase, 0, MN_WAVE);
+            const uint32_t e = tbase + (uint32_t)__popcll(tb & lanemask_lt());
+            if (lead && e < g.tr_cap) te = (uint32_t)phase * g.tr_cap + e;
+            te = __shfl(te, (int)(__lane_id() & ~(MN_NVAR - 1u)), MN_WAVE);
+            if (on && te != MN_INVALID) {
+                float* dst = g.tr_x + ((size_t)te * MN_NVAR + v) * MN_MLP_IN;
+#pragma unroll
+                for (int f = 0; f < MN_MLP_IN; f++) dst[f] = x[f];
+            }
+        }
+        if (on && v == 0) {
+            if (te != MN_INVALID) {
+                g.tr_code[te] = ((uint64_t)phase << 62) | ((uint64_t)var << 56) |
+                                ((uint64_t)P->vars[0] << 32) | (uint64_t)(g.tr_base + i);
+                g.tr_work[te] = 1ull;
+                wcol(R, 1 + R.wv + R.we, r, te);
+            }
+            wcol(R, 0, r, P->vars[var]);
+        }
+    }
 }
 
 __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView R, uint32_t n,
@@ -538,6 +646,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
         }
         lo[r] = a;
         cnt[r] = b - a;
+        if (R.trace) {  // search work below the row's start row
+            const uint32_t e = rcol(R, 1 + R.wv + R.we, r);
+            if (e != MN_INVALID && b > a) atomicAdd(g.tr_work + e, (unsigned long long)(b - a));
+        }
     }
     acc_flush(A, K, 0, stats, nullptr);
 }
@@ -617,7 +729,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     // the first nt blocks are dealt to the XCDs round robin; consecutive tiles
     // go to blocks of one XCD
     const uint32_t tile = xcd_tile(blockIdx.x, nt);
-    const uint32_t ncol = 1 + in.wv + in.we;
+    const uint32_t ncol = 1 + in.wv + in.we + in.trace;
     Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint64_t t0 = c0 + (uint64_t)tile * EX_TILE;
     const uint64_t t1 = min(t0 + (uint64_t)EX_TILE, cend);
@@ -822,6 +934,18 @@ void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, 
     }
 }
 
+void mn_launch_decide(const GraphView& g, RowsView rows, const uint32_t* slots, uint32_t cap, uint32_t expect,
+                      int phase, hipStream_t s) {
+    if (!cap) return;
+    constexpr uint32_t RPB = MN_BLOCK / MN_NVAR;
+    // enough blocks for the expected rows in one pass, at most two per CU
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(512, (expect + RPB - 1) / RPB));
+    if (g.sched_mode == MN_SCHED_LEARNED)
+        k_decide<true><<<blocks, MN_BLOCK, 0, s>>>(g, rows, slots, cap, phase);
+    else
+        k_decide<false><<<blocks, MN_BLOCK, 0, s>>>(g, rows, slots, cap, phase);
+}
+
 void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long long* note, hipStream_t s) {
     k_note_count<<<1, 64, 0, s>>>(count, cap, note);
 }
@@ -876,7 +1000,7 @@ uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const 
     // total leaves a note and the host runs the phase again with more blocks.
     if (T_dev) {
         const uint64_t want = expand_tiles(0, expect + expect / 2, tile) + 64;
-        c1 = std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, EX_MAX_BLOCKS) * tile);
+        c1 = std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, MN_EXPAND_MAX_BLOCKS) * tile);
     }
     const uint64_t tiles = expand_tiles(c0, c1, tile);
     k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, n_dev, c0, c1, T_dev, tile, tile_row, note);

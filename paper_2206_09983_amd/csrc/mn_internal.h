@@ -133,10 +133,16 @@ struct PhaseOut {
 // Start rows: one per (batch slot, start position) whose edgeMatcher bit and
 // endpoint filters pass and whose start-level closing edges exist. Plans with
 // no further level emit their embeddings directly. *n_rows counts every row,
-// also those past rows.cap, which are not written.
+// also those past rows.cap, which are not written. n_plans: the static plans
+// (one per pair); each row takes the order g.sched_mode selects.
 // max_close: the most closing edges any plan has (sizes the kernels' arrays).
 void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans, uint32_t max_close,
                          RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s);
+// Settles the order of the start rows the seed kernel listed in g.dec
+// (learned choice and/or trace entries); cap bounds the list, expect (the
+// rows the host expects) sizes the grid.
+void mn_launch_decide(const GraphView& g, RowsView rows, const uint32_t* slots, uint32_t cap, uint32_t expect,
+                      int phase, hipStream_t s);
 // note[0] = 1 when *count > cap; note[1] = max(note[1], *count).
 void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long long* note, hipStream_t s);
 
@@ -144,6 +150,10 @@ void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long lon
 // row count is min(n, *n_dev), read on the device (n sizes the launch).
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
                            uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s);
+// Grid cap of a device-sized expansion (its candidate total is only known on
+// the device): one launch covers at most this many tiles.
+constexpr uint64_t MN_EXPAND_MAX_BLOCKS = 1u << 20;
+
 // Tests the candidates [c0, c1) of level L (flattened over rows by the
 // offsets `off`); survivors become rows of `out` or, at a plan's last level,
 // emitted embeddings.
@@ -170,3 +180,18 @@ void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 // out[i] = add + in[i] as u64 (sort keys).
 void mn_launch_widen(const uint32_t* in, uint64_t* out, uint64_t add, uint32_t n, const uint32_t* err,
                      hipStream_t s);
+
+// ------------------------------------------------------------ order network
+// The scheduler's 24 -> 64 -> 64 -> 1 network (weights as in mn_common.h).
+// y[i] = net(x[i]) for n samples of 24 floats; bf16 != 0 rounds weights and
+// inputs to bfloat16 first (fp32 sums either way).
+void mn_mlp_predict(const float* w, const float* x, uint64_t n, int bf16, float* y, hipStream_t s);
+// Adds to grad the gradient of mean((net(x[k]) - target[k])^2) over the m
+// samples k = idx[off + t] (t < m; idx NULL: k = off + t), and that mean to *loss.
+void mn_mlp_grad(const float* w, const float* x, const float* target, const uint32_t* idx, uint64_t off,
+                 uint64_t m, float* grad, float* loss, hipStream_t s);
+// One Adam step (step >= 1) on all weights; clears grad.
+void mn_mlp_adam(float* w, float* m1, float* m2, float* grad, float lr, uint32_t step, hipStream_t s);
+void mn_fill_f32(float* p, float v, uint32_t n, hipStream_t s);
+// out[i] = bfloat16 of in[i] (nearest, ties to even).
+void mn_to_bf16(const float* in, uint16_t* out, uint32_t n, hipStream_t s);

@@ -40,16 +40,21 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_parity(B, case, batches=None, flags=None, out_capacity=0, n_elabels=0, check_lists=True, rows_per_level=0):
+def run_parity(B, case, batches=None, flags=None, out_capacity=0, n_elabels=0, check_lists=True, rows_per_level=0,
+               sched=None, weights=None, trace=0):
     batches = case["batches"] if batches is None else batches
     flags = B.F_EMIT if flags is None else flags
     qs = case["queries"]
-    say("parity case", case["name"], "queries", len(qs), "batches", len(batches))
+    say("parity case", case["name"], "queries", len(qs), "batches", len(batches), "scheduler", sched)
     o = Oracle(case["graph"], qs)
     m = B.Matcher(case["graph"], qs, flags=flags, out_capacity=out_capacity, n_elabels=n_elabels,
                   rows_per_level=rows_per_level)
     total = 0
     try:
+        if sched is not None:
+            m.set_scheduler(sched, weights)
+        if trace:
+            m.set_trace(trace)
         for bi, b in enumerate(batches):
             o.apply_batch(b)
             first = m.apply_batch(b)

@@ -1,0 +1,214 @@
+"""GPU tests of the learned scheduler.
+
+* The network's kernels (forward in fp32 and bf16, backward, Adam) against
+  the fp64 CPU reference in oracle/mlp.py.
+* Every matching order, and the learned choice with any weights, gives the
+  oracle's embeddings bit-exact: the scheduler only reorders work.
+* Traces account for all of the enumeration's work and carry the features the
+  graph implies.
+* Training on traces lowers the loss, and the committed network's choice does
+  less work than the static order on a held-out stream with identical results.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2206_09983_amd import synth
+
+sys.path.insert(0, os.path.dirname(__file__))
+from test_gpu_parity import run_parity, say  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2206_09983_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+# ------------------------------------------------------------ network kernels
+def test_forward_matches_reference_fp32_and_bf16(B, torch):
+    rng = np.random.default_rng(11)
+    w = rng.normal(0, 0.25, omlp.N_WEIGHTS).astype(np.float32)
+    for n in (1, 63, 64, 65, 1000, 4097):
+        X = rng.normal(0, 2.0, (n, omlp.N_IN)).astype(np.float32)
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        B.mnemonic_mlp_predict(dev(torch, w), dev(torch, X), y)
+        torch.cuda.synchronize()
+        ref = omlp.forward(w.astype(np.float64), X.astype(np.float64))
+        # fp32 sums of <= 64 products: relative error well under 1e-5 of the scale
+        scale = 1.0 + np.abs(ref).max()
+        np.testing.assert_allclose(y.cpu().numpy(), ref, rtol=0, atol=2e-5 * scale)
+        B.mnemonic_mlp_predict(dev(torch, w), dev(torch, X), y, bf16=True)
+        torch.cuda.synchronize()
+        refb = omlp.forward_bf16(w, X)
+        np.testing.assert_allclose(y.cpu().numpy(), refb, rtol=0, atol=2e-5 * (1.0 + np.abs(refb).max()))
+        # and bf16 stays close to fp32: bound by the inputs' rounding
+        assert np.abs(refb - ref).max() < 0.05 * scale
+    say("forward checked")
+
+
+def test_gradient_matches_reference(B, torch):
+    rng = np.random.default_rng(12)
+    w = rng.normal(0, 0.25, omlp.N_WEIGHTS).astype(np.float32)
+    n = 3000
+    X = rng.normal(0, 1.5, (n, omlp.N_IN)).astype(np.float32)
+    T = rng.normal(2.0, 3.0, n).astype(np.float32)
+    idx = rng.permutation(n).astype(np.uint32)
+    for off, m in ((0, n), (100, 777), (2999, 1), (5, 64)):
+        grad = torch.zeros(omlp.N_WEIGHTS, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        B.mnemonic_mlp_grad(dev(torch, w), dev(torch, X), dev(torch, T), grad, loss,
+                            idx=torch.from_numpy(idx).cuda(), off=off, m=m)
+        torch.cuda.synchronize()
+        sel = idx[off:off + m]
+        L, g = omlp.loss_and_grad(w.astype(np.float64), X[sel].astype(np.float64), T[sel].astype(np.float64))
+        assert abs(loss.item() - L) <= 1e-4 * max(1.0, L), (off, m)
+        gg = grad.cpu().numpy()
+        # fp32 sums in a different order (per-block partials, atomics)
+        np.testing.assert_allclose(gg, g, rtol=2e-3, atol=2e-5 * np.abs(g).max())
+    say("gradients checked")
+
+
+def test_adam_matches_reference(B, torch):
+    rng = np.random.default_rng(13)
+    w = rng.normal(0, 0.3, omlp.N_WEIGHTS)
+    m1 = rng.normal(0, 0.01, omlp.N_WEIGHTS)
+    m2 = rng.uniform(0, 1e-3, omlp.N_WEIGHTS)
+    g = rng.normal(0, 0.1, omlp.N_WEIGHTS)
+    g[::11] = 0.0
+    # the reference starts from the same fp32 values the kernel reads
+    w, m1, m2, g = (a.astype(np.float32).astype(np.float64) for a in (w, m1, m2, g))
+    wd, m1d, m2d, gd = (dev(torch, a) for a in (w, m1, m2, g))
+    for step in (1, 2, 50):
+        B.mnemonic_mlp_adam(wd, m1d, m2d, gd, 1e-3, step)
+        torch.cuda.synchronize()
+        w, m1, m2 = omlp.adam_step(w, m1, m2, g, 1e-3, step)
+        assert np.all(gd.cpu().numpy() == 0.0)  # the step clears the gradient
+        gd.copy_(dev(torch, g))
+        # fp32 rounding of each update: a few units in the last place of the
+        # operands' magnitude (|m1| ~ 0.03, |m2| ~ 1e-3, |w| ~ 1) per step
+        ulp = 2.0 ** -24
+        np.testing.assert_allclose(wd.cpu().numpy(), w, rtol=0, atol=1e-6)
+        np.testing.assert_allclose(m1d.cpu().numpy(), m1, rtol=0, atol=8 * step * ulp * 0.05)
+        np.testing.assert_allclose(m2d.cpu().numpy(), m2, rtol=0, atol=8 * step * ulp * 2e-3)
+
+
+def test_training_on_the_gpu_fits_a_teacher(B, torch):
+    from paper_2206_09983_amd import sched
+    rng = np.random.default_rng(14)
+    teacher = rng.normal(0, 0.2, omlp.N_WEIGHTS)
+    X = rng.normal(0, 1.0, (20000, omlp.N_IN)).astype(np.float32)
+    Y = omlp.forward(teacher, X).astype(np.float32)
+    w, hist = sched.train(X, Y, epochs=40, lr=3e-3, batch=1024, seed=1)
+    var = float(np.var(Y))
+    say("teacher fit: loss %s, target variance %.4f" % (["%.4f" % h for h in hist[::5]], var))
+    # the student explains most of the variance and the loss keeps falling
+    assert hist[-1] < 0.15 * var
+    assert hist[-1] < 0.05 * hist[0]
+    assert hist[-1] < hist[-10]
+    # the trained weights predict, through the CPU reference, what the GPU predicts
+    Xt = X[:512]
+    np.testing.assert_allclose(sched.predict(w, Xt, bf16=False), omlp.forward(w.astype(np.float64), Xt),
+                               rtol=0, atol=1e-4 * (1 + np.abs(Y).max()))
+
+
+# ------------------------------------------------------------ exact results
+def test_every_order_finds_the_same_embeddings(B):
+    cases = [synth.tiny_case(seed) for seed in range(300, 340)]
+    cases += [synth.tiny_case(seed, max_v=4, max_init=12, max_ins=6, n_vlabels=1, n_elabels=1, max_qv=5, wild_p=0.6)
+              for seed in range(2100, 2120)]
+    cases.append(synth.rmat_case(scale=11, n_init=20000, n_stream=4096, batch=2048, n_batches=2))
+    cases.append(synth.multiquery_case(scale=11, n_init=20000, n_stream=12000, n_queries=64, lo=100, hi=6000))
+    multi = 0
+    for case in cases:
+        m = B.Matcher(case["graph"], case["queries"])
+        multi += sum(m.orders(q, j) > 1 for q in range(len(case["queries"]))
+                     for j in range(len(case["queries"][q]["qsrc"])))
+        m.close()
+        for v in range(B.MAX_ORDERS):
+            run_parity(B, case, sched=B.SCHED_FIXED + v, out_capacity=1 << 12)
+    assert multi > 50  # the alternative orders are really exercised
+
+
+def test_learned_choice_with_random_weights_is_exact(B):
+    rng = np.random.default_rng(15)
+    for k, case in enumerate([synth.rmat_case(scale=11, n_init=20000, n_stream=4096, batch=2048, n_batches=2),
+                              synth.chung_lu_case(n_stream=512),
+                              synth.multiquery_case(scale=11, n_init=20000, n_stream=12000, n_queries=64, lo=100,
+                                                    hi=6000)]):
+        w = rng.normal(0, 0.3, omlp.N_WEIGHTS).astype(np.float32)
+        assert run_parity(B, case, sched=B.SCHED_LEARNED, weights=w, out_capacity=1 << 12) > 0
+    # tracing on top changes nothing either
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
+    assert run_parity(B, case, sched=B.SCHED_LEARNED, weights=w, trace=1 << 16) > 0
+
+
+def test_trace_accounts_for_the_enumeration_work(B):
+    import math
+    case = synth.rmat_case(scale=12, n_init=40000, n_stream=8192, batch=2048, n_batches=3)
+    g, qs = case["graph"], case["queries"]
+    m = B.Matcher(g, qs, flags=0)
+    try:
+        m.set_trace(1 << 18)
+        src = np.concatenate([g["src"]] + [b["src"] for b in case["batches"]]).astype(np.int64)
+        dst = np.concatenate([g["dst"]] + [b["dst"] for b in case["batches"]]).astype(np.int64)
+        live = np.zeros(len(src), dtype=bool)
+        live[:len(g["src"])] = True
+        nk = len(g["src"])
+        for b in case["batches"]:
+            first = m.apply_batch(b)
+            assert first == nk
+            ins = np.arange(nk, nk + len(b["src"]))
+            nk += len(b["src"])
+            live[ins] = True
+            st = m.stats()
+            t = m.trace(0)
+            n = len(t["codes"])
+            assert n > 0
+            # every traced start row contributes 1, every candidate below it 1
+            assert int(t["work"].sum()) - n == st["entries_scanned"][0]
+            # features 0-3: log2(1 + degree) of the start edge's endpoints in the
+            # post-insert graph (deleted edges are still present in this phase)
+            idx = (t["codes"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+            s, d = b["src"][idx].astype(np.int64), b["dst"][idx].astype(np.int64)
+            ls, ld = src[live], dst[live]
+            outd = np.bincount(ls, minlength=g["n_vertices"])
+            ind = np.bincount(ld, minlength=g["n_vertices"])
+            exp = np.log2(1.0 + np.stack([outd[s], ind[s], outd[d], ind[d]], axis=1))
+            np.testing.assert_allclose(t["x"][:, 0, :4], exp, rtol=1e-5, atol=1e-5)
+            live[b["del_keys"].astype(np.int64)] = False
+            t1 = m.trace(1)
+            if len(t1["codes"]):
+                assert int(t1["work"].sum()) - len(t1["codes"]) == st["entries_scanned"][1]
+            assert math.isfinite(float(t["x"].sum()))
+    finally:
+        m.close()
+
+
+def test_committed_network_reduces_work_on_a_held_out_stream(B):
+    from paper_2206_09983_amd import sched
+    w = sched.load_weights()
+    case = synth.rmat_case(scale=16, n_init=16 << 16, n_stream=8 << 12, batch=4096, seed=8)
+    batches = case["batches"][:4]
+    st = sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_STATIC, flags=0, warmup=0)
+    le = sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_LEARNED, w, flags=0, warmup=0)
+    say("held-out work: static %d learned %d (%.2fx); ms %.2f vs %.2f" % (
+        st["work"], le["work"], st["work"] / max(1, le["work"]), st["ms"], le["ms"]))
+    assert st["results"] == le["results"]
+    assert le["work"] < st["work"]
