@@ -916,11 +916,10 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
             c->cap_tiles = need_tiles;
         }
         // one event pair serves every launch: the readback below waits for it
-        if (timing) HIPCHK(hipEventRecord(c->ev_x[0], s));
         mn_launch_expand(g, rows_view(c, L), (uint32_t)n, nullptr, B.lo, B.off, c->d_tiles, c0, c1, nullptr, nullptr, 0,
                          c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
-                         rows_view(c, L + 1), n_out, po, c->d_err, s);
-        if (timing) HIPCHK(hipEventRecord(c->ev_x[1], s));
+                         rows_view(c, L + 1), n_out, po, c->d_err, s, timing ? c->ev_x[0] : nullptr,
+                         timing ? c->ev_x[1] : nullptr);
         c->n_expand[po.phase]++;
         const uint64_t n1 = read_u32(c, n_out);
         if (timing) {
@@ -987,18 +986,14 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         uint32_t* n_out = c->d_nrows + L + 1;
         if (next) mn_launch_set_u32(n_out, 0, s);
         unsigned long long* note = c->d_zr + c->note_cand(po.phase, L);
-        std::pair<hipEvent_t, hipEvent_t> ev;
-        if (timing) {
-            ev = event_pair(c, po.phase);
-            HIPCHK(hipEventRecord(ev.first, s));
-        }
+        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
+        if (timing) ev = event_pair(c, po.phase);
         const double rt = c->rate[po.phase][L];
         const uint64_t expect = rt < 0 ? (~0ull >> 8) : (uint64_t)(rt * (double)ns) + 1;
         c->cover[po.phase][L] =
             mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, c->d_tiles, 0, K, c->d_total, note,
                              expect, c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
-                             rows_view(c, L + 1), n_out, po, c->d_err, s);
-        if (timing) HIPCHK(hipEventRecord(ev.second, s));
+                             rows_view(c, L + 1), n_out, po, c->d_err, s, ev.first, ev.second);
         c->n_expand[po.phase]++;
         if (next) {
             mn_launch_note_count(n_out, c->lvb[L + 1].cap, c->d_zr + c->note_rows(po.phase, L), s);
@@ -1083,8 +1078,8 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = 
     auto grow_rows = [&](uint32_t L, uint64_t need) {  // rows of level L
         if (need > c->rows_max)
             host_chunks = true;
-        else if (need > c->lvb[L].cap)
-            grow_level(c, L, std::max<uint64_t>(need + need / 4, 2 * c->lvb[L].cap));
+        else if (need > c->lvb[L].cap)  // twice the need: batches vary, a re-run costs a whole phase
+            grow_level(c, L, std::max<uint64_t>(2 * need, 2 * c->lvb[L].cap));
     };
     const unsigned long long* ns0 = z + c->note_seed(p);
     if (ns0[0]) {  // start rows past their buffer
@@ -1109,7 +1104,7 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = 
             if ((uint64_t)T_est > most / 2)
                 host_chunks = true;
             else if ((uint64_t)T_est > c->cand_k)
-                c->cand_k = std::min<uint64_t>(most, std::max<uint64_t>((uint64_t)T_est + (uint64_t)T_est / 4, 2 * c->cand_k));
+                c->cand_k = std::min<uint64_t>(most, std::max<uint64_t>(2 * (uint64_t)T_est, 2 * c->cand_k));
         }
         if (L + 1 < c->max_levels && nr[1]) {
             const double R_est = (double)nr[1] * cut;

@@ -28,6 +28,8 @@
 // closing-edge instances do not multiply rows: a row keeps the start of each
 // closing edge's instance run, and emission expands every combination of
 // instances (parallel edges are distinct instances, Section I).
+#include <hip/hip_ext.h>
+
 #include "mn_internal.h"
 #include "mn_sched.h"
 
@@ -957,42 +959,48 @@ void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const 
 
 uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return expand_tiles(c0, c1, EX_TILE_MIN); }
 
+// k_expand launches go through hipExtLaunchKernel so that the optional
+// events are stamped by the dispatch itself: they time the kernel, not the
+// queue around it.
 template <int NC, uint32_t ITEMS>
-void launch_expand_nc(bool rows, bool emit, dim3 grid, hipStream_t s, const GraphView& g, RowsView in,
-                      uint32_t n_in, const uint32_t* lo, const uint64_t* off, const uint32_t* tile_row, uint64_t c0,
-                      uint64_t c1, const uint64_t* T_dev, uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po,
-                      const uint32_t* err) {
-    if (rows && emit)
-        k_expand<NC, true, true, ITEMS><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out,
-                                                                  n_out, po, err);
-    else if (rows)
-        k_expand<NC, true, false, ITEMS><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L,
-                                                                   out, n_out, po, err);
-    else
-        k_expand<NC, false, true, ITEMS><<<grid, MN_BLOCK, 0, s>>>(g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L,
-                                                                   out, n_out, po, err);
+void launch_expand_nc(bool rows, bool emit, dim3 grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                      const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo, const uint64_t* off,
+                      const uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev, uint32_t L,
+                      RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err) {
+    auto k = rows && emit ? k_expand<NC, true, true, ITEMS>
+                          : rows ? k_expand<NC, true, false, ITEMS> : k_expand<NC, false, true, ITEMS>;
+    hipExtLaunchKernelGGL(k, grid, dim3(MN_BLOCK), 0, s, ev0, ev1, 0, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L,
+                          out, n_out, po, err);
 }
 
 template <uint32_t ITEMS>
-void launch_expand_items(uint32_t max_close, bool rows, bool emit, dim3 grid, hipStream_t s, const GraphView& g,
-                         RowsView in, uint32_t n_in, const uint32_t* lo, const uint64_t* off, const uint32_t* tile_row,
-                         uint64_t c0, uint64_t c1, const uint64_t* T_dev, uint32_t L, RowsView out, uint32_t* n_out,
-                         PhaseOut po, const uint32_t* err) {
+void launch_expand_items(uint32_t max_close, bool rows, bool emit, dim3 grid, hipStream_t s, hipEvent_t ev0,
+                         hipEvent_t ev1, const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo,
+                         const uint64_t* off, const uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
+                         uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err) {
+#define MN_EXPAND_ARGS rows, emit, grid, s, ev0, ev1, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err
     switch (nc_bucket(max_close)) {
-        case 0: launch_expand_nc<0, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        case 1: launch_expand_nc<1, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        case 2: launch_expand_nc<2, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        case 4: launch_expand_nc<4, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
-        default: launch_expand_nc<8, ITEMS>(rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err); break;
+        case 0: launch_expand_nc<0, ITEMS>(MN_EXPAND_ARGS); break;
+        case 1: launch_expand_nc<1, ITEMS>(MN_EXPAND_ARGS); break;
+        case 2: launch_expand_nc<2, ITEMS>(MN_EXPAND_ARGS); break;
+        case 4: launch_expand_nc<4, ITEMS>(MN_EXPAND_ARGS); break;
+        default: launch_expand_nc<8, ITEMS>(MN_EXPAND_ARGS); break;
     }
+#undef MN_EXPAND_ARGS
 }
 
 uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
                           const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
                           unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
                           bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
-                          hipStream_t s) {
-    if (c1 <= c0 || !n_in) return c1;
+                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (c1 <= c0 || !n_in) {
+        if (ev0) {  // an empty pair keeps the caller's bookkeeping simple
+            (void)hipEventRecord(ev0, s);
+            (void)hipEventRecord(ev1, s);
+        }
+        return c1;
+    }
     if (items != 1 && items != 4) items = 2;
     const uint32_t tile = MN_BLOCK * items;
     // With the total on the device, the grid follows the expected candidate
@@ -1005,11 +1013,13 @@ uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const 
     const uint64_t tiles = expand_tiles(c0, c1, tile);
     k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, n_dev, c0, c1, T_dev, tile, tile_row, note);
     const dim3 grid((uint32_t)tiles);
+#define MN_ITEMS_ARGS max_close, rows, emit, grid, s, ev0, ev1, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err
     if (items == 1)
-        launch_expand_items<1>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
+        launch_expand_items<1>(MN_ITEMS_ARGS);
     else if (items == 4)
-        launch_expand_items<4>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
+        launch_expand_items<4>(MN_ITEMS_ARGS);
     else
-        launch_expand_items<2>(max_close, rows, emit, grid, s, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err);
+        launch_expand_items<2>(MN_ITEMS_ARGS);
+#undef MN_ITEMS_ARGS
     return c1;
 }

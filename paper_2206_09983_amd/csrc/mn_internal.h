@@ -167,12 +167,13 @@ uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1);
 // the candidates the host expects, only sizes the grid. items (1, 2 or 4)
 // sets the tile: 256 x items candidates per block.
 // Returns the end of the candidates the launch covers (c1, lowered to what
-// the grid covers in the device-sized form).
+// the grid covers in the device-sized form). ev0/ev1, when given, are
+// recorded right before and after the k_expand launch itself.
 uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
                       const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
                       unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
                       bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
-                      hipStream_t s);
+                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Stores v into *p (a device word) in stream order.
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
