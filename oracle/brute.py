@@ -16,8 +16,11 @@ import itertools
 import numpy as np
 
 
-def static_set(n_vertices, vmask, live, query):
-    """live: dict key -> (src, dst, label). Returns a set of key tuples."""
+def static_set(n_vertices, vmask, live, query, ts=None):
+    """live: dict key -> (src, dst, label). Returns a set of key tuples.
+    With query["rank"] (temporal order) and ts (key -> timestamp), a tuple is
+    kept only when ts strictly increases from every ranked edge to every edge
+    of a higher rank (rank -1: unconstrained)."""
     nqv = int(query["n_qv"])
     vreq = [int(x) for x in query["vreq"]]
     qs = [int(x) for x in query["qsrc"]]
@@ -34,6 +37,14 @@ def static_set(n_vertices, vmask, live, query):
     # requirement or injectivity, or a query edge with both endpoints fixed
     # has no instance: every full map extending it would fail the same test.
     edges_at = [[k for k in range(len(qs)) if max(qs[k], qd[k]) == u] for u in range(nqv)]
+    rank = query.get("rank")
+
+    def in_time_order(combo):
+        for a, ka in enumerate(combo):
+            for b, kb in enumerate(combo):
+                if rank[a] >= 0 and rank[b] >= 0 and rank[a] < rank[b] and not ts[ka] < ts[kb]:
+                    return False
+        return True
 
     def inst(k, f):
         return [key for key, el in by_pair.get((f[qs[k]], f[qd[k]]), []) if ql[k] < 0 or ql[k] == el]
@@ -43,6 +54,8 @@ def static_set(n_vertices, vmask, live, query):
         if u == nqv:
             choices = [inst(k, f) for k in range(len(qs))]
             for combo in itertools.product(*choices):
+                if rank is not None and not in_time_order(combo):
+                    continue
                 out.add(tuple(combo))
             return
         for v in range(n_vertices):
@@ -62,20 +75,22 @@ def run_stream(graph, batches, query):
     """Per batch: (sorted new tuples, sorted expired tuples), by set differences."""
     n = int(graph["n_vertices"])
     vmask = graph["vlabel_mask"]
-    live = {}
-    for k, (s, d, l) in enumerate(zip(graph["src"], graph["dst"], graph["elabel"])):
+    live, ts = {}, {}
+    for k, (s, d, l, t) in enumerate(zip(graph["src"], graph["dst"], graph["elabel"], graph["ts"])):
         live[k] = (int(s), int(d), int(l))
+        ts[k] = int(t)
     next_key = len(live)
     results = []
     for b in batches:
-        before = static_set(n, vmask, live, query)
-        for s, d, l in zip(b["src"], b["dst"], b["elabel"]):
+        before = static_set(n, vmask, live, query, ts)
+        for s, d, l, t in zip(b["src"], b["dst"], b["elabel"], b["ts"]):
             live[next_key] = (int(s), int(d), int(l))
+            ts[next_key] = int(t)
             next_key += 1
-        mid = static_set(n, vmask, live, query)
+        mid = static_set(n, vmask, live, query, ts)
         for k in b["del_keys"]:
             del live[int(k)]
-        after = static_set(n, vmask, live, query)
+        after = static_set(n, vmask, live, query, ts)
         results.append((sorted(mid - before), sorted(mid - after)))
     return results
 

@@ -31,6 +31,8 @@ def lib():
         L.orc_set_limit.argtypes = [vp, u64]
         L.orc_add_query.restype = i32
         L.orc_add_query.argtypes = [vp, u32, P(u64), u32, P(u32), P(u32), P(C.c_int32), i32]
+        L.orc_set_temporal.restype = i32
+        L.orc_set_temporal.argtypes = [vp, u32, P(C.c_int32)]
         L.orc_insert.restype = i64
         L.orc_insert.argtypes = [vp, u64, P(u32), P(u32), P(C.c_uint8), P(i64), i32]
         L.orc_mark.restype = i32
@@ -107,6 +109,11 @@ class Oracle:
                                 _p(qd, C.c_uint32), _p(ql, C.c_int32), int(q["sem"]))
             if r < 0:
                 raise ValueError("query rejected by oracle: %r" % (q.get("name"),))
+            if q.get("rank") is not None:  # temporal order on the query edges
+                rk = np.ascontiguousarray(q["rank"], dtype=np.int32)
+                if len(rk) != len(qs) or L.orc_set_temporal(self.h, r, _p(rk, C.c_int32)) < 0:
+                    raise ValueError("bad temporal ranks")
+                self._keep.append(rk)
             self.n_qe.append(len(qs))
         if limit:
             L.orc_set_limit(self.h, int(limit))

@@ -18,6 +18,11 @@
  *     caption of the example figure in Section I)
  *   - isomorphism: f injective; homomorphism: no injectivity, one data edge
  *     may serve several query edges (Section III, homomorphism paragraph).
+ *   - temporal order, when the query gives ranks (the time-constrained
+ *     variant of Section II-B's related work, evaluated in Section VII-C):
+ *     ts(g(e_a)) < ts(g(e_b)) whenever rank(e_a) < rank(e_b); edges of equal
+ *     rank, or of rank -1, are unconstrained against each other. Checked on
+ *     each complete embedding.
  *
  * How (Section VI "Embedding Enumeration"): every edge of the batch that
  * matches query edge q_j is a work unit; the enumerator backtracks from it in
@@ -80,6 +85,8 @@ typedef struct {
     uint32_t qsrc[ORC_MAXQE], qdst[ORC_MAXQE];
     int32_t qlab[ORC_MAXQE];
     int sem; /* 0 iso, 1 homo */
+    int temporal;                /* ranks given */
+    int32_t rank[ORC_MAXQE];     /* temporal rank per query edge, -1 = none */
     vec64 res[2];  /* [0] new, [1] expired; flat tuples of n_qe keys */
     uint64_t overflow[2];
 } orc_query;
@@ -243,6 +250,17 @@ int orc_add_query(void *vc, uint32_t n_qv, const uint64_t *vreq, uint32_t n_qe,
     return (int)c->n_q++;
 }
 
+/* Gives query qi temporal ranks (n_qe values, -1 = unconstrained edge).
+ * Returns 0, or -1 for a bad query index. */
+int orc_set_temporal(void *vc, uint32_t qi, const int32_t *rank) {
+    orc_ctx *c = (orc_ctx *)vc;
+    if (qi >= c->n_q) return -1;
+    orc_query *q = &c->q[qi];
+    q->temporal = 1;
+    for (uint32_t k = 0; k < q->n_qe; k++) q->rank[k] = rank[k] < 0 ? -1 : rank[k];
+    return 0;
+}
+
 /* ---------------------------------------------------------------- matching */
 
 static int label_ok(int32_t ql, uint8_t dl) { return ql < 0 || (uint32_t)ql == dl; }
@@ -284,7 +302,19 @@ static void make_order(orc_ctx *c, const orc_query *q, uint32_t j) {
     }
 }
 
+/* Temporal order of a complete embedding: every pair of ranked edges with
+ * rank a < rank b has strictly increasing timestamps. */
+static int temporal_ok(const orc_ctx *c, const orc_query *q) {
+    for (uint32_t a = 0; a < q->n_qe; a++)
+        for (uint32_t b = 0; b < q->n_qe; b++)
+            if (q->rank[a] >= 0 && q->rank[b] >= 0 && q->rank[a] < q->rank[b] &&
+                !(c->ets[c->g[a]] < c->ets[c->g[b]]))
+                return 0;
+    return 1;
+}
+
 static void emit(orc_ctx *c, const orc_query *q) {
+    if (q->temporal && !temporal_ok(c, q)) return;
     if (c->limit && c->sink->n >= c->limit * q->n_qe) {
         (*c->sink_overflow)++;
         return;

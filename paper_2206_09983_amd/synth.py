@@ -64,8 +64,9 @@ def make_batch(src, dst, elabel, ts, del_keys=()):
     }
 
 
-def make_query(n_qv, vreq, edges, sem, name=""):
-    """edges: list of (src, dst, label) with label -1 meaning any label."""
+def make_query(n_qv, vreq, edges, sem, name="", rank=None):
+    """edges: list of (src, dst, label) with label -1 meaning any label.
+    rank: None, or a temporal rank per query edge (-1: unconstrained)."""
     e = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
     return {
         "name": name,
@@ -75,7 +76,15 @@ def make_query(n_qv, vreq, edges, sem, name=""):
         "qdst": np.ascontiguousarray(e[:, 1], dtype=np.uint32),
         "qlabel": np.ascontiguousarray(e[:, 2], dtype=np.int32),
         "sem": int(sem),
+        "rank": None if rank is None else np.ascontiguousarray(rank, dtype=np.int32),
     }
+
+
+def with_ranks(query, rank):
+    """A copy of query with temporal ranks."""
+    q = dict(query)
+    q["rank"] = np.ascontiguousarray(rank, dtype=np.int32)
+    return q
 
 
 def split_stream(n_vertices, vmask, src, dst, elabel, n_init, batch_sizes,
@@ -300,6 +309,24 @@ def random_connected_query(rng, nv, n_extra, n_vlabels, n_elabels, wild_p, sem):
     labs = [(-1 if rng.random() < wild_p else int(rng.integers(0, n_elabels))) for _ in edges]
     return make_query(nv, np.array(vreq, dtype=np.uint64),
                       [(a, b, l) for (a, b), l in zip(edges, labs)], sem, "rand")
+
+
+def temporal_tiny_case(seed, ts_ties=False, **kw):
+    """tiny_case with random temporal ranks on its queries (ranks in
+    -1..m-1, ties allowed); with ts_ties, timestamps are key // 2, so that
+    pairs of edges share a timestamp."""
+    case = tiny_case(seed, **kw)
+    rng = _rng(seed + 7000)
+    m = len(case["queries"][0]["qsrc"])
+    rank = rng.integers(-1, m, size=m)
+    case["queries"] = [with_ranks(q, rank) for q in case["queries"]]
+    if ts_ties:
+        g = dict(case["graph"])
+        g["ts"] = np.arange(len(g["src"]), dtype=np.int64) // 2
+        case["graph"] = g
+        case["batches"] = [dict(b, ts=np.ascontiguousarray(b["ts"] // 2)) for b in case["batches"]]
+    case["name"] = "temporal_" + case["name"] + ("_ties" if ts_ties else "")
+    return case
 
 
 def tiny_case(seed, max_v=6, max_init=10, n_batches=3, max_ins=4, max_del=3,

@@ -314,3 +314,61 @@ def test_rejects_bad_batches_and_unsupported_queries():
     with pytest.raises(ValueError):
         Oracle(g, [synth.make_query(3, [0, 0, 0], [(0, 1, -1)], synth.ISO)])  # disconnected
     o.close()
+
+
+# ------------------------------------------------------------ temporal order
+@pytest.mark.parametrize("ties", [False, True])
+def test_temporal_oracle_equals_brute_force(ties):
+    # random ranks (ties and unranked edges included); with ties, pairs of
+    # edges share a timestamp, so the strict order rejects them
+    total = 0
+    for seed in range(120):
+        total += _check_against_brute(synth.temporal_tiny_case(seed, ts_ties=ties))
+    assert total > 20
+
+
+def test_temporal_rank_permutations_partition_the_embeddings():
+    # with distinct timestamps, an isomorphic embedding maps its m query
+    # edges to m distinct data edges (f is injective), which come in exactly
+    # one time order: the m! strict rank orders split the unconstrained set.
+    # (Under homomorphism two query edges may share a data edge, whose equal
+    # timestamps no strict order accepts.)
+    import itertools
+    checked = 0
+    for seed in range(200, 300):
+        case = synth.tiny_case(seed, max_qv=3)
+        q = case["queries"][0]
+        m = len(q["qsrc"])
+        if m > 4:
+            continue
+        perms = list(itertools.permutations(range(m)))
+        qs = [q] + [synth.with_ranks(q, p) for p in perms]
+        o = Oracle(case["graph"], qs)
+        for b in case["batches"]:
+            o.apply_batch(b)
+            for ph in (False, True):
+                whole = o.result(0, ph)
+                parts = [o.result(1 + i, ph) for i in range(len(perms))]
+                assert sum(len(p) for p in parts) == len(whole)
+                if len(whole):
+                    joined = np.concatenate([p for p in parts if len(p)])
+                    joined = joined[np.lexsort(joined.T[::-1])]
+                    np.testing.assert_array_equal(joined, whole)
+                checked += len(whole)
+        o.close()
+    assert checked > 50
+
+
+def test_equal_or_missing_ranks_change_nothing():
+    for seed in range(300, 330):
+        case = synth.tiny_case(seed)
+        q = case["queries"][0]
+        m = len(q["qsrc"])
+        qs = [q, synth.with_ranks(q, [0] * m), synth.with_ranks(q, [-1] * m)]
+        o = Oracle(case["graph"], qs)
+        for b in case["batches"]:
+            o.apply_batch(b)
+            for ph in (False, True):
+                np.testing.assert_array_equal(o.result(1, ph), o.result(0, ph))
+                np.testing.assert_array_equal(o.result(2, ph), o.result(0, ph))
+        o.close()
