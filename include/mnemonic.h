@@ -66,7 +66,12 @@ typedef struct {
 /* One query graph G_Q (Section II-A). Host pointers, copied at creation.
  * Supported shape: 2..16 vertices, 1..32 edges, weakly connected, no
  * self-loop, at most one edge per ordered vertex pair. Anything else returns
- * MNEMONIC_E_QUERY. */
+ * MNEMONIC_E_QUERY.
+ * qtorder: NULL, or a temporal rank per query edge (the time-constrained
+ * variant listed in Section II-B and evaluated in Section VII-C): an
+ * embedding must then satisfy ts(g(e_a)) < ts(g(e_b)) whenever
+ * 0 <= rank(e_a) < rank(e_b); edges of equal rank, or of rank -1, are not
+ * ordered against each other. Ranks must lie in -1..31. */
 typedef struct {
     uint32_t n_qv;
     const uint64_t *qv_require; /* [n_qv] required label set; 0 = any vertex */
@@ -75,6 +80,7 @@ typedef struct {
     const uint32_t *qdst;       /* [n_qe] */
     const int32_t *qelabel;     /* [n_qe] label, or -1 for any label */
     mnemonic_semantics sem;
+    const int32_t *qtorder;     /* [n_qe] temporal rank, or NULL: no order */
 } mnemonic_query;
 
 /* A batch of insertions. Inserted edges get consecutive keys in array order.
@@ -215,6 +221,17 @@ int mnemonic_get_stats(mnemonic_ctx *ctx, mnemonic_stats *out);
  * valid until the next call on the context. A NULL ctx gives the last error of
  * a failed mnemonic_create on this thread. */
 const char *mnemonic_last_error(const mnemonic_ctx *ctx);
+
+/* Replaces the context's query set between batches (a serving loop admits
+ * and retires queries this way). The graph, its keys and the pending
+ * deletions are kept; everything that depends on the queries is rebuilt from
+ * the edges present: the edgeMatcher words of every live edge, the per-vertex
+ * counters and filter bits (Section V-A), the matching orders, the output
+ * buffers. Results of the following batches are indexed by the new set (in
+ * the order given). Queries follow the rules of mnemonic_create; a bad one
+ * returns MNEMONIC_E_QUERY and changes nothing. Costs O(live edges +
+ * vertices) on the device. Errors: ARG, QUERY, OOM, HIP. */
+int mnemonic_set_queries(mnemonic_ctx *ctx, const mnemonic_query *q, uint32_t n_q);
 
 /* ------------------------------------------------------------- scheduler
  * Matching orders. Section VI computes one matching order per start position

@@ -19,7 +19,8 @@
  *   - isomorphism: f injective; homomorphism: no injectivity, one data edge
  *     may serve several query edges (Section III, homomorphism paragraph).
  *   - temporal order, when the query gives ranks (the time-constrained
- *     variant of Section II-B's related work, evaluated in Section VII-C):
+ *     variant listed among the matching variants of Section II-B, evaluated
+ *     in Section VII-C):
  *     ts(g(e_a)) < ts(g(e_b)) whenever rank(e_a) < rank(e_b); edges of equal
  *     rank, or of rank -1, are unconstrained against each other. Checked on
  *     each complete embedding.

@@ -35,7 +35,7 @@ ERRORS = {
 EXPORTS = ["mnemonic_create", "mnemonic_apply_batch", "mnemonic_get_result", "mnemonic_copy_keys",
            "mnemonic_get_stats", "mnemonic_last_error", "mnemonic_destroy", "mnemonic_set_scheduler",
            "mnemonic_query_orders", "mnemonic_set_trace", "mnemonic_get_trace", "mnemonic_mlp_predict",
-           "mnemonic_mlp_grad", "mnemonic_mlp_adam"]
+           "mnemonic_mlp_grad", "mnemonic_mlp_adam", "mnemonic_set_queries"]
 
 _u8p = C.POINTER(C.c_uint8)
 _u32p = C.POINTER(C.c_uint32)
@@ -51,7 +51,7 @@ class mnemonic_graph(C.Structure):
 
 class mnemonic_query(C.Structure):
     _fields_ = [("n_qv", C.c_uint32), ("qv_require", _u64p), ("n_qe", C.c_uint32), ("qsrc", _u32p),
-                ("qdst", _u32p), ("qelabel", _i32p), ("sem", C.c_int)]
+                ("qdst", _u32p), ("qelabel", _i32p), ("sem", C.c_int), ("qtorder", _i32p)]
 
 
 class mnemonic_edges(C.Structure):
@@ -121,6 +121,8 @@ def load():
     L.mnemonic_last_error.argtypes = [vp]
     L.mnemonic_destroy.restype = None
     L.mnemonic_destroy.argtypes = [vp]
+    L.mnemonic_set_queries.restype = C.c_int
+    L.mnemonic_set_queries.argtypes = [vp, C.POINTER(mnemonic_query), C.c_uint32]
     fp = C.POINTER(C.c_float)
     L.mnemonic_set_scheduler.restype = C.c_int
     L.mnemonic_set_scheduler.argtypes = [vp, C.c_int, fp]
@@ -154,6 +156,21 @@ def _check(rc, ctx):
         raise MnemonicError(rc, mnemonic_last_error(ctx))
 
 
+def _queries(queries, arr):
+    """mnemonic_query array of query dicts (arr keeps the arrays alive)."""
+    qs = (mnemonic_query * len(queries))()
+    for i, q in enumerate(queries):
+        qs[i].n_qv = int(q["n_qv"])
+        qs[i].qv_require = _ptr(arr(q["vreq"], np.uint64), C.c_uint64)
+        qs[i].n_qe = len(q["qsrc"])
+        qs[i].qsrc = _ptr(arr(q["qsrc"], np.uint32), C.c_uint32)
+        qs[i].qdst = _ptr(arr(q["qdst"], np.uint32), C.c_uint32)
+        qs[i].qelabel = _ptr(arr(q["qlabel"], np.int32), C.c_int32)
+        qs[i].sem = int(q["sem"])
+        qs[i].qtorder = _ptr(None if q.get("rank") is None else arr(q["rank"], np.int32), C.c_int32)
+    return qs
+
+
 # ------------------------------------------------------------------- ABI calls
 def mnemonic_create(graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n_elabels=0, rows_per_level=0):
     """graph/queries: dicts as produced by paper_2206_09983_amd.synth. Returns the context."""
@@ -174,15 +191,7 @@ def mnemonic_create(graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n
     g.dst = _ptr(arr(graph["dst"], np.uint32), C.c_uint32)
     g.elabel = _ptr(arr(graph["elabel"], np.uint8), C.c_uint8)
     g.ts = _ptr(arr(graph["ts"], np.int64), C.c_int64)
-    qs = (mnemonic_query * len(queries))()
-    for i, q in enumerate(queries):
-        qs[i].n_qv = int(q["n_qv"])
-        qs[i].qv_require = _ptr(arr(q["vreq"], np.uint64), C.c_uint64)
-        qs[i].n_qe = len(q["qsrc"])
-        qs[i].qsrc = _ptr(arr(q["qsrc"], np.uint32), C.c_uint32)
-        qs[i].qdst = _ptr(arr(q["qdst"], np.uint32), C.c_uint32)
-        qs[i].qelabel = _ptr(arr(q["qlabel"], np.int32), C.c_int32)
-        qs[i].sem = int(q["sem"])
+    qs = _queries(queries, arr)
     opt = mnemonic_options(int(flags), int(out_capacity), int(rows_per_level))
     ctx = C.c_void_p()
     rc = L.mnemonic_create(C.byref(g), qs, len(queries), C.byref(opt),
@@ -254,6 +263,19 @@ def mnemonic_last_error(ctx):
 def mnemonic_destroy(ctx):
     if ctx:
         load().mnemonic_destroy(ctx)
+
+
+def mnemonic_set_queries(ctx, queries):
+    """Replaces the context's query set (between batches)."""
+    keep = []
+
+    def arr(x, dt):
+        a = np.ascontiguousarray(x, dtype=dt)
+        keep.append(a)
+        return a
+
+    qs = _queries(queries, arr)
+    _check(load().mnemonic_set_queries(ctx, qs, len(queries)), ctx)
 
 
 def mnemonic_set_scheduler(ctx, mode, weights=None):
@@ -335,6 +357,10 @@ class Matcher:
 
     def stats(self):
         return mnemonic_get_stats(self.ctx)
+
+    def set_queries(self, queries):
+        mnemonic_set_queries(self.ctx, queries)
+        self.n_q = len(queries)
 
     def set_scheduler(self, mode, weights=None):
         mnemonic_set_scheduler(self.ctx, mode, weights)

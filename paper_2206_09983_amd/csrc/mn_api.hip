@@ -94,6 +94,7 @@ struct mnemonic_ctx {
     hipStream_t stream = nullptr;
     uint32_t flags = MNEMONIC_F_EMIT;
     uint32_t nV = 0, n_elabels = 256, nbr_bits = 1, hb = 1;
+    uint64_t out_cap0 = 1ull << 20;  // initial tuples per result buffer
 
     // vertex classes: distinct label sets in increasing order; internal ids
     // number the vertices class by class (cls_start[c] = first id of class c)
@@ -465,6 +466,26 @@ void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t 
     }
 }
 
+// Temporal ranks of the query's edges on a plan (all -1 without qtorder).
+void set_ranks(SeedPlan& P, const mnemonic_query& q) {
+    P.temporal = 0;
+    for (uint32_t k = 0; k < MN_MAXQE; k++) P.rank[k] = -1;
+    if (!q.qtorder) return;
+    int lo = 1 << 30, hi = -1;
+    for (uint32_t k = 0; k < q.n_qe; k++) {
+        P.rank[k] = (int8_t)q.qtorder[k];
+        if (q.qtorder[k] >= 0) {
+            lo = std::min(lo, q.qtorder[k]);
+            hi = std::max(hi, q.qtorder[k]);
+        }
+    }
+    P.temporal = hi > lo ? 1 : 0;  // two distinct ranks order some pair
+    P.n_ranked = 0;
+    for (int r = lo; r <= hi; r++)
+        for (uint32_t k = 0; k < q.n_qe; k++)
+            if (q.qtorder[k] == r) P.rorder[P.n_ranked++] = (uint8_t)k;
+}
+
 void check_query(const mnemonic_query& q) {
     auto bad = [](const std::string& m) { throw ApiError{MNEMONIC_E_QUERY, m}; };
     if (q.n_qv < 2 || q.n_qv > MN_MAXQV) bad("query needs 2..16 vertices");
@@ -475,6 +496,7 @@ void check_query(const mnemonic_query& q) {
         if (q.qsrc[i] >= q.n_qv || q.qdst[i] >= q.n_qv) bad("query edge endpoint out of range");
         if (q.qsrc[i] == q.qdst[i]) bad("query self-loop");
         if (q.qelabel[i] < -1 || q.qelabel[i] > 255) bad("query edge label out of range");
+        if (q.qtorder && (q.qtorder[i] < -1 || q.qtorder[i] > 31)) bad("temporal rank out of -1..31");
         for (uint32_t k = 0; k < i; k++)
             if (q.qsrc[k] == q.qsrc[i] && q.qdst[k] == q.qdst[i]) bad("repeated query edge");
     }
@@ -571,12 +593,14 @@ void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
             // they follow every static plan)
             SeedPlan P;
             build_plan(c, Q, i, j, P, 0);
+            set_ranks(P, q);
             P.n_var = 1;
             P.variant = 0;
             std::vector<SeedPlan> vs(1, P);
             for (uint32_t v : {3u, 1u, 2u}) {
                 SeedPlan V;
                 build_plan(c, Q, i, j, V, v);
+                set_ranks(V, q);
                 bool dup = false;
                 for (const SeedPlan& W : vs)
                     dup = dup || (memcmp(W.mapped, V.mapped, sizeof(V.mapped)) == 0 &&
@@ -665,6 +689,7 @@ GraphView make_view(const mnemonic_ctx* c, bool next) {
     g.elab_idx = c->d_elab_idx;
     g.vlab_idx = c->d_vlab_idx;
     g.ext2int = c->d_ext2int;
+    g.key2slot = c->d_key2slot;
     g.n_elab_c = c->n_elab_c;
     g.n_vlab_c = c->n_vlab_c;
     g.n_static = c->n_static;
@@ -1619,6 +1644,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         dev_alloc(c->d_zr, c->n_zr);
         // output buffers
         uint64_t cap = opt && opt->out_capacity ? opt->out_capacity : (1ull << 20);
+        c->out_cap0 = cap;
         c->houts.resize(n_q);
         for (uint32_t i = 0; i < n_q; i++)
             for (int p = 0; p < 2; p++) {
@@ -1707,6 +1733,115 @@ int mnemonic_get_stats(mnemonic_ctx* ctx, mnemonic_stats* out) {
 const char* mnemonic_last_error(const mnemonic_ctx* ctx) {
     if (!ctx) return g_create_error.c_str();
     return ctx->err.c_str();
+}
+
+int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_q) {
+    if (!ctx || !q) return MNEMONIC_E_ARG;
+    return guarded(ctx, [&]() -> int {
+        mnemonic_ctx* c = ctx;
+        // plan the new set on a scratch context first: a bad query changes nothing
+        mnemonic_ctx t;
+        t.nV = c->nV;
+        t.n_elabels = c->n_elabels;
+        t.nbr_bits = c->nbr_bits;
+        t.hb = c->hb;
+        t.cls_mask = c->cls_mask;
+        t.cls_start = c->cls_start;
+        t.lab_deg = c->lab_deg;
+        prepare_queries(&t, q, n_q);
+        for (uint32_t i = 0; i < n_q; i++)
+            for (uint32_t k = 0; k < q[i].n_qe; k++)
+                if (q[i].qelabel[k] >= (int32_t)c->n_elabels)
+                    throw ApiError{MNEMONIC_E_QUERY, "query edge label >= n_elabels"};
+        hipStream_t s = c->stream;
+        HIPCHK(hipStreamSynchronize(s));
+        // query tables
+        c->n_q = t.n_q;
+        c->n_plans = t.n_plans;
+        c->n_static = t.n_static;
+        c->max_levels = t.max_levels;
+        c->wv = t.wv;
+        c->we = t.we;
+        c->max_close = t.max_close;
+        memcpy(c->level_rows, t.level_rows, sizeof(c->level_rows));
+        memcpy(c->level_emit, t.level_emit, sizeof(c->level_emit));
+        c->hq.swap(t.hq);
+        c->hplans.swap(t.hplans);
+        c->hdebi.swap(t.hdebi);
+        c->hvf.swap(t.hvf);
+        c->hreq.swap(t.hreq);
+        memcpy(c->elab_idx, t.elab_idx, sizeof(c->elab_idx));
+        memcpy(c->vlab_idx, t.vlab_idx, sizeof(c->vlab_idx));
+        c->n_elab_c = t.n_elab_c;
+        c->n_vlab_c = t.n_vlab_c;
+        c->n_cnt = t.n_cnt;
+        c->vf_words = t.vf_words;
+        const uint32_t old_words = c->debi_words;
+        c->debi_words = t.debi_words;
+        c->n_vf_bits = t.n_vf_bits;
+        c->n_debi_bits = t.n_debi_bits;
+        c->total_qe = t.total_qe;
+        dev_free(c->d_q);
+        dev_free(c->d_plans);
+        dev_free(c->d_debi_bits);
+        dev_free(c->d_vf_bits);
+        dev_free(c->d_req);
+        upload(c->d_q, c->hq, s);
+        upload(c->d_plans, c->hplans, s);
+        upload(c->d_debi_bits, c->hdebi, s);
+        upload(c->d_vf_bits, c->hvf, s);
+        upload(c->d_req, c->hreq, s);
+        HIPCHK(hipMemcpyAsync(c->d_elab_idx, c->elab_idx, sizeof(c->elab_idx), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->d_vlab_idx, c->vlab_idx, sizeof(c->vlab_idx), hipMemcpyHostToDevice, s));
+        // per-vertex filters and counters, per-slot edgeMatcher words: rebuilt
+        // from the edges present
+        dev_free(c->d_vf);
+        dev_free(c->d_cnt);
+        dev_alloc(c->d_vf, (size_t)c->nV * c->vf_words);
+        dev_alloc(c->d_cnt, (size_t)c->nV * c->n_cnt);
+        mn_launch_init_vertices(c->d_vf, c->d_cnt, c->nV, c->vf_words, c->n_cnt, s);
+        if (c->debi_words != old_words && c->cap_slots) {
+            dev_free(c->d_debi);
+            dev_alloc(c->d_debi, c->cap_slots * c->debi_words);
+        }
+        GraphView g = make_view(c, false);
+        mn_launch_reset(c->d_err, nullptr, 0, s);  // a failed batch may have left its error word set
+        mn_launch_reindex(g, c->d_debi_bits, c->n_debi_bits, c->fresh, c->d_key2slot, c->d_del_slot[c->pend],
+                          (uint32_t)c->n_pending, s);
+        mn_launch_vf_refresh(g, c->d_vf_bits, c->n_vf_bits, nullptr, c->nV, c->d_err, s);
+        // outputs and per-phase tallies for the new count of queries
+        for (auto& o : c->houts)
+            for (int p = 0; p < 2; p++) dev_free(o.keys[p]);
+        dev_free(c->d_outs);
+        c->houts.assign(n_q, OutView{});
+        for (uint32_t i = 0; i < n_q; i++)
+            for (int p = 0; p < 2; p++) {
+                c->houts[i].cap[p] = (c->flags & MNEMONIC_F_EMIT) ? c->out_cap0 : 0;
+                c->houts[i].keys[p] = nullptr;
+                if (c->flags & MNEMONIC_F_EMIT) dev_alloc(c->houts[i].keys[p], c->out_cap0 * c->hq[i].n_qe);
+            }
+        dev_alloc(c->d_outs, n_q);
+        HIPCHK(hipMemcpyAsync(c->d_outs, c->houts.data(), n_q * sizeof(OutView), hipMemcpyHostToDevice, s));
+        dev_free(c->d_zr);
+        c->n_zr = c->zr_words();
+        c->h_zr.assign(c->n_zr, 0);
+        dev_alloc(c->d_zr, c->n_zr);
+        // level buffers (their width follows the queries) and the sizing state
+        for (auto& B : c->lvb) {
+            dev_free(B.keys);
+            dev_free(B.rows);
+            dev_free(B.lo);
+            dev_free(B.cnt);
+            dev_free(B.off);
+        }
+        c->lvb.assign(c->max_levels, mnemonic_ctx::LevelBuf{});
+        for (int p = 0; p < 2; p++)
+            for (int L = 0; L <= MN_MAXLV; L++) c->rate[p][L] = -1.0;
+        c->have_result = false;
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));
+        return MNEMONIC_OK;
+    });
 }
 
 int mnemonic_set_scheduler(mnemonic_ctx* ctx, int mode, const float* weights) {

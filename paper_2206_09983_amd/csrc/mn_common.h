@@ -132,6 +132,11 @@ struct SeedPlan {
     LevelDesc lv[MN_MAXLV];
     CloseDesc close[MN_MAXCLOSE];
     uint16_t vars[MN_NVAR];       // plan index of each order of the pair
+    int8_t rank[MN_MAXQE];        // temporal rank per query edge (-1: unordered)
+    uint8_t rorder[MN_MAXQE];     // the ranked edges by ascending rank
+    uint8_t n_ranked;             // their number
+    uint8_t temporal;             // some pair of edges is ordered in time
+    uint8_t pad2[2];
     float lv_est[MN_MAXLV];       // log2(1 + expected candidates per row) of each level, from the
                                   // initial graph's label degrees and the level's class range
 };
@@ -199,6 +204,7 @@ struct GraphView {
     const int16_t* elab_idx;   // [256] compact index of an edge label, -1 if unused
     const int16_t* vlab_idx;   // [64] compact index of a vertex label bit, -1 if unused
     const uint32_t* ext2int;   // [n_vertices] caller's vertex id -> internal id
+    const uint32_t* key2slot;  // key -> slot of every edge present in the adjacency
     uint32_t n_elab_c;         // compact edge labels
     uint32_t n_vlab_c;         // compact vertex labels
     uint32_t n_static;         // plans holding the static orders

@@ -322,12 +322,85 @@ __device__ void grouped_digest(bool active, uint32_t q, uint64_t a, uint64_t b, 
     }
 }
 
+// Combination t of the closing edges' instances: digit i = which accepted
+// instance of close[i] (mixed radix over cnt[]).
+template <int NC>
+__device__ inline void combo_digits(uint64_t t, const uint32_t* cnt, uint32_t* dig) {
+    constexpr int NA = NC > 0 ? NC : 1;
+#pragma unroll
+    for (uint32_t i = 0; i < NA; i++) {
+        dig[i] = 0;
+        if (t) {  // t = 0 (the only tuple when every run holds one instance) has all digits 0
+            dig[i] = (uint32_t)(t % cnt[i]);
+            t /= cnt[i];
+        }
+    }
+}
+
+// Position of the dig-th accepted instance of closing edge ci in its run.
+template <int NC>
+__device__ inline uint32_t close_instance(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                                          const uint32_t* dig, uint32_t ci, RunIt& it) {
+    constexpr int NA = NC > 0 ? NC : 1;
+    uint32_t s_st = 0, s_dig = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < NA; i++)
+        if (i == ci) {
+            s_st = st[i];
+            s_dig = dig[i];
+        }
+    const CloseDesc c = P.close[ci];
+    it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
+    uint32_t unused = 0;
+    uint32_t p = run_next(it, it.p, unused);
+    for (uint32_t n = 0; n < s_dig; n++) p = run_next(it, p + 1, unused);
+    return p;
+}
+
+// Timestamp of the edge that query edge k maps to in combination dig.
+template <int NC>
+__device__ inline int64_t edge_ts(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                                  const uint32_t* dig, uint32_t k, uint32_t aqe, uint64_t akey) {
+    const uint32_t ci = P.close_idx[k];
+    if (k == aqe || ci == TREE_EDGE) {
+        const uint64_t key = k == aqe ? akey : B.tree_key(k);
+        return g.s_ts[g.key2slot[key]];
+    }
+    RunIt it;
+    const uint32_t p = close_instance<NC>(g, P, B, st, dig, ci, it);
+    return g.s_ts[ent_lo(it.adj[p]) & MN_SLOTMASK];
+}
+
+// Temporal order of one complete embedding: walking the ranked edges by
+// ascending rank, every edge's timestamp exceeds the largest timestamp of
+// all lower ranks.
+template <int NC>
+__device__ bool in_time_order(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                              const uint32_t* dig, uint32_t aqe, uint64_t akey) {
+    int64_t below = INT64_MIN, level = INT64_MIN;
+    int cur = -1;
+    for (uint32_t x = 0; x < P.n_ranked; x++) {
+        const uint32_t k = P.rorder[x];
+        if (P.rank[k] != cur) {  // a new rank level: the previous one joins the ranks below
+            below = max(below, level);
+            level = INT64_MIN;
+            cur = P.rank[k];
+        }
+        const int64_t t = edge_ts<NC>(g, P, B, st, dig, k, aqe, akey);
+        if (!(below < t)) return false;
+        level = max(level, t);
+    }
+    return true;
+}
+
 // Number of embeddings of a complete vertex mapping: the product over the
 // closing edges of their accepted instances (st[i] is the run start of
-// close[i]); cnt[i] receives each factor.
+// close[i]; cnt[i] receives each factor), or, for a plan with a temporal
+// order, the combinations of instances that satisfy it. aqe/akey: the anchor
+// query edge of the level and its edge (0xFF: none).
 template <int NC>
 __device__ uint64_t close_mult(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                               uint32_t* cnt, uint32_t& probes) {
+                               uint32_t* cnt, uint32_t& probes, uint32_t aqe, uint64_t akey) {
     constexpr int NA = NC > 0 ? NC : 1;
     uint64_t mult = 1;
 #pragma unroll
@@ -341,6 +414,15 @@ __device__ uint64_t close_mult(const GraphView& g, const SeedPlan& P, const Bind
             cnt[i] = n;
             mult *= n;
         }
+    }
+    if (P.temporal && mult) {
+        uint64_t ok = 0;
+        for (uint64_t t = 0; t < mult; t++) {
+            uint32_t dig[NA];
+            combo_digits<NC>(t, cnt, dig);
+            ok += in_time_order<NC>(g, P, B, st, dig, aqe, akey) ? 1u : 0u;
+        }
+        mult = ok;
     }
     return mult;
 }
@@ -363,21 +445,23 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
     const uint32_t nqe = P.n_qe;
     const uint64_t s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
     const uint64_t s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
-    uint32_t unused = 0;
-    for (uint64_t t = 0; t < mult; t++) {
-        uint32_t dig[NA];
-        uint64_t rem = t;
+    // every combination of instances; under a temporal order only those
+    // that satisfy it (close_mult counted exactly those: mult of them)
+    uint64_t total = mult;
+    if (P.temporal) {
+        total = 1;
 #pragma unroll
-        for (uint32_t i = 0; i < NA; i++) {
-            dig[i] = 0;
-            if (rem) {  // t = 0 (the only tuple when every run holds one instance) has all digits 0
-                dig[i] = (uint32_t)(rem % cnt[i]);
-                rem /= cnt[i];
-            }
-        }
+        for (uint32_t i = 0; i < NA; i++) total *= cnt[i];
+    }
+    uint64_t j = 0;
+    for (uint64_t t = 0; t < total && j < mult; t++) {
+        uint32_t dig[NA];
+        combo_digits<NC>(t, cnt, dig);
+        if (P.temporal && !in_time_order<NC>(g, P, B, st, dig, aqe, akey)) continue;
         uint64_t hA = s0A, hB = s0B;
-        const bool write = po.emit && (pos + t) < cap;
-        uint64_t* row = out + (pos + t) * nqe;
+        const bool write = po.emit && (pos + j) < cap;
+        uint64_t* row = out + (pos + j) * nqe;
+        j++;
         for (uint32_t k = 0; k < nqe; k++) {
             uint64_t key;
             const uint32_t ci = P.close_idx[k];
@@ -386,17 +470,8 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
             } else if (ci == TREE_EDGE) {
                 key = B.tree_key(k);
             } else {
-                uint32_t s_st = 0, s_dig = 0;
-#pragma unroll
-                for (uint32_t i = 0; i < NA; i++)
-                    if (i == ci) {
-                        s_st = st[i];
-                        s_dig = dig[i];
-                    }
-                const CloseDesc c = P.close[ci];
-                const RunIt it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
-                uint32_t p = run_next(it, it.p, unused);  // walks runs counted by close_mult
-                for (uint32_t n = 0; n < s_dig; n++) p = run_next(it, p + 1, unused);
+                RunIt it;
+                const uint32_t p = close_instance<NC>(g, P, B, st, dig, ci, it);  // walks runs counted by close_mult
                 key = p < it.end ? it.adjk[p] : 0ull;  // p < end: the instances were counted
             }
             K.keys++;
@@ -419,7 +494,7 @@ __device__ void emit_complete(const GraphView& g, const SeedPlan& P, const Bind&
                               Cnt& K) {
     constexpr int NA = NC > 0 ? NC : 1;
     uint32_t cnt[NA];
-    const uint64_t mult = active ? close_mult<NC>(g, P, B, st, cnt, K.probes) : 0u;
+    const uint64_t mult = active ? close_mult<NC>(g, P, B, st, cnt, K.probes, aqe, akey) : 0u;
     const uint32_t q = P.q;
     const uint64_t pos = grouped_reserve(mult != 0, q, mult, po.count);
     uint64_t dA = 0, dB = 0;
@@ -791,6 +866,19 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                         break;
                     }
             }
+            if (ok && P->temporal && P->rank[lv.qe] >= 0) {
+                // timestamps never decrease with keys, so the order of two
+                // tree edges' keys must agree with the order of their ranks
+                const uint64_t nk = g.adjk[lv.dir][p];
+                const int rn = P->rank[lv.qe];
+                for (uint32_t l = 0; l <= L && ok; l++) {
+                    const uint32_t k = l == 0 ? P->j : P->lv[l - 1].qe;
+                    const int rk = P->rank[k];
+                    if (rk < 0 || rk == rn) continue;
+                    const uint64_t kk = rkey(in, k, r);
+                    if (rk < rn ? !(kk < nk) : !(nk < kk)) ok = false;
+                }
+            }
 #pragma unroll
             for (uint32_t c = 0; c < NA; c++) {
                 if (ok && c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
@@ -828,7 +916,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                     if (c < (uint32_t)NC && c < P->n_close && !(c >= lv.c_begin && c < lv.c_end))
                         st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
                 uint32_t cnt[NA];
-                mult = close_mult<NC>(g, *P, B, st, cnt, K.probes);
+                mult = close_mult<NC>(g, *P, B, st, cnt, K.probes, lv.qe, P->temporal ? g.adjk[lv.dir][p] : 0ull);
             }
             const uint64_t lpos = grouped_reserve(mult != 0, P->q, mult, s_qn);
             if (mult) loc = (uint32_t)lpos;
@@ -907,7 +995,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                         st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
                 uint32_t cnt[NA];
                 uint32_t unused = 0;
-                const uint64_t mult = close_mult<NC>(g, *P, B, st, cnt, unused);
+                const uint64_t mult = close_mult<NC>(g, *P, B, st, cnt, unused, lv.qe, akey);
                 emit_tuples<NC>(g, *P, B, st, cnt, mult, lv.qe, akey, s_qn[P->q] + loc, po, K, dA, dB);
             }
             grouped_digest(last, P->q, dA, dB, A.dig);

@@ -51,6 +51,25 @@ __device__ void count_edge(const GraphView& g, uint32_t s, uint32_t d, uint32_t 
     }
 }
 
+// edgeMatcher (Section III) of one slot: per query edge, the edge label is
+// equal or the query label empty, and both endpoint label sets contain the
+// query vertices' required sets. Writes the slot's DEBI words.
+__device__ void match_edge(const GraphView& g, const DebiBit* __restrict__ bits, uint32_t n_bits, uint32_t slot,
+                           uint32_t s, uint32_t d, uint32_t l) {
+    const uint64_t ms = g.vmask[s], md = g.vmask[d];
+    for (uint32_t w = 0; w < g.debi_words; w++) {
+        uint32_t word = 0;
+        const uint32_t lo = w * 32, hi = min(lo + 32, n_bits);
+        for (uint32_t bit = lo; bit < hi; bit++) {
+            const DebiBit db = bits[bit];
+            const bool m = (db.label < 0 || (uint32_t)db.label == l) && (db.req_src & ~ms) == 0 &&
+                           (db.req_dst & ~md) == 0;
+            word |= (uint32_t)m << (bit - lo);
+        }
+        g.s_debi[(size_t)slot * g.debi_words + w] = word;
+    }
+}
+
 __global__ __launch_bounds__(MN_BLOCK) void k_reset(uint32_t* err, unsigned long long* a, uint32_t n) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *err = 0;
@@ -103,20 +122,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
     g.s_ts[slot] = b.in_ts[i];
     g.s_key[slot] = key;
     b.key2slot[key] = slot;
-    // edgeMatcher (Section III): edge label equal or query label empty, and
-    // both endpoint label sets contain the query vertices' required sets.
-    uint64_t ms = g.vmask[s], md = g.vmask[d];
-    for (uint32_t w = 0; w < g.debi_words; w++) {
-        uint32_t word = 0;
-        uint32_t lo = w * 32, hi = min(lo + 32, b.n_debi_bits);
-        for (uint32_t bit = lo; bit < hi; bit++) {
-            DebiBit db = b.debi_bits[bit];
-            bool m = (db.label < 0 || (uint32_t)db.label == l) && (db.req_src & ~ms) == 0 &&
-                     (db.req_dst & ~md) == 0;
-            word |= (uint32_t)m << (bit - lo);
-        }
-        g.s_debi[(size_t)slot * g.debi_words + w] = word;
-    }
+    match_edge(g, b.debi_bits, b.n_debi_bits, slot, s, d, l);
     count_edge(g, s, d, l, 1u);
     uint64_t hs = ((uint64_t)l << g.nbr_bits) | d;  // out-entry high word
     uint64_t hd = ((uint64_t)l << g.nbr_bits) | s;  // in-entry high word
@@ -127,6 +133,25 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
     b.ins_slot[i] = slot;
     b.touched[2 * b.n_prev_del + 2 * i] = s;
     b.touched[2 * b.n_prev_del + 2 * i + 1] = d;
+}
+
+// After the query set changed: edgeMatcher words of every live slot, and the
+// local-filter counters of every edge the counters hold: the live ones and
+// those deleted by the last batch (the next batch decrements them).
+__global__ __launch_bounds__(MN_BLOCK) void k_reindex(GraphView g, const DebiBit* __restrict__ bits, uint32_t n_bits,
+                                                      uint32_t n_slots, const uint32_t* __restrict__ key2slot,
+                                                      const uint32_t* __restrict__ pend, uint32_t n_pend) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_slots) {
+        const uint32_t slot = i;
+        if (key2slot[g.s_key[slot]] != slot) return;  // retired (or recycled under another key)
+        const uint32_t s = g.s_src[slot], d = g.s_dst[slot], l = g.s_lab[slot];
+        match_edge(g, bits, n_bits, slot, s, d, l);
+        count_edge(g, s, d, l, 1u);
+    } else if (i < n_slots + n_pend) {
+        const uint32_t slot = pend[i - n_slots];
+        count_edge(g, g.s_src[slot], g.s_dst[slot], g.s_lab[slot], 1u);
+    }
 }
 
 __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __restrict__ off, uint32_t nv,
@@ -411,6 +436,12 @@ void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* a
     if (n_b)
         k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, kbase, bvals, s_key, n_b, dpos,
                                                       dbase, hb, adj_new, adjk_new, inspos, e_new, err);
+}
+
+void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits, uint32_t n_slots,
+                       const uint32_t* key2slot, const uint32_t* pend, uint32_t n_pend, hipStream_t s) {
+    const uint64_t n = (uint64_t)n_slots + n_pend;
+    if (n) k_reindex<<<nblocks(n), MN_BLOCK, 0, s>>>(g, bits, n_bits, n_slots, key2slot, pend, n_pend);
 }
 
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,

@@ -90,6 +90,12 @@ void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* a
                      uint32_t* inspos, uint32_t e_new, uint32_t* tile_v, uint32_t* err, hipStream_t s);
 // Words tile_v needs for a merge of e_old old entries, minus one.
 uint32_t mn_merge_tiles(uint32_t e_old);
+// Query-dependent state of the present edges after a change of the query
+// set: edgeMatcher words of the live slots among [0, n_slots) and counter
+// increments for them and for the n_pend slots deleted by the last batch.
+// The counters must be zero before.
+void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits, uint32_t n_slots,
+                       const uint32_t* key2slot, const uint32_t* pend, uint32_t n_pend, hipStream_t s);
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
 void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,

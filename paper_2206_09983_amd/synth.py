@@ -276,6 +276,38 @@ def rmat_case(scale=20, n_init=1 << 24, n_stream=1 << 23, batch=65536, del_frac=
             "batches": batches, "queries": queries}
 
 
+def serving_edges(scale=22, n_window=1 << 26, n_arrivals=1 << 25, seed=7, n_vlabels=16, n_elabels=32, s=1.2,
+                  multi_p=0.10):
+    """The edges of the serving workload: R-MAT (same parameters and label
+    Zipfs as rmat_case) with n_window edges for the initial window followed by
+    n_arrivals streamed edges. Timestamps come from serving_times."""
+    rng = _rng(seed)
+    m = n_window + n_arrivals
+    src, dst = rmat_pairs(rng, scale, m, multi_p=multi_p)
+    n = 1 << scale
+    vl = zipf_draw(rng, n_vlabels, s, n)
+    el = zipf_draw(rng, n_elabels, s, m).astype(np.uint8)
+    vmask = (np.uint64(1) << vl.astype(np.uint64)).astype(np.uint64)
+    return {"n_vertices": n, "vlabel_mask": vmask, "src": src.astype(np.uint32), "dst": dst.astype(np.uint32),
+            "elabel": el, "n_window": n_window}
+
+
+def serving_times(edges, window_ticks=1 << 24, rate=1e6, tick_s=1e-6, seed=7):
+    """Initial window: its edges spread evenly over window_ticks (ts = key *
+    window / n_window). Arrivals: a Poisson process at `rate` edges per second
+    (exponential gaps, ticks of tick_s seconds, ts rounded down), starting at
+    the end of the window. Returns (graph, (src, dst, elabel, ts))."""
+    nw = edges["n_window"]
+    rng = _rng(seed + 3000 + int(rate))
+    ts0 = (np.arange(nw, dtype=np.float64) * (window_ticks / nw)).astype(np.int64)
+    graph = make_graph(edges["n_vertices"], edges["vlabel_mask"], edges["src"][:nw], edges["dst"][:nw],
+                       edges["elabel"][:nw], ts=ts0)
+    n = len(edges["src"]) - nw
+    gaps = rng.exponential(1.0 / (rate * tick_s), n)
+    ts = (window_ticks + np.floor(np.cumsum(gaps))).astype(np.int64)
+    return graph, (edges["src"][nw:], edges["dst"][nw:], edges["elabel"][nw:], ts)
+
+
 def random_connected_query(rng, nv, n_extra, n_vlabels, n_elabels, wild_p, sem):
     """Random weakly connected simple digraph query (no self-loops, at most one
     edge per ordered pair)."""

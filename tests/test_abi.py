@@ -39,7 +39,8 @@ def test_struct_layouts_match_header_order():
     # field order of the binding's structures follows the header's typedefs
     text = open(HEADER).read()
     for cname, cls in (("mnemonic_graph", binding.mnemonic_graph), ("mnemonic_edges", binding.mnemonic_edges),
-                       ("mnemonic_result", binding.mnemonic_result), ("mnemonic_stats", binding.mnemonic_stats)):
+                       ("mnemonic_result", binding.mnemonic_result), ("mnemonic_stats", binding.mnemonic_stats),
+                       ("mnemonic_query", binding.mnemonic_query)):
         body = re.search(r"typedef struct \{([^}]*)\}\s*%s;" % cname, text).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = re.findall(r"\*?\s*([a-z_]+)(?:\[\d\])?\s*[;,]", body)

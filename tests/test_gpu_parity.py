@@ -261,3 +261,30 @@ def test_device_resident_inputs(B):
     finally:
         m.close()
         o.close()
+
+
+# ------------------------------------------------------------ temporal order
+@pytest.mark.parametrize("ties", [False, True])
+def test_temporal_order_tiny_streams(B, ties):
+    total = 0
+    for seed in range(120):
+        total += run_parity(B, synth.temporal_tiny_case(seed, ts_ties=ties))
+    assert total > 20
+
+
+def test_temporal_order_rmat_and_multiquery():
+    from paper_2206_09983_amd import binding as B
+    B.load()
+    # ranks in query-edge order (each edge later than the one before), and
+    # random ranks with ties and unordered edges
+    case = synth.rmat_case(scale=11, n_init=20000, n_stream=6144, batch=2048, n_batches=3)
+    rng = np.random.default_rng(3)
+    qs = []
+    for q in case["queries"]:
+        m = len(q["qsrc"])
+        qs.append(synth.with_ranks(q, np.arange(m)))
+        qs.append(synth.with_ranks(q, rng.integers(-1, 3, size=m)))
+    assert run_parity(B, dict(case, queries=qs, name=case["name"] + "_temporal")) > 0
+    mq = synth.multiquery_case(scale=11, n_init=20000, n_stream=12000, n_queries=64, lo=100, hi=6000)
+    mq["queries"] = [synth.with_ranks(q, np.arange(len(q["qsrc"]))) for q in mq["queries"]]
+    assert run_parity(B, mq, out_capacity=1 << 12) >= 0
