@@ -146,6 +146,7 @@ struct mnemonic_ctx {
     // key arrays
     uint64_t cap_keys = 0, cap_delbits = 0;
     uint32_t* d_key2slot = nullptr;
+    int64_t* d_key_ts = nullptr;  // timestamp by key (kept for retired keys too)
     uint32_t* d_delbits = nullptr;
 
     // adjacency, double-buffered
@@ -689,7 +690,7 @@ GraphView make_view(const mnemonic_ctx* c, bool next) {
     g.elab_idx = c->d_elab_idx;
     g.vlab_idx = c->d_vlab_idx;
     g.ext2int = c->d_ext2int;
-    g.key2slot = c->d_key2slot;
+    g.key_ts = c->d_key_ts;
     g.n_elab_c = c->n_elab_c;
     g.n_vlab_c = c->n_vlab_c;
     g.n_static = c->n_static;
@@ -729,6 +730,8 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     if (need_keys > c->cap_keys) {
         uint64_t cap = c->cap_keys;
         dev_grow(c->d_key2slot, cap, need_keys, c->next_key, s);
+        uint64_t tcap = c->cap_keys;
+        dev_grow(c->d_key_ts, tcap, need_keys, c->next_key, s);
         uint64_t bcap = c->cap_delbits;
         dev_grow(c->d_delbits, bcap, (cap + 31) / 32 + 1, c->cap_delbits, s);
         if (bcap > c->cap_delbits)
@@ -1484,6 +1487,7 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_debi);
     dev_free(c->d_free);
     dev_free(c->d_key2slot);
+    dev_free(c->d_key_ts);
     dev_free(c->d_delbits);
     for (int k = 0; k < 2; k++) {
         dev_free(c->d_skey[k]);

@@ -204,7 +204,8 @@ struct GraphView {
     const int16_t* elab_idx;   // [256] compact index of an edge label, -1 if unused
     const int16_t* vlab_idx;   // [64] compact index of a vertex label bit, -1 if unused
     const uint32_t* ext2int;   // [n_vertices] caller's vertex id -> internal id
-    const uint32_t* key2slot;  // key -> slot of every edge present in the adjacency
+    int64_t* key_ts;           // key -> timestamp of every edge ever inserted (never invalidated:
+                               // a re-run of a phase may still meet edges its batch deleted)
     uint32_t n_elab_c;         // compact edge labels
     uint32_t n_vlab_c;         // compact vertex labels
     uint32_t n_static;         // plans holding the static orders

@@ -120,6 +120,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
     g.s_dst[slot] = d;
     g.s_lab[slot] = (uint8_t)l;
     g.s_ts[slot] = b.in_ts[i];
+    g.key_ts[key] = b.in_ts[i];
     g.s_key[slot] = key;
     b.key2slot[key] = slot;
     match_edge(g, b.debi_bits, b.n_debi_bits, slot, s, d, l);

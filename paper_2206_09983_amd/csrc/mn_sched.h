@@ -95,75 +95,69 @@ __device__ inline float bf16_round(float v) {
     return __uint_as_float(u & 0xFFFF0000u);
 }
 
-// LDS image of the network: bf16 weights with W2 transposed (W2t[u2][u]) so
-// that the inner products of the second layer read contiguous words.
+// LDS image of the network: the bf16 weights, widened to fp32 once per block
+// (exact: a bf16 value is an fp32 value with a zero low half), W2 transposed
+// (W2t[u2][u]) so that the second layer's inner products read contiguous
+// words. Widening once spares every evaluation two ALU operations per weight.
 struct __align__(16) NetLds {
-    uint16_t w1[NI * NH];
-    uint16_t b1[NH];
-    uint16_t w2t[NH * NH];
-    uint16_t b2[NH];
-    uint16_t w3[NH];
-    uint16_t b3[2];
+    float w1[NI * NH];
+    float b1[NH];
+    float w2t[NH * NH];
+    float b2[NH];
+    float w3[NH];
+    float b3[4];
 };
 
 __device__ inline void load_net(NetLds& N, const uint16_t* __restrict__ w) {
-    for (int i = threadIdx.x; i < NI * NH; i += blockDim.x) N.w1[i] = w[OFF_W1 + i];
+    for (int i = threadIdx.x; i < NI * NH; i += blockDim.x) N.w1[i] = bf(w[OFF_W1 + i]);
     for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {  // consecutive LDS words per wave
         const int u2 = i / NH, u = i % NH;
-        N.w2t[i] = w[OFF_W2 + u * NH + u2];
+        N.w2t[i] = bf(w[OFF_W2 + u * NH + u2]);
     }
     for (int i = threadIdx.x; i < NH; i += blockDim.x) {
-        N.b1[i] = w[OFF_B1 + i];
-        N.b2[i] = w[OFF_B2 + i];
-        N.w3[i] = w[OFF_W3 + i];
+        N.b1[i] = bf(w[OFF_B1 + i]);
+        N.b2[i] = bf(w[OFF_B2 + i]);
+        N.w3[i] = bf(w[OFF_W3 + i]);
     }
-    if (threadIdx.x == 0) N.b3[0] = w[OFF_B3];
-}
-
-// Eight bf16 weights from one 16-byte LDS word.
-__device__ inline void bf8(const uint16_t* p, float* w) {
-    const uint4 q = *reinterpret_cast<const uint4*>(p);
-    const uint32_t a[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        w[2 * k] = __uint_as_float(a[k] << 16);
-        w[2 * k + 1] = __uint_as_float(a[k] & 0xFFFF0000u);
-    }
+    if (threadIdx.x == 0) N.b3[0] = bf(w[OFF_B3]);
 }
 
 // One lane, one sample: inputs rounded to bf16, bf16 weights, fp32 sums. The
-// hidden layer stays in registers; weights stream from LDS eight at a time
-// (every lane of a wave reads the same word, a broadcast).
+// hidden layer stays in registers; weights stream from LDS four at a time
+// (every lane of a wave reads the same words, a broadcast).
 __device__ inline float eval(const NetLds& N, const float* x) {
     float h[NH];
 #pragma unroll
-    for (int u = 0; u < NH; u += 8) bf8(N.b1 + u, h + u);
+    for (int u = 0; u < NH; u++) h[u] = N.b1[u];
 #pragma unroll 1
     for (int i = 0; i < NI; i++) {
         const float xi = bf16_round(x[i]);
+        const float4* row = reinterpret_cast<const float4*>(N.w1 + i * NH);
 #pragma unroll
-        for (int u = 0; u < NH; u += 8) {
-            float w[8];
-            bf8(N.w1 + i * NH + u, w);
-#pragma unroll
-            for (int k = 0; k < 8; k++) h[u + k] = fmaf(xi, w[k], h[u + k]);
+        for (int u = 0; u < NH / 4; u++) {
+            const float4 w = row[u];
+            h[4 * u] = fmaf(xi, w.x, h[4 * u]);
+            h[4 * u + 1] = fmaf(xi, w.y, h[4 * u + 1]);
+            h[4 * u + 2] = fmaf(xi, w.z, h[4 * u + 2]);
+            h[4 * u + 3] = fmaf(xi, w.w, h[4 * u + 3]);
         }
     }
 #pragma unroll
     for (int u = 0; u < NH; u++) h[u] = fmaxf(h[u], 0.0f);
-    float y = bf(N.b3[0]);
+    float y = N.b3[0];
 #pragma unroll 1
     for (int u2 = 0; u2 < NH; u2++) {
-        float z = bf(N.b2[u2]);
-        const uint16_t* col = N.w2t + u2 * NH;
+        float z = N.b2[u2];
+        const float4* col = reinterpret_cast<const float4*>(N.w2t + u2 * NH);
 #pragma unroll
-        for (int u = 0; u < NH; u += 8) {
-            float w[8];
-            bf8(col + u, w);
-#pragma unroll
-            for (int k = 0; k < 8; k++) z = fmaf(h[u + k], w[k], z);
+        for (int u = 0; u < NH / 4; u++) {
+            const float4 w = col[u];
+            z = fmaf(h[4 * u], w.x, z);
+            z = fmaf(h[4 * u + 1], w.y, z);
+            z = fmaf(h[4 * u + 2], w.z, z);
+            z = fmaf(h[4 * u + 3], w.w, z);
         }
-        y = fmaf(fmaxf(z, 0.0f), bf(N.w3[u2]), y);
+        y = fmaf(fmaxf(z, 0.0f), N.w3[u2], y);
     }
     return y;
 }

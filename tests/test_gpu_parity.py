@@ -288,3 +288,15 @@ def test_temporal_order_rmat_and_multiquery():
     mq = synth.multiquery_case(scale=11, n_init=20000, n_stream=12000, n_queries=64, lo=100, hi=6000)
     mq["queries"] = [synth.with_ranks(q, np.arange(len(q["qsrc"]))) for q in mq["queries"]]
     assert run_parity(B, mq, out_capacity=1 << 12) >= 0
+
+
+def test_temporal_order_survives_phase_reruns(B):
+    # Output buffers of one tuple and level buffers of 1,024 rows force
+    # re-runs of both phases after the batch has retired its deleted keys;
+    # the timestamps of those deleted edges must still be readable then.
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=3072, batch=1024, n_batches=3)
+    qs = [synth.with_ranks(q, np.arange(len(q["qsrc"]))) for q in case["queries"]]
+    qs += [synth.with_ranks(q, np.arange(len(q["qsrc"]))[::-1].copy()) for q in case["queries"]]
+    tcase = dict(case, queries=qs, name=case["name"] + "_temporal_reruns")
+    assert run_parity(B, tcase, out_capacity=1) > 0
+    assert run_parity(B, tcase, rows_per_level=1024) > 0
