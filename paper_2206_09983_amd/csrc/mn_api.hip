@@ -76,7 +76,9 @@ void dev_free(T*& p) {
 template <typename T>
 void dev_grow(T*& p, uint64_t& cap, uint64_t need, uint64_t keep, hipStream_t s) {
     if (need <= cap && p) return;
-    uint64_t nc = std::max<uint64_t>(need, cap + cap / 2);
+    // twice the need: a regrowth stalls the stream (allocation, copy, free),
+    // and the device has memory to spare for a stream that keeps growing
+    uint64_t nc = std::max<uint64_t>(2 * need, 2 * cap);
     nc = std::max<uint64_t>(nc, 256);
     T* np = nullptr;
     dev_alloc(np, nc);
@@ -708,6 +710,10 @@ GraphView make_view(const mnemonic_ctx* c, bool next) {
 
 // Makes every buffer large enough for a snapshot of n_ins insertions and
 // n_del deletions.
+// Batch scratch starts sized for this many edges (and doubles past it), so
+// that batches of up to 2^18 insertions or deletions never stop to allocate.
+constexpr uint64_t kScratchMin = 1ull << 18;
+
 void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     hipStream_t s = c->stream;
     uint64_t need_slots = (uint64_t)c->fresh + (n_ins > c->n_free ? n_ins - c->n_free : 0);
@@ -755,7 +761,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         if (d == 1) c->cap_E = t;
     }
     if (n_ins > c->cap_ins) {
-        uint64_t nc = std::max<uint64_t>(n_ins, c->cap_ins + c->cap_ins / 2);
+        uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_ins, kScratchMin), 2 * c->cap_ins);
         dev_free(c->d_in_src);
         dev_free(c->d_in_dst);
         dev_free(c->d_in_lab);
@@ -779,7 +785,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         c->cap_ins = nc;
     }
     if (n_del > c->cap_del) {
-        uint64_t nc = std::max<uint64_t>(n_del, c->cap_del + c->cap_del / 2);
+        uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_del, kScratchMin), 2 * c->cap_del);
         dev_free(c->d_del_keys);
         dev_alloc(c->d_del_keys, nc);
         c->cap_del = nc;
@@ -787,7 +793,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     // the delete buffer that receives this snapshot's deletions
     int cur = 1 - c->pend;
     if (n_del > c->cap_delbuf[cur]) {
-        uint64_t nc = std::max<uint64_t>(n_del, c->cap_delbuf[cur] + c->cap_delbuf[cur] / 2);
+        uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_del, kScratchMin), 2 * c->cap_delbuf[cur]);
         dev_free(c->d_del_slot[cur]);
         dev_alloc(c->d_del_slot[cur], nc);
         for (int d = 0; d < 2; d++) {
@@ -798,7 +804,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     }
     uint64_t n_sort = std::max<uint64_t>(n_ins, c->n_pending);
     if (n_sort > c->cap_sort) {
-        uint64_t nc = std::max<uint64_t>(n_sort, c->cap_sort + c->cap_sort / 2);
+        uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_sort, kScratchMin), 2 * c->cap_sort);
         for (int k = 0; k < 2; k++) {
             dev_free(c->d_dkey[k]);
             dev_free(c->d_dval[k]);
@@ -807,7 +813,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         }
         c->cap_sort = nc;
     }
-    uint64_t ssw = mn_sort_scratch_words((uint32_t)std::max<uint64_t>(2 * n_sort, 1));
+    uint64_t ssw = mn_sort_scratch_words((uint32_t)std::max<uint64_t>(2 * n_sort, 2 * kScratchMin));
     if (ssw > c->cap_sort_scratch) {
         dev_free(c->d_sort_scratch);
         dev_alloc(c->d_sort_scratch, ssw);
@@ -815,7 +821,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     }
     uint64_t n_touch = 2 * (c->n_pending + n_ins);
     if (n_touch > c->cap_touch) {
-        uint64_t nc = std::max<uint64_t>(n_touch, c->cap_touch + c->cap_touch / 2);
+        uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_touch, 2 * kScratchMin), 2 * c->cap_touch);
         dev_free(c->d_touched);
         dev_alloc(c->d_touched, nc);
         c->cap_touch = nc;
