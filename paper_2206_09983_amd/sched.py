@@ -174,8 +174,11 @@ def choice_work(w, x, work, plan=None, queries=None, bf16=True):
     pick = np.argmin(y, axis=1)
     best = np.where(work >= 0, work, np.iinfo(np.int64).max).min(axis=1)
     chosen = work[np.arange(n), pick]
-    out = {"static": int(work[:, 0].sum()), "learned": int(chosen.sum()), "best": int(best.sum()), "entries": n,
-           "picked_other": float(np.mean(pick != 0))}
+    # a plain rule for comparison: the order whose first level has the fewest candidates
+    first = np.where(work >= 0, x[:, :, 4], np.inf)
+    rule = work[np.arange(n), np.argmin(first, axis=1)]
+    out = {"static": int(work[:, 0].sum()), "learned": int(chosen.sum()), "best": int(best.sum()),
+           "smallest_first_level": int(rule.sum()), "entries": n, "picked_other": float(np.mean(pick != 0))}
     if plan is not None and queries is not None:
         base = np.cumsum([0] + [len(q["qsrc"]) for q in queries])
         qi = np.searchsorted(base, plan, side="right") - 1
@@ -246,7 +249,8 @@ def main(argv=None):
     ap.add_argument("--out", required=True)
     ap.add_argument("--entries", type=int, default=2_000_000, help="traced start rows per workload (at most)")
     ap.add_argument("--batches", type=int, default=128, help="most batches traced per workload")
-    ap.add_argument("--epochs", type=int, default=24)
+    ap.add_argument("--epochs", type=int, default=48)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-batches", type=int, default=10)
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--workloads", default="rmat,multiquery")
@@ -278,7 +282,7 @@ def main(argv=None):
     val, tr = perm[:n_val], perm[n_val:]
     X, Y = samples(x[tr], work[tr])
     Xv, Yv = samples(x[val], work[val])
-    w, hist = train(X, Y, epochs=a.epochs, log_every=1)
+    w, hist = train(X, Y, epochs=a.epochs, lr=a.lr, log_every=1)
     yv = predict(w, Xv, bf16=True)
     val_mse = float(np.mean((yv - Yv) ** 2))
     base_mse = float(np.mean((Yv - np.mean(Y)) ** 2))
