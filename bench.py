@@ -281,10 +281,11 @@ def main():
             log("no order-cost network weights found: timing the static order only")
             args.scheduler = "static"
 
-    def run(mode, tag):
-        """Warm-up, then the timed steps, under one scheduler mode."""
+    def run(mode, tag, fl=None):
+        """Warm-up, then the timed steps, under one scheduler mode (and flags)."""
         t0 = time.perf_counter()
-        m = binding.Matcher(case["graph"], case["queries"], flags=flags, out_capacity=args.out_capacity,
+        m = binding.Matcher(case["graph"], case["queries"], flags=flags if fl is None else fl,
+                            out_capacity=args.out_capacity,
                             stream=stream.cuda_stream, n_elabels=32)
         m.set_scheduler(mode, weights if mode == binding.SCHED_LEARNED else None)
         torch.cuda.synchronize()
@@ -341,6 +342,19 @@ def main():
             learned["ms_per_step"], elapsed * 1e3 / args.steps, learned["ratio"], learned["identical_results"]))
         if not learned["identical_results"]:
             raise SystemExit("the learned scheduler changed the results")
+    # the same batches without writing tuples (counts and digests only), and
+    # with the index maintained but nothing enumerated
+    rates = None
+    if args.scheduler != "learned" and not args.count_only:
+        C = run(binding.SCHED_STATIC, "count-only", binding.F_TIMING)
+        I = run(binding.SCHED_STATIC, "index-only", binding.F_TIMING | binding.F_INDEX_ONLY)
+        if C["results"] != R["results"]:
+            raise SystemExit("count-only mode changed the counts or digests")
+        rates = {"count_only": C["edges"] / C["elapsed"], "index_only": I["edges"] / I["elapsed"],
+                 "count_only_ms_per_step": C["elapsed"] * 1e3 / args.steps,
+                 "index_only_ms_per_step": I["elapsed"] * 1e3 / args.steps}
+        log("count-only %.3f ms per step, index-only %.3f ms per step" % (
+            rates["count_only_ms_per_step"], rates["index_only_ms_per_step"]))
 
     if args.count_only:
         tot["tuple_words"] = 0
@@ -387,6 +401,7 @@ def main():
         "scheduler": args.scheduler if args.scheduler != "both" else "static",
         "learned_vs_plain": learned["ratio"] if learned else None,
         "learned": learned,
+        "rates": rates,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -101,6 +101,9 @@ typedef struct {
 #define MNEMONIC_F_AUTOTUNE 4u /* the first batches try each expansion tile size (256, 512,
                                   1024 candidates per block) twice and keep the fastest per
                                   candidate; results do not depend on the choice */
+#define MNEMONIC_F_INDEX_ONLY 8u /* maintain the graph and its index (Algorithm 2's updates,
+                                    edgeMatcher, filters) but enumerate nothing: results stay
+                                    empty; measures the update path alone */
 
 typedef struct {
     uint32_t flags;          /* MNEMONIC_F_* */

@@ -19,6 +19,7 @@ HOMO = 1
 F_EMIT = 1
 F_TIMING = 2
 F_AUTOTUNE = 4
+F_INDEX_ONLY = 8
 SCHED_STATIC = 0
 SCHED_LEARNED = 1
 SCHED_FIXED = 2

@@ -1294,12 +1294,13 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     };
     swap_in();
     uint32_t err = 0;
+    const bool enum_on = enumerate && !(c->flags & MNEMONIC_F_INDEX_ONLY);
     try {
-        if (enumerate) enumerate_phase(c, 0, c->d_ins_slot, n_ins);
+        if (enum_on) enumerate_phase(c, 0, c->d_ins_slot, n_ins);
         for (int d = 0; d < 2; d++) mn_launch_set_flags(adjn[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
         GraphView g2 = make_view(c, false);
         mn_launch_flag_del(g2, adjn[0], adjn[1], b, s);
-        if (enumerate) enumerate_phase(c, 1, c->d_del_slot[cur], n_del);
+        if (enum_on) enumerate_phase(c, 1, c->d_del_slot[cur], n_del);
         uint32_t n_free_after = c->n_free - (uint32_t)std::min<uint64_t>(n_ins, c->n_free);
         mn_launch_finalize(b, n_free_after, s);
         if (timing) HIPCHK(hipEventRecord(c->ev[5], s));
@@ -1332,7 +1333,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     c->n_pending = n_del;
     c->pend = cur;
 
-    if (enumerate) {
+    if (enum_on) {
         // outputs too small, or a level's buffers too small: grow and
         // enumerate the phase again on the same state (the flags of the
         // phase being re-run are restored first)

@@ -300,3 +300,22 @@ def test_temporal_order_survives_phase_reruns(B):
     tcase = dict(case, queries=qs, name=case["name"] + "_temporal_reruns")
     assert run_parity(B, tcase, out_capacity=1) > 0
     assert run_parity(B, tcase, rows_per_level=1024) > 0
+
+
+def test_index_only_mode_keeps_the_graph_and_reports_nothing(B):
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=3072, batch=1024, n_batches=3)
+    m = B.Matcher(case["graph"], case["queries"], flags=B.F_INDEX_ONLY)
+    try:
+        live = len(case["graph"]["src"])
+        for b in case["batches"]:
+            m.apply_batch(b)
+            live += len(b["src"]) - len(b["del_keys"])
+            assert m.stats()["n_live_edges"] == live
+            for q in range(len(case["queries"])):
+                r = m.result(q)
+                assert r["n_new"] == 0 and r["n_expired"] == 0
+        # bad batches are still rejected atomically
+        with pytest.raises(B.MnemonicError):
+            m.apply_batch(synth.make_batch([], [], [], [], [0, 0]))
+    finally:
+        m.close()
