@@ -92,6 +92,7 @@ def parse():
                     help="both: the line reports the static order and times the learned scheduler on the same "
                          "batches for learned_vs_plain; static or learned: time that one only")
     ap.add_argument("--weights", default=None, help="order-cost network (default: the committed weights)")
+    ap.add_argument("--no-rates", action="store_true", help="skip the count-only and index-only runs")
     return ap.parse_args()
 
 
@@ -345,14 +346,16 @@ def main():
     # the same batches without writing tuples (counts and digests only), and
     # with the index maintained but nothing enumerated
     rates = None
-    if args.scheduler != "learned" and not args.count_only:
+    if args.scheduler == "both" and not args.count_only and not args.no_rates:
         C = run(binding.SCHED_STATIC, "count-only", binding.F_TIMING)
         I = run(binding.SCHED_STATIC, "index-only", binding.F_TIMING | binding.F_INDEX_ONLY)
         if C["results"] != R["results"]:
             raise SystemExit("count-only mode changed the counts or digests")
         rates = {"count_only": C["edges"] / C["elapsed"], "index_only": I["edges"] / I["elapsed"],
                  "count_only_ms_per_step": C["elapsed"] * 1e3 / args.steps,
-                 "index_only_ms_per_step": I["elapsed"] * 1e3 / args.steps}
+                 "index_only_ms_per_step": I["elapsed"] * 1e3 / args.steps,
+                 "count_only_median_batch_ms": float(np.median(C["lat"])),
+                 "index_only_median_batch_ms": float(np.median(I["lat"]))}
         log("count-only %.3f ms per step, index-only %.3f ms per step" % (
             rates["count_only_ms_per_step"], rates["index_only_ms_per_step"]))
 
