@@ -101,6 +101,10 @@ typedef struct {
 #define MNEMONIC_F_AUTOTUNE 4u /* the first batches try each expansion tile size (256, 512,
                                   1024 candidates per block) twice and keep the fastest per
                                   candidate; results do not depend on the choice */
+#define MNEMONIC_F_SORT 16u /* with MNEMONIC_F_EMIT: each result list is sorted on the device into
+                               lexicographic order of its key tuples before the call returns
+                               (the canonical order the oracle lists; Section II-B leaves the
+                               order open) */
 #define MNEMONIC_F_INDEX_ONLY 8u /* maintain the graph and its index (Algorithm 2's updates,
                                     edgeMatcher, filters) but enumerate nothing: results stay
                                     empty; measures the update path alone */

@@ -20,6 +20,7 @@ F_EMIT = 1
 F_TIMING = 2
 F_AUTOTUNE = 4
 F_INDEX_ONLY = 8
+F_SORT = 16
 SCHED_STATIC = 0
 SCHED_LEARNED = 1
 SCHED_FIXED = 2

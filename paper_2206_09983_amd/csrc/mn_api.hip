@@ -230,6 +230,12 @@ struct mnemonic_ctx {
     uint32_t sched_mode = MN_SCHED_STATIC;
     uint16_t* d_sched_w = nullptr;
     float* d_sched_f32 = nullptr;
+    // lexicographic sort of result tuples (MNEMONIC_F_SORT): scratch
+    uint64_t* d_srt_k[2] = {nullptr, nullptr};
+    uint32_t* d_srt_v[2] = {nullptr, nullptr};
+    uint64_t* d_srt_rows = nullptr;
+    uint32_t* d_srt_scr = nullptr;
+    uint64_t cap_srt = 0, cap_srt_rows = 0, cap_srt_scr = 0;
     // start rows whose order the decision kernel settles
     uint64_t* d_dec = nullptr;
     uint64_t cap_dec = 0;
@@ -1153,6 +1159,51 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = 
     return again;
 }
 
+// Puts every query's result tuples of both phases in lexicographic order.
+void sort_outputs(mnemonic_ctx* c) {
+    hipStream_t s = c->stream;
+    const uint32_t key_bits = std::max<uint32_t>(1, ceil_log2(c->next_key + 1));
+    for (uint32_t q = 0; q < c->n_q; q++)
+        for (int p = 0; p < 2; p++) {
+            const uint64_t n = std::min<uint64_t>(c->h_zr[c->zr_count(p) + q], c->houts[q].cap[p]);
+            if (n <= 1) continue;
+            if (n >= (1ull << 32)) throw ApiError{MNEMONIC_E_LIMIT, "more than 2^32 tuples to sort"};
+            const uint32_t m = c->hq[q].n_qe;
+            if (n > c->cap_srt) {
+                HIPCHK(hipStreamSynchronize(s));
+                for (int k = 0; k < 2; k++) {
+                    dev_free(c->d_srt_k[k]);
+                    dev_free(c->d_srt_v[k]);
+                }
+                c->cap_srt = 0;
+                const uint64_t nc = 2 * n;
+                for (int k = 0; k < 2; k++) {
+                    dev_alloc(c->d_srt_k[k], nc);
+                    dev_alloc(c->d_srt_v[k], nc);
+                }
+                c->cap_srt = nc;
+            }
+            if (n * m > c->cap_srt_rows) {
+                HIPCHK(hipStreamSynchronize(s));
+                dev_free(c->d_srt_rows);
+                c->cap_srt_rows = 0;
+                dev_alloc(c->d_srt_rows, 2 * n * m);
+                c->cap_srt_rows = 2 * n * m;
+            }
+            const uint64_t sw = mn_tuple_sort_scratch_words((uint32_t)n);
+            if (sw > c->cap_srt_scr) {
+                HIPCHK(hipStreamSynchronize(s));
+                dev_free(c->d_srt_scr);
+                c->cap_srt_scr = 0;
+                dev_alloc(c->d_srt_scr, 2 * sw);
+                c->cap_srt_scr = 2 * sw;
+            }
+            mn_sort_tuples(c->houts[q].keys[p], (uint32_t)n, m, key_bits, c->d_srt_k[0], c->d_srt_k[1], c->d_srt_v[0],
+                           c->d_srt_v[1], c->d_srt_rows, c->d_srt_scr, s);
+        }
+    HIPCHK(hipGetLastError());
+}
+
 // One snapshot; `enumerate` is false only for the initial load.
 int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32_t* dst,
               const uint8_t* lab, const int64_t* ts, const uint64_t* del_keys, uint64_t n_del,
@@ -1387,6 +1438,10 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             HIPCHK(hipStreamSynchronize(s));
             c->summarize();
         }
+        if (emit && (c->flags & MNEMONIC_F_SORT)) {
+            sort_outputs(c);
+            HIPCHK(hipStreamSynchronize(s));
+        }
         if (timing) resolve_events(c);
         if (tune) {
             const uint32_t k = c->tune_batch % 3;
@@ -1554,6 +1609,12 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_tr_work);
     dev_free(c->d_dec);
     dev_free(c->d_dec_n);
+    for (int k = 0; k < 2; k++) {
+        dev_free(c->d_srt_k[k]);
+        dev_free(c->d_srt_v[k]);
+    }
+    dev_free(c->d_srt_rows);
+    dev_free(c->d_srt_scr);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     c->h_ctl = nullptr;
 }

@@ -27,6 +27,13 @@ size_t mn_sort_scratch_words(uint32_t n);
 void mn_radix_sort(uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp, uint32_t n,
                    uint32_t nbits, uint32_t* scratch, hipStream_t s);
 
+// Sorts n rows of m u64 keys (row-major, keys < 2^key_bits) into
+// lexicographic order in place. Scratch: k0, k1 (n u64 each), v0, v1 (n u32
+// each), tmp_rows (n * m u64), scratch (mn_tuple_sort_scratch_words(n) u32).
+size_t mn_tuple_sort_scratch_words(uint32_t n);
+void mn_sort_tuples(uint64_t* rows, uint32_t n, uint32_t m, uint32_t key_bits, uint64_t* k0, uint64_t* k1,
+                    uint32_t* v0, uint32_t* v1, uint64_t* tmp_rows, uint32_t* scratch, hipStream_t s);
+
 // ------------------------------------------------------------------ batches
 // Per-bit descriptors precomputed on the host.
 struct DebiBit {  // one edgeMatcher bit: query edge label and endpoint requirements

@@ -310,3 +310,50 @@ void mn_radix_sort(uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*&
         vtmp = tv;
     }
 }
+
+// ------------------------------------------------------ tuple canonical order
+// Lexicographic order of result tuples (rows of m u64 keys): an index
+// permutation sorted column by column from the last (LSD, each pass a stable
+// radix sort of (key, index) pairs), then the rows gathered in that order.
+namespace {
+
+__global__ __launch_bounds__(MN_BLOCK) void k_iota(uint32_t* __restrict__ v, uint32_t n) {
+    const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
+    if (i < n) v[i] = i;
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_gather_col(const uint64_t* __restrict__ rows, uint32_t m, uint32_t col,
+                                                         const uint32_t* __restrict__ idx, uint32_t n,
+                                                         uint64_t* __restrict__ out) {
+    const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
+    if (i < n) out[i] = rows[(size_t)idx[i] * m + col];
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_permute_rows(const uint64_t* __restrict__ src, uint32_t m,
+                                                           const uint32_t* __restrict__ idx, uint32_t n,
+                                                           uint64_t* __restrict__ dst) {
+    const uint64_t t = (uint64_t)blockIdx.x * MN_BLOCK + threadIdx.x;  // one key per thread
+    if (t >= (uint64_t)n * m) return;
+    const uint64_t r = t / m, k = t % m;
+    dst[t] = src[(size_t)idx[r] * m + k];
+}
+
+}  // namespace
+
+size_t mn_tuple_sort_scratch_words(uint32_t n) { return mn_sort_scratch_words(n); }
+
+void mn_sort_tuples(uint64_t* rows, uint32_t n, uint32_t m, uint32_t key_bits, uint64_t* k0, uint64_t* k1,
+                    uint32_t* v0, uint32_t* v1, uint64_t* tmp_rows, uint32_t* scratch, hipStream_t s) {
+    if (n <= 1 || m == 0) return;
+    const uint32_t nb = (n + MN_BLOCK - 1) / MN_BLOCK;
+    k_iota<<<nb, MN_BLOCK, 0, s>>>(v0, n);
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    for (uint32_t c = m; c-- > 0;) {
+        k_gather_col<<<nb, MN_BLOCK, 0, s>>>(rows, m, c, va, n, ka);
+        mn_radix_sort(ka, va, kb, vb, n, key_bits, scratch, s);
+    }
+    const uint64_t tot = (uint64_t)n * m;
+    k_permute_rows<<<(uint32_t)((tot + MN_BLOCK - 1) / MN_BLOCK), MN_BLOCK, 0, s>>>(rows, m, va, n, tmp_rows);
+    (void)hipMemcpyAsync(rows, tmp_rows, tot * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+}

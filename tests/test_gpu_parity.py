@@ -319,3 +319,27 @@ def test_index_only_mode_keeps_the_graph_and_reports_nothing(B):
             m.apply_batch(synth.make_batch([], [], [], [], [0, 0]))
     finally:
         m.close()
+
+
+def test_device_sort_returns_the_canonical_lists(B):
+    # with MNEMONIC_F_SORT the lists come back in the oracle's lexicographic
+    # order as they are, no host sort
+    for case in (synth.rmat_case(scale=11, n_init=20000, n_stream=4096, batch=2048, n_batches=2),
+                 synth.multiquery_case(scale=11, n_init=20000, n_stream=12000, n_queries=64, lo=100, hi=6000)):
+        qs = case["queries"]
+        o = Oracle(case["graph"], qs)
+        m = B.Matcher(case["graph"], qs, flags=B.F_EMIT | B.F_SORT, out_capacity=1 << 12)
+        seen = 0
+        try:
+            for b in case["batches"]:
+                o.apply_batch(b)
+                m.apply_batch(b)
+                for qi in range(len(qs)):
+                    for ph in (False, True):
+                        got = m.keys(qi, ph)
+                        np.testing.assert_array_equal(got, o.result(qi, ph))
+                        seen += len(got)
+        finally:
+            m.close()
+            o.close()
+        assert seen > 0
