@@ -18,16 +18,21 @@
 // lane's work no matter how skewed the subtrees are:
 //   k_seed_rows    one row per work unit (start pair mapped, start-level
 //                  closing edges found); 2-vertex queries emit here
+//   k_decide       (learned scheduler, traces) the matching order of each row
 //   k_level_range  per row, the candidate run [lo, lo + cnt) of the level
 //   scan           u64 offsets of the runs (flattened candidate space)
-//   k_expand       one lane per candidate: filters, closing edges, then a
-//                  new row for the next level or, at the plan's last level,
-//                  the embeddings themselves
-// The host walks the levels depth first over chunks of the candidate space,
-// so each level's row buffer stays bounded whatever the fan-out. Parallel
-// closing-edge instances do not multiply rows: a row keeps the start of each
-// closing edge's instance run, and emission expands every combination of
-// instances (parallel edges are distinct instances, Section I).
+//   k_partition    the first row of every expansion tile
+//   k_expand       one lane per candidate: filters, closing edges, temporal
+//                  order, then a new row for the next level or, at the plan's
+//                  last level, the embeddings themselves
+// Normally every launch of a phase reads its row count and candidate total
+// from device memory (no host round trip); a level that outgrows its buffers
+// leaves a note and the host re-runs the phase with larger ones, or walks the
+// levels in host-sized chunks, depth first over chunks, so each level's row
+// buffer stays bounded whatever the fan-out. Parallel closing-edge instances
+// do not multiply rows: a row keeps the start of each closing edge's instance
+// run, and emission expands every combination of instances (parallel edges
+// are distinct instances, Section I).
 #include <hip/hip_ext.h>
 
 #include "mn_internal.h"
