@@ -18,7 +18,9 @@ Pins (tests/test_oracle_mlp.py): the analytic gradient equals central finite
 differences; closed forms for networks whose hidden units are all off or all
 linear; Adam's first step moves every weight with a nonzero gradient by
 lr * g / (|g| + eps); bfloat16 rounding against exactly representable values
-and ties, and the half-unit error bound.
+and ties, and the half-unit error bound; bf16 inference rounds the first
+hidden layer and not the second (a one-path network whose activations sit
+just off a bfloat16 value).
 """
 import numpy as np
 
@@ -106,8 +108,14 @@ def bf16_round(a):
 
 
 def forward_bf16(w, X):
-    """The network with weights and inputs first rounded to bfloat16 (exact
-    fp64 arithmetic afterwards): the value bf16 inference approximates."""
-    wr = bf16_round(np.asarray(w, dtype=np.float32))
+    """bf16 inference: every operand of the two matrix products in bfloat16
+    (weights, inputs, and the first hidden layer's activations, each rounded
+    from float32), exact fp64 sums otherwise. The output layer multiplies the
+    rounded W3 with the second hidden layer as computed (not rounded), as the
+    library's matrix-core evaluator does with its fp32 accumulators."""
+    W1, b1, W2, b2, W3, b3 = unpack(bf16_round(np.asarray(w, dtype=np.float32)))
     Xr = bf16_round(np.asarray(X, dtype=np.float32))
-    return forward(wr, Xr)
+    h1 = np.maximum(Xr @ W1 + b1, 0.0)
+    h1r = bf16_round(h1.astype(np.float32))
+    h2 = np.maximum(h1r @ W2 + b2, 0.0)
+    return h2 @ W3 + b3

@@ -114,3 +114,30 @@ def test_bf16_rounding_exact_values_and_ties():
     a = rng.normal(size=10000).astype(np.float32)
     r = mlp.bf16_round(a)
     assert np.all(np.abs(r - a) <= np.abs(a) * 2.0 ** -8)
+
+
+def test_bf16_inference_rounds_the_first_hidden_layer_only():
+    # one active path: x0 -> unit 0 -> unit 0 -> y, every weight 1 (exact in
+    # bfloat16), biases 2^-9 (a power of two, also exact). The first hidden
+    # unit is 1 + 2^-9, below the midpoint 1 + 2^-8 between 1 and the next
+    # bfloat16 value 1 + 2^-7, so bf16 inference passes 1.0 to the second
+    # layer; the second unit, 1.0 + 2^-9, reaches the output unrounded.
+    W1 = np.zeros((mlp.N_IN, mlp.N_HID))
+    W2 = np.zeros((mlp.N_HID, mlp.N_HID))
+    W3 = np.zeros(mlp.N_HID)
+    b1 = np.zeros(mlp.N_HID)
+    b2 = np.zeros(mlp.N_HID)
+    W1[0, 0] = W2[0, 0] = W3[0] = 1.0
+    b1[0] = b2[0] = 2.0 ** -9
+    w = mlp.pack(W1, b1, W2, b2, W3, 0.0)
+    X = np.zeros((2, mlp.N_IN))
+    X[0, 0] = 1.0
+    X[1, 0] = 1.0 + 2.0 ** -8 - 2.0 ** -9  # rounds to 1.0 on input: the same path as sample 0
+    assert mlp.forward(w, X[:1])[0] == 1.0 + 2.0 ** -8
+    y = mlp.forward_bf16(w, X)
+    assert y[0] == 1.0 + 2.0 ** -9
+    assert y[1] == 1.0 + 2.0 ** -9
+    # with the first unit at 1 + 3 * 2^-8 (a tie) the even neighbour 1 + 2^-6 goes on
+    b1[0] = 3 * 2.0 ** -8
+    w = mlp.pack(W1, b1, W2, b2, W3, 0.0)
+    assert mlp.forward_bf16(w, X[:1])[0] == 1.0 + 2.0 ** -6 + 2.0 ** -9
