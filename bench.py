@@ -317,10 +317,11 @@ def main():
             res = [m.result(q) for q in range(len(case["queries"]))]
             r["results"].append([(x["n_new"], x["dig_new"], x["n_expired"], x["dig_expired"]) for x in res])
             log("[%s] step %d: %.2f ms (enumerate %.2f + %.2f ms, of which k_expand %.2f + %.2f ms in %s launches), "
-                "seeds %s, rows %s, candidates %s, tuples %s" % (
+                "seeds %s, rows %s, candidates %s, tuples %s%s" % (
                     tag, i, r["lat"][-1], st["ms_enumerate"][0], st["ms_enumerate"][1], st["ms_expand"][0],
                     st["ms_expand"][1], st["expand_launches"], st["seeds"], st["frontier_rows"],
-                    st["entries_scanned"], st["tuples"]))
+                    st["entries_scanned"], st["tuples"],
+                    ", re-runs %s (causes %s)" % (st["reruns"], st["rerun_causes"]) if any(st["reruns"]) else ""))
         torch.cuda.synchronize()
         r["elapsed"] = time.perf_counter() - t_start
         r["tile"] = m.stats()["expand_tile"]

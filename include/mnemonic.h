@@ -152,6 +152,11 @@ typedef struct {
  *   expand_launches    launches of the expansion kernel
  *   expand_tile        candidates per expansion block in use (autotuned with
  *                      MNEMONIC_F_AUTOTUNE, else 512)
+ *   reruns             times the phase ran again after a buffer proved too
+ *                      small (the buffers grow; results are unaffected)
+ *   rerun_causes       what was too small, OR-ed over the re-runs: 1 start
+ *                      rows, 2 a level's candidates past the launch's grid,
+ *                      4 a level's rows, 8 a query's output buffer
  * With MNEMONIC_F_TIMING: ms_expand = summed device time of the expansion
  * launches, ms_enumerate = the whole enumeration phase, ms_batch = the whole
  * snapshot on the device. */
@@ -172,6 +177,8 @@ typedef struct {
     double ms_expand[2];
     double ms_enumerate[2];
     double ms_batch;
+    uint64_t reruns[2];
+    uint64_t rerun_causes[2];
 } mnemonic_stats;
 
 /*
@@ -297,8 +304,10 @@ int mnemonic_get_trace(mnemonic_ctx *ctx, int phase, uint64_t *n, uint64_t *code
 
 /* Training and inference kernels of the order-cost network, on caller-owned
  * device memory (fp32), on hip_stream (NULL: default stream). No context.
- *   predict: y[i] = net(x[i]) for n samples of MNEMONIC_MLP_IN floats; bf16 != 0
- *     rounds weights and inputs to bfloat16 first (sums stay fp32).
+ *   predict: y[i] = net(x[i]) for n samples of MNEMONIC_MLP_IN floats. bf16 != 0:
+ *     the operands of both matrix products (weights, inputs, first hidden
+ *     layer) rounded to bfloat16, sums in fp32, on the matrix cores: the
+ *     arithmetic of the learned scheduler's decisions. bf16 == 0: fp32.
  *   grad: adds to grad[MNEMONIC_MLP_WEIGHTS] the gradient of
  *     L = mean over t < m of (net(x[k]) - target[k])^2, k = idx[off + t]
  *     (idx NULL: k = off + t), and adds L to *loss. grad and loss accumulate.

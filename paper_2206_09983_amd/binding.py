@@ -77,7 +77,8 @@ class mnemonic_stats(C.Structure):
                 ("range_probe_words", C.c_uint64 * 2), ("key_reads", C.c_uint64 * 2),
                 ("tuples", C.c_uint64 * 2), ("tuple_words", C.c_uint64 * 2), ("vf_reads", C.c_uint64 * 2),
                 ("frontier_rows", C.c_uint64 * 2), ("expand_launches", C.c_uint64 * 2),
-                ("expand_tile", C.c_uint64), ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2), ("ms_batch", C.c_double)]
+                ("expand_tile", C.c_uint64), ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2),
+                ("ms_batch", C.c_double), ("reruns", C.c_uint64 * 2), ("rerun_causes", C.c_uint64 * 2)]
 
 
 class MnemonicError(RuntimeError):

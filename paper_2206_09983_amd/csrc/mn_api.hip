@@ -173,6 +173,7 @@ struct mnemonic_ctx {
     uint64_t* d_skey[2] = {nullptr, nullptr};
     uint32_t* d_sval[2] = {nullptr, nullptr};
     uint32_t* d_inspos[2] = {nullptr, nullptr};
+    uint32_t* d_ub[2] = {nullptr, nullptr};  // insertion points of the batch entries in the old adjacency
     uint32_t* d_touched = nullptr;
     uint32_t* d_del_slot[2] = {nullptr, nullptr};        // [buffer]
     uint32_t* d_delpos[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buffer][dir]
@@ -199,8 +200,6 @@ struct mnemonic_ctx {
     uint64_t cap_scan64 = 0;
     uint32_t* d_tiles = nullptr;     // first row of every expansion tile
     uint64_t cap_tiles = 0;
-    uint32_t* d_mtiles = nullptr;    // first vertex of every merge tile
-    uint64_t cap_mtiles = 0;
     uint32_t* d_nrows = nullptr;     // [MN_MAXLV + 1] row counters
     uint64_t* d_total = nullptr;     // candidate total of the last scan
     uint64_t* h_ctl = nullptr;       // pinned: readback of counters
@@ -225,6 +224,7 @@ struct mnemonic_ctx {
     bool tuning() const { return (flags & MNEMONIC_F_AUTOTUNE) && tune_batch < 3 * TUNE_TRIALS; }
     double ms_expand[2] = {0, 0};
     uint64_t n_expand[2] = {0, 0};
+    uint64_t reruns[2] = {0, 0}, rerun_causes[2] = {0, 0};  // this batch's phase re-runs
 
     // scheduler: matching-order choice (MN_SCHED_*) and the network's bf16 weights
     uint32_t sched_mode = MN_SCHED_STATIC;
@@ -786,7 +786,9 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         }
         for (int d = 0; d < 2; d++) {
             dev_free(c->d_inspos[d]);
+            dev_free(c->d_ub[d]);
             dev_alloc(c->d_inspos[d], nc);
+            dev_alloc(c->d_ub[d], nc);
         }
         c->cap_ins = nc;
     }
@@ -956,7 +958,8 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
             c->cap_tiles = need_tiles;
         }
         // one event pair serves every launch: the readback below waits for it
-        mn_launch_expand(g, rows_view(c, L), (uint32_t)n, nullptr, B.lo, B.off, c->d_tiles, c0, c1, nullptr, nullptr, 0,
+        mn_launch_expand(g, rows_view(c, L), (uint32_t)n, nullptr, B.lo, B.off, nullptr, c->d_tiles, c0, c1, nullptr,
+                         nullptr, 0,
                          c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
                          rows_view(c, L + 1), n_out, po, c->d_err, s, timing ? c->ev_x[0] : nullptr,
                          timing ? c->ev_x[1] : nullptr);
@@ -1017,28 +1020,27 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
     for (uint32_t L = 0; L < c->max_levels; L++) {
         auto& B = c->lvb[L];
         const uint32_t* n_dev = c->d_nrows + L;
-        mn_launch_level_range(g, rows_view(c, L), (uint32_t)n_max, n_dev, L, B.lo, B.cnt, po.stats, c->d_err, s);
-        mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n_max, c->d_scan64, c->d_total, s, n_dev);
         const bool next = L + 1 < c->max_levels;
+        uint32_t* n_out = c->d_nrows + L + 1;
+        // the rows level L - 1 made are noted against this buffer here, and
+        // the next level's row counter starts at zero
+        mn_launch_level_range(g, rows_view(c, L), (uint32_t)n_max, n_dev, L, B.lo, B.cnt, po.stats, c->d_err, s,
+                              next ? n_out : nullptr, L ? c->d_zr + c->note_rows(po.phase, L - 1) : nullptr);
+        mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n_max, c->d_scan64, nullptr, s, n_dev);
         // candidates are bounded by the tile buffer and the grid only; rows
         // past the next level's buffer are counted and noted
         const uint64_t K = c->cand_k;
-        uint32_t* n_out = c->d_nrows + L + 1;
-        if (next) mn_launch_set_u32(n_out, 0, s);
         unsigned long long* note = c->d_zr + c->note_cand(po.phase, L);
         std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
         if (timing) ev = event_pair(c, po.phase);
         const double rt = c->rate[po.phase][L];
         const uint64_t expect = rt < 0 ? (~0ull >> 8) : (uint64_t)(rt * (double)ns) + 1;
         c->cover[po.phase][L] =
-            mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, c->d_tiles, 0, K, c->d_total, note,
-                             expect, c->tile_items, L, c->max_close, c->level_rows[L] != 0, c->level_emit[L] != 0,
-                             rows_view(c, L + 1), n_out, po, c->d_err, s, ev.first, ev.second);
+            mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, B.cnt, c->d_tiles, 0, K,
+                             c->d_total, note, expect, c->tile_items, L, c->max_close, c->level_rows[L] != 0,
+                             c->level_emit[L] != 0, rows_view(c, L + 1), n_out, po, c->d_err, s, ev.first, ev.second);
         c->n_expand[po.phase]++;
-        if (next) {
-            mn_launch_note_count(n_out, c->lvb[L + 1].cap, c->d_zr + c->note_rows(po.phase, L), s);
-            n_max = c->lvb[L + 1].cap;
-        }
+        if (next) n_max = c->lvb[L + 1].cap;
     }
 }
 
@@ -1100,7 +1102,8 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
 // After a device-sized phase: grows what its notes say was too small.
 // Returns true when the phase must run again; host_chunks is set when a level
 // needs more rows than one buffer may hold.
-bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = nullptr) {
+// cause receives the stats' rerun_causes bits of what was too small.
+bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, uint64_t& cause, std::string* why = nullptr) {
     const unsigned long long* z = c->h_zr.data();
     bool again = false;
     auto say = [&](const char* what, uint32_t L, uint64_t got, uint64_t room) {
@@ -1124,6 +1127,7 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = 
     const unsigned long long* ns0 = z + c->note_seed(p);
     if (ns0[0]) {  // start rows past their buffer
         again = true;
+        cause |= 1u;
         say("start rows", 0, ns0[1], c->max_levels ? c->lvb[0].cap : 0);
         c->rate[p][MN_MAXLV] = std::max<double>(c->rate[p][MN_MAXLV], (double)ns0[1] / ns);
         if (c->max_levels && c->lvb[0].cap) cut = std::max<double>(1.0, (double)ns0[1] / (double)c->lvb[0].cap);
@@ -1137,6 +1141,7 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = 
         if (nc[0] || cut > 1.0) c->rate[p][L] = std::max<double>(c->rate[p][L], T_est / ns);
         if (nc[0]) {  // more candidates than the launch covered
             again = true;
+            cause |= 2u;
             say("candidates", L, nc[1], c->cover[p][L]);
             if (c->cover[p][L] > 0) cut *= std::max<double>(1.0, (double)nc[1] / (double)c->cover[p][L]);
             // past what one device-sized launch can cover, the levels are walked in host chunks
@@ -1151,6 +1156,7 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, std::string* why = 
             if (nr[0] || cut > 1.0) grow_rows(L + 1, (uint64_t)R_est);
             if (nr[0]) {  // rows past the next level's buffer
                 again = true;
+                cause |= 4u;
                 say("rows", L + 1, nr[1], c->lvb[L + 1].cap);
                 cut *= std::max<double>(1.0, (double)nr[1] / (double)std::max<uint64_t>(1, c->lvb[L + 1].cap));
             }
@@ -1218,6 +1224,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     for (int p = 0; p < 2; p++) {
         c->ms_expand[p] = 0;
         c->n_expand[p] = 0;
+        c->reruns[p] = c->rerun_causes[p] = 0;
     }
     c->ev_used = 0;
     if (timing) HIPCHK(hipEventRecord(c->ev[4], s));
@@ -1300,14 +1307,6 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         uint32_t* tv = c->d_sval[1];
         mn_radix_sort(bk, bv, tk, tv, (uint32_t)(2 * n_ins), c->hb + c->nbr_bits + 1, c->d_sort_scratch, s);
         const uint64_t dbit = 1ull << c->hb_pos;
-        const uint64_t need_mt = (uint64_t)mn_merge_tiles((uint32_t)c->E) + 1;
-        if (need_mt > c->cap_mtiles) {
-            HIPCHK(hipStreamSynchronize(s));
-            dev_free(c->d_mtiles);
-            c->cap_mtiles = 0;
-            dev_alloc(c->d_mtiles, need_mt + need_mt / 2);
-            c->cap_mtiles = need_mt + need_mt / 2;
-        }
         uint64_t* dk = c->d_dkey[0];
         if (n_prev) {
             uint32_t* v0 = c->d_dval[0];
@@ -1324,9 +1323,9 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             const uint64_t* dpd = n_prev ? dk + d * n_prev : nullptr;
             mn_launch_vertex_meta(c->d_off[d], c->nV, (uint32_t)c->E, bkd, kb, (uint32_t)n_ins, dpd, db, n_prev,
                                   c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
-            mn_launch_merge(c->d_off[d], c->d_adj[d], c->d_adjk[d], c->nV, (uint32_t)c->E, c->d_off2[d],
-                            c->d_meta[d], bkd, kb, bvd, c->d_key, (uint32_t)n_ins, dpd, db, c->hb, c->d_adj2[d],
-                            c->d_adjk2[d], c->d_inspos[d], (uint32_t)E_new, c->d_mtiles, c->d_err, s);
+            mn_launch_merge(c->d_off[d], c->d_adj[d], c->d_adjk[d], (uint32_t)c->E, c->d_off2[d], c->d_meta[d], bkd,
+                            kb, bvd, c->d_key, (uint32_t)n_ins, dpd, db, n_prev, c->hb, c->d_adj2[d], c->d_adjk2[d],
+                            c->d_inspos[d], c->d_ub[d], (uint32_t)E_new, c->d_err, s);
         }
     }
     // from here on the kernels work on the merged adjacency
@@ -1403,8 +1402,9 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             bool redo[2] = {false, false};
             std::string why;
             const bool last = attempt == max_attempts - 1;
+            uint64_t cause[2] = {0, 0};
             for (int p = 0; p < 2; p++) {
-                redo[p] = absorb_notes(c, p, host_chunks[p], last ? &why : nullptr);
+                redo[p] = absorb_notes(c, p, host_chunks[p], cause[p], last ? &why : nullptr);
                 if (redo[p] && attempt + 1 >= DEVICE_RUNS) host_chunks[p] = true;
             }
             for (uint32_t q = 0; q < c->n_q; q++)
@@ -1412,8 +1412,14 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                     need[2 * q + p] = c->h_zr[c->zr_count(p) + q];
                     if (emit && need[2 * q + p] > c->houts[q].cap[p]) {
                         redo[p] = true;
+                        cause[p] |= 8u;
                         if (last) why += " [query " + std::to_string(q) + " output " + std::to_string(need[2 * q + p]) + "]";
                     }
+                }
+            for (int p = 0; p < 2; p++)
+                if (redo[p]) {
+                    c->reruns[p]++;
+                    c->rerun_causes[p] |= cause[p];
                 }
             if (!redo[0] && !redo[1]) break;
             if (last) throw ApiError{MNEMONIC_E_HIP, "enumeration did not settle (internal)" + why};
@@ -1487,6 +1493,8 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             st.vf_reads[p] = z[6];
             st.frontier_rows[p] = z[7];
             st.expand_launches[p] = c->n_expand[p];
+            st.reruns[p] = c->reruns[p];
+            st.rerun_causes[p] = c->rerun_causes[p];
             st.expand_tile = (uint64_t)MN_BLOCK * c->tile_items;
             st.ms_expand[p] = c->ms_expand[p];
             uint64_t words = 0;
@@ -1565,6 +1573,7 @@ void free_all(mnemonic_ctx* c) {
         dev_free(c->d_adjk[d]);
         dev_free(c->d_adjk2[d]);
         dev_free(c->d_inspos[d]);
+        dev_free(c->d_ub[d]);
         dev_free(c->d_del_slot[d]);
         for (int k = 0; k < 2; k++) dev_free(c->d_delpos[d][k]);
     }
@@ -1589,7 +1598,6 @@ void free_all(mnemonic_ctx* c) {
     for (auto& e : c->ev_pool)
         if (e) (void)hipEventDestroy(e);
     dev_free(c->d_tiles);
-    dev_free(c->d_mtiles);
     for (auto& B : c->lvb) {
         dev_free(B.keys);
         dev_free(B.rows);

@@ -42,6 +42,7 @@ namespace {
 
 // candidates per lane in one expansion tile (tile = 256 x items): 1, 2 or 4
 constexpr uint32_t EX_TILE_MIN = MN_BLOCK;  // the smallest tile sizes the tile_row buffer
+constexpr uint64_t EX_SPARE_TILES = 8192;   // grid margin of a device-sized expansion past the expected tiles
 constexpr uint32_t NO_RUN = 0xFFFFFFFFu;
 constexpr uint32_t RUN_SWAP = 0x80000000u;
 constexpr uint8_t TREE_EDGE = 0xFF;
@@ -621,9 +622,14 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
 template <bool LEARN>
 __global__ __launch_bounds__(MN_BLOCK) void k_decide(GraphView g, RowsView R, const uint32_t* __restrict__ slots,
                                                      uint32_t cap, int phase) {
-    __shared__ sched::NetLds N;
+    __shared__ sched::NetVec V;
+    __shared__ __align__(16) uint16_t s_xs[LEARN ? MN_BLOCK / MN_WAVE : 1][MN_WAVE * sched::XS_STRIDE];
+    sched::NetFrag F;
     if (LEARN) {
-        sched::load_net(N, g.sched_w);
+        const uint16_t* w = g.sched_w;
+        auto W = [w](uint32_t i) { return w[i]; };
+        sched::load_frag(F, W);
+        sched::load_vec(V, W);
         __syncthreads();
     }
     const uint32_t total = min(*g.dec_n, cap);
@@ -649,7 +655,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_decide(GraphView g, RowsView R, co
             sched::features(g, g.plans[P->vars[v]], rcol(R, 1 + P->qa, r), rcol(R, 1 + P->qb, r), g.s_lab[slot], x);
         }
         float y = has ? 0.0f : 3.4e38f;
-        if (LEARN && has) y = sched::eval(N, x);
+        if (LEARN) {  // the whole block evaluates together (the loop is uniform per block)
+            const float p = sched::eval_wave(F, V, x, s_xs[threadIdx.x / MN_WAVE]);
+            if (has) y = p;
+        }
         // the order of the row: smallest prediction (lowest order on ties),
         // or the fixed variant, or the static order
         uint32_t best = v;
@@ -699,13 +708,26 @@ __global__ __launch_bounds__(MN_BLOCK) void k_decide(GraphView g, RowsView R, co
     }
 }
 
+// Device-sized levels fold two bookkeeping steps in here: thread 0 compares
+// the row count with the buffer (note[0] = 1 when *n_dev > n, note[1] = the
+// largest count seen) and zeroes the next level's row counter (zero_next).
 __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView R, uint32_t n,
                                                           const uint32_t* n_dev, uint32_t L,
                                                           uint32_t* __restrict__ lo, uint32_t* __restrict__ cnt,
-                                                          EnumStats* stats, const uint32_t* err) {
+                                                          EnumStats* stats, uint32_t* zero_next,
+                                                          unsigned long long* note, const uint32_t* err) {
     __shared__ BlockAcc A;
+    if (n_dev) {
+        const uint32_t nd = *n_dev;
+        if (note && blockIdx.x == 0 && threadIdx.x == 0) {
+            if (nd > n) note[0] = 1ull;
+            atomicMax(note + 1, (unsigned long long)nd);
+        }
+        n = min(n, nd);
+    }
+    if (zero_next && blockIdx.x == 0 && threadIdx.x == 0) *zero_next = 0u;
+    if (blockIdx.x * MN_BLOCK >= n) return;  // the grid covers the capacity; the same for the whole block
     acc_init(A, 0, err);
-    if (n_dev) n = min(n, *n_dev);
     const uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x;
     Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
     if (r < n && !A.dead) {
@@ -753,22 +775,31 @@ __host__ __device__ inline uint32_t expand_tiles(uint64_t c0, uint64_t cend, uin
 
 // First row of every expansion tile: tile_row[i] = row of candidate
 // c0 + i * tile for i < nt, tile_row[nt] = row of candidate cend - 1.
-// With the total on the device, thread 0 also records it in `note`
-// (note[0] = 1 when it exceeds c1, the candidates the next level's rows can
-// take; note[1] = the largest total seen), so the host can grow and re-run.
-__global__ __launch_bounds__(MN_BLOCK) void k_partition(const uint64_t* __restrict__ off, uint32_t n,
+// In the device-sized form (n_dev, cnt and T_dev given) every thread derives
+// the candidate total from the last row's offset and count, thread 0 stores
+// it in *T_dev for the expansion and records it in `note` (note[0] = 1 when
+// it exceeds c1, the candidates the next level's rows can take; note[1] = the
+// largest total seen), so the host can grow and re-run.
+__global__ __launch_bounds__(MN_BLOCK) void k_partition(const uint64_t* __restrict__ off,
+                                                        const uint32_t* __restrict__ cnt, uint32_t n,
                                                         const uint32_t* n_dev, uint64_t c0, uint64_t c1,
-                                                        const uint64_t* T_dev, uint32_t tile,
+                                                        uint64_t* T_dev, uint32_t tile,
                                                         uint32_t* __restrict__ tile_row, unsigned long long* note) {
     if (n_dev) n = min(n, *n_dev);
-    const uint64_t cend = expand_end(c1, T_dev);
-    const uint32_t nt = expand_tiles(c0, cend, tile);
     const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
-    if (i == 0 && T_dev && note) {
-        const unsigned long long T = *T_dev;
-        if (T > c1) note[0] = 1ull;
-        atomicMax(note + 1, T);
+    uint64_t cend = c1;
+    if (T_dev) {
+        const uint64_t T = n ? off[n - 1] + cnt[n - 1] : 0ull;
+        cend = min(c1, T);
+        if (i == 0) {
+            *T_dev = T;
+            if (note) {
+                if (T > c1) note[0] = 1ull;
+                atomicMax(note + 1, (unsigned long long)T);
+            }
+        }
     }
+    const uint32_t nt = expand_tiles(c0, cend, tile);
     if (nt == 0 || i > nt) return;
     const uint64_t t = i < nt ? c0 + (uint64_t)i * tile : cend - 1;
     tile_row[i] = row_of(off, 0, n, t);
@@ -1043,8 +1074,9 @@ void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long lon
 }
 
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
-                           uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s) {
-    if (n) k_level_range<<<nblocks(n), MN_BLOCK, 0, s>>>(g, rows, n, n_dev, L, lo, cnt, st, err);
+                           uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s,
+                           uint32_t* zero_next, unsigned long long* note) {
+    k_level_range<<<nblocks(n ? n : 1), MN_BLOCK, 0, s>>>(g, rows, n, n_dev, L, lo, cnt, st, zero_next, note, err);
 }
 
 uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return expand_tiles(c0, c1, EX_TILE_MIN); }
@@ -1080,7 +1112,8 @@ void launch_expand_items(uint32_t max_close, bool rows, bool emit, dim3 grid, hi
 }
 
 uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
-                          const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
+                          const uint64_t* off, const uint32_t* cnt, uint32_t* tile_row, uint64_t c0, uint64_t c1,
+                          uint64_t* T_dev,
                           unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
                           bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
@@ -1096,12 +1129,16 @@ uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const 
     // With the total on the device, the grid follows the expected candidate
     // count with a margin, and the candidates it can cover bound c1: a larger
     // total leaves a note and the host runs the phase again with more blocks.
+    // The margin is relative (batches vary) plus a fixed EX_SPARE_TILES:
+    // blocks past the candidates present leave at once, so spare blocks cost
+    // little, while a re-run costs the whole phase (a deletion phase that
+    // meets a hub can take several times its usual candidates).
     if (T_dev) {
-        const uint64_t want = expand_tiles(0, expect + expect / 2, tile) + 64;
+        const uint64_t want = expand_tiles(0, expect + expect / 2, tile) + EX_SPARE_TILES;
         c1 = std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, MN_EXPAND_MAX_BLOCKS) * tile);
     }
     const uint64_t tiles = expand_tiles(c0, c1, tile);
-    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, n_in, n_dev, c0, c1, T_dev, tile, tile_row, note);
+    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, cnt, n_in, n_dev, c0, c1, T_dev, tile, tile_row, note);
     const dim3 grid((uint32_t)tiles);
 #define MN_ITEMS_ARGS max_close, rows, emit, grid, s, ev0, ev1, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err
     if (items == 1)

@@ -155,6 +155,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_reindex(GraphView g, const DebiBit
     }
 }
 
+// Per vertex: its run of batch entries [bs, be) in bk and of deleted positions
+// [ds, de) in dpos, and its offset in the merged adjacency. Four threads first
+// bound the block's 256 vertices in both sorted arrays, so that every
+// vertex searches only its block's window.
 __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __restrict__ off, uint32_t nv,
                                                           uint32_t e_old, const uint64_t* __restrict__ bk,
                                                           uint64_t kbase, uint32_t n_b,
@@ -162,17 +166,28 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __rest
                                                           uint32_t n_d, uint32_t hb,
                                                           uint32_t* __restrict__ newoff,
                                                           uint4* __restrict__ meta, const uint32_t* err) {
-    uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nv || failed(err)) return;
-    uint32_t bs = 0, be = 0, ds = 0, de = 0;
-    if (n_b) {
-        bs = lower_bound_dev<uint64_t>(bk, 0, n_b, kbase + ((uint64_t)v << hb));
-        be = lower_bound_dev<uint64_t>(bk, bs, n_b, kbase + ((uint64_t)(v + 1) << hb));
+    __shared__ uint32_t s_w[4];
+    const uint32_t v0 = blockIdx.x * MN_BLOCK, v1 = min(v0 + MN_BLOCK, nv);
+    const uint32_t tid = threadIdx.x;
+    if (tid < 2) {
+        const uint32_t u = tid ? v1 : v0;
+        s_w[tid] = n_b ? lower_bound_dev<uint64_t>(bk, 0, n_b, kbase + ((uint64_t)u << hb)) : 0u;
+    } else if (tid < 4) {
+        const uint32_t u = tid == 3 ? v1 : v0;
+        s_w[tid] = n_d ? lower_bound_dev<uint64_t>(dpos, 0, n_d, dbase + off[u]) : 0u;
     }
-    uint32_t o0 = off[v], o1 = off[v + 1];
-    if (n_d) {
-        ds = lower_bound_dev<uint64_t>(dpos, 0, n_d, dbase + o0);
-        de = lower_bound_dev<uint64_t>(dpos, ds, n_d, dbase + o1);
+    __syncthreads();
+    const uint32_t v = v0 + tid;
+    if (v >= nv || failed(err)) return;
+    uint32_t bs = s_w[0], be = s_w[0], ds = s_w[2], de = s_w[2];
+    if (s_w[0] < s_w[1]) {
+        bs = lower_bound_dev<uint64_t>(bk, s_w[0], s_w[1], kbase + ((uint64_t)v << hb));
+        be = lower_bound_dev<uint64_t>(bk, bs, s_w[1], kbase + ((uint64_t)(v + 1) << hb));
+    }
+    const uint32_t o0 = off[v], o1 = off[v + 1];
+    if (s_w[2] < s_w[3]) {
+        ds = lower_bound_dev<uint64_t>(dpos, s_w[2], s_w[3], dbase + o0);
+        de = lower_bound_dev<uint64_t>(dpos, ds, s_w[3], dbase + o1);
     }
     newoff[v] = o0 - ds + bs;
     meta[v] = make_uint4(bs, be - bs, ds, de - ds);
@@ -182,96 +197,16 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __rest
 constexpr uint32_t MG_ITEMS = 8;
 constexpr uint32_t MG_TILE = MN_BLOCK * MG_ITEMS;
 
-constexpr uint32_t MG_LDS = MG_TILE + 1;
-
-// First vertex of every merge tile: tile_v[i] = vertex holding old entry
-// i * MG_TILE for i < nt, tile_v[nt] = vertex holding the last old entry.
-__global__ __launch_bounds__(MN_BLOCK) void k_merge_partition(const uint32_t* __restrict__ off, uint32_t nv,
-                                                              uint32_t e_old, uint32_t nt,
-                                                              uint32_t* __restrict__ tile_v) {
-    const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
-    if (i > nt) return;
-    const uint32_t p = i < nt ? i * MG_TILE : e_old - 1;
-    tile_v[i] = upper_bound_dev<uint32_t>(off, 0, nv + 1, p) - 1;
-}
-
-// Old entries: each block takes a tile of the old flat array. The tile's
-// vertices (offsets, shift to the new offsets, touched or not) are staged in
-// LDS; an entry of a vertex the batch leaves alone moves by its vertex's
-// shift, others also count the deleted entries before them and the batch
-// entries that sort before them.
-__global__ __launch_bounds__(MN_BLOCK) void k_merge_old(
-    const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj, const uint64_t* __restrict__ adjk,
-    const uint32_t* __restrict__ tile_v, uint32_t e_old, const uint32_t* __restrict__ newoff,
-    const uint4* __restrict__ meta, const uint64_t* __restrict__ bk, uint64_t kbase,
-    const uint64_t* __restrict__ dpos, uint64_t dbase, uint32_t hb, uint64_t* __restrict__ adj_new,
-    uint64_t* __restrict__ adjk_new, uint32_t e_new, uint32_t* err) {
-    __shared__ uint32_t s_off[MG_LDS + 1];
-    __shared__ uint32_t s_shift[MG_LDS];  // newoff[v] - off[v] (mod 2^32), or MN_INVALID when touched
-    __shared__ uint32_t s_dead;
-    const uint32_t p0 = blockIdx.x * MG_TILE;
-    const uint32_t p1 = min(p0 + MG_TILE, e_old);
-    const uint32_t vlo = tile_v[blockIdx.x], vhi = tile_v[blockIdx.x + 1];
-    const uint32_t span = vhi - vlo + 1;
-    const bool staged = span <= MG_LDS;
-    if (threadIdx.x == 0) s_dead = failed(err) ? 1u : 0u;
-    if (staged) {
-        for (uint32_t x = threadIdx.x; x <= span; x += MN_BLOCK) s_off[x] = off[vlo + x];
-        for (uint32_t x = threadIdx.x; x < span; x += MN_BLOCK) {
-            const uint4 m = meta[vlo + x];
-            s_shift[x] = (m.y | m.w) ? MN_INVALID : newoff[vlo + x] - off[vlo + x];
-        }
-    }
-    __syncthreads();
-    if (s_dead) return;
-    for (uint32_t k = 0; k < MG_ITEMS; k++) {
-        const uint32_t p = p0 + k * MN_BLOCK + threadIdx.x;
-        if (p >= p1) break;
-        const uint64_t e = adj[p];
-        if (ent_lo(e) & MN_FLAG) continue;  // deleted by the previous snapshot
-        uint32_t v, shift = MN_INVALID;
-        if (staged) {
-            uint32_t a = 0, b = span;  // largest x with s_off[x] <= p
-            while (a + 1 < b) {
-                const uint32_t mid = (a + b) >> 1;
-                if (s_off[mid] <= p)
-                    a = mid;
-                else
-                    b = mid;
-            }
-            v = vlo + a;
-            shift = s_shift[a];
-        } else {
-            v = upper_bound_dev<uint32_t>(off, vlo, vhi + 1, p) - 1;
-        }
-        uint32_t dst;
-        if (shift != MN_INVALID) {
-            dst = p + shift;
-        } else {
-            const uint4 m = meta[v];
-            uint32_t kept = p - off[v];
-            if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, dbase + p) - m.z;
-            uint32_t ins = 0;
-            if (m.y) ins = lower_bound_dev<uint64_t>(bk, m.x, m.x + m.y, kbase + (((uint64_t)v << hb) | ent_hi(e))) - m.x;
-            dst = newoff[v] + kept + ins;
-        }
-        if (dst >= e_new) {  // never expected; refuse rather than write out of bounds
-            set_err(err, MN_ERR_INTERNAL);
-            continue;
-        }
-        adj_new[dst] = e;
-        adjk_new[dst] = adjk[p];
-    }
-}
-
-// Batch entries: placed after every kept old entry with a high word <= theirs.
+// Batch entries: placed after every kept old entry of their vertex with a high
+// word <= theirs. ub[r] records that insertion point (the first old position
+// after the batch entry), which places the old entries in k_merge_old.
 __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
     const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj,
     const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
     const uint64_t* __restrict__ bk, uint64_t kbase, const uint32_t* __restrict__ bv,
     const uint64_t* __restrict__ s_key, uint32_t n_b, const uint64_t* __restrict__ dpos, uint64_t dbase,
     uint32_t hb, uint64_t* __restrict__ adj_new, uint64_t* __restrict__ adjk_new, uint32_t* __restrict__ inspos,
-    uint32_t e_new, uint32_t* err) {
+    uint32_t* __restrict__ ub_out, uint32_t e_new, uint32_t* err) {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_b || failed(err)) return;
     uint64_t key = bk[r] - kbase;
@@ -279,6 +214,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
     uint32_t h = (uint32_t)(key & ((1ull << hb) - 1));
     uint32_t o0 = off[v], o1 = off[v + 1];
     uint32_t ub = upper_hi(adj, o0, o1, h);
+    ub_out[r] = ub;
     uint4 m = meta[v];
     uint32_t kept = ub - o0;
     if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, dbase + ub) - m.z;
@@ -291,6 +227,95 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
     adj_new[out] = ((uint64_t)h << 32) | MN_FLAG | bv[r];
     adjk_new[out] = s_key[bv[r]];
     inspos[r] = out;
+}
+
+// Old entries keep their order: the kept entry at old position p moves to
+// p - (deleted entries before p) + (batch entries whose insertion point is
+// <= p), whatever its vertex. Each block takes a tile of the old array; two
+// binary searches give both counts at the tile's start, the deletions and
+// insertion points inside the tile are marked in LDS and prefix-summed, and
+// every entry then costs one LDS read between its loads and its stores.
+// ub (n_b, sorted) comes from k_merge_new, which must run first.
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_old(const uint64_t* __restrict__ adj,
+                                                        const uint64_t* __restrict__ adjk, uint32_t e_old,
+                                                        const uint32_t* __restrict__ ub, uint32_t n_b,
+                                                        const uint64_t* __restrict__ dpos, uint64_t dbase,
+                                                        uint32_t n_d, uint64_t* __restrict__ adj_new,
+                                                        uint64_t* __restrict__ adjk_new, uint32_t e_new,
+                                                        uint32_t* err) {
+    __shared__ __align__(16) int32_t s_m[MG_TILE];
+    __shared__ uint32_t s_lim[4];
+    __shared__ int32_t s_wsum[MN_BLOCK / MN_WAVE];
+    __shared__ uint32_t s_dead;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t p0 = blockIdx.x * MG_TILE;
+    const uint32_t p1 = min(p0 + MG_TILE, e_old);
+    // the tile's entries are requested before anything waits on them
+    uint64_t e[MG_ITEMS], ek[MG_ITEMS];
+#pragma unroll
+    for (uint32_t k = 0; k < MG_ITEMS; k++) {
+        const uint32_t p = p0 + k * MN_BLOCK + tid;
+        e[k] = p < p1 ? adj[p] : 0ull;
+        ek[k] = p < p1 ? adjk[p] : 0ull;
+    }
+    if (tid < 4) {  // insertion points below p0 / p1, deletions below p0 / p1
+        const uint32_t at = (tid & 1) ? p1 : p0;
+        s_lim[tid] = tid < 2 ? lower_bound_dev<uint32_t>(ub, 0, n_b, at)
+                             : lower_bound_dev<uint64_t>(dpos, 0, n_d, dbase + at);
+    }
+    if (tid == 0) s_dead = failed(err) ? 1u : 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < MG_ITEMS; k++) s_m[k * MN_BLOCK + tid] = 0;
+    __syncthreads();
+    if (s_dead) return;
+    const uint32_t uA = s_lim[0], uB = s_lim[1], dA = s_lim[2], dB = s_lim[3];
+    const bool marks = uA < uB || dA < dB;  // the same for every thread of the block
+    if (marks) {
+        for (uint32_t r = uA + tid; r < uB; r += MN_BLOCK) {
+            const uint32_t i = ub[r] - p0;
+            if (i < MG_TILE) atomicAdd(&s_m[i], 1);
+        }
+        for (uint32_t k = dA + tid; k < dB; k += MN_BLOCK) {
+            const uint32_t i = (uint32_t)(dpos[k] - dbase) - p0 + 1;  // counts for the entries after it
+            if (i < MG_TILE) atomicAdd(&s_m[i], -1);
+        }
+        __syncthreads();
+        // inclusive scan over the tile: eight consecutive marks per thread,
+        // then across the lanes and the waves
+        int4* q = reinterpret_cast<int4*>(s_m + tid * MG_ITEMS);
+        const int4 a = q[0], b = q[1];
+        int32_t v[MG_ITEMS] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (uint32_t k = 1; k < MG_ITEMS; k++) v[k] += v[k - 1];
+        const int32_t run = v[MG_ITEMS - 1];
+        const uint32_t lane = __lane_id(), wave = tid / MN_WAVE;
+        int32_t incl = run;
+#pragma unroll
+        for (int d = 1; d < MN_WAVE; d <<= 1) {
+            const int32_t y = __shfl_up(incl, d, MN_WAVE);
+            if (lane >= (uint32_t)d) incl += y;
+        }
+        if (lane == MN_WAVE - 1) s_wsum[wave] = incl;
+        __syncthreads();
+        int32_t pre = incl - run;
+        for (uint32_t w = 0; w < wave; w++) pre += s_wsum[w];
+        q[0] = make_int4(v[0] + pre, v[1] + pre, v[2] + pre, v[3] + pre);
+        q[1] = make_int4(v[4] + pre, v[5] + pre, v[6] + pre, v[7] + pre);
+        __syncthreads();
+    }
+    const int64_t base = (int64_t)uA - (int64_t)dA;
+#pragma unroll
+    for (uint32_t k = 0; k < MG_ITEMS; k++) {
+        const uint32_t p = p0 + k * MN_BLOCK + tid;
+        if (p >= p1 || (ent_lo(e[k]) & MN_FLAG)) continue;  // past the end, or deleted by the previous snapshot
+        const int64_t dst = (int64_t)p + base + (marks ? s_m[k * MN_BLOCK + tid] : 0);
+        if (dst < 0 || dst >= (int64_t)e_new) {  // never expected; refuse rather than write out of bounds
+            set_err(err, MN_ERR_INTERNAL);
+            continue;
+        }
+        adj_new[dst] = e[k];
+        adjk_new[dst] = ek[k];
+    }
 }
 
 // VF bit of (query, vertex u) at data vertex v: label requirement plus the
@@ -389,7 +414,6 @@ inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_
 
 }  // namespace
 
-uint32_t mn_merge_tiles(uint32_t e_old) { return (e_old + MG_TILE - 1) / MG_TILE; }
 
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) { k_set_u32<<<1, 64, 0, s>>>(p, v); }
 
@@ -423,20 +447,17 @@ void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_
                                                            dbase, n_d, hb, newoff, meta, err);
 }
 
-void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t n_vertices,
-                     uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
-                     uint64_t kbase, const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b,
-                     const uint64_t* dpos, uint64_t dbase, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t e_new, uint32_t* tile_v, uint32_t* err, hipStream_t s) {
-    if (e_old) {
-        const uint32_t nt = (e_old + MG_TILE - 1) / MG_TILE;
-        k_merge_partition<<<nblocks(nt + 1), MN_BLOCK, 0, s>>>(off, n_vertices, e_old, nt, tile_v);
-        k_merge_old<<<nt, MN_BLOCK, 0, s>>>(off, adj, adjk, tile_v, e_old, newoff, meta, bkeys, kbase, dpos, dbase,
-                                            hb, adj_new, adjk_new, e_new, err);
-    }
+void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t e_old,
+                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys, uint64_t kbase,
+                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
+                     uint64_t dbase, uint32_t n_d, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
+                     uint32_t* inspos, uint32_t* ub, uint32_t e_new, uint32_t* err, hipStream_t s) {
     if (n_b)
         k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, kbase, bvals, s_key, n_b, dpos,
-                                                      dbase, hb, adj_new, adjk_new, inspos, e_new, err);
+                                                      dbase, hb, adj_new, adjk_new, inspos, ub, e_new, err);
+    if (e_old)
+        k_merge_old<<<(e_old + MG_TILE - 1) / MG_TILE, MN_BLOCK, 0, s>>>(adj, adjk, e_old, ub, n_b, dpos, dbase, n_d,
+                                                                         adj_new, adjk_new, e_new, err);
 }
 
 void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits, uint32_t n_slots,

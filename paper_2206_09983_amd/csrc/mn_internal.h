@@ -13,8 +13,8 @@ size_t mn_scan_scratch_words(uint32_t n);
 void mn_scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* scratch,
                        hipStream_t s);
 
-// Exclusive prefix sum of n u32 values into u64 offsets; *total receives the
-// sum. `scratch` must hold mn_scan64_scratch_words(n) u64 words. With n_dev,
+// Exclusive prefix sum of n u32 values into u64 offsets; *total (when given)
+// receives the sum. `scratch` must hold mn_scan64_scratch_words(n) u64 words. With n_dev,
 // the count is min(n, *n_dev), read on the device (n sizes the launch).
 size_t mn_scan64_scratch_words(uint32_t n);
 void mn_scan_exclusive64(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* scratch,
@@ -90,13 +90,13 @@ void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_
                            const uint64_t* bkeys, uint64_t kbase, uint32_t n_b, const uint64_t* dpos,
                            uint64_t dbase, uint32_t n_d, uint32_t hb, uint32_t* newoff, uint4* meta,
                            const uint32_t* err, hipStream_t s);
-void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t n_vertices,
-                     uint32_t e_old, const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys,
-                     uint64_t kbase, const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b,
-                     const uint64_t* dpos, uint64_t dbase, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t e_new, uint32_t* tile_v, uint32_t* err, hipStream_t s);
-// Words tile_v needs for a merge of e_old old entries, minus one.
-uint32_t mn_merge_tiles(uint32_t e_old);
+// Merged adjacency of one direction: batch entries first (their insertion
+// points go to ub, n_b words), then the kept old entries placed by them.
+void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t e_old,
+                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys, uint64_t kbase,
+                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
+                     uint64_t dbase, uint32_t n_d, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
+                     uint32_t* inspos, uint32_t* ub, uint32_t e_new, uint32_t* err, hipStream_t s);
 // Query-dependent state of the present edges after a change of the query
 // set: edgeMatcher words of the live slots among [0, n_slots) and counter
 // increments for them and for the n_pend slots deleted by the last batch.
@@ -160,9 +160,12 @@ void mn_launch_decide(const GraphView& g, RowsView rows, const uint32_t* slots, 
 void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long long* note, hipStream_t s);
 
 // Candidate range of every row at level L: lo[r] and cnt[r]. With n_dev the
-// row count is min(n, *n_dev), read on the device (n sizes the launch).
+// row count is min(n, *n_dev), read on the device (n sizes the launch), and
+// note (optional) records it against n: note[0] = 1 when it is larger,
+// note[1] = the largest count seen. zero_next (optional) is set to 0.
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
-                           uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s);
+                           uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s,
+                           uint32_t* zero_next = nullptr, unsigned long long* note = nullptr);
 // Grid cap of a device-sized expansion (its candidate total is only known on
 // the device): one launch covers at most this many tiles.
 constexpr uint64_t MN_EXPAND_MAX_BLOCKS = 1u << 20;
@@ -173,17 +176,19 @@ constexpr uint64_t MN_EXPAND_MAX_BLOCKS = 1u << 20;
 // tile_row must hold mn_expand_tiles(c0, c1) + 1 words (enough for any tile size).
 uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1);
 // rows: some plan continues past level L; emit: some plan ends at level L.
-// Host-sized form: n_dev = T_dev = note = NULL, candidates exactly [c0, c1).
-// Device-sized form: the row count is min(n_in, *n_dev) and the candidates
-// are [c0, min(c1, *T_dev)); note[0] is set when *T_dev > c1 and note[1]
-// keeps the largest *T_dev (the host grows buffers and re-runs); `expect`,
+// Host-sized form: n_dev = cnt = T_dev = note = NULL, candidates exactly
+// [c0, c1). Device-sized form: the row count is min(n_in, *n_dev), the
+// candidate total T = off[n-1] + cnt[n-1] is stored in *T_dev and the
+// candidates are [c0, min(c1, T)); note[0] is set when T > c1 and note[1]
+// keeps the largest T (the host grows buffers and re-runs); `expect`,
 // the candidates the host expects, only sizes the grid. items (1, 2 or 4)
 // sets the tile: 256 x items candidates per block.
 // Returns the end of the candidates the launch covers (c1, lowered to what
 // the grid covers in the device-sized form). ev0/ev1, when given, are
 // recorded right before and after the k_expand launch itself.
 uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
-                      const uint64_t* off, uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
+                      const uint64_t* off, const uint32_t* cnt, uint32_t* tile_row, uint64_t c0, uint64_t c1,
+                      uint64_t* T_dev,
                       unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
                       bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
@@ -197,8 +202,9 @@ void mn_launch_widen(const uint32_t* in, uint64_t* out, uint64_t add, uint32_t n
 
 // ------------------------------------------------------------ order network
 // The scheduler's 24 -> 64 -> 64 -> 1 network (weights as in mn_common.h).
-// y[i] = net(x[i]) for n samples of 24 floats; bf16 != 0 rounds weights and
-// inputs to bfloat16 first (fp32 sums either way).
+// y[i] = net(x[i]) for n samples of 24 floats. bf16 != 0: bf16 inference on
+// the matrix cores (weights, inputs and first hidden layer rounded to
+// bfloat16, fp32 sums), as the decision kernel evaluates; else fp32 throughout.
 void mn_mlp_predict(const float* w, const float* x, uint64_t n, int bf16, float* y, hipStream_t s);
 // Adds to grad the gradient of mean((net(x[k]) - target[k])^2) over the m
 // samples k = idx[off + t] (t < m; idx NULL: k = off + t), and that mean to *loss.

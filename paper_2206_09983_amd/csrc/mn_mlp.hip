@@ -8,9 +8,11 @@
 // in LDS; thread t works on sample t / 4 and a quarter of its units.
 // Backward forms the weight gradients of the block as small products over
 // its 64 samples in LDS, then adds them to the global gradient once per
-// block. The sizes are tiny next to the matcher, so the products are plain
-// FMA loops rather than matrix-core tiles.
+// block. The sizes are tiny next to the matcher, so the training products are
+// plain FMA loops. Inference in bf16 runs on the matrix cores instead, through
+// the same wave-level evaluator the decision kernel uses (mn_sched.h).
 #include "mn_internal.h"
+#include "mn_sched.h"
 
 namespace {
 
@@ -85,6 +87,25 @@ __global__ __launch_bounds__(MN_BLOCK) void k_mlp_predict(const float* __restric
     const float v = forward(L);
     const int s = threadIdx.x >> 2;
     if ((threadIdx.x & 3) == 0 && base + s < n) y[base + s] = v;
+}
+
+// bf16 inference: weights, inputs and hidden activations rounded to bf16,
+// fp32 sums, one sample per lane on the matrix cores.
+__global__ __launch_bounds__(MN_BLOCK) void k_mlp_predict_mm(const float* __restrict__ w, const float* __restrict__ x,
+                                                             uint64_t n, float* __restrict__ y) {
+    __shared__ sched::NetVec V;
+    __shared__ __align__(16) uint16_t s_xs[MN_BLOCK / MN_WAVE][MN_WAVE * sched::XS_STRIDE];
+    auto W = [w](uint32_t i) { return sched::bf16_bits(w[i]); };
+    sched::NetFrag F;
+    sched::load_frag(F, W);
+    sched::load_vec(V, W);
+    __syncthreads();
+    const uint64_t s = (uint64_t)blockIdx.x * MN_BLOCK + threadIdx.x;
+    float xv[NI];
+#pragma unroll
+    for (int f = 0; f < NI; f++) xv[f] = s < n ? x[s * NI + f] : 0.0f;
+    const float v = sched::eval_wave(F, V, xv, s_xs[threadIdx.x / MN_WAVE]);
+    if (s < n) y[s] = v;
 }
 
 // Gradient of the mean squared error over the m samples idx[off .. off + m)
@@ -183,7 +204,11 @@ inline uint32_t mlp_blocks(uint64_t n) { return (uint32_t)((n + SPB - 1) / SPB);
 }  // namespace
 
 void mn_mlp_predict(const float* w, const float* x, uint64_t n, int bf16, float* y, hipStream_t s) {
-    if (n) k_mlp_predict<<<mlp_blocks(n), MN_BLOCK, 0, s>>>(w, x, n, bf16, y);
+    if (!n) return;
+    if (bf16)
+        k_mlp_predict_mm<<<(uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK), MN_BLOCK, 0, s>>>(w, x, n, y);
+    else
+        k_mlp_predict<<<mlp_blocks(n), MN_BLOCK, 0, s>>>(w, x, n, 0, y);
 }
 
 void mn_mlp_grad(const float* w, const float* x, const float* target, const uint32_t* idx, uint64_t off,

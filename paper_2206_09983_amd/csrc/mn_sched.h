@@ -87,79 +87,123 @@ __device__ inline void features(const GraphView& g, const SeedPlan& V, uint32_t 
 
 __device__ inline float bf(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// bfloat16 rounding (nearest, ties to even) of a finite float.
-__device__ inline float bf16_round(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7F800000u) == 0x7F800000u) return v;
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xFFFF0000u);
+// bfloat16 bits of a float, rounded to nearest, ties to even (inf and nan
+// keep their top half).
+__device__ inline uint16_t bf16_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(u >> 16);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// LDS image of the network: the bf16 weights, widened to fp32 once per block
-// (exact: a bf16 value is an fp32 value with a zero low half), W2 transposed
-// (W2t[u2][u]) so that the second layer's inner products read contiguous
-// words. Widening once spares every evaluation two ALU operations per weight.
-struct __align__(16) NetLds {
-    float w1[NI * NH];
-    float b1[NH];
-    float w2t[NH * NH];
-    float b2[NH];
-    float w3[NH];
-    float b3[4];
+// ---- matrix-core evaluation (v_mfma_f32_16x16x32_bf16)
+//
+// One wave evaluates 64 samples, four tiles of 16. Both layers are computed
+// transposed, units x samples, so that the first layer's accumulators already
+// sit where the second layer's B operand needs them:
+//   A (16 units x 32 k): lane i + 16 g holds unit i, k-slots 8 g .. 8 g + 7
+//   B (32 k x 16 samples): lane j + 16 g holds sample j, the same k-slots
+//   D (16 units x 16 samples): lane j + 16 g holds sample j, units 4 g .. 4 g + 3
+// Layer 1: k-slot = input (24 used, 8 zero). Layer 2 contracts over the 64
+// hidden units in two K-slices; slot t of group g in slice kc is hidden unit
+// 32 kc + 16 (t / 4) + 4 g + t % 4, exactly the unit the lane holds in
+// element t % 4 of layer-1 tile 2 kc + t / 4. The A fragments use the same
+// slot order, so the hidden layer never leaves the registers. The hidden
+// activations are rounded to bf16 for the second product; every sum is fp32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int XS_STRIDE = 40;  // bf16 per sample row in LDS (32 used; 80 bytes keeps rows 16-byte aligned)
+
+__device__ inline __bf16 as_bf16(uint16_t h) { return __builtin_bit_cast(__bf16, h); }
+
+__device__ inline uint32_t hidden_of_slot(uint32_t kc, uint32_t g, uint32_t t) {
+    return 32u * kc + 16u * (t / 4u) + 4u * g + (t % 4u);
+}
+
+// The lane's A fragments, loaded once per wave.
+struct NetFrag {
+    bf16x8 a1[4];     // layer 1, unit tile mt
+    bf16x8 a2[4][2];  // layer 2, unit tile mt, K-slice kc
 };
 
-__device__ inline void load_net(NetLds& N, const uint16_t* __restrict__ w) {
-    for (int i = threadIdx.x; i < NI * NH; i += blockDim.x) N.w1[i] = bf(w[OFF_W1 + i]);
-    for (int i = threadIdx.x; i < NH * NH; i += blockDim.x) {  // consecutive LDS words per wave
-        const int u2 = i / NH, u = i % NH;
-        N.w2t[i] = bf(w[OFF_W2 + u * NH + u2]);
+// Biases and output weights (fp32 widenings of the bf16 values), shared by
+// the block in LDS.
+struct NetVec {
+    float b1[NH], b2[NH], w3[NH], b3;
+};
+
+// W(i) returns the bf16 bits of flat weight i.
+template <typename WF>
+__device__ inline void load_frag(NetFrag& F, WF W) {
+    const uint32_t lane = __lane_id(), i = lane % 16u, g = lane / 16u;
+#pragma unroll
+    for (uint32_t mt = 0; mt < 4; mt++) {
+#pragma unroll
+        for (uint32_t t = 0; t < 8; t++) {
+            const uint32_t in = 8u * g + t;
+            F.a1[mt][t] = as_bf16(in < (uint32_t)NI ? W(OFF_W1 + in * NH + 16u * mt + i) : (uint16_t)0);
+#pragma unroll
+            for (uint32_t kc = 0; kc < 2; kc++)
+                F.a2[mt][kc][t] = as_bf16(W(OFF_W2 + hidden_of_slot(kc, g, t) * NH + 16u * mt + i));
+        }
     }
-    for (int i = threadIdx.x; i < NH; i += blockDim.x) {
-        N.b1[i] = bf(w[OFF_B1 + i]);
-        N.b2[i] = bf(w[OFF_B2 + i]);
-        N.w3[i] = bf(w[OFF_W3 + i]);
-    }
-    if (threadIdx.x == 0) N.b3[0] = bf(w[OFF_B3]);
 }
 
-// One lane, one sample: inputs rounded to bf16, bf16 weights, fp32 sums. The
-// hidden layer stays in registers; weights stream from LDS four at a time
-// (every lane of a wave reads the same words, a broadcast).
-__device__ inline float eval(const NetLds& N, const float* x) {
-    float h[NH];
-#pragma unroll
-    for (int u = 0; u < NH; u++) h[u] = N.b1[u];
-#pragma unroll 1
-    for (int i = 0; i < NI; i++) {
-        const float xi = bf16_round(x[i]);
-        const float4* row = reinterpret_cast<const float4*>(N.w1 + i * NH);
-#pragma unroll
-        for (int u = 0; u < NH / 4; u++) {
-            const float4 w = row[u];
-            h[4 * u] = fmaf(xi, w.x, h[4 * u]);
-            h[4 * u + 1] = fmaf(xi, w.y, h[4 * u + 1]);
-            h[4 * u + 2] = fmaf(xi, w.z, h[4 * u + 2]);
-            h[4 * u + 3] = fmaf(xi, w.w, h[4 * u + 3]);
-        }
+template <typename WF>
+__device__ inline void load_vec(NetVec& V, WF W) {
+    for (int u = threadIdx.x; u < NH; u += blockDim.x) {
+        V.b1[u] = bf(W(OFF_B1 + u));
+        V.b2[u] = bf(W(OFF_B2 + u));
+        V.w3[u] = bf(W(OFF_W3 + u));
     }
+    if (threadIdx.x == 0) V.b3 = bf(W(OFF_B3));
+}
+
+// Prediction for the lane's sample x (24 features; rounded to bf16 here).
+// xs is the wave's LDS staging area (64 x XS_STRIDE bf16). Every lane of the
+// wave must call this, and the wave's LDS traffic is ordered by the caller's
+// barriers: the call waits on the block at entry and at exit, so the whole
+// block must call it together.
+__device__ inline float eval_wave(const NetFrag& F, const NetVec& V, const float* x, uint16_t* xs) {
+    const uint32_t lane = __lane_id(), i = lane % 16u, g = lane / 16u;
+    uint32_t* row = reinterpret_cast<uint32_t*>(xs + lane * XS_STRIDE);
 #pragma unroll
-    for (int u = 0; u < NH; u++) h[u] = fmaxf(h[u], 0.0f);
-    float y = N.b3[0];
-#pragma unroll 1
-    for (int u2 = 0; u2 < NH; u2++) {
-        float z = N.b2[u2];
-        const float4* col = reinterpret_cast<const float4*>(N.w2t + u2 * NH);
+    for (int p = 0; p < NI / 2; p++) row[p] = (uint32_t)bf16_bits(x[2 * p]) | ((uint32_t)bf16_bits(x[2 * p + 1]) << 16);
 #pragma unroll
-        for (int u = 0; u < NH / 4; u++) {
-            const float4 w = col[u];
-            z = fmaf(h[4 * u], w.x, z);
-            z = fmaf(h[4 * u + 1], w.y, z);
-            z = fmaf(h[4 * u + 2], w.z, z);
-            z = fmaf(h[4 * u + 3], w.w, z);
+    for (int p = NI / 2; p < 16; p++) row[p] = 0u;
+    __syncthreads();
+    float mine = 0.0f;
+#pragma unroll
+    for (uint32_t nt = 0; nt < 4; nt++) {
+        const bf16x8 xb = *reinterpret_cast<const bf16x8*>(xs + (16u * nt + i) * XS_STRIDE + 8u * g);
+        f32x4 h[4];
+#pragma unroll
+        for (uint32_t mt = 0; mt < 4; mt++) {
+            const f32x4 c = {V.b1[16 * mt + 4 * g], V.b1[16 * mt + 4 * g + 1], V.b1[16 * mt + 4 * g + 2],
+                             V.b1[16 * mt + 4 * g + 3]};
+            h[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a1[mt], xb, c, 0, 0, 0);
         }
-        y = fmaf(fmaxf(z, 0.0f), N.w3[u2], y);
+        bf16x8 hb[2];
+#pragma unroll
+        for (uint32_t kc = 0; kc < 2; kc++)
+#pragma unroll
+            for (uint32_t t = 0; t < 8; t++) hb[kc][t] = as_bf16(bf16_bits(fmaxf(h[2 * kc + t / 4][t % 4], 0.0f)));
+        float part = 0.0f;
+#pragma unroll
+        for (uint32_t mt = 0; mt < 4; mt++) {
+            f32x4 z = {V.b2[16 * mt + 4 * g], V.b2[16 * mt + 4 * g + 1], V.b2[16 * mt + 4 * g + 2],
+                       V.b2[16 * mt + 4 * g + 3]};
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[mt][0], hb[0], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[mt][1], hb[1], z, 0, 0, 0);
+#pragma unroll
+            for (uint32_t r = 0; r < 4; r++) part = fmaf(fmaxf(z[r], 0.0f), V.w3[16 * mt + 4 * g + r], part);
+        }
+        part += __shfl_xor(part, 16, MN_WAVE);
+        part += __shfl_xor(part, 32, MN_WAVE);
+        if (nt == g) mine = part + V.b3;  // lane 16 g + j holds sample 16 g + j: its own
     }
-    return y;
+    __syncthreads();
+    return mine;
 }
 
 }  // namespace sched

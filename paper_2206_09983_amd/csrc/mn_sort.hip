@@ -4,16 +4,22 @@
 // scatter ranks keys stably inside a tile with wave ballots: eight ballots on
 // the digit bits give each lane the mask of lanes holding the same digit, and
 // per-wave digit counts in LDS order the four waves of a round.
+#include <algorithm>
+#include <utility>
+
 #include "mn_internal.h"
 
 namespace {
 
 constexpr uint32_t SC_ITEMS = 8;
 constexpr uint32_t SC_TILE = MN_BLOCK * SC_ITEMS;  // 2048
-constexpr uint32_t RS_ROUNDS = 16;
-constexpr uint32_t RS_TILE = MN_BLOCK * RS_ROUNDS;  // 4096
+// A radix tile is 256 x ROUNDS keys. Small inputs take short tiles so that a
+// pass still spreads over many blocks (a tile's rounds run one after another).
+constexpr uint32_t RS_ROUNDS_MAX = 16;
+constexpr uint32_t RS_TILE_MAX = MN_BLOCK * RS_ROUNDS_MAX;  // 4096
+constexpr uint32_t RS_TILE_MIN = MN_BLOCK * 4;             // 1024
 constexpr uint32_t RS_WAVES = MN_BLOCK / MN_WAVE;
-constexpr uint32_t RS_FUSE_BLOCKS = 64;  // inputs up to 64 tiles scan their histograms in the scatter
+constexpr uint32_t RS_FUSE_BLOCKS = 128;  // inputs up to 128 tiles scan their histograms in the scatter
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x) {
     uint32_t lane = __lane_id();
@@ -65,6 +71,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_scan_add(uint32_t* __restrict__ ou
     }
 }
 
+template <uint32_t ROUNDS>
 __global__ __launch_bounds__(MN_BLOCK) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n,
                                                       uint32_t shift, uint32_t* __restrict__ hist,
                                                       uint32_t nblk) {
@@ -72,16 +79,22 @@ __global__ __launch_bounds__(MN_BLOCK) void k_rs_hist(const uint64_t* __restrict
     uint32_t tid = threadIdx.x;
     h[tid] = 0;
     __syncthreads();
-    size_t base = (size_t)blockIdx.x * RS_TILE;
-    for (uint32_t r = 0; r < RS_ROUNDS; r++) {
-        size_t idx = base + (size_t)r * MN_BLOCK + tid;
-        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    size_t base = (size_t)blockIdx.x * (MN_BLOCK * ROUNDS);
+    uint64_t k[ROUNDS];
+#pragma unroll
+    for (uint32_t r = 0; r < ROUNDS; r++) {
+        const size_t idx = base + (size_t)r * MN_BLOCK + tid;
+        k[r] = idx < n ? keys[idx] : 0ull;
     }
+#pragma unroll
+    for (uint32_t r = 0; r < ROUNDS; r++)
+        if (base + (size_t)r * MN_BLOCK + tid < n) atomicAdd(&h[(uint32_t)(k[r] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(size_t)tid * nblk + blockIdx.x] = h[tid];
 }
 
 // Stable scatter of one tile by digit, starting at base_off[digit] (LDS).
+template <uint32_t ROUNDS>
 __device__ void rs_scatter_tile(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                 uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
                                 uint32_t shift, uint32_t* base_off, uint32_t (*wcnt)[256]) {
@@ -90,11 +103,22 @@ __device__ void rs_scatter_tile(const uint64_t* __restrict__ kin, const uint32_t
     for (uint32_t w = 0; w < RS_WAVES; w++) wcnt[w][tid] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
-    size_t base = (size_t)blockIdx.x * RS_TILE;
-    for (uint32_t r = 0; r < RS_ROUNDS; r++) {
+    size_t base = (size_t)blockIdx.x * (MN_BLOCK * ROUNDS);
+    // every round's keys and values are requested before the first round
+    // waits on them
+    uint64_t keys[ROUNDS];
+    uint32_t vals[ROUNDS];
+#pragma unroll
+    for (uint32_t r = 0; r < ROUNDS; r++) {
+        const size_t idx = base + (size_t)r * MN_BLOCK + tid;
+        keys[r] = idx < n ? kin[idx] : 0ull;
+        vals[r] = idx < n ? vin[idx] : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < ROUNDS; r++) {
         size_t idx = base + (size_t)r * MN_BLOCK + tid;
         bool valid = idx < n;
-        uint64_t key = valid ? kin[idx] : 0ull;
+        uint64_t key = keys[r];
         uint32_t d = (uint32_t)(key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -112,7 +136,7 @@ __device__ void rs_scatter_tile(const uint64_t* __restrict__ kin, const uint32_t
             for (uint32_t w = 0; w < wave; w++) rank += wcnt[w][d];
             if (rank < n) {  // always true for a consistent histogram
                 kout[rank] = key;
-                vout[rank] = vin[idx];
+                vout[rank] = vals[r];
             }
         }
         __syncthreads();
@@ -126,6 +150,7 @@ __device__ void rs_scatter_tile(const uint64_t* __restrict__ kin, const uint32_t
     }
 }
 
+template <uint32_t ROUNDS>
 __global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          uint64_t* __restrict__ kout,
@@ -136,13 +161,14 @@ __global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter(const uint64_t* __restr
     __shared__ uint32_t base_off[256];
     __shared__ uint32_t wcnt[RS_WAVES][256];
     base_off[threadIdx.x] = hist[(size_t)threadIdx.x * nblk + blockIdx.x];
-    rs_scatter_tile(kin, vin, kout, vout, n, shift, base_off, wcnt);
+    rs_scatter_tile<ROUNDS>(kin, vin, kout, vout, n, shift, base_off, wcnt);
 }
 
 // Scatter for small inputs (nblk <= RS_FUSE_BLOCKS): each block derives its
 // digit offsets from the unscanned per-block histograms itself (column sums
 // scanned over digits, plus the counts of earlier blocks), saving the
 // device-wide scan launches.
+template <uint32_t ROUNDS>
 __global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter_fused(const uint64_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint64_t* __restrict__ kout,
@@ -155,8 +181,20 @@ __global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter_fused(const uint64_t* _
     __shared__ uint32_t wsum[RS_WAVES];
     const uint32_t d = threadIdx.x;
     uint32_t col = 0, before = 0;
-    for (uint32_t b = 0; b < nblk; b++) {
-        const uint32_t h = hist[(size_t)d * nblk + b];
+    const uint32_t* row = hist + (size_t)d * nblk;
+    uint32_t b = 0;
+    if ((nblk & 3u) == 0) {  // rows of 16-byte words: independent wide loads
+        const uint4* row4 = reinterpret_cast<const uint4*>(row);
+#pragma unroll 8
+        for (; b < nblk; b += 4) {
+            const uint4 h = row4[b >> 2];
+            col += h.x + h.y + h.z + h.w;
+            before += (b < blockIdx.x ? h.x : 0u) + (b + 1 < blockIdx.x ? h.y : 0u) +
+                      (b + 2 < blockIdx.x ? h.z : 0u) + (b + 3 < blockIdx.x ? h.w : 0u);
+        }
+    }
+    for (; b < nblk; b++) {
+        const uint32_t h = row[b];
         col += h;
         if (b < blockIdx.x) before += h;
     }
@@ -166,7 +204,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_rs_scatter_fused(const uint64_t* _
     uint32_t wpre = 0;
     for (uint32_t w = 0; w < d / MN_WAVE; w++) wpre += wsum[w];
     base_off[d] = wpre + incl - col + before;
-    rs_scatter_tile(kin, vin, kout, vout, n, shift, base_off, wcnt);
+    rs_scatter_tile<ROUNDS>(kin, vin, kout, vout, n, shift, base_off, wcnt);
 }
 
 __device__ inline uint64_t wave_incl_scan64(uint64_t x) {
@@ -215,9 +253,12 @@ __global__ __launch_bounds__(MN_BLOCK) void k_scan64_local(const TI* in, uint64_
 }
 
 __global__ __launch_bounds__(MN_BLOCK) void k_scan64_add(uint64_t* __restrict__ out,
-                                                         const uint64_t* __restrict__ sums, uint32_t n) {
-    uint64_t add = sums[blockIdx.x];
+                                                         const uint64_t* __restrict__ sums, uint32_t n,
+                                                         const uint32_t* n_dev) {
+    if (n_dev) n = min(n, *n_dev);
     size_t base = (size_t)blockIdx.x * SC_TILE;
+    if (base >= n) return;  // past the elements present
+    uint64_t add = sums[blockIdx.x];
     for (uint32_t i = threadIdx.x; i < SC_TILE; i += MN_BLOCK) {
         size_t idx = base + i;
         if (idx < n) out[idx] += add;
@@ -240,7 +281,7 @@ void scan64_rec(const TI* in, uint64_t* out, uint32_t n, const uint32_t* n_dev, 
     k_scan64_local<TI><<<nb, MN_BLOCK, 0, s>>>(in, out, sums, n, n_dev);
     if (nb == 1) return;
     scan64_rec<uint64_t>(sums, sums, nb, nullptr, scratch + nb + 1, s);
-    k_scan64_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n);  // past the device count it adds into unused slots
+    k_scan64_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n, n_dev);
 }
 
 }  // namespace
@@ -258,7 +299,7 @@ size_t mn_scan64_scratch_words(uint32_t n) {
 void mn_scan_exclusive64(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* scratch,
                          uint64_t* total, hipStream_t s, const uint32_t* n_dev) {
     if (n) scan64_rec<uint32_t>(in, out, n, n_dev, scratch, s);
-    k_scan64_total<<<1, 64, 0, s>>>(in, out, n, n_dev, total);
+    if (total) k_scan64_total<<<1, 64, 0, s>>>(in, out, n, n_dev, total);
 }
 
 size_t mn_scan_scratch_words(uint32_t n) {
@@ -282,8 +323,42 @@ void mn_scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* 
     k_scan_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n);
 }
 
+namespace {
+
+// Rounds per tile for n keys: the shortest tile that keeps the histogram scan
+// inside the scatter, else the longest.
+uint32_t rs_rounds(uint32_t n) {
+    for (uint32_t r = RS_TILE_MIN / MN_BLOCK; r < RS_ROUNDS_MAX; r *= 2)
+        if (ceil_div(n, MN_BLOCK * r) <= RS_FUSE_BLOCKS) return r;
+    return RS_ROUNDS_MAX;
+}
+
+template <uint32_t ROUNDS>
+void rs_passes(uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp, uint32_t n, uint32_t nbits,
+               uint32_t* scratch, hipStream_t s) {
+    const uint32_t nblk = ceil_div(n, MN_BLOCK * ROUNDS);
+    uint32_t* hist = scratch;
+    uint32_t* sscr = scratch + (size_t)256 * nblk;
+    for (uint32_t shift = 0; shift < nbits; shift += 8) {
+        k_rs_hist<ROUNDS><<<nblk, MN_BLOCK, 0, s>>>(keys, n, shift, hist, nblk);
+        if (nblk <= RS_FUSE_BLOCKS) {
+            k_rs_scatter_fused<ROUNDS><<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
+        } else {
+            mn_scan_exclusive(hist, hist, 256 * nblk, sscr, s);
+            k_rs_scatter<ROUNDS><<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
+        }
+        std::swap(keys, ktmp);
+        std::swap(vals, vtmp);
+    }
+}
+
+}  // namespace
+
 size_t mn_sort_scratch_words(uint32_t n) {
-    uint32_t nblk = ceil_div(n ? n : 1, RS_TILE);
+    // a smaller input may take shorter tiles, hence more of them: size for
+    // the most tiles any input up to n can use
+    const uint32_t m = n ? n : 1;
+    const uint32_t nblk = std::max(std::min(ceil_div(m, RS_TILE_MIN), RS_FUSE_BLOCKS), ceil_div(m, RS_TILE_MAX));
     size_t hist = (size_t)256 * nblk;
     return hist + mn_scan_scratch_words((uint32_t)hist);
 }
@@ -291,23 +366,10 @@ size_t mn_sort_scratch_words(uint32_t n) {
 void mn_radix_sort(uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp, uint32_t n,
                    uint32_t nbits, uint32_t* scratch, hipStream_t s) {
     if (n <= 1 || nbits == 0) return;
-    uint32_t nblk = ceil_div(n, RS_TILE);
-    uint32_t* hist = scratch;
-    uint32_t* sscr = scratch + (size_t)256 * nblk;
-    for (uint32_t shift = 0; shift < nbits; shift += 8) {
-        k_rs_hist<<<nblk, MN_BLOCK, 0, s>>>(keys, n, shift, hist, nblk);
-        if (nblk <= RS_FUSE_BLOCKS) {
-            k_rs_scatter_fused<<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
-        } else {
-            mn_scan_exclusive(hist, hist, 256 * nblk, sscr, s);
-            k_rs_scatter<<<nblk, MN_BLOCK, 0, s>>>(keys, vals, ktmp, vtmp, n, shift, hist, nblk);
-        }
-        uint64_t* tk = keys;
-        keys = ktmp;
-        ktmp = tk;
-        uint32_t* tv = vals;
-        vals = vtmp;
-        vtmp = tv;
+    switch (rs_rounds(n)) {
+        case 4: rs_passes<4>(keys, vals, ktmp, vtmp, n, nbits, scratch, s); break;
+        case 8: rs_passes<8>(keys, vals, ktmp, vtmp, n, nbits, scratch, s); break;
+        default: rs_passes<16>(keys, vals, ktmp, vtmp, n, nbits, scratch, s); break;
     }
 }
 

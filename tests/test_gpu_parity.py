@@ -41,7 +41,10 @@ def say(*a):
 
 
 def run_parity(B, case, batches=None, flags=None, out_capacity=0, n_elabels=0, check_lists=True, rows_per_level=0,
-               sched=None, weights=None, trace=0):
+               sched=None, weights=None, trace=0, reruns=None):
+    """Checks every batch against the oracle; returns the embeddings seen.
+    reruns (a dict), when given, receives the phase re-runs summed over the
+    batches ("count") and their causes OR-ed ("causes")."""
     batches = case["batches"] if batches is None else batches
     flags = B.F_EMIT if flags is None else flags
     qs = case["queries"]
@@ -59,6 +62,10 @@ def run_parity(B, case, batches=None, flags=None, out_capacity=0, n_elabels=0, c
             o.apply_batch(b)
             first = m.apply_batch(b)
             assert first == o.n_keys - len(b["src"])
+            if reruns is not None:
+                st = m.stats()
+                reruns["count"] = reruns.get("count", 0) + sum(st["reruns"])
+                reruns["causes"] = reruns.get("causes", 0) | st["rerun_causes"][0] | st["rerun_causes"][1]
             for qi in range(len(qs)):
                 r = m.result(qi)
                 for ph, name in ((False, "new"), (True, "expired")):
@@ -163,14 +170,41 @@ def test_multiquery_random_shapes(B):
 
 def test_output_overflow_regrows_and_reruns(B):
     case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
-    assert run_parity(B, case, out_capacity=1) > 0
+    rr = {}
+    assert run_parity(B, case, out_capacity=1, reruns=rr) > 0
+    # the stats report the re-runs and that output buffers caused them
+    assert rr["count"] > 0 and rr["causes"] & 8
 
 
 def test_small_level_buffers_force_chunked_levels(B):
-    # 1024 rows per level: the device-sized levels overflow, the buffers
-    # cannot grow past the limit and the phase is re-run in host-walked chunks
+    # 1024 rows per level: the start rows are split into chunks that fit, and
+    # a level that outgrows its buffer (which cannot grow past the limit)
+    # sends the phase to host-walked chunks
     case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
     assert run_parity(B, case, rows_per_level=1024) > 0
+
+
+def test_candidate_spike_is_covered_without_a_rerun(B):
+    # Batch 1's start edges all point into a hub with 2,000 out-edges, so a
+    # 2-path's second level has about 10^6 candidates, far past what batch 0
+    # (no hub edges) predicts. The expansion grid follows that prediction
+    # plus a fixed reserve of spare blocks, which must take the spike without
+    # a re-run of the phase.
+    rng = np.random.default_rng(21)
+    n, m0, nb = 4096, 16000, 512
+    hub = 0
+    S = [rng.integers(1, n, m0), np.full(2000, hub), rng.integers(1, n, nb), rng.integers(1, n, nb)]
+    D = [rng.integers(1, n, m0), rng.choice(np.arange(1, n), 2000, replace=False), rng.integers(1, n, nb),
+         np.full(nb, hub)]
+    S = np.concatenate(S).astype(np.uint32)
+    D = np.concatenate(D).astype(np.uint32)
+    graph, batches = synth.split_stream(n, np.ones(n, np.uint64), S, D, np.zeros(len(S), np.uint8), m0 + 2000,
+                                        [nb, nb])
+    qs = [synth.make_query(3, [0, 0, 0], [(0, 1, -1), (1, 2, -1)], sem, "p3") for sem in (synth.ISO, synth.HOMO)]
+    case = {"name": "hub_spike", "graph": graph, "batches": batches, "queries": qs}
+    rr = {}
+    assert run_parity(B, case, check_lists=False, reruns=rr) > 10 ** 6
+    assert not rr.get("causes", 0) & 2, rr
 
 
 def test_count_only_mode_gives_same_counts_and_digests(B):

@@ -57,8 +57,19 @@ def test_forward_matches_reference_fp32_and_bf16(B, torch):
         B.mnemonic_mlp_predict(dev(torch, w), dev(torch, X), y, bf16=True)
         torch.cuda.synchronize()
         refb = omlp.forward_bf16(w, X)
-        np.testing.assert_allclose(y.cpu().numpy(), refb, rtol=0, atol=2e-5 * (1.0 + np.abs(refb).max()))
-        # and bf16 stays close to fp32: bound by the inputs' rounding
+        err = np.abs(y.cpu().numpy() - refb)
+        tight = 2e-5 * (1.0 + np.abs(refb).max())
+        # The first hidden layer is rounded to bf16 from fp32 sums taken in
+        # another order than the reference's: where a sum lands on the other
+        # side of a rounding boundary, that unit moves by one bf16 step
+        # (<= 2^-7 of its value). Bound: every unit moving at once, carried
+        # through the (1-Lipschitz) ReLU by the absolute weights.
+        W1, b1, W2, b2, W3, b3 = omlp.unpack(omlp.bf16_round(w))
+        h1 = np.maximum(omlp.bf16_round(X) @ W1 + b1, 0.0)
+        flip = (2.0 ** -7 * h1) @ np.abs(W2) @ np.abs(W3)
+        assert np.all(err <= tight + flip), (n, float((err - tight - flip).max()))
+        assert np.mean(err <= tight) >= 0.99, (n, float(np.mean(err <= tight)))
+        # and bf16 stays close to fp32: bound by the operands' rounding
         assert np.abs(refb - ref).max() < 0.05 * scale
     say("forward checked")
 
