@@ -256,6 +256,9 @@ def main(argv=None):
     ap.add_argument("--workloads", default="rmat,multiquery")
     ap.add_argument("--train-seed", type=int, default=9)
     ap.add_argument("--eval-seed", type=int, default=7)
+    ap.add_argument("--eval-only", metavar="WEIGHTS", default=None,
+                    help="evaluate these weights (a sched_weights.json) instead of training; the report's "
+                         "validation uses the same held-back tenth of the training traces")
     a = ap.parse_args(argv)
     import torch
     os.makedirs(a.out, exist_ok=True)
@@ -282,12 +285,21 @@ def main(argv=None):
     val, tr = perm[:n_val], perm[n_val:]
     X, Y = samples(x[tr], work[tr])
     Xv, Yv = samples(x[val], work[val])
-    w, hist = train(X, Y, epochs=a.epochs, lr=a.lr, log_every=1)
+    if a.eval_only:
+        w, hist = load_weights(a.eval_only), []
+        with open(a.eval_only) as f:
+            trained = json.load(f)["meta"]
+        prev = os.path.join(os.path.dirname(os.path.abspath(a.eval_only)), "sched_report.json")
+        if os.path.exists(prev):  # keep the loss curve of the run that trained these weights
+            with open(prev) as f:
+                hist = json.load(f)["train"].get("loss", [])
+    else:
+        w, hist = train(X, Y, epochs=a.epochs, lr=a.lr, log_every=1)
+        trained = {"stream_seed": a.train_seed, "workloads": names, "entries": int(len(tr)), "epochs": a.epochs}
     yv = predict(w, Xv, bf16=True)
     val_mse = float(np.mean((yv - Yv) ** 2))
     base_mse = float(np.mean((Yv - np.mean(Y)) ** 2))
-    report = {"train": {"stream_seed": a.train_seed, "workloads": names, "entries": int(len(tr)), "samples": int(len(X)),
-                        "epochs": a.epochs, "loss": hist},
+    report = {"train": dict(trained, samples=int(len(X)), loss=hist, evaluated_only=bool(a.eval_only)),
               "validation": {"mse": val_mse, "constant_mse": base_mse}, "held_out": {},
               "device": torch.cuda.get_device_name(0)}
     for i, name in enumerate(names):
@@ -295,9 +307,8 @@ def main(argv=None):
         report["validation"][name] = choice_work(w, x[sel], work[sel], plan[sel], queries[name])
         say("validation %s: %s" % (name, json.dumps({k: v for k, v in report["validation"][name].items()
                                                       if k != "per_query"})))
-    save_weights(w, os.path.join(a.out, "sched_weights.json"),
-                 {"stream_seed": a.train_seed, "workloads": names, "entries": int(len(tr)), "epochs": a.epochs,
-                  "val_mse": val_mse})
+    if not a.eval_only:
+        save_weights(w, os.path.join(a.out, "sched_weights.json"), dict(trained, val_mse=val_mse))
     del x, work, xs, ws
     same_all = True
     for name in names:
