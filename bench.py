@@ -101,10 +101,11 @@ def enum_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic():
+def read_traffic(workload):
     """Per-launch HBM bytes of the enumerator from the committed counter
-    summary, or None when absent or taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary, or None when absent, taken on a different kernel source, or
+    taken on another workload (the counters cover the default R-MAT stream)."""
+    if workload != "rmat" or not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
     with open(TRAFFIC_FILE) as f:
@@ -366,7 +367,7 @@ def main():
     per_launch = alg_bytes / max(launches, 1)
     avg_ms = expand_ms / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = read_traffic()
+    traffic = read_traffic(args.workload)
     lat_s = sorted(lat)
 
     def pct(p):
