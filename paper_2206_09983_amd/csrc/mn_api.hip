@@ -213,6 +213,7 @@ struct mnemonic_ctx {
     // (index MN_MAXLV) and candidates per level; negative = not seen yet. They
     // size grids and buffers for the next batch, whatever its size.
     double rate[2][MN_MAXLV + 1];
+    double row_rate[2][MN_MAXLV + 1];  // largest rows of level L per start slot seen (-1: none yet)
     uint64_t chunk_ns[2] = {1, 1};  // slots of the largest start chunk of the last run of each phase
     uint64_t cover[2][MN_MAXLV];    // candidates each level's launch covered in the last device-sized run
     uint32_t tile_items = 2;       // expansion tile = 256 x tile_items candidates
@@ -257,6 +258,10 @@ struct mnemonic_ctx {
 
     // outputs
     std::vector<OutView> houts;
+    // Largest tuples per phase edge seen, per (query, phase) (-1: none yet):
+    // sizes the output buffers before a batch, so that a batch larger than
+    // any before does not re-run a phase to grow them.
+    std::vector<double> out_rate;
     OutView* d_outs = nullptr;
 
     // host mirrors
@@ -1006,8 +1011,22 @@ void resolve_events(mnemonic_ctx* c) {
 void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint64_t n0_max, uint64_t ns) {
     hipStream_t s = c->stream;
     const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
-    // every level takes some candidates, so that an overflow always leaves a note
-    for (uint32_t L = 1; L < c->max_levels; L++) grow_level(c, L, 1ull << 16);
+    // every level takes some rows, so that an overflow always leaves a note;
+    // levels and the candidate buffer are sized at the largest rates seen
+    // with a margin, so that a batch larger than any before does not re-run
+    // the phase to grow them
+    for (uint32_t L = 1; L < c->max_levels; L++) {
+        const double rr = c->row_rate[po.phase][L];
+        const uint64_t want = rr > 0 ? (uint64_t)(1.5 * rr * (double)ns) : 0;
+        grow_level(c, L, std::min<uint64_t>(c->rows_max, std::max<uint64_t>(1ull << 16, want)));
+    }
+    {
+        const uint64_t most = MN_EXPAND_MAX_BLOCKS * MN_BLOCK * c->tile_items;
+        uint64_t want = 0;
+        for (uint32_t L = 0; L < c->max_levels; L++)
+            if (c->rate[po.phase][L] > 0) want = std::max<uint64_t>(want, (uint64_t)(1.5 * c->rate[po.phase][L] * (double)ns));
+        if (want > c->cand_k && want <= most / 2) c->cand_k = std::min<uint64_t>(most, std::max<uint64_t>(want, 2 * c->cand_k));
+    }
     const uint64_t need_tiles = mn_expand_tiles(0, c->cand_k) + 1;
     if (need_tiles > c->cap_tiles) {
         HIPCHK(hipStreamSynchronize(s));
@@ -1286,6 +1305,20 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     b.debi_bits = c->d_debi_bits;
     b.vf_bits = c->d_vf_bits;
 
+    if (enumerate && (c->flags & MNEMONIC_F_EMIT) && !(c->flags & MNEMONIC_F_INDEX_ONLY)) {
+        // outputs sized for this batch at the largest per-edge rates seen,
+        // with a margin; at most 4x per batch, so one unusual batch cannot
+        // claim a large share of the device
+        std::vector<uint64_t> want(2 * (size_t)c->n_q, 0);
+        for (uint32_t q = 0; q < c->n_q; q++)
+            for (int p = 0; p < 2; p++) {
+                const double r = c->out_rate[2 * (size_t)q + p];
+                if (r <= 0) continue;
+                const double est = 1.5 * r * (double)(p ? n_del : n_ins);
+                want[2 * (size_t)q + p] = (uint64_t)std::min<double>(est, 4.0 * (double)c->houts[q].cap[p]);
+            }
+        grow_outputs(c, want);
+    }
     GraphView g0 = make_view(c, false);
     mn_launch_reset(c->d_err, c->d_zr, c->n_zr, s);
     if (c->tr_cap) {  // the trace holds this batch's start rows only
@@ -1466,6 +1499,14 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                 c->tile_items = kItems[best];
             }
         }
+        // output rates of this batch for the next one
+        for (uint32_t q = 0; q < c->n_q; q++)
+            for (int p = 0; p < 2; p++) {
+                const uint64_t ne = p ? n_del : n_ins;
+                const uint64_t n = c->h_zr[c->zr_count(p) + q];
+                double& r = c->out_rate[2 * (size_t)q + p];
+                if (ne) r = std::max<double>(r, (double)n / (double)ne);
+            }
         // rates of this batch for the next one (levels that saw candidates)
         for (int p = 0; p < 2; p++) {
             const double ns = (double)std::max<uint64_t>(1, c->chunk_ns[p]);
@@ -1476,6 +1517,11 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                 // generous one only idle blocks
                 const uint64_t T = c->h_zr[L < MN_MAXLV ? c->note_cand(p, L) + 1 : c->note_seed(p) + 1];
                 if (T) c->rate[p][L] = std::max<double>((double)T / ns, c->rate[p][L]);
+                // rows of level L (noted when level L's ranges were taken)
+                if (L >= 1 && L < c->max_levels) {
+                    const uint64_t R = c->h_zr[c->note_rows(p, L - 1) + 1];
+                    if (R) c->row_rate[p][L] = std::max<double>((double)R / ns, c->row_rate[p][L]);
+                }
             }
         }
         // stats
@@ -1690,7 +1736,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         HIPCHK(hipMemcpyAsync(c->d_ext2int, ext2int.data(), (size_t)c->nV * 4, hipMemcpyHostToDevice, s));
         c->lvb.resize(c->max_levels);
         for (int p = 0; p < 2; p++)
-            for (int L = 0; L <= MN_MAXLV; L++) c->rate[p][L] = -1.0;  // unknown: size by capacity
+            for (int L = 0; L <= MN_MAXLV; L++) c->rate[p][L] = c->row_rate[p][L] = -1.0;  // unknown: size by capacity
         dev_alloc(c->d_nrows, MN_MAXLV + 2);
         dev_alloc(c->d_dec_n, 1);
         dev_alloc(c->d_total, 1);
@@ -1726,6 +1772,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         uint64_t cap = opt && opt->out_capacity ? opt->out_capacity : (1ull << 20);
         c->out_cap0 = cap;
         c->houts.resize(n_q);
+        c->out_rate.assign(2 * (size_t)n_q, -1.0);
         for (uint32_t i = 0; i < n_q; i++)
             for (int p = 0; p < 2; p++) {
                 c->houts[i].cap[p] = (c->flags & MNEMONIC_F_EMIT) ? cap : 0;
@@ -1894,6 +1941,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
             for (int p = 0; p < 2; p++) dev_free(o.keys[p]);
         dev_free(c->d_outs);
         c->houts.assign(n_q, OutView{});
+        c->out_rate.assign(2 * (size_t)n_q, -1.0);
         for (uint32_t i = 0; i < n_q; i++)
             for (int p = 0; p < 2; p++) {
                 c->houts[i].cap[p] = (c->flags & MNEMONIC_F_EMIT) ? c->out_cap0 : 0;
@@ -1916,7 +1964,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         }
         c->lvb.assign(c->max_levels, mnemonic_ctx::LevelBuf{});
         for (int p = 0; p < 2; p++)
-            for (int L = 0; L <= MN_MAXLV; L++) c->rate[p][L] = -1.0;
+            for (int L = 0; L <= MN_MAXLV; L++) c->rate[p][L] = c->row_rate[p][L] = -1.0;
         c->have_result = false;
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
