@@ -134,15 +134,62 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
 
 
+def copy_gbps(reps=5):
+    """Achievable HBM rate on this device: the best of `reps` timed 1 GiB
+    device-to-device copies (read + write bytes per second), in GB/s."""
+    import torch
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * n / (best * 1e-3) / 1e9
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(case, budget_s):
-    """Times the CPU oracle (single thread) on a prefix of the first stream
-    batch, applied as consecutive sub-batches of doubling size, until the
-    budget is spent. Returns edges/s over the sample and its description."""
+    """Times the CPU oracle (single thread, pinned to one core where the OS
+    allows) on a prefix of the first stream batch, applied as consecutive
+    sub-batches of doubling size, until the budget is spent. Returns edges/s
+    over the sample, its description and the core it ran on."""
     import numpy as np
 
     from oracle.core import Oracle
     from paper_2206_09983_amd import synth
 
+    core, saved = None, None
+    if hasattr(os, "sched_setaffinity"):
+        saved = os.sched_getaffinity(0)
+        core = min(saved)
+        os.sched_setaffinity(0, {core})
+    try:
+        return _cpu_baseline(case, budget_s, np, Oracle, synth) + (core,)
+    finally:
+        if saved is not None:
+            os.sched_setaffinity(0, saved)
+
+
+def _cpu_baseline(case, budget_s, np, Oracle, synth):
     b = case["batches"][0]
     n_ins, n_del = len(b["src"]), len(b["del_keys"])
     t0 = time.perf_counter()
@@ -414,10 +461,15 @@ def main():
             "launches": launches, "frontier_rows_per_launch": rows / max(launches, 1),
         },
     }
+    # the achievable HBM rate on this device (a plain copy), beside the published peak
+    cg = copy_gbps()
+    out["roofline"]["copy_gbps"] = cg
+    out["roofline"]["frac_of_copy"] = achieved / cg if cg else None
     if not args.no_cpu_baseline:
-        rate, desc, _ = cpu_baseline(case, args.cpu_seconds)
+        rate, desc, _, core = cpu_baseline(case, args.cpu_seconds)
         out["cpu_baseline"] = {"value": rate, "unit": "matched data edges/s", "cores": 1, "kind": "oracle",
-                               "sample": desc}
+                               "sample": desc, "pinned_core": core, "cpu_model": cpu_model(),
+                               "host_threads": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 
