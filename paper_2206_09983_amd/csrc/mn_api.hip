@@ -841,21 +841,35 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     }
 }
 
+// Each buffer is replaced only once its successor is allocated, and the
+// device's copy of the table follows the host's whenever anything changed,
+// also when an allocation fails part way (the error then leaves every buffer
+// valid at its recorded capacity).
 void grow_outputs(mnemonic_ctx* c, const std::vector<uint64_t>& need) {
     bool changed = false;
-    for (uint32_t q = 0; q < c->n_q; q++)
-        for (int p = 0; p < 2; p++) {
-            uint64_t n = need[2 * q + p];
-            if (n <= c->houts[q].cap[p]) continue;
-            uint64_t nc = std::max<uint64_t>(n + n / 4, c->houts[q].cap[p] * 2);
-            dev_free(c->houts[q].keys[p]);
-            dev_alloc(c->houts[q].keys[p], nc * c->hq[q].n_qe);
-            c->houts[q].cap[p] = nc;
-            changed = true;
-        }
-    if (changed)
+    auto upload = [&]() {
         HIPCHK(hipMemcpyAsync(c->d_outs, c->houts.data(), c->houts.size() * sizeof(OutView),
                               hipMemcpyHostToDevice, c->stream));
+    };
+    try {
+        for (uint32_t q = 0; q < c->n_q; q++)
+            for (int p = 0; p < 2; p++) {
+                uint64_t n = need[2 * q + p];
+                if (n <= c->houts[q].cap[p]) continue;
+                uint64_t nc = std::max<uint64_t>(n + n / 4, c->houts[q].cap[p] * 2);
+                uint64_t* fresh = nullptr;
+                dev_alloc(fresh, nc * c->hq[q].n_qe);
+                HIPCHK(hipStreamSynchronize(c->stream));  // no launch still writes the old buffer
+                dev_free(c->houts[q].keys[p]);
+                c->houts[q].keys[p] = fresh;
+                c->houts[q].cap[p] = nc;
+                changed = true;
+            }
+    } catch (...) {
+        if (changed) upload();
+        throw;
+    }
+    if (changed) upload();
 }
 
 PhaseOut phase_out(mnemonic_ctx* c, int p) {
