@@ -773,6 +773,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     }
     if (n_ins > c->cap_ins) {
         uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_ins, kScratchMin), 2 * c->cap_ins);
+        c->cap_ins = 0;  // until every buffer below exists again (an allocation may fail)
         dev_free(c->d_in_src);
         dev_free(c->d_in_dst);
         dev_free(c->d_in_lab);
@@ -799,6 +800,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     }
     if (n_del > c->cap_del) {
         uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_del, kScratchMin), 2 * c->cap_del);
+        c->cap_del = 0;
         dev_free(c->d_del_keys);
         dev_alloc(c->d_del_keys, nc);
         c->cap_del = nc;
@@ -807,6 +809,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     int cur = 1 - c->pend;
     if (n_del > c->cap_delbuf[cur]) {
         uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_del, kScratchMin), 2 * c->cap_delbuf[cur]);
+        c->cap_delbuf[cur] = 0;
         dev_free(c->d_del_slot[cur]);
         dev_alloc(c->d_del_slot[cur], nc);
         for (int d = 0; d < 2; d++) {
@@ -818,6 +821,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     uint64_t n_sort = std::max<uint64_t>(n_ins, c->n_pending);
     if (n_sort > c->cap_sort) {
         uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_sort, kScratchMin), 2 * c->cap_sort);
+        c->cap_sort = 0;
         for (int k = 0; k < 2; k++) {
             dev_free(c->d_dkey[k]);
             dev_free(c->d_dval[k]);
@@ -828,6 +832,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     }
     uint64_t ssw = mn_sort_scratch_words((uint32_t)std::max<uint64_t>(2 * n_sort, 2 * kScratchMin));
     if (ssw > c->cap_sort_scratch) {
+        c->cap_sort_scratch = 0;
         dev_free(c->d_sort_scratch);
         dev_alloc(c->d_sort_scratch, ssw);
         c->cap_sort_scratch = ssw;
@@ -835,6 +840,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
     uint64_t n_touch = 2 * (c->n_pending + n_ins);
     if (n_touch > c->cap_touch) {
         uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_touch, 2 * kScratchMin), 2 * c->cap_touch);
+        c->cap_touch = 0;
         dev_free(c->d_touched);
         dev_alloc(c->d_touched, nc);
         c->cap_touch = nc;
@@ -915,6 +921,7 @@ void grow_level(mnemonic_ctx* c, uint32_t L, uint64_t need) {
     B.cap = nc;
     uint64_t sw = mn_scan64_scratch_words((uint32_t)nc);
     if (sw > c->cap_scan64) {
+        c->cap_scan64 = 0;
         dev_free(c->d_scan64);
         dev_alloc(c->d_scan64, sw);
         c->cap_scan64 = sw;
