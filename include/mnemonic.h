@@ -244,7 +244,10 @@ const char *mnemonic_last_error(const mnemonic_ctx *ctx);
  * buffers. Results of the following batches are indexed by the new set (in
  * the order given). Queries follow the rules of mnemonic_create; a bad one
  * returns MNEMONIC_E_QUERY and changes nothing. Costs O(live edges +
- * vertices) on the device. Errors: ARG, QUERY, OOM, HIP. */
+ * vertices) on the device. Errors: ARG, QUERY, OOM, HIP. After OOM or HIP
+ * the rebuild is incomplete: every later call on the context except
+ * mnemonic_last_error and mnemonic_destroy returns MNEMONIC_E_HIP, and the
+ * context must be destroyed. */
 int mnemonic_set_queries(mnemonic_ctx *ctx, const mnemonic_query *q, uint32_t n_q);
 
 /* ------------------------------------------------------------- scheduler

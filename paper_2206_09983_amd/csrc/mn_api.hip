@@ -258,6 +258,9 @@ struct mnemonic_ctx {
 
     // outputs
     std::vector<OutView> houts;
+    // Set while mnemonic_set_queries rebuilds the query-dependent state; left
+    // set when that fails part way, after which the context only reports it.
+    bool broken = false;
     // Largest tuples per phase edge seen, per (query, phase) (-1: none yet):
     // sizes the output buffers before a batch, so that a batch larger than
     // any before does not re-run a phase to grow them.
@@ -1585,6 +1588,10 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
 template <typename F>
 int guarded(mnemonic_ctx* c, F&& f) {
     try {
+        if (c && c->broken) {
+            c->err = "context unusable: a query-set change failed part way; destroy it";
+            return MNEMONIC_E_HIP;
+        }
         if (c) c->err.clear();
         return f();
     } catch (const ApiError& e) {
@@ -1833,6 +1840,7 @@ int mnemonic_apply_batch(mnemonic_ctx* ctx, const mnemonic_edges* ins, const uin
 
 int mnemonic_get_result(mnemonic_ctx* ctx, uint32_t query, mnemonic_result* out) {
     if (!ctx || !out || query >= ctx->n_q) return MNEMONIC_E_ARG;
+    if (ctx->broken) return MNEMONIC_E_HIP;
     memset(out, 0, sizeof(*out));
     out->n_qe = ctx->hq[query].n_qe;
     if (!ctx->have_result) return MNEMONIC_OK;
@@ -1872,6 +1880,7 @@ int mnemonic_copy_keys(mnemonic_ctx* ctx, uint32_t query, int expired, uint64_t*
 
 int mnemonic_get_stats(mnemonic_ctx* ctx, mnemonic_stats* out) {
     if (!ctx || !out) return MNEMONIC_E_ARG;
+    if (ctx->broken) return MNEMONIC_E_HIP;
     *out = ctx->stats;
     out->n_live_edges = ctx->n_live;
     out->slot_high_water = ctx->fresh;
@@ -1903,6 +1912,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
                     throw ApiError{MNEMONIC_E_QUERY, "query edge label >= n_elabels"};
         hipStream_t s = c->stream;
         HIPCHK(hipStreamSynchronize(s));
+        c->broken = true;  // until every query-dependent part is rebuilt below
         // query tables
         c->n_q = t.n_q;
         c->n_plans = t.n_plans;
@@ -1989,6 +1999,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         c->have_result = false;
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
+        c->broken = false;
         return MNEMONIC_OK;
     });
 }
@@ -2015,7 +2026,9 @@ int mnemonic_set_scheduler(mnemonic_ctx* ctx, int mode, const float* weights) {
 }
 
 int mnemonic_query_orders(mnemonic_ctx* ctx, uint32_t query, uint32_t j, uint32_t* n_orders) {
-    if (!ctx || !n_orders || query >= ctx->n_q || j >= ctx->hq[query].n_qe) return MNEMONIC_E_ARG;
+    if (!ctx || !n_orders) return MNEMONIC_E_ARG;
+    if (ctx->broken) return MNEMONIC_E_HIP;
+    if (query >= ctx->n_q || j >= ctx->hq[query].n_qe) return MNEMONIC_E_ARG;
     *n_orders = ctx->hplans[ctx->hq[query].plan_base + j].n_var;
     return MNEMONIC_OK;
 }
