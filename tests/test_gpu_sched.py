@@ -223,3 +223,19 @@ def test_committed_network_reduces_work_on_a_held_out_stream(B):
         st["work"], le["work"], st["work"] / max(1, le["work"]), st["ms"], le["ms"]))
     assert st["results"] == le["results"]
     assert le["work"] < st["work"]
+
+
+def test_committed_network_cuts_the_64_query_streams_work_at_least_in_half(B):
+    # The 64-query stream is where matching orders matter (cycles and
+    # cliques). On its first batches (stream seed 7; the network was trained
+    # on seed 9) the learned choice must at least halve the candidates
+    # examined, with identical counts and digests.
+    from paper_2206_09983_amd import sched
+    w = sched.load_weights()
+    case = sched.workload("multiquery", 7)
+    batches = case["batches"][:6]
+    st = sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_STATIC, flags=0, warmup=0)
+    le = sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_LEARNED, w, flags=0, warmup=0)
+    say("64-query work: static %d learned %d (%.2fx)" % (st["work"], le["work"], st["work"] / max(1, le["work"])))
+    assert st["results"] == le["results"]
+    assert le["work"] * 2 <= st["work"]
