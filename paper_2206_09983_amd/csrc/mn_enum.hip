@@ -528,66 +528,126 @@ __device__ inline uint32_t row_of(const uint64_t* off, uint32_t a, uint32_t b, u
 // Start rows. Each row takes the static order, or the fixed variant; rows
 // whose order the decision kernel settles (learned choice, traces) are
 // listed in g.dec as (row << 32 | index into slots).
+// Block (x, y) takes slots [256x, 256x + 256) against plans [ppb * y, ppb * y
+// + ppb), ppb <= SR_MAX_PPB. Few (slot, plan) pairs pass the edgeMatcher bit,
+// and they are spread thinly over the waves, so the block works in two
+// passes: the first tests the bit of every pair (the slot's matcher word is
+// re-read only when the plan moves to another word) and lists the passing
+// pairs in LDS; the second runs the dependent loads (endpoints, filters,
+// start-level closing edges, row writes) over that list, 256 pairs per step,
+// each lane with its own plan.
+constexpr uint32_t SR_MAX_PPB = 32;
+
 template <int NC>
 __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint32_t* __restrict__ slots,
-                                                        uint32_t n, RowsView R, uint32_t* n_rows,
-                                                        PhaseOut po, const uint32_t* err) {
+                                                        uint32_t n, uint32_t n_plans, uint32_t ppb, RowsView R,
+                                                        uint32_t* n_rows, PhaseOut po, const uint32_t* err) {
     __shared__ BlockAcc A;
-    acc_init(A, 2 * po.n_q, err);
-    const SeedPlan& P = g.plans[blockIdx.y];
+    __shared__ uint32_t s_slot[MN_BLOCK];
+    __shared__ uint16_t s_pair[MN_BLOCK * SR_MAX_PPB];  // lane | plan offset << 8, grouped by plan
+    __shared__ uint32_t s_cnt[SR_MAX_PPB];
+    __shared__ uint32_t s_n;
+    if (threadIdx.x < SR_MAX_PPB) s_cnt[threadIdx.x] = 0;
+    acc_init(A, 2 * po.n_q, err);  // ends with a barrier
     const uint32_t i = blockIdx.x * MN_BLOCK + threadIdx.x;
-    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
-    bool ok = i < n && !A.dead;
-    uint32_t slot = 0, s = 0, d = 0;
-    if (ok) {
-        slot = slots[i];
+    const bool live = i < n && !A.dead;
+    const uint32_t slot = live ? slots[i] : 0u;
+    s_slot[threadIdx.x] = slot;
+    const uint32_t p0 = blockIdx.y * ppb, p1 = min(n_plans, p0 + min(ppb, SR_MAX_PPB));
+    // pass 1: the edgeMatcher bit of every (slot, plan) pair, counted per plan
+    uint32_t word = 0, word_at = 0xFFFFFFFFu, hits = 0;
+    for (uint32_t pi = p0; pi < p1; pi++) {  // block-uniform
+        const SeedPlan& P = g.plans[pi];
         const uint32_t bit = P.debi_base + P.j;
-        ok = (g.s_debi[(size_t)slot * g.debi_words + (bit >> 5)] >> (bit & 31)) & 1u;
+        if ((bit >> 5) != word_at) {  // uniform
+            word_at = bit >> 5;
+            word = live ? g.s_debi[(size_t)slot * g.debi_words + word_at] : 0u;
+        }
+        const bool hit = (word >> (bit & 31)) & 1u;
+        hits |= (uint32_t)hit << (pi - p0);
+        const uint64_t bal = __ballot(hit);
+        if (bal && __lane_id() == 0) atomicAdd(&s_cnt[pi - p0], (uint32_t)__popcll(bal));
     }
-    if (ok) {
-        s = g.s_src[slot];
-        d = g.s_dst[slot];
-        K.vf += 2;
-        ok = !(P.sem == MN_SEM_ISO && s == d) && vf_bit(g, s, P.vf_base + P.qa) &&
-             vf_bit(g, d, P.vf_base + P.qb);
+    __syncthreads();
+    if (threadIdx.x == 0) {  // at most 32 plans: exclusive offsets, serially
+        uint32_t run = 0;
+        for (uint32_t k = 0; k < p1 - p0; k++) {
+            const uint32_t c = s_cnt[k];
+            s_cnt[k] = run;
+            run += c;
+        }
+        s_n = run;
     }
-    Bind B;
-    B.R = R;
-    B.row = false;
-    B.r = 0;
-    B.qa = P.qa;
-    B.fa = s;
-    B.qb = P.qb;
-    B.fb = d;
-    B.skey = ok ? g.s_key[slot] : 0ull;
-    B.cv = 0xFF;
-    B.fw = 0;
-    constexpr int NA = NC > 0 ? NC : 1;
-    uint32_t st[NA];
-#pragma unroll
-    for (uint32_t c = 0; c < NA; c++) {
-        st[c] = 0;
-        if (ok && c < (uint32_t)NC && c < P.c0_end) {
-            const CloseDesc cd = P.close[c];
-            st[c] = close_find(g, cd, B.f(cd.other), B.f(cd.nv), K.probes);
-            if (st[c] == NO_RUN) ok = false;
+    __syncthreads();
+    // the passing pairs, plan by plan, so that rows of one plan stay together
+    for (uint32_t pi = p0; pi < p1; pi++) {  // block-uniform
+        const bool hit = (hits >> (pi - p0)) & 1u;
+        const uint64_t bal = __ballot(hit);
+        if (bal) {
+            uint32_t base = 0;
+            if (__lane_id() == 0) base = atomicAdd(&s_cnt[pi - p0], (uint32_t)__popcll(bal));
+            base = __shfl(base, 0, MN_WAVE);
+            if (hit)
+                s_pair[base + (uint32_t)__popcll(bal & lanemask_lt())] =
+                    (uint16_t)(threadIdx.x | ((pi - p0) << 8));
         }
     }
-    if (ok) K.seeds++;
-    if (P.n_levels == 0) {  // block-uniform: every lane takes this branch or none
-        emit_complete<NC>(g, P, B, st, 0xFF, 0ull, ok, po, A, K);
-    } else {
-        // block-uniform: does the decision kernel settle this pair's rows?
+    __syncthreads();
+    const uint32_t m = s_n;
+    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int NA = NC > 0 ? NC : 1;
+    // pass 2: the listed pairs, densely
+    for (uint32_t k0 = 0; k0 < m; k0 += MN_BLOCK) {  // block-uniform
+        const uint32_t k = k0 + threadIdx.x;
+        bool ok = k < m;
+        const uint32_t e = ok ? s_pair[k] : 0u;
+        const uint32_t lane = e & 0xFFu, pslot = s_slot[lane];
+        const SeedPlan& P = g.plans[p0 + (e >> 8)];
+        uint32_t s = 0, d = 0;
+        if (ok) {
+            s = g.s_src[pslot];
+            d = g.s_dst[pslot];
+            K.vf += 2;
+            ok = !(P.sem == MN_SEM_ISO && s == d) && vf_bit(g, s, P.vf_base + P.qa) &&
+                 vf_bit(g, d, P.vf_base + P.qb);
+        }
+        Bind B;
+        B.R = R;
+        B.row = false;
+        B.r = 0;
+        B.qa = P.qa;
+        B.fa = s;
+        B.qb = P.qb;
+        B.fb = d;
+        B.skey = ok ? g.s_key[pslot] : 0ull;
+        B.cv = 0xFF;
+        B.fw = 0;
+        uint32_t st[NA];
+#pragma unroll
+        for (uint32_t c = 0; c < NA; c++) {
+            st[c] = 0;
+            if (ok && c < (uint32_t)NC && c < P.c0_end) {
+                const CloseDesc cd = P.close[c];
+                st[c] = close_find(g, cd, B.f(cd.other), B.f(cd.nv), K.probes);
+                if (st[c] == NO_RUN) ok = false;
+            }
+        }
+        if (ok) K.seeds++;
+        // 2-vertex queries: the pair is already a complete mapping (every
+        // lane of the wave takes part in the call)
+        emit_complete<NC>(g, P, B, st, 0xFF, 0ull, ok && P.n_levels == 0, po, A, K);
+        const bool to_row = ok && P.n_levels != 0;
+        // does the decision kernel settle this pair's rows?
         const bool decide = g.dec && (g.tr_cap || (g.sched_mode == MN_SCHED_LEARNED && P.n_var > 1));
         uint32_t var = 0;
         if (!decide && g.sched_mode >= MN_SCHED_FIXED && g.sched_mode - MN_SCHED_FIXED < P.n_var)
             var = g.sched_mode - MN_SCHED_FIXED;
-        const uint64_t bal = __ballot(ok);
+        const uint64_t bal = __ballot(to_row);
         uint32_t base = 0;
         if (__lane_id() == 0 && bal) base = atomicAdd(n_rows, (uint32_t)__popcll(bal));
         base = __shfl(base, 0, MN_WAVE);
         uint32_t r = MN_INVALID;
-        if (ok) {
+        if (to_row) {
             r = base + (uint32_t)__popcll(bal & lanemask_lt());
             if (r < R.cap) {
                 wcol(R, 0, r, P.vars[var]);
@@ -603,13 +663,15 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
                 r = MN_INVALID;  // rows past the buffer are counted, not written: the host grows it and runs again
             }
         }
-        if (decide) {
-            const bool listed = r != MN_INVALID;
-            const uint64_t lb = __ballot(listed);
+        const bool listed = decide && r != MN_INVALID;
+        const uint64_t lb = __ballot(listed);
+        if (lb) {
             uint32_t lbase = 0;
-            if (__lane_id() == 0 && lb) lbase = atomicAdd(g.dec_n, (uint32_t)__popcll(lb));
+            if (__lane_id() == 0) lbase = atomicAdd(g.dec_n, (uint32_t)__popcll(lb));
             lbase = __shfl(lbase, 0, MN_WAVE);
-            if (listed) g.dec[lbase + (uint32_t)__popcll(lb & lanemask_lt())] = ((uint64_t)r << 32) | i;
+            if (listed)
+                g.dec[lbase + (uint32_t)__popcll(lb & lanemask_lt())] =
+                    ((uint64_t)r << 32) | (blockIdx.x * MN_BLOCK + lane);
         }
     }
     acc_flush(A, K, 2 * po.n_q, po.stats, po.digest);
@@ -1047,14 +1109,21 @@ inline int nc_bucket(uint32_t nc) { return nc == 0 ? 0 : nc == 1 ? 1 : nc == 2 ?
 void mn_launch_seed_rows(const GraphView& g, const uint32_t* slots, uint32_t n, uint32_t n_plans, uint32_t max_close,
                          RowsView rows, uint32_t* n_rows, PhaseOut po, const uint32_t* err, hipStream_t s) {
     if (!n || !n_plans) return;
-    dim3 grid(nblocks(n), n_plans);
+    // about 4,096 blocks when there is that much work, never more than 32
+    // plans per block
+    const uint32_t nbx = nblocks(n);
+    const uint32_t ppb =
+        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(SR_MAX_PPB, (uint64_t)n_plans * nbx / 4096));
+    dim3 grid(nbx, (n_plans + ppb - 1) / ppb);
+#define MN_SEED_ARGS g, slots, n, n_plans, ppb, rows, n_rows, po, err
     switch (nc_bucket(max_close)) {
-        case 0: k_seed_rows<0><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
-        case 1: k_seed_rows<1><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
-        case 2: k_seed_rows<2><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
-        case 4: k_seed_rows<4><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
-        default: k_seed_rows<8><<<grid, MN_BLOCK, 0, s>>>(g, slots, n, rows, n_rows, po, err); break;
+        case 0: k_seed_rows<0><<<grid, MN_BLOCK, 0, s>>>(MN_SEED_ARGS); break;
+        case 1: k_seed_rows<1><<<grid, MN_BLOCK, 0, s>>>(MN_SEED_ARGS); break;
+        case 2: k_seed_rows<2><<<grid, MN_BLOCK, 0, s>>>(MN_SEED_ARGS); break;
+        case 4: k_seed_rows<4><<<grid, MN_BLOCK, 0, s>>>(MN_SEED_ARGS); break;
+        default: k_seed_rows<8><<<grid, MN_BLOCK, 0, s>>>(MN_SEED_ARGS); break;
     }
+#undef MN_SEED_ARGS
 }
 
 void mn_launch_decide(const GraphView& g, RowsView rows, const uint32_t* slots, uint32_t cap, uint32_t expect,

@@ -321,28 +321,37 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(const uint64_t* __restri
 // VF bit of (query, vertex u) at data vertex v: label requirement plus the
 // counting filters of Section V-A (f2: edges per direction and label; f3:
 // edges per direction towards each neighbour label), thresholds prepared on
-// the host per semantics.
+// the host per semantics. A half-wave of 32 lanes serves one vertex: lane j
+// tests bit 32w + j of word w, and one wave-wide ballot assembles the words
+// of the wave's two vertices, so no lane walks the bits one by one. The loop
+// runs over vertex pairs with a wave-uniform bound, which the ballot needs.
 __global__ __launch_bounds__(MN_BLOCK) void k_vf_refresh(GraphView g, const VfBit* __restrict__ bits,
                                                          uint32_t n_bits, const uint32_t* __restrict__ list,
                                                          uint32_t n, const uint32_t* err) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || failed(err)) return;
-    uint32_t v = list ? list[i] : i;
-    uint64_t mv = g.vmask[v];
-    const uint32_t* c = g.cnt + (size_t)v * g.n_cnt;
-    for (uint32_t w = 0; w < g.vf_words; w++) {
-        uint32_t word = 0;
-        uint32_t lo = w * 32, hi = min(lo + 32, n_bits);
-        for (uint32_t bit = lo; bit < hi; bit++) {
-            VfBit vb = bits[bit];
-            bool ok = (vb.vreq & ~mv) == 0;
-            for (uint32_t r = vb.req_begin; ok && r < vb.req_end; r++) {
-                VfReq q = g.vfreq[r];
-                ok = c[q.cnt] >= q.need;
+    if (failed(err)) return;  // the same word for every lane: whole waves leave
+    constexpr uint32_t WPB = MN_BLOCK / 64;
+    const uint32_t lane = threadIdx.x & 63, half = lane >> 5, j = lane & 31;
+    const uint64_t n_pairs = ((uint64_t)n + 1) / 2, stride = (uint64_t)gridDim.x * WPB;
+    for (uint64_t pair = (uint64_t)blockIdx.x * WPB + threadIdx.x / 64; pair < n_pairs; pair += stride) {
+        const uint64_t i = 2 * pair + half;
+        const bool live = i < n;
+        const uint32_t v = live ? (list ? list[i] : (uint32_t)i) : 0u;
+        const uint64_t mv = live ? g.vmask[v] : 0ull;
+        const uint32_t* c = g.cnt + (size_t)v * g.n_cnt;
+        for (uint32_t w = 0; w < g.vf_words; w++) {
+            const uint32_t bit = w * 32 + j;
+            bool ok = false;
+            if (live && bit < n_bits) {
+                const VfBit vb = bits[bit];
+                ok = (vb.vreq & ~mv) == 0;
+                for (uint32_t r = vb.req_begin; ok && r < vb.req_end; r++) {
+                    const VfReq q = g.vfreq[r];
+                    ok = c[q.cnt] >= q.need;
+                }
             }
-            word |= (uint32_t)ok << (bit - lo);
+            const uint64_t m = __ballot(ok);
+            if (live && j == 0) g.vf[(size_t)v * g.vf_words + w] = (uint32_t)(m >> (32 * half));
         }
-        g.vf[(size_t)v * g.vf_words + w] = word;
     }
 }
 
@@ -468,7 +477,10 @@ void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits,
 
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s) {
-    if (n) k_vf_refresh<<<nblocks(n), MN_BLOCK, 0, s>>>(g, bits, n_bits, list, n, err);
+    // two vertices per wave, a grid of at most 65,536 blocks looping over the rest
+    constexpr uint32_t VPB = 2 * (MN_BLOCK / 64);
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(65536, ((uint64_t)n + VPB - 1) / VPB);
+    if (n) k_vf_refresh<<<blocks, MN_BLOCK, 0, s>>>(g, bits, n_bits, list, n, err);
 }
 
 void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
