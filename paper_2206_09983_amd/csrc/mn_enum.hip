@@ -155,8 +155,8 @@ __device__ void acc_flush(BlockAcc& A, const Cnt& K, uint32_t n_dig, EnumStats* 
         if (A.dig[i]) atomicAdd(&gdig[i], A.dig[i]);
 }
 
-// Binary searches over the high words of a sorted segment, counting the
-// words they read.
+// Lower bound over the high words of a sorted segment, counting the words
+// it reads.
 __device__ inline uint32_t lower_hi_c(const uint64_t* adj, uint32_t lo, uint32_t hi, uint32_t key,
                                       uint32_t& probes) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(adj);
@@ -171,18 +171,36 @@ __device__ inline uint32_t lower_hi_c(const uint64_t* adj, uint32_t lo, uint32_t
     return lo;
 }
 
-__device__ inline uint32_t upper_hi_c(const uint64_t* adj, uint32_t lo, uint32_t hi, uint32_t key,
-                                      uint32_t& probes) {
+// Both ends of the run of high words in [key_lo, key_hi] of a sorted
+// segment: the lower and the upper bound advance in lockstep, so each step
+// issues its two loads together and the chain of dependent loads is one
+// search long instead of two.
+__device__ inline void run_bounds_c(const uint64_t* adj, uint32_t s0, uint32_t s1, uint32_t key_lo, uint32_t key_hi,
+                                    uint32_t& a, uint32_t& b, uint32_t& probes) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(adj);
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        probes++;
-        if (w[2 * (size_t)mid + 1] <= key)
-            lo = mid + 1;
-        else
-            hi = mid;
+    uint32_t la = s0, ha = s1, lb = s0, hb = s1;
+    while (la < ha || lb < hb) {
+        const bool ga = la < ha, gb = lb < hb;
+        const uint32_t ma = (la + ha) >> 1, mb = (lb + hb) >> 1;
+        const uint32_t va = ga ? w[2 * (size_t)ma + 1] : 0u;
+        const uint32_t vb = gb ? w[2 * (size_t)mb + 1] : 0u;
+        if (ga) {
+            probes++;
+            if (va < key_lo)
+                la = ma + 1;
+            else
+                ha = ma;
+        }
+        if (gb) {
+            probes++;
+            if (vb <= key_hi)
+                lb = mb + 1;
+            else
+                hb = mb;
+        }
     }
-    return lo;
+    a = la;
+    b = max(la, lb);  // an empty key range gives an empty run
 }
 
 // Where the images of query vertices come from while a candidate is tested:
@@ -803,8 +821,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
                 a = s0;
                 b = s1;
             } else {
-                a = lower_hi_c(g.adj[lv.dir], s0, s1, lv.key_lo, K.range_probes);
-                b = upper_hi_c(g.adj[lv.dir], a, s1, lv.key_hi, K.range_probes);
+                run_bounds_c(g.adj[lv.dir], s0, s1, lv.key_lo, lv.key_hi, a, b, K.range_probes);
             }
         }
         lo[r] = a;
