@@ -174,6 +174,8 @@ struct mnemonic_ctx {
     uint32_t* d_sval[2] = {nullptr, nullptr};
     uint32_t* d_inspos[2] = {nullptr, nullptr};
     uint32_t* d_ub[2] = {nullptr, nullptr};  // insertion points of the batch entries in the old adjacency
+    uint32_t* d_mlim = nullptr;              // the merge's counts at every tile start (both directions use it in turn)
+    uint64_t cap_mlim = 0;
     uint32_t* d_touched = nullptr;
     uint32_t* d_del_slot[2] = {nullptr, nullptr};        // [buffer]
     uint32_t* d_delpos[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [buffer][dir]
@@ -774,6 +776,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         dev_grow(c->d_adj2[d], t, need_E, 0, s);
         if (d == 1) c->cap_E = t;
     }
+    dev_grow(c->d_mlim, c->cap_mlim, mn_merge_limit_words(c->E), 0, s);
     if (n_ins > c->cap_ins) {
         uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_ins, kScratchMin), 2 * c->cap_ins);
         c->cap_ins = 0;  // until every buffer below exists again (an allocation may fail)
@@ -1382,7 +1385,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                                   c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
             mn_launch_merge(c->d_off[d], c->d_adj[d], c->d_adjk[d], (uint32_t)c->E, c->d_off2[d], c->d_meta[d], bkd,
                             kb, bvd, c->d_key, (uint32_t)n_ins, dpd, db, n_prev, c->hb, c->d_adj2[d], c->d_adjk2[d],
-                            c->d_inspos[d], c->d_ub[d], (uint32_t)E_new, c->d_err, s);
+                            c->d_inspos[d], c->d_ub[d], c->d_mlim, (uint32_t)E_new, c->d_err, s);
         }
     }
     // from here on the kernels work on the merged adjacency
@@ -1651,6 +1654,7 @@ void free_all(mnemonic_ctx* c) {
         dev_free(c->d_del_slot[d]);
         for (int k = 0; k < 2; k++) dev_free(c->d_delpos[d][k]);
     }
+    dev_free(c->d_mlim);
     dev_free(c->d_in_src);
     dev_free(c->d_in_dst);
     dev_free(c->d_in_lab);

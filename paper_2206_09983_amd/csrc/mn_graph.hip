@@ -229,22 +229,44 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
     inspos[r] = out;
 }
 
+// Both counts at every tile start of the old array: lim[t] = insertion points
+// below t * MG_TILE and lim[nt + 1 + t] = deletions below it, t in [0, nt].
+// Thread i owns the boundary before sorted value i and writes the tiles whose
+// start falls between values i - 1 and i, so the limits cost one pass over
+// the batch instead of a binary search per tile. A side with no values is not
+// written (k_merge_old reads zero for it).
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_limits(const uint32_t* __restrict__ ub, uint32_t n_b,
+                                                           const uint64_t* __restrict__ dpos, uint64_t dbase,
+                                                           uint32_t n_d, uint32_t nt, uint32_t* __restrict__ lim) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n_b && i <= n_b) {
+        const uint32_t t0 = i ? ub[i - 1] / MG_TILE + 1 : 0u;
+        const uint32_t t1 = i < n_b ? min(nt, ub[i] / MG_TILE) : nt;
+        for (uint32_t t = t0; t <= t1; t++) lim[t] = i;
+    }
+    if (n_d && i <= n_d) {
+        const uint32_t t0 = i ? (uint32_t)(dpos[i - 1] - dbase) / MG_TILE + 1 : 0u;
+        const uint32_t t1 = i < n_d ? min(nt, (uint32_t)(dpos[i] - dbase) / MG_TILE) : nt;
+        for (uint32_t t = t0; t <= t1; t++) lim[nt + 1 + t] = i;
+    }
+}
+
 // Old entries keep their order: the kept entry at old position p moves to
 // p - (deleted entries before p) + (batch entries whose insertion point is
-// <= p), whatever its vertex. Each block takes a tile of the old array; two
-// binary searches give both counts at the tile's start, the deletions and
-// insertion points inside the tile are marked in LDS and prefix-summed, and
-// every entry then costs one LDS read between its loads and its stores.
+// <= p), whatever its vertex. Each block takes a tile of the old array; both
+// counts at the tile's start and end come from k_merge_limits, the deletions
+// and insertion points inside the tile are marked in LDS and prefix-summed,
+// and every entry then costs one LDS read between its loads and its stores.
 // ub (n_b, sorted) comes from k_merge_new, which must run first.
 __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(const uint64_t* __restrict__ adj,
                                                         const uint64_t* __restrict__ adjk, uint32_t e_old,
                                                         const uint32_t* __restrict__ ub, uint32_t n_b,
                                                         const uint64_t* __restrict__ dpos, uint64_t dbase,
-                                                        uint32_t n_d, uint64_t* __restrict__ adj_new,
+                                                        uint32_t n_d, const uint32_t* __restrict__ lim,
+                                                        uint64_t* __restrict__ adj_new,
                                                         uint64_t* __restrict__ adjk_new, uint32_t e_new,
                                                         uint32_t* err) {
     __shared__ __align__(16) int32_t s_m[MG_TILE];
-    __shared__ uint32_t s_lim[4];
     __shared__ int32_t s_wsum[MN_BLOCK / MN_WAVE];
     __shared__ uint32_t s_dead;
     const uint32_t tid = threadIdx.x;
@@ -258,17 +280,17 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(const uint64_t* __restri
         e[k] = p < p1 ? adj[p] : 0ull;
         ek[k] = p < p1 ? adjk[p] : 0ull;
     }
-    if (tid < 4) {  // insertion points below p0 / p1, deletions below p0 / p1
-        const uint32_t at = (tid & 1) ? p1 : p0;
-        s_lim[tid] = tid < 2 ? lower_bound_dev<uint32_t>(ub, 0, n_b, at)
-                             : lower_bound_dev<uint64_t>(dpos, 0, n_d, dbase + at);
-    }
+    // insertion points and deletions below the tile's start and end (at the
+    // last tile the end limit counts up to nt * MG_TILE: insertion points at
+    // e_old or beyond mark places past p1, which nothing reads)
+    const uint32_t nt = gridDim.x, t = blockIdx.x;
+    const uint32_t uA = n_b ? lim[t] : 0u, uB = n_b ? lim[t + 1] : 0u;
+    const uint32_t dA = n_d ? lim[nt + 1 + t] : 0u, dB = n_d ? lim[nt + 2 + t] : 0u;
     if (tid == 0) s_dead = failed(err) ? 1u : 0u;
 #pragma unroll
     for (uint32_t k = 0; k < MG_ITEMS; k++) s_m[k * MN_BLOCK + tid] = 0;
     __syncthreads();
     if (s_dead) return;
-    const uint32_t uA = s_lim[0], uB = s_lim[1], dA = s_lim[2], dB = s_lim[3];
     const bool marks = uA < uB || dA < dB;  // the same for every thread of the block
     if (marks) {
         for (uint32_t r = uA + tid; r < uB; r += MN_BLOCK) {
@@ -460,14 +482,21 @@ void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* a
                      const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys, uint64_t kbase,
                      const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
                      uint64_t dbase, uint32_t n_d, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t* ub, uint32_t e_new, uint32_t* err, hipStream_t s) {
+                     uint32_t* inspos, uint32_t* ub, uint32_t* lim, uint32_t e_new, uint32_t* err, hipStream_t s) {
     if (n_b)
         k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, kbase, bvals, s_key, n_b, dpos,
                                                       dbase, hb, adj_new, adjk_new, inspos, ub, e_new, err);
-    if (e_old)
-        k_merge_old<<<(e_old + MG_TILE - 1) / MG_TILE, MN_BLOCK, 0, s>>>(adj, adjk, e_old, ub, n_b, dpos, dbase, n_d,
-                                                                         adj_new, adjk_new, e_new, err);
+    if (e_old) {
+        const uint32_t nt = (e_old + MG_TILE - 1) / MG_TILE;
+        if (n_b || n_d)
+            k_merge_limits<<<nblocks((uint64_t)std::max(n_b, n_d) + 1), MN_BLOCK, 0, s>>>(ub, n_b, dpos, dbase, n_d,
+                                                                                          nt, lim);
+        k_merge_old<<<nt, MN_BLOCK, 0, s>>>(adj, adjk, e_old, ub, n_b, dpos, dbase, n_d, lim, adj_new, adjk_new,
+                                            e_new, err);
+    }
 }
+
+uint64_t mn_merge_limit_words(uint64_t e_old) { return 2 * ((e_old + MG_TILE - 1) / MG_TILE + 1); }
 
 void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits, uint32_t n_slots,
                        const uint32_t* key2slot, const uint32_t* pend, uint32_t n_pend, hipStream_t s) {

@@ -96,7 +96,9 @@ void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* a
                      const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys, uint64_t kbase,
                      const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
                      uint64_t dbase, uint32_t n_d, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t* ub, uint32_t e_new, uint32_t* err, hipStream_t s);
+                     uint32_t* inspos, uint32_t* ub, uint32_t* lim, uint32_t e_new, uint32_t* err, hipStream_t s);
+// Words of the merge's tile-limit buffer for an old adjacency of e_old entries.
+uint64_t mn_merge_limit_words(uint64_t e_old);
 // Query-dependent state of the present edges after a change of the query
 // set: edgeMatcher words of the live slots among [0, n_slots) and counter
 // increments for them and for the n_pend slots deleted by the last batch.
