@@ -174,7 +174,7 @@ struct mnemonic_ctx {
     uint32_t* d_sval[2] = {nullptr, nullptr};
     uint32_t* d_inspos[2] = {nullptr, nullptr};
     uint32_t* d_ub[2] = {nullptr, nullptr};  // insertion points of the batch entries in the old adjacency
-    uint32_t* d_mlim = nullptr;              // the merge's counts at every tile start (both directions use it in turn)
+    uint32_t* d_mlim = nullptr;              // the merge's counts at every tile start, one half per direction
     uint64_t cap_mlim = 0;
     uint32_t* d_touched = nullptr;
     uint32_t* d_del_slot[2] = {nullptr, nullptr};        // [buffer]
@@ -776,7 +776,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         dev_grow(c->d_adj2[d], t, need_E, 0, s);
         if (d == 1) c->cap_E = t;
     }
-    dev_grow(c->d_mlim, c->cap_mlim, mn_merge_limit_words(c->E), 0, s);
+    dev_grow(c->d_mlim, c->cap_mlim, 2 * mn_merge_limit_words(c->E), 0, s);
     if (n_ins > c->cap_ins) {
         uint64_t nc = std::max<uint64_t>(std::max<uint64_t>(n_ins, kScratchMin), 2 * c->cap_ins);
         c->cap_ins = 0;  // until every buffer below exists again (an allocation may fail)
@@ -1376,17 +1376,27 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             mn_launch_widen(c->d_delpos[pend][1], dk + n_prev, dbit, n_prev, c->d_err, s);
             mn_radix_sort(dk, v0, k1, v1, 2 * n_prev, c->hb_pos + 1, c->d_sort_scratch, s);
         }
+        MergeSide side[2];
         for (int d = 0; d < 2; d++) {
-            const uint64_t kb = d ? dirbit : 0, db = d ? dbit : 0;
-            const uint64_t* bkd = bk + d * n_ins;
-            const uint32_t* bvd = bv + d * n_ins;
-            const uint64_t* dpd = n_prev ? dk + d * n_prev : nullptr;
-            mn_launch_vertex_meta(c->d_off[d], c->nV, (uint32_t)c->E, bkd, kb, (uint32_t)n_ins, dpd, db, n_prev,
-                                  c->hb, c->d_off2[d], c->d_meta[d], c->d_err, s);
-            mn_launch_merge(c->d_off[d], c->d_adj[d], c->d_adjk[d], (uint32_t)c->E, c->d_off2[d], c->d_meta[d], bkd,
-                            kb, bvd, c->d_key, (uint32_t)n_ins, dpd, db, n_prev, c->hb, c->d_adj2[d], c->d_adjk2[d],
-                            c->d_inspos[d], c->d_ub[d], c->d_mlim, (uint32_t)E_new, c->d_err, s);
+            MergeSide& m = side[d];
+            m.off = c->d_off[d];
+            m.adj = c->d_adj[d];
+            m.adjk = c->d_adjk[d];
+            m.bk = bk + d * n_ins;
+            m.kbase = d ? dirbit : 0;
+            m.bv = bv + d * n_ins;
+            m.dpos = n_prev ? dk + d * n_prev : nullptr;
+            m.dbase = d ? dbit : 0;
+            m.newoff = c->d_off2[d];
+            m.meta = c->d_meta[d];
+            m.adj_new = c->d_adj2[d];
+            m.adjk_new = c->d_adjk2[d];
+            m.inspos = c->d_inspos[d];
+            m.ub = c->d_ub[d];
+            m.lim = c->d_mlim + d * mn_merge_limit_words(c->E);
         }
+        mn_launch_merge(side, c->nV, (uint32_t)c->E, c->d_key, (uint32_t)n_ins, n_prev, c->hb, (uint32_t)E_new,
+                        c->d_err, s);
     }
     // from here on the kernels work on the merged adjacency
     GraphView g1 = make_view(c, merge);

@@ -158,14 +158,15 @@ __global__ __launch_bounds__(MN_BLOCK) void k_reindex(GraphView g, const DebiBit
 // Per vertex: its run of batch entries [bs, be) in bk and of deleted positions
 // [ds, de) in dpos, and its offset in the merged adjacency. Four threads first
 // bound the block's 256 vertices in both sorted arrays, so that every
-// vertex searches only its block's window.
-__global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __restrict__ off, uint32_t nv,
-                                                          uint32_t e_old, const uint64_t* __restrict__ bk,
-                                                          uint64_t kbase, uint32_t n_b,
-                                                          const uint64_t* __restrict__ dpos, uint64_t dbase,
-                                                          uint32_t n_d, uint32_t hb,
-                                                          uint32_t* __restrict__ newoff,
-                                                          uint4* __restrict__ meta, const uint32_t* err) {
+// vertex searches only its block's window. blockIdx.y is the direction.
+__global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(MergeSide m0, MergeSide m1, uint32_t nv, uint32_t e_old,
+                                                          uint32_t n_b, uint32_t n_d, uint32_t hb,
+                                                          const uint32_t* err) {
+    const MergeSide& m = blockIdx.y ? m1 : m0;
+    const uint32_t* __restrict__ off = m.off;
+    const uint64_t* __restrict__ bk = m.bk;
+    const uint64_t* __restrict__ dpos = m.dpos;
+    const uint64_t kbase = m.kbase, dbase = m.dbase;
     __shared__ uint32_t s_w[4];
     const uint32_t v0 = blockIdx.x * MN_BLOCK, v1 = min(v0 + MN_BLOCK, nv);
     const uint32_t tid = threadIdx.x;
@@ -189,9 +190,9 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(const uint32_t* __rest
         ds = lower_bound_dev<uint64_t>(dpos, s_w[2], s_w[3], dbase + o0);
         de = lower_bound_dev<uint64_t>(dpos, ds, s_w[3], dbase + o1);
     }
-    newoff[v] = o0 - ds + bs;
-    meta[v] = make_uint4(bs, be - bs, ds, de - ds);
-    if (v == nv - 1) newoff[nv] = e_old - n_d + n_b;
+    m.newoff[v] = o0 - ds + bs;
+    m.meta[v] = make_uint4(bs, be - bs, ds, de - ds);
+    if (v == nv - 1) m.newoff[nv] = e_old - n_d + n_b;
 }
 
 constexpr uint32_t MG_ITEMS = 8;
@@ -200,33 +201,31 @@ constexpr uint32_t MG_TILE = MN_BLOCK * MG_ITEMS;
 // Batch entries: placed after every kept old entry of their vertex with a high
 // word <= theirs. ub[r] records that insertion point (the first old position
 // after the batch entry), which places the old entries in k_merge_old.
-__global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
-    const uint32_t* __restrict__ off, const uint64_t* __restrict__ adj,
-    const uint32_t* __restrict__ newoff, const uint4* __restrict__ meta,
-    const uint64_t* __restrict__ bk, uint64_t kbase, const uint32_t* __restrict__ bv,
-    const uint64_t* __restrict__ s_key, uint32_t n_b, const uint64_t* __restrict__ dpos, uint64_t dbase,
-    uint32_t hb, uint64_t* __restrict__ adj_new, uint64_t* __restrict__ adjk_new, uint32_t* __restrict__ inspos,
-    uint32_t* __restrict__ ub_out, uint32_t e_new, uint32_t* err) {
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_new(MergeSide m0, MergeSide m1,
+                                                        const uint64_t* __restrict__ s_key, uint32_t n_b,
+                                                        uint32_t hb, uint32_t e_new, uint32_t* err) {
+    const MergeSide& m = blockIdx.y ? m1 : m0;
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_b || failed(err)) return;
-    uint64_t key = bk[r] - kbase;
+    uint64_t key = m.bk[r] - m.kbase;
     uint32_t v = (uint32_t)(key >> hb);
     uint32_t h = (uint32_t)(key & ((1ull << hb) - 1));
-    uint32_t o0 = off[v], o1 = off[v + 1];
-    uint32_t ub = upper_hi(adj, o0, o1, h);
-    ub_out[r] = ub;
-    uint4 m = meta[v];
+    uint32_t o0 = m.off[v], o1 = m.off[v + 1];
+    uint32_t ub = upper_hi(m.adj, o0, o1, h);
+    m.ub[r] = ub;
+    uint4 mt = m.meta[v];
     uint32_t kept = ub - o0;
-    if (m.w) kept -= lower_bound_dev<uint64_t>(dpos, m.z, m.z + m.w, dbase + ub) - m.z;
-    uint32_t out = newoff[v] + kept + (r - m.x);
+    if (mt.w) kept -= lower_bound_dev<uint64_t>(m.dpos, mt.z, mt.z + mt.w, m.dbase + ub) - mt.z;
+    uint32_t out = m.newoff[v] + kept + (r - mt.x);
     if (out >= e_new) {  // never expected; refuse rather than write out of bounds
         set_err(err, MN_ERR_INTERNAL);
-        inspos[r] = 0;
+        m.inspos[r] = 0;
         return;
     }
-    adj_new[out] = ((uint64_t)h << 32) | MN_FLAG | bv[r];
-    adjk_new[out] = s_key[bv[r]];
-    inspos[r] = out;
+    const uint32_t slot = m.bv[r];
+    m.adj_new[out] = ((uint64_t)h << 32) | MN_FLAG | slot;
+    m.adjk_new[out] = s_key[slot];
+    m.inspos[r] = out;
 }
 
 // Both counts at every tile start of the old array: lim[t] = insertion points
@@ -234,10 +233,14 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_new(
 // Thread i owns the boundary before sorted value i and writes the tiles whose
 // start falls between values i - 1 and i, so the limits cost one pass over
 // the batch instead of a binary search per tile. A side with no values is not
-// written (k_merge_old reads zero for it).
-__global__ __launch_bounds__(MN_BLOCK) void k_merge_limits(const uint32_t* __restrict__ ub, uint32_t n_b,
-                                                           const uint64_t* __restrict__ dpos, uint64_t dbase,
-                                                           uint32_t n_d, uint32_t nt, uint32_t* __restrict__ lim) {
+// written (k_merge_old reads zero for it). blockIdx.y is the direction.
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_limits(MergeSide m0, MergeSide m1, uint32_t n_b, uint32_t n_d,
+                                                           uint32_t nt) {
+    const MergeSide& m = blockIdx.y ? m1 : m0;
+    const uint32_t* __restrict__ ub = m.ub;
+    const uint64_t* __restrict__ dpos = m.dpos;
+    const uint64_t dbase = m.dbase;
+    uint32_t* __restrict__ lim = m.lim;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (n_b && i <= n_b) {
         const uint32_t t0 = i ? ub[i - 1] / MG_TILE + 1 : 0u;
@@ -257,15 +260,19 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_limits(const uint32_t* __res
 // counts at the tile's start and end come from k_merge_limits, the deletions
 // and insertion points inside the tile are marked in LDS and prefix-summed,
 // and every entry then costs one LDS read between its loads and its stores.
-// ub (n_b, sorted) comes from k_merge_new, which must run first.
-__global__ __launch_bounds__(MN_BLOCK) void k_merge_old(const uint64_t* __restrict__ adj,
-                                                        const uint64_t* __restrict__ adjk, uint32_t e_old,
-                                                        const uint32_t* __restrict__ ub, uint32_t n_b,
-                                                        const uint64_t* __restrict__ dpos, uint64_t dbase,
-                                                        uint32_t n_d, const uint32_t* __restrict__ lim,
-                                                        uint64_t* __restrict__ adj_new,
-                                                        uint64_t* __restrict__ adjk_new, uint32_t e_new,
-                                                        uint32_t* err) {
+// ub (n_b, sorted) comes from k_merge_new, which must run first. blockIdx.y
+// is the direction.
+__global__ __launch_bounds__(MN_BLOCK) void k_merge_old(MergeSide m0, MergeSide m1, uint32_t e_old, uint32_t n_b,
+                                                        uint32_t n_d, uint32_t e_new, uint32_t* err) {
+    const MergeSide& m = blockIdx.y ? m1 : m0;
+    const uint64_t* __restrict__ adj = m.adj;
+    const uint64_t* __restrict__ adjk = m.adjk;
+    const uint32_t* __restrict__ ub = m.ub;
+    const uint64_t* __restrict__ dpos = m.dpos;
+    const uint64_t dbase = m.dbase;
+    const uint32_t* __restrict__ lim = m.lim;
+    uint64_t* __restrict__ adj_new = m.adj_new;
+    uint64_t* __restrict__ adjk_new = m.adjk_new;
     __shared__ __align__(16) int32_t s_m[MG_TILE];
     __shared__ int32_t s_wsum[MN_BLOCK / MN_WAVE];
     __shared__ uint32_t s_dead;
@@ -470,29 +477,17 @@ void mn_launch_ingest(const GraphView& g, const BatchView& b, hipStream_t s) {
     if (b.n_ins) k_ingest<<<nblocks(b.n_ins), MN_BLOCK, 0, s>>>(g, b);
 }
 
-void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_old,
-                           const uint64_t* bkeys, uint64_t kbase, uint32_t n_b, const uint64_t* dpos,
-                           uint64_t dbase, uint32_t n_d, uint32_t hb, uint32_t* newoff, uint4* meta,
-                           const uint32_t* err, hipStream_t s) {
-    k_vertex_meta<<<nblocks(n_vertices), MN_BLOCK, 0, s>>>(off, n_vertices, e_old, bkeys, kbase, n_b, dpos,
-                                                           dbase, n_d, hb, newoff, meta, err);
-}
-
-void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t e_old,
-                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys, uint64_t kbase,
-                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
-                     uint64_t dbase, uint32_t n_d, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t* ub, uint32_t* lim, uint32_t e_new, uint32_t* err, hipStream_t s) {
-    if (n_b)
-        k_merge_new<<<nblocks(n_b), MN_BLOCK, 0, s>>>(off, adj, newoff, meta, bkeys, kbase, bvals, s_key, n_b, dpos,
-                                                      dbase, hb, adj_new, adjk_new, inspos, ub, e_new, err);
+void mn_launch_merge(const MergeSide* side, uint32_t n_vertices, uint32_t e_old, const uint64_t* s_key,
+                     uint32_t n_b, uint32_t n_d, uint32_t hb, uint32_t e_new, uint32_t* err, hipStream_t s) {
+    const MergeSide m0 = side[0], m1 = side[1];
+    k_vertex_meta<<<dim3(nblocks(n_vertices), 2), MN_BLOCK, 0, s>>>(m0, m1, n_vertices, e_old, n_b, n_d, hb, err);
+    if (n_b) k_merge_new<<<dim3(nblocks(n_b), 2), MN_BLOCK, 0, s>>>(m0, m1, s_key, n_b, hb, e_new, err);
     if (e_old) {
         const uint32_t nt = (e_old + MG_TILE - 1) / MG_TILE;
         if (n_b || n_d)
-            k_merge_limits<<<nblocks((uint64_t)std::max(n_b, n_d) + 1), MN_BLOCK, 0, s>>>(ub, n_b, dpos, dbase, n_d,
-                                                                                          nt, lim);
-        k_merge_old<<<nt, MN_BLOCK, 0, s>>>(adj, adjk, e_old, ub, n_b, dpos, dbase, n_d, lim, adj_new, adjk_new,
-                                            e_new, err);
+            k_merge_limits<<<dim3(nblocks((uint64_t)std::max(n_b, n_d) + 1), 2), MN_BLOCK, 0, s>>>(m0, m1, n_b, n_d,
+                                                                                                  nt);
+        k_merge_old<<<dim3(nt, 2), MN_BLOCK, 0, s>>>(m0, m1, e_old, n_b, n_d, e_new, err);
     }
 }
 

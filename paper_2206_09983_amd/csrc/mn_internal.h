@@ -84,19 +84,34 @@ void mn_launch_reset(uint32_t* err, unsigned long long* zero_a, uint32_t n_a, hi
 void mn_launch_validate(const GraphView& g, const BatchView& b, hipStream_t s);
 void mn_launch_prev_del(const GraphView& g, const BatchView& b, hipStream_t s);
 void mn_launch_ingest(const GraphView& g, const BatchView& b, hipStream_t s);
-// bkeys (n_b) and dpos (n_d) are sorted and carry the constant kbase / dbase
-// (the direction bit of the combined sort) on top of every value.
-void mn_launch_vertex_meta(const uint32_t* off, uint32_t n_vertices, uint32_t e_old,
-                           const uint64_t* bkeys, uint64_t kbase, uint32_t n_b, const uint64_t* dpos,
-                           uint64_t dbase, uint32_t n_d, uint32_t hb, uint32_t* newoff, uint4* meta,
-                           const uint32_t* err, hipStream_t s);
-// Merged adjacency of one direction: batch entries first (their insertion
-// points go to ub, n_b words), then the kept old entries placed by them.
-void mn_launch_merge(const uint32_t* off, const uint64_t* adj, const uint64_t* adjk, uint32_t e_old,
-                     const uint32_t* newoff, const uint4* meta, const uint64_t* bkeys, uint64_t kbase,
-                     const uint32_t* bvals, const uint64_t* s_key, uint32_t n_b, const uint64_t* dpos,
-                     uint64_t dbase, uint32_t n_d, uint32_t hb, uint64_t* adj_new, uint64_t* adjk_new,
-                     uint32_t* inspos, uint32_t* ub, uint32_t* lim, uint32_t e_new, uint32_t* err, hipStream_t s);
+// One direction of the per-batch adjacency merge. Old arrays: off (nv + 1),
+// adj and adjk (e_old). Batch: bk (n_b sorted keys, kbase + vertex << hb |
+// high word) with their slots bv; dpos (n_d sorted deleted positions plus
+// dbase, or null); kbase and dbase are the direction bit of the combined sort.
+// Outputs: newoff (nv + 1), meta (nv), adj_new and adjk_new (e_new), inspos
+// and ub (n_b), lim (mn_merge_limit_words(e_old)).
+struct MergeSide {
+    const uint32_t* off;
+    const uint64_t* adj;
+    const uint64_t* adjk;
+    const uint64_t* bk;
+    uint64_t kbase;
+    const uint32_t* bv;
+    const uint64_t* dpos;
+    uint64_t dbase;
+    uint32_t* newoff;
+    uint4* meta;
+    uint64_t* adj_new;
+    uint64_t* adjk_new;
+    uint32_t* inspos;
+    uint32_t* ub;
+    uint32_t* lim;
+};
+// Merged adjacency of both directions (side[0], side[1]) in one launch per
+// step: vertex runs and offsets, batch entries at their insertion points,
+// the tile limits, then the kept old entries.
+void mn_launch_merge(const MergeSide* side, uint32_t n_vertices, uint32_t e_old, const uint64_t* s_key,
+                     uint32_t n_b, uint32_t n_d, uint32_t hb, uint32_t e_new, uint32_t* err, hipStream_t s);
 // Words of the merge's tile-limit buffer for an old adjacency of e_old entries.
 uint64_t mn_merge_limit_words(uint64_t e_old);
 // Query-dependent state of the present edges after a change of the query
