@@ -265,6 +265,31 @@ __global__ __launch_bounds__(MN_BLOCK) void k_scan64_add(uint64_t* __restrict__ 
     }
 }
 
+// As k_scan64_add, for few blocks: each block first sums the block totals
+// before it (at most SC_DIRECT_MAX of them, a few loads per thread), which
+// saves scanning the totals in launches of their own.
+constexpr uint32_t SC_DIRECT_MAX = 2048;
+
+__global__ __launch_bounds__(MN_BLOCK) void k_scan64_add_direct(uint64_t* __restrict__ out,
+                                                                const uint64_t* __restrict__ sums, uint32_t n,
+                                                                const uint32_t* n_dev) {
+    __shared__ uint64_t wsum[RS_WAVES];
+    if (n_dev) n = min(n, *n_dev);
+    const size_t base = (size_t)blockIdx.x * SC_TILE;
+    if (base >= n) return;  // past the elements present: the same for the whole block
+    uint64_t part = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += MN_BLOCK) part += sums[i];
+    part = wave_incl_scan64(part);  // the last lane holds the wave's total
+    if (__lane_id() == MN_WAVE - 1) wsum[threadIdx.x / MN_WAVE] = part;
+    __syncthreads();
+    uint64_t add = 0;
+    for (uint32_t w = 0; w < RS_WAVES; w++) add += wsum[w];
+    for (uint32_t i = threadIdx.x; i < SC_TILE; i += MN_BLOCK) {
+        const size_t idx = base + i;
+        if (idx < n) out[idx] += add;
+    }
+}
+
 __global__ void k_scan64_total(const uint32_t* __restrict__ in, const uint64_t* __restrict__ out,
                                uint32_t n, const uint32_t* n_dev, uint64_t* total) {
     if (n_dev) n = min(n, *n_dev);
@@ -280,6 +305,10 @@ void scan64_rec(const TI* in, uint64_t* out, uint32_t n, const uint32_t* n_dev, 
     uint64_t* sums = scratch;
     k_scan64_local<TI><<<nb, MN_BLOCK, 0, s>>>(in, out, sums, n, n_dev);
     if (nb == 1) return;
+    if (nb <= SC_DIRECT_MAX) {
+        k_scan64_add_direct<<<nb, MN_BLOCK, 0, s>>>(out, sums, n, n_dev);
+        return;
+    }
     scan64_rec<uint64_t>(sums, sums, nb, nullptr, scratch + nb + 1, s);
     k_scan64_add<<<nb, MN_BLOCK, 0, s>>>(out, sums, n, n_dev);
 }
