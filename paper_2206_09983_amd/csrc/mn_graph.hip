@@ -373,9 +373,16 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vf_refresh(GraphView g, const VfBi
             if (live && bit < n_bits) {
                 const VfBit vb = bits[bit];
                 ok = (vb.vreq & ~mv) == 0;
-                for (uint32_t r = vb.req_begin; ok && r < vb.req_end; r++) {
-                    const VfReq q = g.vfreq[r];
-                    ok = c[q.cnt] >= q.need;
+                // four requirements per step, their loads issued together
+                for (uint32_t r = vb.req_begin; ok && r < vb.req_end; r += 4) {
+                    VfReq q[4];
+                    uint32_t have[4];
+#pragma unroll
+                    for (uint32_t k = 0; k < 4; k++) q[k] = r + k < vb.req_end ? g.vfreq[r + k] : VfReq{0, 0};
+#pragma unroll
+                    for (uint32_t k = 0; k < 4; k++) have[k] = r + k < vb.req_end ? c[q[k].cnt] : 0u;
+#pragma unroll
+                    for (uint32_t k = 0; k < 4; k++) ok = ok && have[k] >= q[k].need;
                 }
             }
             const uint64_t m = __ballot(ok);
