@@ -1072,19 +1072,31 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         // the next level's row counter starts at zero
         mn_launch_level_range(g, rows_view(c, L), (uint32_t)n_max, n_dev, L, B.lo, B.cnt, po.stats, c->d_err, s,
                               next ? n_out : nullptr, L ? c->d_zr + c->note_rows(po.phase, L - 1) : nullptr);
-        mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n_max, c->d_scan64, nullptr, s, n_dev);
         // candidates are bounded by the tile buffer and the grid only; rows
         // past the next level's buffer are counted and noted
         const uint64_t K = c->cand_k;
         unsigned long long* note = c->d_zr + c->note_cand(po.phase, L);
-        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
-        if (timing) ev = event_pair(c, po.phase);
         const double rt = c->rate[po.phase][L];
         const uint64_t expect = rt < 0 ? (~0ull >> 8) : (uint64_t)(rt * (double)ns) + 1;
+        // offsets, total and partition in two launches where the rows fit
+        // MN_SCAN_DIRECT_MAX scan tiles, else the general scan and partition
+        const uint32_t nb = (uint32_t)((n_max + MN_SCAN_TILE - 1) / MN_SCAN_TILE);
+        const bool fused = n_max > 0 && K > 0 && nb <= MN_SCAN_DIRECT_MAX;
+        if (fused) {
+            mn_scan64_local(B.cnt, B.off, (uint32_t)n_max, c->d_scan64, s, n_dev);
+            mn_launch_offsets_partition(B.cnt, B.off, c->d_scan64, nb, (uint32_t)n_max, n_dev, 0,
+                                        mn_expand_end(0, K, expect, c->tile_items), c->d_total, c->tile_items,
+                                        c->d_tiles, note, s);
+        } else {
+            mn_scan_exclusive64(B.cnt, B.off, (uint32_t)n_max, c->d_scan64, nullptr, s, n_dev);
+        }
+        std::pair<hipEvent_t, hipEvent_t> ev(nullptr, nullptr);
+        if (timing) ev = event_pair(c, po.phase);
         c->cover[po.phase][L] =
             mn_launch_expand(g, rows_view(c, L), (uint32_t)n_max, n_dev, B.lo, B.off, B.cnt, c->d_tiles, 0, K,
                              c->d_total, note, expect, c->tile_items, L, c->max_close, c->level_rows[L] != 0,
-                             c->level_emit[L] != 0, rows_view(c, L + 1), n_out, po, c->d_err, s, ev.first, ev.second);
+                             c->level_emit[L] != 0, rows_view(c, L + 1), n_out, po, c->d_err, s, ev.first, ev.second,
+                             fused);
         c->n_expand[po.phase]++;
         if (next) n_max = c->lvb[L + 1].cap;
     }

@@ -884,6 +884,65 @@ __global__ __launch_bounds__(MN_BLOCK) void k_partition(const uint64_t* __restri
     tile_row[i] = row_of(off, 0, n, t);
 }
 
+// Completes a level's candidate offsets and partitions them in one launch.
+// off holds exclusive sums within tiles of MN_SCAN_TILE rows and sums[b] the
+// total of tile b (nb tiles): every block adds the totals in front of it and
+// sums all of them for the level's total T. Each row with candidates [o, o +
+// cnt) inside [c0, cend), cend = min(c1, T), writes tile_row[i] for every
+// expansion tile i whose first candidate c0 + i * tile it holds, and
+// tile_row[nt] if it holds cend - 1 (nt tiles cover [c0, cend)): the row of a
+// candidate is the one that contains it, as k_partition finds by search.
+// Block 0 stores T and notes it against c1.
+__global__ __launch_bounds__(MN_BLOCK) void k_offsets_partition(const uint32_t* __restrict__ cnt,
+                                                                uint64_t* __restrict__ off,
+                                                                const uint64_t* __restrict__ sums, uint32_t nb,
+                                                                uint32_t n, const uint32_t* n_dev, uint64_t c0,
+                                                                uint64_t c1, uint64_t* T_dev, uint32_t tile,
+                                                                uint32_t* __restrict__ tile_row,
+                                                                unsigned long long* note) {
+    __shared__ uint64_t s_pre[MN_BLOCK / MN_WAVE], s_tot[MN_BLOCK / MN_WAVE];
+    if (n_dev) n = min(n, *n_dev);
+    uint64_t pre = 0, tot = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += MN_BLOCK) {
+        const uint64_t v = sums[i];
+        tot += v;
+        if (i < blockIdx.x) pre += v;
+    }
+    pre = wave_sum64(pre);
+    tot = wave_sum64(tot);
+    if (__lane_id() == 0) {
+        s_pre[threadIdx.x / MN_WAVE] = pre;
+        s_tot[threadIdx.x / MN_WAVE] = tot;
+    }
+    __syncthreads();
+    uint64_t add = 0, T = 0;
+    for (uint32_t w = 0; w < MN_BLOCK / MN_WAVE; w++) {
+        add += s_pre[w];
+        T += s_tot[w];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *T_dev = T;
+        if (note) {
+            if (T > c1) note[0] = 1ull;
+            atomicMax(note + 1, (unsigned long long)T);
+        }
+    }
+    const uint64_t cend = min(c1, T);
+    const uint32_t nt = expand_tiles(c0, cend, tile);
+    const size_t base = (size_t)blockIdx.x * MN_SCAN_TILE;
+    for (uint32_t k = threadIdx.x; k < MN_SCAN_TILE; k += MN_BLOCK) {
+        const size_t r = base + k;
+        if (r >= n) break;
+        const uint64_t o = off[r] + add;
+        off[r] = o;
+        const uint32_t m = cnt[r];
+        const uint64_t a = max(o, c0), b = min(o + m, cend);
+        if (a >= b) continue;  // no candidates in the window
+        for (uint64_t i = (a - c0 + tile - 1) / tile; c0 + i * tile < b; i++) tile_row[i] = (uint32_t)r;
+        if (b == cend) tile_row[nt] = (uint32_t)r;
+    }
+}
+
 constexpr uint32_t NO_LOC = 0xFFFFFFFFu;
 
 // One block tests a tile of 256 x ITEMS candidates in two passes. Pass 1 runs the
@@ -1197,12 +1256,28 @@ void launch_expand_items(uint32_t max_close, bool rows, bool emit, dim3 grid, hi
 #undef MN_EXPAND_ARGS
 }
 
+inline uint32_t expand_items(uint32_t items) { return items == 1 || items == 4 ? items : 2u; }
+
+uint64_t mn_expand_end(uint64_t c0, uint64_t c1, uint64_t expect, uint32_t items) {
+    const uint32_t tile = MN_BLOCK * expand_items(items);
+    const uint64_t want = expand_tiles(0, expect + expect / 2, tile) + EX_SPARE_TILES;
+    return std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, MN_EXPAND_MAX_BLOCKS) * tile);
+}
+
+void mn_launch_offsets_partition(const uint32_t* cnt, uint64_t* off, const uint64_t* sums, uint32_t nb, uint32_t n,
+                                 const uint32_t* n_dev, uint64_t c0, uint64_t c1, uint64_t* T_dev, uint32_t items,
+                                 uint32_t* tile_row, unsigned long long* note, hipStream_t s) {
+    if (!nb) return;
+    k_offsets_partition<<<nb, MN_BLOCK, 0, s>>>(cnt, off, sums, nb, n, n_dev, c0, c1, T_dev,
+                                                MN_BLOCK * expand_items(items), tile_row, note);
+}
+
 uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* n_dev, const uint32_t* lo,
                           const uint64_t* off, const uint32_t* cnt, uint32_t* tile_row, uint64_t c0, uint64_t c1,
                           uint64_t* T_dev,
                           unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
                           bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
-                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool partitioned) {
     if (c1 <= c0 || !n_in) {
         if (ev0) {  // an empty pair keeps the caller's bookkeeping simple
             (void)hipEventRecord(ev0, s);
@@ -1210,7 +1285,7 @@ uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const 
         }
         return c1;
     }
-    if (items != 1 && items != 4) items = 2;
+    items = expand_items(items);
     const uint32_t tile = MN_BLOCK * items;
     // With the total on the device, the grid follows the expected candidate
     // count with a margin, and the candidates it can cover bound c1: a larger
@@ -1219,12 +1294,11 @@ uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const 
     // blocks past the candidates present leave at once, so spare blocks cost
     // little, while a re-run costs the whole phase (a deletion phase that
     // meets a hub can take several times its usual candidates).
-    if (T_dev) {
-        const uint64_t want = expand_tiles(0, expect + expect / 2, tile) + EX_SPARE_TILES;
-        c1 = std::min<uint64_t>(c1, c0 + std::min<uint64_t>(want, MN_EXPAND_MAX_BLOCKS) * tile);
-    }
+    if (T_dev) c1 = mn_expand_end(c0, c1, expect, items);
     const uint64_t tiles = expand_tiles(c0, c1, tile);
-    k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, cnt, n_in, n_dev, c0, c1, T_dev, tile, tile_row, note);
+    if (!partitioned)
+        k_partition<<<nblocks(tiles + 1), MN_BLOCK, 0, s>>>(off, cnt, n_in, n_dev, c0, c1, T_dev, tile, tile_row,
+                                                            note);
     const dim3 grid((uint32_t)tiles);
 #define MN_ITEMS_ARGS max_close, rows, emit, grid, s, ev0, ev1, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err
     if (items == 1)

@@ -17,6 +17,12 @@ void mn_scan_exclusive(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* 
 // receives the sum. `scratch` must hold mn_scan64_scratch_words(n) u64 words. With n_dev,
 // the count is min(n, *n_dev), read on the device (n sizes the launch).
 size_t mn_scan64_scratch_words(uint32_t n);
+// The per-tile pass alone: out holds exclusive sums within tiles of
+// MN_SCAN_TILE values, sums[b] the total of tile b; returns the tile count.
+constexpr uint32_t MN_SCAN_TILE = 2048;
+constexpr uint32_t MN_SCAN_DIRECT_MAX = 2048;  // tiles a block may sum in front of itself
+uint32_t mn_scan64_local(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* sums, hipStream_t s,
+                         const uint32_t* n_dev);
 void mn_scan_exclusive64(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* scratch,
                          uint64_t* total, hipStream_t s, const uint32_t* n_dev = nullptr);
 
@@ -208,7 +214,17 @@ uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const 
                       uint64_t* T_dev,
                       unsigned long long* note, uint64_t expect, uint32_t items, uint32_t L, uint32_t max_close,
                       bool rows, bool emit, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err,
-                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool partitioned = false);
+// The device-sized form of a level in fewer launches: after mn_scan64_local
+// over the row counts (nb tiles, nb <= MN_SCAN_DIRECT_MAX), completes off,
+// stores the candidate total in *T_dev (noted against c1) and writes the
+// tile_row partition that mn_launch_expand(..., partitioned = true) then
+// uses. c1 must be mn_expand_end(c0, c1, expect, items), the end that launch
+// covers.
+uint64_t mn_expand_end(uint64_t c0, uint64_t c1, uint64_t expect, uint32_t items);
+void mn_launch_offsets_partition(const uint32_t* cnt, uint64_t* off, const uint64_t* sums, uint32_t nb, uint32_t n,
+                                 const uint32_t* n_dev, uint64_t c0, uint64_t c1, uint64_t* T_dev, uint32_t items,
+                                 uint32_t* tile_row, unsigned long long* note, hipStream_t s);
 
 // Stores v into *p (a device word) in stream order.
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);

@@ -13,6 +13,7 @@ namespace {
 
 constexpr uint32_t SC_ITEMS = 8;
 constexpr uint32_t SC_TILE = MN_BLOCK * SC_ITEMS;  // 2048
+static_assert(SC_TILE == MN_SCAN_TILE, "scan tile");
 // A radix tile is 256 x ROUNDS keys. Small inputs take short tiles so that a
 // pass still spreads over many blocks (a tile's rounds run one after another).
 constexpr uint32_t RS_ROUNDS_MAX = 16;
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_scan64_add(uint64_t* __restrict__ 
 // As k_scan64_add, for few blocks: each block first sums the block totals
 // before it (at most SC_DIRECT_MAX of them, a few loads per thread), which
 // saves scanning the totals in launches of their own.
-constexpr uint32_t SC_DIRECT_MAX = 2048;
+constexpr uint32_t SC_DIRECT_MAX = MN_SCAN_DIRECT_MAX;
 
 __global__ __launch_bounds__(MN_BLOCK) void k_scan64_add_direct(uint64_t* __restrict__ out,
                                                                 const uint64_t* __restrict__ sums, uint32_t n,
@@ -314,6 +315,13 @@ void scan64_rec(const TI* in, uint64_t* out, uint32_t n, const uint32_t* n_dev, 
 }
 
 }  // namespace
+
+uint32_t mn_scan64_local(const uint32_t* in, uint64_t* out, uint32_t n, uint64_t* sums, hipStream_t s,
+                         const uint32_t* n_dev) {
+    const uint32_t nb = ceil_div(n, SC_TILE);
+    if (nb) k_scan64_local<uint32_t><<<nb, MN_BLOCK, 0, s>>>(in, out, sums, n, n_dev);
+    return nb;
+}
 
 size_t mn_scan64_scratch_words(uint32_t n) {
     size_t words = 4;
