@@ -257,6 +257,10 @@ struct mnemonic_ctx {
     unsigned long long* d_zr = nullptr;
     uint32_t n_zr = 0;
     std::vector<unsigned long long> h_zr;
+    // pinned staging for the end-of-batch readback: the n_zr words, then the
+    // error word (its low half); both copies are queued before one wait
+    unsigned long long* h_zr_pin = nullptr;
+    uint64_t cap_zr_pin = 0;
 
     // outputs
     std::vector<OutView> houts;
@@ -948,6 +952,30 @@ RowsView rows_view(const mnemonic_ctx* c, uint32_t L) {
     return R;
 }
 
+// Pinned staging of n_zr + 1 words (the readback block and the error word).
+void size_zr_pin(mnemonic_ctx* c) {
+    if (c->cap_zr_pin >= c->n_zr + 1) return;
+    if (c->h_zr_pin) (void)hipHostFree(c->h_zr_pin);
+    c->h_zr_pin = nullptr;
+    c->cap_zr_pin = 0;
+    HIPCHK(hipHostMalloc((void**)&c->h_zr_pin, (c->n_zr + 1) * 8, hipHostMallocDefault));
+    c->cap_zr_pin = c->n_zr + 1;
+}
+
+// The readback block into h_zr (and the error word into *err when given):
+// both copies land in pinned memory, then one wait.
+void read_zr(mnemonic_ctx* c, uint32_t* err) {
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->h_zr_pin, c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
+    if (err) {
+        c->h_zr_pin[c->n_zr] = 0;
+        HIPCHK(hipMemcpyAsync(c->h_zr_pin + c->n_zr, c->d_err, 4, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(c->h_zr.data(), c->h_zr_pin, c->n_zr * 8);
+    if (err) *err = (uint32_t)c->h_zr_pin[c->n_zr];
+}
+
 uint64_t read_u32(mnemonic_ctx* c, const uint32_t* d) {
     HIPCHK(hipMemcpyAsync(c->h_ctl, d, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1436,9 +1464,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         uint32_t n_free_after = c->n_free - (uint32_t)std::min<uint64_t>(n_ins, c->n_free);
         mn_launch_finalize(b, n_free_after, s);
         if (timing) HIPCHK(hipEventRecord(c->ev[5], s));
-        HIPCHK(hipMemcpyAsync(&err, c->d_err, 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        read_zr(c, &err);
         c->summarize();
     } catch (...) {
         swap_in();  // a swap is its own inverse: back to the pre-batch arrays
@@ -1522,8 +1548,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                 reset_phase(c, 1);
                 enumerate_phase(c, 1, c->d_del_slot[cur], n_del, host_chunks[1]);
             }
-            HIPCHK(hipMemcpyAsync(c->h_zr.data(), c->d_zr, c->n_zr * 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            read_zr(c, nullptr);
             c->summarize();
         }
         if (emit && (c->flags & MNEMONIC_F_SORT)) {
@@ -1725,6 +1750,9 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_srt_scr);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     c->h_ctl = nullptr;
+    if (c->h_zr_pin) (void)hipHostFree(c->h_zr_pin);
+    c->h_zr_pin = nullptr;
+    c->cap_zr_pin = 0;
 }
 
 }  // namespace
@@ -1821,6 +1849,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         HIPCHK(hipMemcpyAsync(c->d_last_ts, &mn, 8, hipMemcpyHostToDevice, s));
         c->n_zr = c->zr_words();
         c->h_zr.assign(c->n_zr, 0);
+        size_zr_pin(c);
         dev_alloc(c->d_zr, c->n_zr);
         // output buffers
         uint64_t cap = opt && opt->out_capacity ? opt->out_capacity : (1ull << 20);
@@ -2010,6 +2039,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         dev_free(c->d_zr);
         c->n_zr = c->zr_words();
         c->h_zr.assign(c->n_zr, 0);
+        size_zr_pin(c);
         dev_alloc(c->d_zr, c->n_zr);
         // level buffers (their width follows the queries) and the sizing state
         for (auto& B : c->lvb) {
