@@ -347,6 +347,7 @@ def main():
                 tag, i, len(case["batches"][i]["src"]), st["ms_batch"], st["tuples"], st["expand_tile"]))
         r = {"lat": [], "tot": {k: 0 for k in BYTES}, "expand_ms": 0.0, "launches": 0, "rows": 0, "tuples": 0,
              "edges": 0, "results": []}
+        steps = []
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for i in range(args.warmup, n_batches):
@@ -364,14 +365,16 @@ def main():
             r["edges"] += len(case["batches"][i]["src"]) + len(case["batches"][i]["del_keys"])
             res = [m.result(q) for q in range(len(case["queries"]))]
             r["results"].append([(x["n_new"], x["dig_new"], x["n_expired"], x["dig_expired"]) for x in res])
+            steps.append((i, r["lat"][-1], st))
+        torch.cuda.synchronize()
+        r["elapsed"] = time.perf_counter() - t_start
+        for i, lat, st in steps:  # logged after the timed region
             log("[%s] step %d: %.2f ms (enumerate %.2f + %.2f ms, of which k_expand %.2f + %.2f ms in %s launches), "
                 "seeds %s, rows %s, candidates %s, tuples %s%s" % (
-                    tag, i, r["lat"][-1], st["ms_enumerate"][0], st["ms_enumerate"][1], st["ms_expand"][0],
+                    tag, i, lat, st["ms_enumerate"][0], st["ms_enumerate"][1], st["ms_expand"][0],
                     st["ms_expand"][1], st["expand_launches"], st["seeds"], st["frontier_rows"],
                     st["entries_scanned"], st["tuples"],
                     ", re-runs %s (causes %s)" % (st["reruns"], st["rerun_causes"]) if any(st["reruns"]) else ""))
-        torch.cuda.synchronize()
-        r["elapsed"] = time.perf_counter() - t_start
         r["tile"] = m.stats()["expand_tile"]
         m.close()
         return r
