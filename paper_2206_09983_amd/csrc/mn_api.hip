@@ -1412,8 +1412,8 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             uint32_t* v0 = c->d_dval[0];
             uint64_t* k1 = c->d_dkey[1];
             uint32_t* v1 = c->d_dval[1];
-            mn_launch_widen(c->d_delpos[pend][0], dk, 0, n_prev, c->d_err, s);
-            mn_launch_widen(c->d_delpos[pend][1], dk + n_prev, dbit, n_prev, c->d_err, s);
+            mn_launch_widen(c->d_delpos[pend][0], dk, 0, c->d_delpos[pend][1], dk + n_prev, dbit, n_prev, c->d_err,
+                            s);
             mn_radix_sort(dk, v0, k1, v1, 2 * n_prev, c->hb_pos + 1, c->d_sort_scratch, s);
         }
         MergeSide side[2];
@@ -1457,7 +1457,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     const bool enum_on = enumerate && !(c->flags & MNEMONIC_F_INDEX_ONLY);
     try {
         if (enum_on) enumerate_phase(c, 0, c->d_ins_slot, n_ins);
-        for (int d = 0; d < 2; d++) mn_launch_set_flags(adjn[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
+        mn_launch_set_flags(adjn[0], c->d_inspos[0], adjn[1], c->d_inspos[1], (uint32_t)n_ins, 0, c->d_err, s);
         GraphView g2 = make_view(c, false);
         mn_launch_flag_del(g2, adjn[0], adjn[1], b, s);
         if (enum_on) enumerate_phase(c, 1, c->d_del_slot[cur], n_del);
@@ -1533,16 +1533,17 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             if (last) throw ApiError{MNEMONIC_E_HIP, "enumeration did not settle (internal)" + why};
             grow_outputs(c, need);
             if (redo[0]) {
-                for (int d = 0; d < 2; d++) {
-                    mn_launch_set_flags(c->d_adj[d], c->d_delpos[cur][d], (uint32_t)n_del, 0, c->d_err, s);
-                    mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 1, c->d_err, s);
-                }
+                // per direction: deletion flags cleared before insertion flags are set
+                mn_launch_set_flags(c->d_adj[0], c->d_delpos[cur][0], c->d_adj[1], c->d_delpos[cur][1],
+                                    (uint32_t)n_del, 0, c->d_err, s);
+                mn_launch_set_flags(c->d_adj[0], c->d_inspos[0], c->d_adj[1], c->d_inspos[1], (uint32_t)n_ins, 1,
+                                    c->d_err, s);
                 reset_phase(c, 0);
                 enumerate_phase(c, 0, c->d_ins_slot, n_ins, host_chunks[0]);
-                for (int d = 0; d < 2; d++) {
-                    mn_launch_set_flags(c->d_adj[d], c->d_inspos[d], (uint32_t)n_ins, 0, c->d_err, s);
-                    mn_launch_set_flags(c->d_adj[d], c->d_delpos[cur][d], (uint32_t)n_del, 1, c->d_err, s);
-                }
+                mn_launch_set_flags(c->d_adj[0], c->d_inspos[0], c->d_adj[1], c->d_inspos[1], (uint32_t)n_ins, 0,
+                                    c->d_err, s);
+                mn_launch_set_flags(c->d_adj[0], c->d_delpos[cur][0], c->d_adj[1], c->d_delpos[cur][1],
+                                    (uint32_t)n_del, 1, c->d_err, s);
             }
             if (redo[1]) {
                 reset_phase(c, 1);

@@ -391,10 +391,14 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vf_refresh(GraphView g, const VfBi
     }
 }
 
-__global__ __launch_bounds__(MN_BLOCK) void k_set_flags(uint64_t* adj, const uint32_t* __restrict__ pos,
+// blockIdx.y picks the direction: (adj0, pos0) or (adj1, pos1).
+__global__ __launch_bounds__(MN_BLOCK) void k_set_flags(uint64_t* adj0, const uint32_t* __restrict__ pos0,
+                                                        uint64_t* adj1, const uint32_t* __restrict__ pos1,
                                                         uint32_t n, int set, const uint32_t* err) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || failed(err)) return;
+    uint64_t* adj = blockIdx.y ? adj1 : adj0;
+    const uint32_t* pos = blockIdx.y ? pos1 : pos0;
     uint32_t* lo = reinterpret_cast<uint32_t*>(adj) + 2 * (size_t)pos[i];
     *lo = set ? (*lo | MN_FLAG) : (*lo & MN_SLOTMASK);
 }
@@ -449,10 +453,17 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-__global__ __launch_bounds__(MN_BLOCK) void k_widen(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
-                                                    uint64_t add, uint32_t n, const uint32_t* err) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && !failed(err)) out[i] = add + in[i];
+// blockIdx.y picks the direction: (in0, out0, add0) or (in1, out1, add1).
+__global__ __launch_bounds__(MN_BLOCK) void k_widen(const uint32_t* __restrict__ in0, uint64_t* __restrict__ out0,
+                                                    uint64_t add0, const uint32_t* __restrict__ in1,
+                                                    uint64_t* __restrict__ out1, uint64_t add1, uint32_t n,
+                                                    const uint32_t* err) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || failed(err)) return;
+    if (blockIdx.y)
+        out1[i] = add1 + in1[i];
+    else
+        out0[i] = add0 + in0[i];
 }
 
 inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK); }
@@ -462,9 +473,9 @@ inline uint32_t nblocks(uint64_t n) { return (uint32_t)((n + MN_BLOCK - 1) / MN_
 
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) { k_set_u32<<<1, 64, 0, s>>>(p, v); }
 
-void mn_launch_widen(const uint32_t* in, uint64_t* out, uint64_t add, uint32_t n, const uint32_t* err,
-                     hipStream_t s) {
-    if (n) k_widen<<<nblocks(n), MN_BLOCK, 0, s>>>(in, out, add, n, err);
+void mn_launch_widen(const uint32_t* in0, uint64_t* out0, uint64_t add0, const uint32_t* in1, uint64_t* out1,
+                     uint64_t add1, uint32_t n, const uint32_t* err, hipStream_t s) {
+    if (n) k_widen<<<dim3(nblocks(n), 2), MN_BLOCK, 0, s>>>(in0, out0, add0, in1, out1, add1, n, err);
 }
 
 void mn_launch_reset(uint32_t* err, unsigned long long* zero_a, uint32_t n_a, hipStream_t s) {
@@ -514,9 +525,9 @@ void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits
     if (n) k_vf_refresh<<<blocks, MN_BLOCK, 0, s>>>(g, bits, n_bits, list, n, err);
 }
 
-void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
-                         const uint32_t* err, hipStream_t s) {
-    if (n) k_set_flags<<<nblocks(n), MN_BLOCK, 0, s>>>(adj, pos, n, set, err);
+void mn_launch_set_flags(uint64_t* adj0, const uint32_t* pos0, uint64_t* adj1, const uint32_t* pos1, uint32_t n,
+                         int set, const uint32_t* err, hipStream_t s) {
+    if (n) k_set_flags<<<dim3(nblocks(n), 2), MN_BLOCK, 0, s>>>(adj0, pos0, adj1, pos1, n, set, err);
 }
 
 void mn_launch_flag_del(const GraphView& g, uint64_t* adj_out, uint64_t* adj_in, const BatchView& b,

@@ -128,8 +128,10 @@ void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits,
                        const uint32_t* key2slot, const uint32_t* pend, uint32_t n_pend, hipStream_t s);
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
-void mn_launch_set_flags(uint64_t* adj, const uint32_t* pos, uint32_t n, int set,
-                         const uint32_t* err, hipStream_t s);
+// Sets (set != 0) or clears the flag bit of the entries at pos0[i] of adj0
+// and pos1[i] of adj1 (both directions, i < n) in one launch.
+void mn_launch_set_flags(uint64_t* adj0, const uint32_t* pos0, uint64_t* adj1, const uint32_t* pos1, uint32_t n,
+                         int set, const uint32_t* err, hipStream_t s);
 void mn_launch_flag_del(const GraphView& g, uint64_t* adj_out, uint64_t* adj_in, const BatchView& b,
                         hipStream_t s);
 void mn_launch_finalize(const BatchView& b, uint32_t n_free_after, hipStream_t s);
@@ -230,8 +232,9 @@ void mn_launch_offsets_partition(const uint32_t* cnt, uint64_t* off, const uint6
 void mn_launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 
 // out[i] = add + in[i] as u64 (sort keys).
-void mn_launch_widen(const uint32_t* in, uint64_t* out, uint64_t add, uint32_t n, const uint32_t* err,
-                     hipStream_t s);
+// out0[i] = add0 + in0[i] and out1[i] = add1 + in1[i] for i < n, in one launch.
+void mn_launch_widen(const uint32_t* in0, uint64_t* out0, uint64_t add0, const uint32_t* in1, uint64_t* out1,
+                     uint64_t add1, uint32_t n, const uint32_t* err, hipStream_t s);
 
 // ------------------------------------------------------------ order network
 // The scheduler's 24 -> 64 -> 64 -> 1 network (weights as in mn_common.h).
