@@ -38,6 +38,7 @@ against the 8 TB/s HBM peak. ``cpu_baseline`` times the single-threaded CPU
 oracle on a bounded prefix of the same stream.
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -348,6 +349,8 @@ def main():
         r = {"lat": [], "tot": {k: 0 for k in BYTES}, "expand_ms": 0.0, "launches": 0, "rows": 0, "tuples": 0,
              "edges": 0, "results": []}
         steps = []
+        gc.collect()
+        gc.disable()  # no collector pass inside the timed region
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for i in range(args.warmup, n_batches):
@@ -368,6 +371,7 @@ def main():
             steps.append((i, r["lat"][-1], st))
         torch.cuda.synchronize()
         r["elapsed"] = time.perf_counter() - t_start
+        gc.enable()
         for i, lat, st in steps:  # logged after the timed region
             log("[%s] step %d: %.2f ms (enumerate %.2f + %.2f ms, of which k_expand %.2f + %.2f ms in %s launches), "
                 "seeds %s, rows %s, candidates %s, tuples %s%s" % (
