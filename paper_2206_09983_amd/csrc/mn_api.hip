@@ -1096,10 +1096,12 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         const uint32_t* n_dev = c->d_nrows + L;
         const bool next = L + 1 < c->max_levels;
         uint32_t* n_out = c->d_nrows + L + 1;
-        // the rows level L - 1 made are noted against this buffer here, and
-        // the next level's row counter starts at zero
+        // the rows level L - 1 made (the start rows at level 0) are noted
+        // against this buffer here, and the next level's row counter starts
+        // at zero
         mn_launch_level_range(g, rows_view(c, L), (uint32_t)n_max, n_dev, L, B.lo, B.cnt, po.stats, c->d_err, s,
-                              next ? n_out : nullptr, L ? c->d_zr + c->note_rows(po.phase, L - 1) : nullptr);
+                              next ? n_out : nullptr,
+                              c->d_zr + (L ? c->note_rows(po.phase, L - 1) : c->note_seed(po.phase)));
         // candidates are bounded by the tile buffer and the grid only; rows
         // past the next level's buffer are counted and noted
         const uint64_t K = c->cand_k;
@@ -1173,8 +1175,8 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
             if (decide)
                 mn_launch_decide(g, rows_view(c, 0), slots + s0, (uint32_t)c->cap_dec,
                                  (uint32_t)std::min<double>((double)c->cap_dec, per_slot * (double)ns + 1.0), p, s);
-            mn_launch_note_count(c->d_nrows, c->lvb[0].cap, c->d_zr + c->note_seed(p), s);
             if (host_chunks) {
+                mn_launch_note_count(c->d_nrows, c->lvb[0].cap, c->d_zr + c->note_seed(p), s);
                 const uint64_t n0 = read_u32(c, c->d_nrows);
                 process_level(c, g, po, 0, n0);
             } else {
