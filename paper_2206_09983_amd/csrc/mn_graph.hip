@@ -155,6 +155,32 @@ __global__ __launch_bounds__(MN_BLOCK) void k_reindex(GraphView g, const DebiBit
     }
 }
 
+// Lower bounds of k1 <= k2 in sorted a[lo, hi), searched in lockstep: each
+// step issues both loads before either is used.
+__device__ inline void lower_bounds2(const uint64_t* __restrict__ a, uint32_t lo, uint32_t hi, uint64_t k1,
+                                     uint64_t k2, uint32_t& r1, uint32_t& r2) {
+    uint32_t l1 = lo, h1 = hi, l2 = lo, h2 = hi;
+    while (l1 < h1 || l2 < h2) {
+        const bool g1 = l1 < h1, g2 = l2 < h2;
+        const uint32_t m1 = (l1 + h1) >> 1, m2 = (l2 + h2) >> 1;
+        const uint64_t v1 = g1 ? a[m1] : 0ull, v2 = g2 ? a[m2] : 0ull;
+        if (g1) {
+            if (v1 < k1)
+                l1 = m1 + 1;
+            else
+                h1 = m1;
+        }
+        if (g2) {
+            if (v2 < k2)
+                l2 = m2 + 1;
+            else
+                h2 = m2;
+        }
+    }
+    r1 = l1;
+    r2 = l2;
+}
+
 // Per vertex: its run of batch entries [bs, be) in bk and of deleted positions
 // [ds, de) in dpos, and its offset in the merged adjacency. Four threads first
 // bound the block's 256 vertices in both sorted arrays, so that every
@@ -181,15 +207,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(MergeSide m0, MergeSid
     const uint32_t v = v0 + tid;
     if (v >= nv || failed(err)) return;
     uint32_t bs = s_w[0], be = s_w[0], ds = s_w[2], de = s_w[2];
-    if (s_w[0] < s_w[1]) {
-        bs = lower_bound_dev<uint64_t>(bk, s_w[0], s_w[1], kbase + ((uint64_t)v << hb));
-        be = lower_bound_dev<uint64_t>(bk, bs, s_w[1], kbase + ((uint64_t)(v + 1) << hb));
-    }
     const uint32_t o0 = off[v], o1 = off[v + 1];
-    if (s_w[2] < s_w[3]) {
-        ds = lower_bound_dev<uint64_t>(dpos, s_w[2], s_w[3], dbase + o0);
-        de = lower_bound_dev<uint64_t>(dpos, ds, s_w[3], dbase + o1);
-    }
+    if (s_w[0] < s_w[1])
+        lower_bounds2(bk, s_w[0], s_w[1], kbase + ((uint64_t)v << hb), kbase + ((uint64_t)(v + 1) << hb), bs, be);
+    if (s_w[2] < s_w[3]) lower_bounds2(dpos, s_w[2], s_w[3], dbase + o0, dbase + o1, ds, de);
     m.newoff[v] = o0 - ds + bs;
     m.meta[v] = make_uint4(bs, be - bs, ds, de - ds);
     if (v == nv - 1) m.newoff[nv] = e_old - n_d + n_b;
