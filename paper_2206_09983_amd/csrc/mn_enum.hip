@@ -20,8 +20,11 @@
 //                  closing edges found); 2-vertex queries emit here
 //   k_decide       (learned scheduler, traces) the matching order of each row
 //   k_level_range  per row, the candidate run [lo, lo + cnt) of the level
-//   scan           u64 offsets of the runs (flattened candidate space)
-//   k_partition    the first row of every expansion tile
+//   scan           u64 offsets of the runs (flattened candidate space); with
+//                  k_offsets_partition the offsets, the candidate total and
+//                  the first row of every expansion tile in one more launch
+//   k_partition    the first row of every expansion tile (levels too wide
+//                  for k_offsets_partition, and host-walked chunks)
 //   k_expand       one lane per candidate: filters, closing edges, temporal
 //                  order, then a new row for the next level or, at the plan's
 //                  last level, the embeddings themselves

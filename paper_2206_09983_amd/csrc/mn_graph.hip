@@ -9,8 +9,10 @@
 //   k_ingest       slot allocation (recycled slots first), attribute writes,
 //                  edgeMatcher -> DEBI words, counter increments, sort keys
 //   k_vertex_meta  per-vertex new offsets of the merged adjacency
-//   k_merge_old/new  merged, sorted adjacency: old entries minus the deleted
-//                  ones, plus the batch entries (flagged)
+//   k_merge_new/limits/old  merged, sorted adjacency: the batch entries
+//                  (flagged) at their insertion points, the counts at every
+//                  tile start of the old array, then the old entries minus
+//                  the deleted ones (both directions in each launch)
 //   k_vf_refresh   per-vertex local filters (f2/f3 of Section V-A) as VF bits
 //   k_flag_del     locate and flag the deletion batch's adjacency entries
 //   k_finalize     retire deleted keys, push their slots on the free stack
