@@ -426,29 +426,29 @@ __global__ __launch_bounds__(MN_BLOCK) void k_set_flags(uint64_t* adj0, const ui
     *lo = set ? (*lo | MN_FLAG) : (*lo & MN_SLOTMASK);
 }
 
+// blockIdx.y is the direction: both directions' searches run side by side.
 __global__ __launch_bounds__(MN_BLOCK) void k_flag_del(GraphView g, uint64_t* adj_out, uint64_t* adj_in,
                                                        BatchView b) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t dir = blockIdx.y;
     if (i >= b.n_del || failed(b.err)) return;
-    uint64_t k = b.del_keys[i];
-    uint32_t slot = b.key2slot[k];
-    b.del_slot[i] = slot;
-    uint32_t s = g.s_src[slot], d = g.s_dst[slot], l = g.s_lab[slot];
-    for (uint32_t dir = 0; dir < 2; dir++) {
-        uint32_t v = dir ? d : s;
-        uint32_t h = (l << g.nbr_bits) | (dir ? s : d);
-        uint64_t* adj = dir ? adj_in : adj_out;
-        uint32_t end = g.off[dir][v + 1];
-        uint32_t pos = lower_hi(adj, g.off[dir][v], end, h);
-        uint32_t* w = reinterpret_cast<uint32_t*>(adj);
-        while (pos < end && (w[2 * (size_t)pos] & MN_SLOTMASK) != slot) pos++;  // the run holds this slot
-        if (pos == end) {  // internal inconsistency: never expected
-            set_err(b.err, MN_ERR_INTERNAL);
-            return;
-        }
-        w[2 * (size_t)pos] |= MN_FLAG;
-        b.delpos[dir][i] = pos;
+    const uint64_t k = b.del_keys[i];
+    const uint32_t slot = b.key2slot[k];
+    if (dir == 0) b.del_slot[i] = slot;
+    const uint32_t s = g.s_src[slot], d = g.s_dst[slot], l = g.s_lab[slot];
+    const uint32_t v = dir ? d : s;
+    const uint32_t h = (l << g.nbr_bits) | (dir ? s : d);
+    uint64_t* adj = dir ? adj_in : adj_out;
+    const uint32_t end = g.off[dir][v + 1];
+    uint32_t pos = lower_hi(adj, g.off[dir][v], end, h);
+    uint32_t* w = reinterpret_cast<uint32_t*>(adj);
+    while (pos < end && (w[2 * (size_t)pos] & MN_SLOTMASK) != slot) pos++;  // the run holds this slot
+    if (pos == end) {  // internal inconsistency: never expected
+        set_err(b.err, MN_ERR_INTERNAL);
+        return;
     }
+    w[2 * (size_t)pos] |= MN_FLAG;
+    b.delpos[dir][i] = pos;
 }
 
 __global__ __launch_bounds__(MN_BLOCK) void k_finalize(BatchView b, uint32_t n_free_after) {
@@ -555,7 +555,7 @@ void mn_launch_set_flags(uint64_t* adj0, const uint32_t* pos0, uint64_t* adj1, c
 
 void mn_launch_flag_del(const GraphView& g, uint64_t* adj_out, uint64_t* adj_in, const BatchView& b,
                         hipStream_t s) {
-    if (b.n_del) k_flag_del<<<nblocks(b.n_del), MN_BLOCK, 0, s>>>(g, adj_out, adj_in, b);
+    if (b.n_del) k_flag_del<<<dim3(nblocks(b.n_del), 2), MN_BLOCK, 0, s>>>(g, adj_out, adj_in, b);
 }
 
 void mn_launch_finalize(const BatchView& b, uint32_t n_free_after, hipStream_t s) {
