@@ -384,6 +384,13 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vf_refresh(GraphView g, const VfBi
     constexpr uint32_t WPB = MN_BLOCK / 64;
     const uint32_t lane = threadIdx.x & 63, half = lane >> 5, j = lane & 31;
     const uint64_t n_pairs = ((uint64_t)n + 1) / 2, stride = (uint64_t)gridDim.x * WPB;
+    // the lane's bit of the first word and its first four requirements are
+    // the same for every vertex: loaded once, ahead of the vertex loads
+    const VfBit vb0 = j < n_bits ? bits[j] : VfBit{0, 0, 0};
+    VfReq q0[4];
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++)
+        q0[k] = vb0.req_begin + k < vb0.req_end ? g.vfreq[vb0.req_begin + k] : VfReq{0, 0};
     for (uint64_t pair = (uint64_t)blockIdx.x * WPB + threadIdx.x / 64; pair < n_pairs; pair += stride) {
         const uint64_t i = 2 * pair + half;
         const bool live = i < n;
@@ -394,14 +401,16 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vf_refresh(GraphView g, const VfBi
             const uint32_t bit = w * 32 + j;
             bool ok = false;
             if (live && bit < n_bits) {
-                const VfBit vb = bits[bit];
+                const VfBit vb = w ? bits[bit] : vb0;
                 ok = (vb.vreq & ~mv) == 0;
                 // four requirements per step, their loads issued together
                 for (uint32_t r = vb.req_begin; ok && r < vb.req_end; r += 4) {
+                    const bool first = w == 0 && r == vb.req_begin;
                     VfReq q[4];
                     uint32_t have[4];
 #pragma unroll
-                    for (uint32_t k = 0; k < 4; k++) q[k] = r + k < vb.req_end ? g.vfreq[r + k] : VfReq{0, 0};
+                    for (uint32_t k = 0; k < 4; k++)
+                        q[k] = first ? q0[k] : r + k < vb.req_end ? g.vfreq[r + k] : VfReq{0, 0};
 #pragma unroll
                     for (uint32_t k = 0; k < 4; k++) have[k] = r + k < vb.req_end ? c[q[k].cnt] : 0u;
 #pragma unroll
