@@ -372,3 +372,116 @@ def test_equal_or_missing_ranks_change_nothing():
                 np.testing.assert_array_equal(o.result(1, ph), o.result(0, ph))
                 np.testing.assert_array_equal(o.result(2, ph), o.result(0, ph))
         o.close()
+
+
+# ---------------------------------------------------------------- work units
+def _units_of_phase(o, qi, keys, n_qe, mode):
+    """Per work unit (edge key at position j) lists of one phase, by orc_seed."""
+    out = []
+    for k in keys:
+        for j in range(n_qe):
+            rows, ovf = o.seed(qi, int(k), j, mode)
+            assert ovf == 0
+            out.append((int(k), j, rows))
+    return out
+
+
+def _check_units(units, batch_keys, expect, n_qe):
+    """Section VI's exactly-once argument, stated on the lists themselves:
+    every tuple of unit (k, j) maps q_j to k and uses no batch edge at a
+    position before j; the units' lists are disjoint, and their union is the
+    phase's list `expect` (sorted)."""
+    batch = {int(x) for x in batch_keys}
+    seen = set()
+    total = 0
+    for k, j, rows in units:
+        for r in rows.tolist():
+            assert r[j] == k
+            assert not any(r[i] in batch for i in range(j))
+            t = tuple(r)
+            assert t not in seen  # disjoint units
+            seen.add(t)
+            total += 1
+    assert total == len(expect)
+    assert sorted(seen) == [tuple(r) for r in expect.tolist()]
+
+
+def _per_unit_stream(case, ref_lists):
+    """Walks the stream with insert(enumerate=False) + per-unit seeds (mode
+    1), then mark + per-unit seeds (mode 2); ref_lists[qi][bi] = (new,
+    expired) sorted arrays to compare the unions with."""
+    qs = case["queries"]
+    o = Oracle(case["graph"], qs)
+    checked = 0
+    for bi, b in enumerate(case["batches"]):
+        first = o.insert(b, enumerate=False)
+        ins_keys = range(first, first + len(b["src"]))
+        for qi, q in enumerate(qs):
+            m = len(q["qsrc"])
+            _check_units(_units_of_phase(o, qi, ins_keys, m, 1), ins_keys, ref_lists[qi][bi][0], m)
+            checked += len(ref_lists[qi][bi][0])
+        dk = [int(x) for x in b["del_keys"]]
+        o.mark(dk)
+        for qi, q in enumerate(qs):
+            m = len(q["qsrc"])
+            _check_units(_units_of_phase(o, qi, dk, m, 2), dk, ref_lists[qi][bi][1], m)
+            checked += len(ref_lists[qi][bi][1])
+        # unmarking takes the mask away: a deleted key seeded with mode 2 now
+        # sees the same embeddings as with no mask at all
+        o.unmark(dk)
+        for qi, q in enumerate(qs):
+            for k in dk:
+                for j in range(len(q["qsrc"])):
+                    np.testing.assert_array_equal(o.seed(qi, k, j, 2)[0], o.seed(qi, k, j, 0)[0])
+        o.delete(dk, enumerate=False)
+    o.close()
+    return checked
+
+
+def test_work_units_partition_the_phase_lists_tiny():
+    # Reference: brute force over every vertex map (independent of the
+    # oracle's phase code), on tiny multigraph streams, iso and homo.
+    checked = 0
+    for seed in range(40):
+        case = synth.tiny_case(seed)
+        refs = []
+        for q in case["queries"]:
+            m = len(q["qsrc"])
+            refs.append([(brute.as_array(n, m), brute.as_array(e, m))
+                         for n, e in brute.run_stream(case["graph"], case["batches"], q)])
+        checked += _per_unit_stream(case, refs)
+    assert checked > 20
+
+
+def test_work_units_partition_the_phase_lists_small_rmat():
+    # Reference: the phase lists of a second oracle, which the recompute
+    # invariant pins on this same stream.
+    case = synth.rmat_case(scale=9, n_init=3000, n_stream=256, batch=128, n_batches=2, n_vlabels=3, n_elabels=4)
+    o = Oracle(case["graph"], case["queries"])
+    refs = [[] for _ in case["queries"]]
+    for b in case["batches"]:
+        o.apply_batch(b)
+        for qi in range(len(case["queries"])):
+            refs[qi].append((o.result(qi), o.result(qi, True)))
+    o.close()
+    assert _per_unit_stream(case, refs) > 10000
+
+
+def test_mark_rejects_bad_keys_and_changes_nothing():
+    case = synth.tiny_case(3, max_init=8)
+    g = case["graph"]
+    o = Oracle(g, case["queries"])
+    n0 = len(g["src"])
+    assert n0 >= 2
+    for bad in ([0, 0], [n0 + 5], [1, n0 + 5]):
+        with pytest.raises(ValueError):
+            o.mark(bad)
+        # nothing stays marked: mode 2 masks nothing, so every unit sees the
+        # same embeddings as without a mask
+        for k in range(n0):
+            for j in range(len(case["queries"][0]["qsrc"])):
+                np.testing.assert_array_equal(o.seed(0, k, j, 2)[0], o.seed(0, k, j, 0)[0])
+    o.delete([0], enumerate=False)
+    with pytest.raises(ValueError):
+        o.mark([0])  # no longer live
+    o.close()
