@@ -115,7 +115,8 @@ typedef struct {
     uint64_t rows_per_level; /* partial embeddings one search level may hold (bounds the
                                 enumerator's memory; larger fan-outs are processed in
                                 chunks; buffers grow on demand up to it); 0 = 2^25,
-                                minimum 1024 */
+                                minimum 1024, maximum 2^26 (larger values are
+                                lowered to it) */
 } mnemonic_options;
 
 /* Result of the last successful mnemonic_apply_batch for one query.

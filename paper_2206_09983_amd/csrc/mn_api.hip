@@ -1780,7 +1780,9 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         HIPCHK(hipGetDevice(&c->device));
         c->stream = static_cast<hipStream_t>(hip_stream);
         if (opt) c->flags = opt->flags;
-        if (opt && opt->rows_per_level) c->rows_max = std::max<uint64_t>(1024, opt->rows_per_level);
+        // at most 2^26 rows per level: the kernels index a level's columns in 32 bits
+        if (opt && opt->rows_per_level)
+            c->rows_max = std::min<uint64_t>(1ull << 26, std::max<uint64_t>(1024, opt->rows_per_level));
         c->nV = g->n_vertices;
         c->n_elabels = g->n_elabels ? g->n_elabels : 256;
         c->nbr_bits = std::max<uint32_t>(1, ceil_log2(c->nV));

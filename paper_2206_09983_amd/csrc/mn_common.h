@@ -27,6 +27,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #define MN_MAXQV 16
@@ -89,22 +90,24 @@ struct CloseDesc {
 // classes that can satisfy vtx's label requirement), or the whole list when
 // the anchor label is a wildcard. Closing edges close[c_begin, c_end) join
 // vtx to vertices mapped earlier.
-struct LevelDesc {
+// 16 bytes, 16-byte aligned: the expansion kernel reads a level with one load.
+struct alignas(16) LevelDesc {
     uint8_t vtx;
     uint8_t qe;
     uint8_t from;
-    uint8_t dir;
-    uint8_t masked;
     uint8_t c_begin;
     uint8_t c_end;
-    uint8_t n_mapped;  // query vertices mapped before this level (start pair + earlier levels)
-    uint8_t whole;     // wildcard anchor label: every entry of the list is a candidate
-    uint8_t empty;     // no vertex class satisfies vtx's labels: no candidates
-    uint8_t need_vf;   // candidates must pass the vertex-filter bit of vtx
+    uint8_t n_mapped;     // query vertices mapped before this level (start pair + earlier levels)
+    uint8_t dir : 1;
+    uint8_t masked : 1;
+    uint8_t whole : 1;    // wildcard anchor label: every entry of the list is a candidate
+    uint8_t empty : 1;    // no vertex class satisfies vtx's labels: no candidates
+    uint8_t need_vf : 1;  // candidates must pass the vertex-filter bit of vtx
     uint8_t pad;
-    uint32_t key_lo;   // inclusive bounds of the candidates' high words
+    uint32_t key_lo;      // inclusive bounds of the candidates' high words
     uint32_t key_hi;
 };
+static_assert(sizeof(LevelDesc) == 16, "one 16-byte load per level");
 
 // Matching order for one (query, start position j) pair (Section VI,
 // matching order computation): the start edge maps qa -> qb; closing edges
@@ -114,6 +117,8 @@ struct LevelDesc {
 // plan of the pair lists its n_var distinct orders (vars[0]: the static one).
 // All orders of a pair share the start-level closing edges, so a start row
 // may take any of them.
+// The first 16 bytes (the header) are read with one load by the expansion
+// kernel; `mapped` and `close_idx` are 16-byte aligned for the same reason.
 struct SeedPlan {
     uint16_t q;        // query index
     uint8_t j;         // start position
@@ -124,22 +129,25 @@ struct SeedPlan {
     uint8_t sem;
     uint8_t n_close;
     uint8_t n_var;       // distinct matching orders of this (query, j) pair
-    uint8_t variant;     // which of them this plan is
+    uint8_t temporal;    // some pair of edges is ordered in time
     uint32_t vf_base;    // first vertex-filter bit of the query
-    uint32_t debi_base;  // first edgeMatcher bit of the query
     uint8_t mapped[MN_MAXQV];     // query vertices in mapping order: qa, qb, level vtx...
     uint8_t close_idx[MN_MAXQE];  // per query edge: index into close[], or 0xFF for a tree edge
+    uint32_t debi_base;  // first edgeMatcher bit of the query
+    uint8_t variant;     // which order of the pair this plan is
+    uint8_t n_ranked;    // edges with a temporal rank
+    uint8_t pad1[10];
     LevelDesc lv[MN_MAXLV];
     CloseDesc close[MN_MAXCLOSE];
     uint16_t vars[MN_NVAR];       // plan index of each order of the pair
     int8_t rank[MN_MAXQE];        // temporal rank per query edge (-1: unordered)
     uint8_t rorder[MN_MAXQE];     // the ranked edges by ascending rank
-    uint8_t n_ranked;             // their number
-    uint8_t temporal;             // some pair of edges is ordered in time
-    uint8_t pad2[2];
     float lv_est[MN_MAXLV];       // log2(1 + expected candidates per row) of each level, from the
                                   // initial graph's label degrees and the level's class range
 };
+static_assert(offsetof(SeedPlan, temporal) == 11 && offsetof(SeedPlan, vf_base) == 12, "plan header");
+static_assert(offsetof(SeedPlan, mapped) == 16 && offsetof(SeedPlan, close_idx) == 32, "aligned plan arrays");
+static_assert(offsetof(SeedPlan, lv) % 16 == 0 && sizeof(SeedPlan) % 16 == 0, "aligned levels");
 
 // Partial embeddings between levels, stored column-wise (row r of column c at
 // col[c * cap + r]): column 0 the plan index, 1 + u the data vertex of query
@@ -204,6 +212,12 @@ struct GraphView {
     const int16_t* elab_idx;   // [256] compact index of an edge label, -1 if unused
     const int16_t* vlab_idx;   // [64] compact index of a vertex label bit, -1 if unused
     const uint32_t* ext2int;   // [n_vertices] caller's vertex id -> internal id
+    // The arrays of direction d. A select between the two kernel-argument
+    // pointers, not an index into the argument struct: a lane-dependent index
+    // into a by-value struct makes the compiler load the pointer from memory.
+    __device__ const uint32_t* offs(uint32_t d) const { return d ? off[1] : off[0]; }
+    __device__ const uint64_t* adjs(uint32_t d) const { return d ? adj[1] : adj[0]; }
+    __device__ const uint64_t* keys(uint32_t d) const { return d ? adjk[1] : adjk[0]; }
     int64_t* key_ts;           // key -> timestamp of every edge ever inserted (never invalidated:
                                // a re-run of a phase may still meet edges its batch deleted)
     uint32_t n_elab_c;         // compact edge labels

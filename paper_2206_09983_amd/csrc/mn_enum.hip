@@ -65,14 +65,38 @@ __device__ inline uint64_t shfl64(uint64_t x, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Wave sums through DPP lane moves (no LDS traffic): pairs and quads by quad
+// permutes, rows of 16 by the half-row and row mirrors, then row 0's total
+// into row 1 and row 2's into row 3 (row_bcast:15), rows 0-1 into rows 2-3
+// (row_bcast:31); lane 63 ends with the wave's total, read back uniformly.
+// Every lane of the wave must be active.
+#define MN_DPP_STEPS(STEP) \
+    STEP(0xB1, 0xF)        \
+    STEP(0x4E, 0xF)        \
+    STEP(0x141, 0xF)       \
+    STEP(0x140, 0xF)       \
+    STEP(0x142, 0xA)       \
+    STEP(0x143, 0xC)
+
+__device__ inline uint32_t wave_sum32(uint32_t x) {
+#define MN_STEP32(ctrl, rows) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, ctrl, rows, 0xF, false);
+    MN_DPP_STEPS(MN_STEP32)
+#undef MN_STEP32
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 __device__ inline uint64_t wave_sum64(uint64_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        uint32_t lo = __shfl_xor((uint32_t)x, d, MN_WAVE);
-        uint32_t hi = __shfl_xor((uint32_t)(x >> 32), d, MN_WAVE);
-        x += ((uint64_t)hi << 32) | lo;
+#define MN_STEP64(ctrl, rows)                                                                          \
+    {                                                                                                  \
+        const uint32_t lo_ = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, ctrl, rows, 0xF, false); \
+        const uint32_t hi_ = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), ctrl, rows, 0xF, false); \
+        x += ((uint64_t)hi_ << 32) | lo_;                                                              \
     }
-    return x;
+    MN_DPP_STEPS(MN_STEP64)
+#undef MN_STEP64
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Exclusive prefix sum over the wave (all 64 lanes must take part).
@@ -89,23 +113,21 @@ __device__ inline uint64_t wave_excl_scan64(uint64_t x, uint64_t& total) {
     return incl - x;
 }
 
+// Vertices < 2^24 and at most 128 filter words (256 queries x 16 vertices)
+// keep the index below 2^31.
 __device__ inline bool vf_bit(const GraphView& g, uint32_t v, uint32_t bit) {
-    return (g.vf[(size_t)v * g.vf_words + (bit >> 5)] >> (bit & 31)) & 1u;
+    return (g.vf[v * g.vf_words + (bit >> 5)] >> (bit & 31)) & 1u;
 }
 
-__device__ inline uint32_t rcol(const RowsView& R, uint32_t c, uint32_t r) {
-    return R.col[(size_t)c * R.cap + r];
-}
+// Column c of row r. The library keeps a level's rows at most 2^26 and its
+// columns at most 50, so c * cap + r fits in 32 bits.
+__device__ inline uint32_t rcol(const RowsView& R, uint32_t c, uint32_t r) { return R.col[c * R.cap + r]; }
 
-__device__ inline void wcol(const RowsView& R, uint32_t c, uint32_t r, uint32_t v) {
-    R.col[(size_t)c * R.cap + r] = v;
-}
+__device__ inline void wcol(const RowsView& R, uint32_t c, uint32_t r, uint32_t v) { R.col[c * R.cap + r] = v; }
 
-__device__ inline uint64_t rkey(const RowsView& R, uint32_t k, uint32_t r) { return R.kcol[(size_t)k * R.cap + r]; }
+__device__ inline uint64_t rkey(const RowsView& R, uint32_t k, uint32_t r) { return R.kcol[k * R.cap + r]; }
 
-__device__ inline void wkey(const RowsView& R, uint32_t k, uint32_t r, uint64_t v) {
-    R.kcol[(size_t)k * R.cap + r] = v;
-}
+__device__ inline void wkey(const RowsView& R, uint32_t k, uint32_t r, uint64_t v) { R.kcol[k * R.cap + r] = v; }
 
 // Per-lane work tallies of one launch (32 bits suffice per lane and launch).
 struct Cnt {
@@ -141,9 +163,10 @@ __device__ void acc_init(BlockAcc& A, uint32_t n_dig, const uint32_t* err) {
 // Every thread of the block must call it.
 __device__ void acc_flush(BlockAcc& A, const Cnt& K, uint32_t n_dig, EnumStats* stats,
                           unsigned long long* digest) {
-    const uint64_t v[8] = {wave_sum64(K.seeds), wave_sum64(K.entries), wave_sum64(K.probes),
-                           wave_sum64(K.range_probes), wave_sum64(K.keys), wave_sum64(K.tuples),
-                           wave_sum64(K.vf), wave_sum64(K.rows)};
+    // a lane's tallies of one launch fit in 32 bits, and so do a wave's
+    const uint32_t v[8] = {wave_sum32(K.seeds), wave_sum32(K.entries), wave_sum32(K.probes),
+                           wave_sum32(K.range_probes), wave_sum32(K.keys), wave_sum32(K.tuples),
+                           wave_sum32(K.vf), wave_sum32(K.rows)};
     if (__lane_id() == 0) {
 #pragma unroll
         for (int i = 0; i < 8; i++)
@@ -237,13 +260,15 @@ struct Bind {
 __device__ uint32_t close_find(const GraphView& g, const CloseDesc& c, uint32_t fo, uint32_t fn,
                                uint32_t& probes) {
     const uint32_t d0 = c.dir, d1 = 1u - c.dir;
-    const uint32_t a0 = g.off[d0][fo], a1 = g.off[d0][fo + 1];
-    const uint32_t b0 = g.off[d1][fn], b1 = g.off[d1][fn + 1];
+    const uint32_t* oa = g.offs(d0);
+    const uint32_t* ob = g.offs(d1);
+    const uint32_t a0 = oa[fo], a1 = oa[fo + 1];
+    const uint32_t b0 = ob[fn], b1 = ob[fn + 1];
     probes += 4;
     const bool sw = (b1 - b0) < (a1 - a0);
     const uint32_t dir = sw ? d1 : d0;
     const uint32_t s0 = sw ? b0 : a0, s1 = sw ? b1 : a1, tgt = sw ? fo : fn;
-    const uint64_t* adj = g.adj[dir];
+    const uint64_t* adj = g.adjs(dir);
     const uint32_t flag = sw ? RUN_SWAP : 0u;
     if (c.label >= 0) {
         const uint32_t key = ((uint32_t)c.label << g.nbr_bits) | tgt;
@@ -278,10 +303,10 @@ __device__ inline RunIt run_open(const GraphView& g, const CloseDesc& c, uint32_
     const bool sw = (st & RUN_SWAP) != 0;
     const uint32_t dir = sw ? 1u - c.dir : (uint32_t)c.dir;
     const uint32_t x = sw ? fn : fo;
-    it.adj = g.adj[dir];
-    it.adjk = g.adjk[dir];
+    it.adj = g.adjs(dir);
+    it.adjk = g.keys(dir);
     it.p = st & ~RUN_SWAP;
-    it.end = g.off[dir][x + 1];
+    it.end = g.offs(dir)[x + 1];
     it.tgt = sw ? fo : fn;
     it.lab = c.label >= 0;
     it.key = it.lab ? (((uint32_t)c.label << g.nbr_bits) | it.tgt) : 0u;
@@ -818,13 +843,14 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
         uint32_t a = 0, b = 0;
         if (!lv.empty) {
             const uint32_t x = rcol(R, 1 + lv.from, r);
-            const uint32_t s0 = g.off[lv.dir][x], s1 = g.off[lv.dir][x + 1];
+            const uint32_t* of = g.offs(lv.dir);
+            const uint32_t s0 = of[x], s1 = of[x + 1];
             K.range_probes += 2;
             if (lv.whole) {
                 a = s0;
                 b = s1;
             } else {
-                run_bounds_c(g.adj[lv.dir], s0, s1, lv.key_lo, lv.key_hi, a, b, K.range_probes);
+                run_bounds_c(g.adjs(lv.dir), s0, s1, lv.key_lo, lv.key_hi, a, b, K.range_probes);
             }
         }
         lo[r] = a;
@@ -948,12 +974,107 @@ __global__ __launch_bounds__(MN_BLOCK) void k_offsets_partition(const uint32_t* 
 
 constexpr uint32_t NO_LOC = 0xFFFFFFFFu;
 
-// One block tests a tile of 256 x ITEMS candidates in two passes. Pass 1 runs the
-// filters and gives every survivor a place inside the block (LDS counters per
-// query for embeddings, one for new rows); one global atomic per query and
-// block then reserves the block's places; pass 2 writes rows and embeddings.
-// Contended device-scope atomics (they serialise across the XCDs) drop from
-// one per wave and item to one per block.
+// The fields of a plan the expansion reads for every candidate, from one
+// 16-byte load of the plan's header.
+struct PlanHead {
+    uint32_t q, n_qe, n_levels, sem, n_close, temporal, vf_base;
+};
+
+__device__ inline PlanHead plan_head(const SeedPlan* P) {
+    const uint4 h = *reinterpret_cast<const uint4*>(P);
+    PlanHead H;
+    H.q = h.x & 0xFFFFu;
+    H.n_qe = h.x >> 24;
+    H.n_levels = (h.y >> 16) & 0xFFu;
+    H.sem = h.z & 0xFFu;
+    H.n_close = (h.z >> 8) & 0xFFu;
+    H.temporal = h.z >> 24;
+    H.vf_base = h.w;
+    return H;
+}
+
+// Level L of plan P, one 16-byte load.
+__device__ inline LevelDesc load_level(const SeedPlan* P, uint32_t L) {
+    return __builtin_bit_cast(LevelDesc, *reinterpret_cast<const uint4*>(&P->lv[L]));
+}
+
+// Byte i (< 16) of a 16-byte vector.
+__device__ inline uint32_t byte_of(const uint4& v, uint32_t i) {
+    const uint32_t w = i < 8 ? (i < 4 ? v.x : v.y) : (i < 12 ? v.z : v.w);
+    return (w >> (8 * (i & 3))) & 0xFFu;
+}
+
+// Exclusive count of the set bits of `mask` below this lane.
+__device__ inline uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Largest a in [0, span) with s_off[a] <= t (s_off[0] <= t is required), and
+// s_off[a] itself, searched in LDS.
+__device__ inline uint32_t row_in_lds(const uint64_t* s_off, uint32_t span, uint64_t t, uint64_t& o) {
+    uint32_t a = 0, b = span;
+    uint64_t oa = s_off[0];
+    while (a + 1 < b) {
+        const uint32_t m = (a + b) >> 1;
+        const uint64_t om = s_off[m];
+        if (om <= t) {
+            a = m;
+            oa = om;
+        } else {
+            b = m;
+        }
+    }
+    o = oa;
+    return a;
+}
+
+// The same over global offsets [lo, hi) (tiles whose rows do not fit in LDS).
+__device__ inline uint32_t row_in_global(const uint64_t* off, uint32_t a, uint32_t b, uint64_t t, uint64_t& o) {
+    uint64_t oa = off[a];
+    while (a + 1 < b) {
+        const uint32_t m = (a + b) >> 1;
+        const uint64_t om = off[m];
+        if (om <= t) {
+            a = m;
+            oa = om;
+        } else {
+            b = m;
+        }
+    }
+    o = oa;
+    return a;
+}
+
+// Digests of one complete mapping with a single embedding whose query edges
+// other than the anchor aqe are all tree edges (no closing edge, no temporal
+// order): the tuple is the row's tree keys with akey at aqe. Writes it at
+// place pos when emitting.
+__device__ inline void emit_tree_tuple(const RowsView& R, uint32_t r, uint32_t nqe, uint32_t aqe, uint64_t akey,
+                                       uint64_t hA, uint64_t hB, uint64_t* row, bool write, Cnt& K,
+                                       uint64_t& dA, uint64_t& dB) {
+    for (uint32_t k = 0; k < nqe; k++) {
+        const uint64_t key = k == aqe ? akey : rkey(R, k, r);
+        hA = mn_mix64(hA + key);
+        hB = mn_mix64(hB + key);
+        if (write) row[k] = key;
+    }
+    K.keys += nqe;
+    K.tuples++;
+    dA += hA;
+    dB += hB;
+}
+
+// One block tests a tile of 256 x ITEMS candidates in two passes. Pass 1 runs
+// the filters and gives every survivor a place inside the block (LDS counters
+// per query for embeddings, one for new rows); one global atomic per query
+// and block then reserves the block's places; pass 2 writes rows and
+// embeddings. Contended device-scope atomics (they serialise across the XCDs)
+// drop from one per wave and item to one per block.
+// What pass 1 learns about a candidate (its row, entry position, neighbour
+// and closing-run starts) waits in LDS for pass 2. Each lane keeps the
+// digests of the embeddings it emits in registers and the block reduces them
+// once; waves whose survivors each have one embedding of one query take their
+// places with a ballot count instead of a scan.
 template <int NC, bool ROWS, bool EMIT, uint32_t ITEMS>
 __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, uint32_t n_in,
                                                      const uint32_t* __restrict__ lo,
@@ -967,7 +1088,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     constexpr uint32_t EX_LDS_ROWS = EX_TILE + 1;
     __shared__ uint64_t s_off[EX_LDS_ROWS];
     __shared__ BlockAcc A;
-    __shared__ uint32_t s_r[EX_TILE], s_p[EX_TILE], s_loc[EX_TILE];
+    __shared__ uint32_t s_r[EX_TILE], s_p[EX_TILE], s_loc[EX_TILE], s_w[EX_TILE];
     __shared__ uint32_t s_st[NA][EX_TILE];
     __shared__ unsigned long long s_qn[MAXQ];  // places per query: counts, then global bases
     __shared__ uint32_t s_nrows, s_rbase;
@@ -1001,49 +1122,40 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
         bool ok = t < t1 && !A.dead;
         uint32_t r = 0, w = 0, p = 0;
         LevelDesc lv = {};
+        PlanHead H = {};
         uint32_t st[NA];
 #pragma unroll
         for (uint32_t c = 0; c < NA; c++) st[c] = 0;
         const SeedPlan* P = g.plans;
         if (ok) {
             uint64_t o;
-            if (staged) {  // largest r with off[r] <= t, searched in LDS
-                uint32_t a = 0, b = span;
-                while (a + 1 < b) {
-                    const uint32_t m = (a + b) >> 1;
-                    if (s_off[m] <= t)
-                        a = m;
-                    else
-                        b = m;
-                }
-                r = rlo + a;
-                o = s_off[a];
-            } else {
-                r = row_of(off, rlo, rhi, t);
-                o = off[r];
-            }
+            r = staged ? rlo + row_in_lds(s_off, span, t, o) : row_in_global(off, rlo, rhi, t, o);
             P = &g.plans[rcol(in, 0, r)];
-            lv = P->lv[L];
-            p = lo[r] + (uint32_t)(t - o);
-            const uint64_t e = g.adj[lv.dir][p];
+            const uint32_t base = lo[r];
+            lv = load_level(P, L);
+            H = plan_head(P);
+            p = base + (uint32_t)(t - o);
+            const uint64_t e = g.adjs(lv.dir)[p];
             K.entries++;
             w = ent_hi(e) & g.nbr_mask;
             if (lv.masked && (ent_lo(e) & MN_FLAG)) ok = false;
             if (ok && lv.need_vf) {
                 K.vf++;
-                ok = vf_bit(g, w, P->vf_base + lv.vtx);
+                ok = vf_bit(g, w, H.vf_base + lv.vtx);
             }
-            if (ok && P->sem == MN_SEM_ISO) {
-                for (uint32_t m = 0; m < lv.n_mapped; m++)
-                    if (rcol(in, 1 + P->mapped[m], r) == w) {
-                        ok = false;
-                        break;
-                    }
+            if (ok && H.sem == MN_SEM_ISO) {
+                // the images of the mapped query vertices, loaded together
+                const uint4 mv = *reinterpret_cast<const uint4*>(P->mapped);
+                bool clash = false;
+#pragma unroll
+                for (uint32_t m = 0; m < MN_MAXQV; m++)
+                    if (m < lv.n_mapped) clash |= rcol(in, 1 + byte_of(mv, m), r) == w;
+                ok = !clash;
             }
-            if (ok && P->temporal && P->rank[lv.qe] >= 0) {
+            if (ok && H.temporal && P->rank[lv.qe] >= 0) {
                 // timestamps never decrease with keys, so the order of two
                 // tree edges' keys must agree with the order of their ranks
-                const uint64_t nk = g.adjk[lv.dir][p];
+                const uint64_t nk = g.keys(lv.dir)[p];
                 const int rn = P->rank[lv.qe];
                 for (uint32_t l = 0; l <= L && ok; l++) {
                     const uint32_t k = l == 0 ? P->j : P->lv[l - 1].qe;
@@ -1062,7 +1174,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                 }
             }
         }
-        const bool last = ok && (L + 1 == P->n_levels);
+        const bool last = ok && (L + 1 == H.n_levels);
         const bool to_row = ok && !last;
         uint32_t loc = NO_LOC;
         if (ROWS) {
@@ -1070,30 +1182,49 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
             uint32_t base = 0;
             if (__lane_id() == 0 && bal) base = atomicAdd(&s_nrows, (uint32_t)__popcll(bal));
             base = __shfl(base, 0, MN_WAVE);
-            if (to_row) loc = base + (uint32_t)__popcll(bal & lanemask_lt());
+            if (to_row) loc = base + lane_rank(bal);
         } else if (to_row) {
             set_err(err, MN_ERR_INTERNAL);  // the host launches ROWS wherever a plan continues
         }
         if (EMIT) {
             uint64_t mult = 0;
             if (last) {
-                Bind B;
-                B.R = in;
-                B.row = true;
-                B.r = r;
-                B.qa = B.fa = B.qb = B.fb = 0;
-                B.skey = 0;
-                B.cv = lv.vtx;
-                B.fw = w;
+                if (!H.temporal && (NC == 0 || H.n_close == 0)) {
+                    mult = 1;
+                } else {
+                    Bind B;
+                    B.R = in;
+                    B.row = true;
+                    B.r = r;
+                    B.qa = B.fa = B.qb = B.fb = 0;
+                    B.skey = 0;
+                    B.cv = lv.vtx;
+                    B.fw = w;
 #pragma unroll
-                for (uint32_t c = 0; c < NA; c++)
-                    if (c < (uint32_t)NC && c < P->n_close && !(c >= lv.c_begin && c < lv.c_end))
-                        st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
-                uint32_t cnt[NA];
-                mult = close_mult<NC>(g, *P, B, st, cnt, K.probes, lv.qe, P->temporal ? g.adjk[lv.dir][p] : 0ull);
+                    for (uint32_t c = 0; c < NA; c++)
+                        if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
+                            st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
+                    uint32_t cnt[NA];
+                    mult = close_mult<NC>(g, *P, B, st, cnt, K.probes, lv.qe,
+                                          H.temporal ? g.keys(lv.dir)[p] : 0ull);
+                }
             }
-            const uint64_t lpos = grouped_reserve(mult != 0, P->q, mult, s_qn);
-            if (mult) loc = (uint32_t)lpos;
+            const bool has = mult != 0;
+            const uint64_t hb = __ballot(has);
+            if (hb) {  // uniform
+                const uint32_t lead = (uint32_t)__ffsll((unsigned long long)hb) - 1;
+                const uint32_t qlead = (uint32_t)__builtin_amdgcn_readlane((int)H.q, (int)lead);
+                if (__ballot(has && (mult != 1 || H.q != qlead)) == 0) {
+                    // one embedding per survivor, one query: a ballot count
+                    unsigned long long b0 = 0;
+                    if (__lane_id() == lead) b0 = atomicAdd(&s_qn[qlead], (unsigned long long)__popcll(hb));
+                    const uint32_t basel = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b0, (int)lead);
+                    if (has) loc = basel + lane_rank(hb);
+                } else {
+                    const uint64_t lpos = grouped_reserve(has, H.q, mult, s_qn);
+                    if (has) loc = (uint32_t)lpos;
+                }
+            }
         } else if (last) {
             set_err(err, MN_ERR_INTERNAL);  // the host launches EMIT wherever a plan ends
         }
@@ -1101,6 +1232,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
             s_loc[idx] = loc;
             s_r[idx] = r;
             s_p[idx] = p;
+            s_w[idx] = w;
 #pragma unroll
             for (uint32_t c = 0; c < NA; c++) s_st[c][idx] = st[c];
         }
@@ -1114,30 +1246,23 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     __syncthreads();
 
     // ---- pass 2: write rows and embeddings at their places
+    uint32_t dq = MAXQ, sq = MAXQ;  // query of the lane's digest sums, and of its cached seeds
+    uint64_t dA = 0, dB = 0, s0A = 0, s0B = 0;
     for (uint32_t it = 0; it < ITEMS; it++) {
         const uint32_t idx = it * MN_BLOCK + threadIdx.x;
         const uint64_t t = t0 + idx;
         const uint32_t loc = t < t1 ? s_loc[idx] : NO_LOC;
-        const bool active = loc != NO_LOC;
-        uint32_t r = 0, w = 0;
-        uint64_t akey = 0;
-        LevelDesc lv = {};
-        lv.vtx = 0xFF;
-        lv.qe = 0xFF;
+        if (loc == NO_LOC) continue;
+        const uint32_t r = s_r[idx], w = s_w[idx], p = s_p[idx];
+        const SeedPlan* P = &g.plans[rcol(in, 0, r)];
+        const LevelDesc lv = load_level(P, L);
+        const PlanHead H = plan_head(P);
+        const uint64_t akey = g.keys(lv.dir)[p];
+        const bool last = L + 1 == H.n_levels;
         uint32_t st[NA];
 #pragma unroll
-        for (uint32_t c = 0; c < NA; c++) st[c] = active ? s_st[c][idx] : 0u;
-        const SeedPlan* P = g.plans;
-        if (active) {
-            r = s_r[idx];
-            P = &g.plans[rcol(in, 0, r)];
-            lv = P->lv[L];
-            const uint32_t p = s_p[idx];
-            w = ent_hi(g.adj[lv.dir][p]) & g.nbr_mask;
-            akey = g.adjk[lv.dir][p];
-        }
-        const bool last = active && (L + 1 == P->n_levels);
-        if (ROWS && active && !last) {
+        for (uint32_t c = 0; c < NA; c++) st[c] = s_st[c][idx];
+        if (ROWS && !last) {
             const uint32_t dst = s_rbase + loc;
             if (dst < out.cap) {
                 for (uint32_t c = 0; c < ncol; c++) wcol(out, c, dst, rcol(in, c, r));
@@ -1152,9 +1277,28 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                 K.rows++;
             }  // rows past the buffer are counted, not written: the host grows it and runs again
         }
-        if (EMIT) {
-            uint64_t dA = 0, dB = 0;
-            if (last) {
+        if (EMIT && last) {
+            const uint32_t q = H.q;
+            if (q != sq) {
+                sq = q;
+                s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
+                s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
+            }
+            if (q != dq) {  // the lane's sums so far belong to another query
+                if (dq != MAXQ) {
+                    atomicAdd(&A.dig[2 * dq], (unsigned long long)dA);
+                    atomicAdd(&A.dig[2 * dq + 1], (unsigned long long)dB);
+                }
+                dq = q;
+                dA = dB = 0;
+            }
+            const uint64_t pos = s_qn[q] + loc;
+            if (!H.temporal && (NC == 0 || H.n_close == 0)) {
+                const OutView& ov = po.outs[q];
+                const bool write = po.emit && pos < ov.cap[po.phase];
+                emit_tree_tuple(in, r, H.n_qe, lv.qe, akey, s0A, s0B, ov.keys[po.phase] + pos * H.n_qe, write, K,
+                                dA, dB);
+            } else {
                 Bind B;
                 B.R = in;
                 B.row = true;
@@ -1165,16 +1309,16 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                 B.fw = w;
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
-                    if (c < (uint32_t)NC && c < P->n_close && !(c >= lv.c_begin && c < lv.c_end))
+                    if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
                         st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
                 uint32_t cnt[NA];
                 uint32_t unused = 0;
                 const uint64_t mult = close_mult<NC>(g, *P, B, st, cnt, unused, lv.qe, akey);
-                emit_tuples<NC>(g, *P, B, st, cnt, mult, lv.qe, akey, s_qn[P->q] + loc, po, K, dA, dB);
+                emit_tuples<NC>(g, *P, B, st, cnt, mult, lv.qe, akey, pos, po, K, dA, dB);
             }
-            grouped_digest(last, P->q, dA, dB, A.dig);
         }
     }
+    if (EMIT) grouped_digest(dq != MAXQ, dq, dA, dB, A.dig);
     acc_flush(A, K, EMIT ? 2 * po.n_q : 0, po.stats, po.digest);
 }
 

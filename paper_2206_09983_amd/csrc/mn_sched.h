@@ -24,7 +24,7 @@ __device__ inline float log2p1(uint32_t v) { return __log2f(1.0f + (float)v); }
 // this is its candidate run before the restriction to the vertex classes
 // that can carry the new vertex's labels.
 __device__ inline uint32_t label_degree(const GraphView& g, uint32_t x, uint32_t dir, int32_t lab) {
-    if (lab < 0) return g.off[dir][x + 1] - g.off[dir][x];
+    if (lab < 0) return g.offs(dir)[x + 1] - g.offs(dir)[x];
     const int16_t e = g.elab_idx[lab];
     if (e < 0) return 0;
     return g.cnt[(size_t)x * g.n_cnt + cnt_index(dir, 1 + (uint32_t)e, g.n_elab_c, g.n_vlab_c)];
