@@ -194,6 +194,7 @@ struct mnemonic_ctx {
         uint32_t* lo = nullptr;
         uint32_t* cnt = nullptr;
         uint64_t* off = nullptr;
+        uint64_t* hpre = nullptr;  // 2 x cap digest prefixes of rows whose plan ends at this level
         uint64_t cap = 0;
     };
     std::vector<LevelBuf> lvb;
@@ -922,12 +923,14 @@ void grow_level(mnemonic_ctx* c, uint32_t L, uint64_t need) {
     dev_free(B.lo);
     dev_free(B.cnt);
     dev_free(B.off);
+    dev_free(B.hpre);
     B.cap = 0;
     dev_alloc(B.rows, nc * c->ncol());
     dev_alloc(B.keys, nc * c->we);
     dev_alloc(B.lo, nc);
     dev_alloc(B.cnt, nc);
     dev_alloc(B.off, nc);
+    dev_alloc(B.hpre, 2 * nc);
     B.cap = nc;
     uint64_t sw = mn_scan64_scratch_words((uint32_t)nc);
     if (sw > c->cap_scan64) {
@@ -947,6 +950,7 @@ RowsView rows_view(const mnemonic_ctx* c, uint32_t L) {
     if (L < c->lvb.size()) {
         R.col = c->lvb[L].rows;
         R.kcol = c->lvb[L].keys;
+        R.hpre = c->lvb[L].hpre;
         R.cap = (uint32_t)c->lvb[L].cap;
     }
     return R;
@@ -1732,6 +1736,7 @@ void free_all(mnemonic_ctx* c) {
         dev_free(B.lo);
         dev_free(B.cnt);
         dev_free(B.off);
+        dev_free(B.hpre);
     }
     dev_free(c->d_scan64);
     dev_free(c->d_nrows);
@@ -2053,6 +2058,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
             dev_free(B.lo);
             dev_free(B.cnt);
             dev_free(B.off);
+            dev_free(B.hpre);
         }
         c->lvb.assign(c->max_levels, mnemonic_ctx::LevelBuf{});
         for (int p = 0; p < 2; p++)
@@ -2106,6 +2112,7 @@ int mnemonic_set_trace(mnemonic_ctx* ctx, uint64_t capacity) {
             dev_free(B.lo);
             dev_free(B.cnt);
             dev_free(B.off);
+            dev_free(B.hpre);
             B.cap = 0;
         }
         dev_free(ctx->d_tr_n);

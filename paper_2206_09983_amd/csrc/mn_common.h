@@ -155,9 +155,14 @@ static_assert(offsetof(SeedPlan, lv) % 16 == 0 && sizeof(SeedPlan) % 16 == 0, "a
 // instance run in the adjacency list that was searched (bit 31 set when that
 // was the list of f(nv)); kcol[k * cap + r] the key of tree edge k. When
 // tracing, column 1 + wv + we holds the trace entry of the row's start row.
+// hpre[r] and hpre[cap + r]: for a row whose plan ends at this level with no
+// closing edge and no temporal order, both digest chains (seeds A and B) over
+// the keys of the query edges before the level's anchor edge; its embeddings
+// differ only from the anchor edge on.
 struct RowsView {
     uint32_t* col;
     uint64_t* kcol;
+    uint64_t* hpre;
     uint32_t cap;
     uint32_t wv;
     uint32_t we;

@@ -816,6 +816,66 @@ __global__ __launch_bounds__(MN_BLOCK) void k_decide(GraphView g, RowsView R, co
     }
 }
 
+// The fields of a plan the expansion reads for every candidate, from one
+// 16-byte load of the plan's header.
+struct PlanHead {
+    uint32_t q, n_qe, n_levels, sem, n_close, temporal, vf_base;
+};
+
+__device__ inline PlanHead plan_head(const SeedPlan* P) {
+    const uint4 h = *reinterpret_cast<const uint4*>(P);
+    PlanHead H;
+    H.q = h.x & 0xFFFFu;
+    H.n_qe = h.x >> 24;
+    H.n_levels = (h.y >> 16) & 0xFFu;
+    H.sem = h.z & 0xFFu;
+    H.n_close = (h.z >> 8) & 0xFFu;
+    H.temporal = h.z >> 24;
+    H.vf_base = h.w;
+    return H;
+}
+
+// Level L of plan P, one 16-byte load.
+__device__ inline LevelDesc load_level(const SeedPlan* P, uint32_t L) {
+    return __builtin_bit_cast(LevelDesc, *reinterpret_cast<const uint4*>(&P->lv[L]));
+}
+
+// Byte i (< 16) of a 16-byte vector.
+__device__ inline uint32_t byte_of(const uint4& v, uint32_t i) {
+    const uint32_t w = i < 8 ? (i < 4 ? v.x : v.y) : (i < 12 ? v.z : v.w);
+    return (w >> (8 * (i & 3))) & 0xFFu;
+}
+
+// Exclusive count of the set bits of `mask` below this lane.
+__device__ inline uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Stores a key of an emitted embedding: a global-memory store marked
+// non-temporal (the tuples stream out and are not read again here).
+__device__ inline void store_key(uint64_t* p, uint64_t v) {
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) uint64_t*)p);
+}
+
+// Both digest chains over the keys of query edges [0, aqe) of row r (all tree
+// edges of a plan with no closing edge), from query q's seeds.
+__device__ inline void digest_prefix(const RowsView& R, uint32_t r, uint32_t q, uint32_t aqe, uint64_t& hA,
+                                     uint64_t& hB) {
+    hA = mn_mix64(MN_SEED_A ^ (uint64_t)q);
+    hB = mn_mix64(MN_SEED_B ^ (uint64_t)q);
+    for (uint32_t k0 = 0; k0 < aqe; k0 += 8) {
+        uint64_t kv[8];
+#pragma unroll
+        for (uint32_t i = 0; i < 8; i++) kv[i] = k0 + i < aqe ? rkey(R, k0 + i, r) : 0ull;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; i++)
+            if (k0 + i < aqe) {
+                hA = mn_mix64(hA + kv[i]);
+                hB = mn_mix64(hB + kv[i]);
+            }
+    }
+}
+
 // Device-sized levels fold two bookkeeping steps in here: thread 0 compares
 // the row count with the buffer (note[0] = 1 when *n_dev > n, note[1] = the
 // largest count seen) and zeroes the next level's row counter (zero_next).
@@ -839,7 +899,19 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
     const uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x;
     Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
     if (r < n && !A.dead) {
-        const LevelDesc& lv = g.plans[rcol(R, 0, r)].lv[L];
+        const SeedPlan* P = &g.plans[rcol(R, 0, r)];
+        const LevelDesc lv = load_level(P, L);
+        if (R.hpre) {
+            // a row whose embeddings end at this level and are all tree edges:
+            // its digest chains up to the anchor edge, once for all its candidates
+            const PlanHead H = plan_head(P);
+            if (L + 1 == H.n_levels && H.n_close == 0 && !H.temporal) {
+                uint64_t hA, hB;
+                digest_prefix(R, r, H.q, lv.qe, hA, hB);
+                R.hpre[r] = hA;
+                R.hpre[R.cap + r] = hB;
+            }
+        }
         uint32_t a = 0, b = 0;
         if (!lv.empty) {
             const uint32_t x = rcol(R, 1 + lv.from, r);
@@ -974,41 +1046,6 @@ __global__ __launch_bounds__(MN_BLOCK) void k_offsets_partition(const uint32_t* 
 
 constexpr uint32_t NO_LOC = 0xFFFFFFFFu;
 
-// The fields of a plan the expansion reads for every candidate, from one
-// 16-byte load of the plan's header.
-struct PlanHead {
-    uint32_t q, n_qe, n_levels, sem, n_close, temporal, vf_base;
-};
-
-__device__ inline PlanHead plan_head(const SeedPlan* P) {
-    const uint4 h = *reinterpret_cast<const uint4*>(P);
-    PlanHead H;
-    H.q = h.x & 0xFFFFu;
-    H.n_qe = h.x >> 24;
-    H.n_levels = (h.y >> 16) & 0xFFu;
-    H.sem = h.z & 0xFFu;
-    H.n_close = (h.z >> 8) & 0xFFu;
-    H.temporal = h.z >> 24;
-    H.vf_base = h.w;
-    return H;
-}
-
-// Level L of plan P, one 16-byte load.
-__device__ inline LevelDesc load_level(const SeedPlan* P, uint32_t L) {
-    return __builtin_bit_cast(LevelDesc, *reinterpret_cast<const uint4*>(&P->lv[L]));
-}
-
-// Byte i (< 16) of a 16-byte vector.
-__device__ inline uint32_t byte_of(const uint4& v, uint32_t i) {
-    const uint32_t w = i < 8 ? (i < 4 ? v.x : v.y) : (i < 12 ? v.z : v.w);
-    return (w >> (8 * (i & 3))) & 0xFFu;
-}
-
-// Exclusive count of the set bits of `mask` below this lane.
-__device__ inline uint32_t lane_rank(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 // Largest a in [0, span) with s_off[a] <= t (s_off[0] <= t is required), and
 // s_off[a] itself, searched in LDS.
 __device__ inline uint32_t row_in_lds(const uint64_t* s_off, uint32_t span, uint64_t t, uint64_t& o) {
@@ -1045,18 +1082,34 @@ __device__ inline uint32_t row_in_global(const uint64_t* off, uint32_t a, uint32
     return a;
 }
 
-// Digests of one complete mapping with a single embedding whose query edges
-// other than the anchor aqe are all tree edges (no closing edge, no temporal
-// order): the tuple is the row's tree keys with akey at aqe. Writes it at
-// place pos when emitting.
+// One complete mapping with a single embedding whose query edges other than
+// the anchor aqe are all tree edges (no closing edge, no temporal order): the
+// tuple is the row's tree keys with akey at aqe. Both digest chains continue
+// from the row's prefix (the edges before aqe); the tuple is written at `row`
+// when emitting.
 __device__ inline void emit_tree_tuple(const RowsView& R, uint32_t r, uint32_t nqe, uint32_t aqe, uint64_t akey,
-                                       uint64_t hA, uint64_t hB, uint64_t* row, bool write, Cnt& K,
-                                       uint64_t& dA, uint64_t& dB) {
-    for (uint32_t k = 0; k < nqe; k++) {
-        const uint64_t key = k == aqe ? akey : rkey(R, k, r);
-        hA = mn_mix64(hA + key);
-        hB = mn_mix64(hB + key);
-        if (write) row[k] = key;
+                                       uint64_t* row, bool write, Cnt& K, uint64_t& dA, uint64_t& dB) {
+    uint64_t hA = R.hpre[r], hB = R.hpre[R.cap + r];
+    for (uint32_t k0 = 0; k0 < nqe; k0 += 8) {  // one pass for up to 8 edges
+        uint64_t kv[8];
+#pragma unroll
+        for (uint32_t i = 0; i < 8; i++) {
+            const uint32_t k = k0 + i;
+            kv[i] = k < nqe && k != aqe ? rkey(R, k, r) : akey;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < 8; i++) {
+            const uint32_t k = k0 + i;
+            if (k >= aqe && k < nqe) {
+                hA = mn_mix64(hA + kv[i]);
+                hB = mn_mix64(hB + kv[i]);
+            }
+        }
+        if (write) {
+#pragma unroll
+            for (uint32_t i = 0; i < 8; i++)
+                if (k0 + i < nqe) store_key(row + k0 + i, kv[i]);
+        }
     }
     K.keys += nqe;
     K.tuples++;
@@ -1246,8 +1299,8 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     __syncthreads();
 
     // ---- pass 2: write rows and embeddings at their places
-    uint32_t dq = MAXQ, sq = MAXQ;  // query of the lane's digest sums, and of its cached seeds
-    uint64_t dA = 0, dB = 0, s0A = 0, s0B = 0;
+    uint32_t dq = MAXQ;  // query of the lane's digest sums
+    uint64_t dA = 0, dB = 0;
     for (uint32_t it = 0; it < ITEMS; it++) {
         const uint32_t idx = it * MN_BLOCK + threadIdx.x;
         const uint64_t t = t0 + idx;
@@ -1265,8 +1318,23 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
         if (ROWS && !last) {
             const uint32_t dst = s_rbase + loc;
             if (dst < out.cap) {
-                for (uint32_t c = 0; c < ncol; c++) wcol(out, c, dst, rcol(in, c, r));
-                for (uint32_t k = 0; k < in.we; k++) wkey(out, k, dst, rkey(in, k, r));
+                // the row's columns and keys, eight loads in flight at a time
+                for (uint32_t c0 = 0; c0 < ncol; c0 += 8) {
+                    uint32_t v[8];
+#pragma unroll
+                    for (uint32_t i = 0; i < 8; i++) v[i] = c0 + i < ncol ? rcol(in, c0 + i, r) : 0u;
+#pragma unroll
+                    for (uint32_t i = 0; i < 8; i++)
+                        if (c0 + i < ncol) wcol(out, c0 + i, dst, v[i]);
+                }
+                for (uint32_t k0 = 0; k0 < in.we; k0 += 8) {
+                    uint64_t v[8];
+#pragma unroll
+                    for (uint32_t i = 0; i < 8; i++) v[i] = k0 + i < in.we ? rkey(in, k0 + i, r) : 0ull;
+#pragma unroll
+                    for (uint32_t i = 0; i < 8; i++)
+                        if (k0 + i < in.we) wkey(out, k0 + i, dst, v[i]);
+                }
                 wcol(out, 1 + lv.vtx, dst, w);
                 wkey(out, lv.qe, dst, akey);
                 K.keys++;
@@ -1279,11 +1347,6 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
         }
         if (EMIT && last) {
             const uint32_t q = H.q;
-            if (q != sq) {
-                sq = q;
-                s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
-                s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
-            }
             if (q != dq) {  // the lane's sums so far belong to another query
                 if (dq != MAXQ) {
                     atomicAdd(&A.dig[2 * dq], (unsigned long long)dA);
@@ -1296,8 +1359,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
             if (!H.temporal && (NC == 0 || H.n_close == 0)) {
                 const OutView& ov = po.outs[q];
                 const bool write = po.emit && pos < ov.cap[po.phase];
-                emit_tree_tuple(in, r, H.n_qe, lv.qe, akey, s0A, s0B, ov.keys[po.phase] + pos * H.n_qe, write, K,
-                                dA, dB);
+                emit_tree_tuple(in, r, H.n_qe, lv.qe, akey, ov.keys[po.phase] + pos * H.n_qe, write, K, dA, dB);
             } else {
                 Bind B;
                 B.R = in;
