@@ -1046,22 +1046,17 @@ __global__ __launch_bounds__(MN_BLOCK) void k_offsets_partition(const uint32_t* 
 
 constexpr uint32_t NO_LOC = 0xFFFFFFFFu;
 
-// Largest a in [0, span) with s_off[a] <= t (s_off[0] <= t is required), and
-// s_off[a] itself, searched in LDS.
-__device__ inline uint32_t row_in_lds(const uint64_t* s_off, uint32_t span, uint64_t t, uint64_t& o) {
+// Largest a in [0, span) with rel[a] <= i (rel[0] = 0), searched in LDS over
+// the rows' first candidates relative to the tile's first (32 bits).
+__device__ inline uint32_t row_in_lds(const uint32_t* rel, uint32_t span, uint32_t i) {
     uint32_t a = 0, b = span;
-    uint64_t oa = s_off[0];
     while (a + 1 < b) {
         const uint32_t m = (a + b) >> 1;
-        const uint64_t om = s_off[m];
-        if (om <= t) {
+        if (rel[m] <= i)
             a = m;
-            oa = om;
-        } else {
+        else
             b = m;
-        }
     }
-    o = oa;
     return a;
 }
 
@@ -1139,7 +1134,11 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     constexpr int NA = NC > 0 ? NC : 1;
     constexpr uint32_t EX_TILE = MN_BLOCK * ITEMS;
     constexpr uint32_t EX_LDS_ROWS = EX_TILE + 1;
-    __shared__ uint64_t s_off[EX_LDS_ROWS];
+    // the tile's rows when they fit: first candidate relative to the tile's
+    // (the first row's is 0; d0 = how far it starts before the tile), first
+    // adjacency position of the run, plan
+    __shared__ uint32_t s_rel[EX_LDS_ROWS], s_lo[EX_LDS_ROWS];
+    __shared__ uint16_t s_pl[EX_LDS_ROWS];
     __shared__ BlockAcc A;
     __shared__ uint32_t s_r[EX_TILE], s_p[EX_TILE], s_loc[EX_TILE], s_w[EX_TILE];
     __shared__ uint32_t s_st[NA][EX_TILE];
@@ -1161,8 +1160,15 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     const uint32_t rlo = tile_row[tile], rhi = tile_row[tile + 1] + 1;  // rows of this tile lie in [rlo, rhi)
     const uint32_t span = rhi - rlo;
     const bool staged = span <= EX_LDS_ROWS;
+    const uint32_t d0 = (uint32_t)(t0 - off[rlo]);  // the runs' positions fit in 32 bits
     if (staged)
-        for (uint32_t x = threadIdx.x; x < span; x += MN_BLOCK) s_off[x] = off[rlo + x];
+        for (uint32_t x = threadIdx.x; x < span; x += MN_BLOCK) {
+            const uint32_t rr = rlo + x;
+            const uint64_t o = off[rr];
+            s_rel[x] = x ? (uint32_t)(o - t0) : 0u;  // rows after the first start inside the tile or past it
+            s_lo[x] = lo[rr];
+            s_pl[x] = (uint16_t)rcol(in, 0, rr);
+        }
     if (EMIT)
         for (uint32_t x = threadIdx.x; x < po.n_q; x += MN_BLOCK) s_qn[x] = 0;
     if (threadIdx.x == 0) s_nrows = 0;
@@ -1181,13 +1187,22 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
         for (uint32_t c = 0; c < NA; c++) st[c] = 0;
         const SeedPlan* P = g.plans;
         if (ok) {
-            uint64_t o;
-            r = staged ? rlo + row_in_lds(s_off, span, t, o) : row_in_global(off, rlo, rhi, t, o);
-            P = &g.plans[rcol(in, 0, r)];
-            const uint32_t base = lo[r];
+            uint32_t base, pl;
+            if (staged) {
+                const uint32_t a = row_in_lds(s_rel, span, idx);
+                r = rlo + a;
+                base = s_lo[a] + (a ? idx - s_rel[a] : idx + d0);  // position of the candidate in its run
+                pl = s_pl[a];
+            } else {
+                uint64_t o;
+                r = row_in_global(off, rlo, rhi, t, o);
+                base = lo[r] + (uint32_t)(t - o);
+                pl = rcol(in, 0, r);
+            }
+            P = &g.plans[pl];
             lv = load_level(P, L);
             H = plan_head(P);
-            p = base + (uint32_t)(t - o);
+            p = base;
             const uint64_t e = g.adjs(lv.dir)[p];
             K.entries++;
             w = ent_hi(e) & g.nbr_mask;
@@ -1197,12 +1212,17 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                 ok = vf_bit(g, w, H.vf_base + lv.vtx);
             }
             if (ok && H.sem == MN_SEM_ISO) {
-                // the images of the mapped query vertices, loaded together
+                // the images of the L + 2 mapped query vertices, loaded together
+                // (the trip count is the launch's, the same for every lane)
                 const uint4 mv = *reinterpret_cast<const uint4*>(P->mapped);
+                uint32_t img[MN_MAXQV];
+#pragma unroll
+                for (uint32_t m = 0; m < MN_MAXQV; m++)
+                    if (m < L + 2) img[m] = rcol(in, 1 + byte_of(mv, m), r);
                 bool clash = false;
 #pragma unroll
                 for (uint32_t m = 0; m < MN_MAXQV; m++)
-                    if (m < lv.n_mapped) clash |= rcol(in, 1 + byte_of(mv, m), r) == w;
+                    if (m < L + 2) clash |= img[m] == w;
                 ok = !clash;
             }
             if (ok && H.temporal && P->rank[lv.qe] >= 0) {
@@ -1307,7 +1327,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
         const uint32_t loc = t < t1 ? s_loc[idx] : NO_LOC;
         if (loc == NO_LOC) continue;
         const uint32_t r = s_r[idx], w = s_w[idx], p = s_p[idx];
-        const SeedPlan* P = &g.plans[rcol(in, 0, r)];
+        const SeedPlan* P = &g.plans[staged ? (uint32_t)s_pl[r - rlo] : rcol(in, 0, r)];
         const LevelDesc lv = load_level(P, L);
         const PlanHead H = plan_head(P);
         const uint64_t akey = g.keys(lv.dir)[p];
