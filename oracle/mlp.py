@@ -18,9 +18,9 @@ Pins (tests/test_oracle_mlp.py): the analytic gradient equals central finite
 differences; closed forms for networks whose hidden units are all off or all
 linear; Adam's first step moves every weight with a nonzero gradient by
 lr * g / (|g| + eps); bfloat16 rounding against exactly representable values
-and ties, and the half-unit error bound; bf16 inference rounds the first
-hidden layer and not the second (a one-path network whose activations sit
-just off a bfloat16 value).
+and ties, and the half-unit error bound; bf16 inference rounds the inputs
+and both hidden layers (a one-path network whose activations sit just off,
+on, and past bfloat16 midpoints, with hand-derived outputs).
 """
 import numpy as np
 
@@ -108,14 +108,15 @@ def bf16_round(a):
 
 
 def forward_bf16(w, X):
-    """bf16 inference: every operand of the two matrix products in bfloat16
-    (weights, inputs, and the first hidden layer's activations, each rounded
-    from float32), exact fp64 sums otherwise. The output layer multiplies the
-    rounded W3 with the second hidden layer as computed (not rounded), as the
-    library's matrix-core evaluator does with its fp32 accumulators."""
+    """bf16 inference, by the usual mixed-precision convention: every operand
+    of every product is bfloat16 (all weights and biases, the inputs, and
+    both hidden layers' activations, each rounded to nearest-even from
+    float32), and every sum is taken in wider precision (exact fp64 here).
+    The output is not rounded."""
     W1, b1, W2, b2, W3, b3 = unpack(bf16_round(np.asarray(w, dtype=np.float32)))
     Xr = bf16_round(np.asarray(X, dtype=np.float32))
     h1 = np.maximum(Xr @ W1 + b1, 0.0)
     h1r = bf16_round(h1.astype(np.float32))
     h2 = np.maximum(h1r @ W2 + b2, 0.0)
-    return h2 @ W3 + b3
+    h2r = bf16_round(h2.astype(np.float32))
+    return h2r @ W3 + b3

@@ -107,8 +107,10 @@ __device__ inline uint16_t bf16_bits(float v) {
 // hidden units in two K-slices; slot t of group g in slice kc is hidden unit
 // 32 kc + 16 (t / 4) + 4 g + t % 4, exactly the unit the lane holds in
 // element t % 4 of layer-1 tile 2 kc + t / 4. The A fragments use the same
-// slot order, so the hidden layer never leaves the registers. The hidden
-// activations are rounded to bf16 for the second product; every sum is fp32.
+// slot order, so the hidden layer never leaves the registers. Every operand
+// of every product is bf16: the first hidden layer is rounded for the second
+// product, the second hidden layer for the output's dot product with W3;
+// every sum is fp32.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -196,7 +198,8 @@ __device__ inline float eval_wave(const NetFrag& F, const NetVec& V, const float
             z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[mt][0], hb[0], z, 0, 0, 0);
             z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a2[mt][1], hb[1], z, 0, 0, 0);
 #pragma unroll
-            for (uint32_t r = 0; r < 4; r++) part = fmaf(fmaxf(z[r], 0.0f), V.w3[16 * mt + 4 * g + r], part);
+            for (uint32_t r = 0; r < 4; r++)  // the second hidden layer enters its product as bf16 too
+                part = fmaf(bf(bf16_bits(fmaxf(z[r], 0.0f))), V.w3[16 * mt + 4 * g + r], part);
         }
         part += __shfl_xor(part, 16, MN_WAVE);
         part += __shfl_xor(part, 32, MN_WAVE);

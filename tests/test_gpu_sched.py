@@ -59,14 +59,18 @@ def test_forward_matches_reference_fp32_and_bf16(B, torch):
         refb = omlp.forward_bf16(w, X)
         err = np.abs(y.cpu().numpy() - refb)
         tight = 2e-5 * (1.0 + np.abs(refb).max())
-        # The first hidden layer is rounded to bf16 from fp32 sums taken in
+        # Both hidden layers are rounded to bf16 from fp32 sums taken in
         # another order than the reference's: where a sum lands on the other
         # side of a rounding boundary, that unit moves by one bf16 step
-        # (<= 2^-7 of its value). Bound: every unit moving at once, carried
-        # through the (1-Lipschitz) ReLU by the absolute weights.
+        # (<= 2^-7 of its value). Bound: every first-layer unit moving at
+        # once, carried through the (1-Lipschitz) ReLU by the absolute
+        # weights into the second layer's sums (dz2), and every second-layer
+        # unit then moving by that change plus one step of its perturbed value.
         W1, b1, W2, b2, W3, b3 = omlp.unpack(omlp.bf16_round(w))
         h1 = np.maximum(omlp.bf16_round(X) @ W1 + b1, 0.0)
-        flip = (2.0 ** -7 * h1) @ np.abs(W2) @ np.abs(W3)
+        h2 = np.maximum(omlp.bf16_round(h1) @ W2 + b2, 0.0)
+        dz2 = (2.0 ** -7 * h1) @ np.abs(W2)
+        flip = (dz2 + 2.0 ** -7 * (h2 + dz2)) @ np.abs(W3)
         assert np.all(err <= tight + flip), (n, float((err - tight - flip).max()))
         assert np.mean(err <= tight) >= 0.99, (n, float(np.mean(err <= tight)))
         # and bf16 stays close to fp32: bound by the operands' rounding

@@ -116,28 +116,33 @@ def test_bf16_rounding_exact_values_and_ties():
     assert np.all(np.abs(r - a) <= np.abs(a) * 2.0 ** -8)
 
 
-def test_bf16_inference_rounds_the_first_hidden_layer_only():
+def test_bf16_inference_rounds_every_product_operand():
     # one active path: x0 -> unit 0 -> unit 0 -> y, every weight 1 (exact in
-    # bfloat16), biases 2^-9 (a power of two, also exact). The first hidden
-    # unit is 1 + 2^-9, below the midpoint 1 + 2^-8 between 1 and the next
-    # bfloat16 value 1 + 2^-7, so bf16 inference passes 1.0 to the second
-    # layer; the second unit, 1.0 + 2^-9, reaches the output unrounded.
-    W1 = np.zeros((mlp.N_IN, mlp.N_HID))
-    W2 = np.zeros((mlp.N_HID, mlp.N_HID))
-    W3 = np.zeros(mlp.N_HID)
-    b1 = np.zeros(mlp.N_HID)
-    b2 = np.zeros(mlp.N_HID)
-    W1[0, 0] = W2[0, 0] = W3[0] = 1.0
-    b1[0] = b2[0] = 2.0 ** -9
-    w = mlp.pack(W1, b1, W2, b2, W3, 0.0)
+    # bfloat16) and b3 = 0; the biases are powers of two (also exact). Near 1
+    # the bfloat16 values are 2^-7 apart, so the midpoints sit at odd
+    # multiples of 2^-8. Values derived by hand:
+    def net(b1, b2):
+        W1 = np.zeros((mlp.N_IN, mlp.N_HID))
+        W2 = np.zeros((mlp.N_HID, mlp.N_HID))
+        W3 = np.zeros(mlp.N_HID)
+        bb1 = np.zeros(mlp.N_HID)
+        bb2 = np.zeros(mlp.N_HID)
+        W1[0, 0] = W2[0, 0] = W3[0] = 1.0
+        bb1[0], bb2[0] = b1, b2
+        return mlp.pack(W1, bb1, W2, bb2, W3, 0.0)
+
     X = np.zeros((2, mlp.N_IN))
     X[0, 0] = 1.0
-    X[1, 0] = 1.0 + 2.0 ** -8 - 2.0 ** -9  # rounds to 1.0 on input: the same path as sample 0
-    assert mlp.forward(w, X[:1])[0] == 1.0 + 2.0 ** -8
+    X[1, 0] = 1.0 + 2.0 ** -8 - 2.0 ** -9  # below the midpoint: the input rounds to 1.0
+    # h1 = 1 + 2^-9 rounds down to 1; h2 = 1 + 2^-9 rounds down to 1: y = 1
+    w = net(2.0 ** -9, 2.0 ** -9)
+    assert mlp.forward(w, X[:1])[0] == 1.0 + 2.0 ** -8  # fp64: nothing rounded
     y = mlp.forward_bf16(w, X)
-    assert y[0] == 1.0 + 2.0 ** -9
-    assert y[1] == 1.0 + 2.0 ** -9
-    # with the first unit at 1 + 3 * 2^-8 (a tie) the even neighbour 1 + 2^-6 goes on
-    b1[0] = 3 * 2.0 ** -8
-    w = mlp.pack(W1, b1, W2, b2, W3, 0.0)
-    assert mlp.forward_bf16(w, X[:1])[0] == 1.0 + 2.0 ** -6 + 2.0 ** -9
+    assert y[0] == 1.0 and y[1] == 1.0
+    # h1 = 1 + 3 * 2^-8 is a tie between 1 + 2^-7 and 1 + 2^-6: the even one,
+    # 1 + 2^-6, goes on; h2 = 1 + 2^-6 + 2^-9 rounds back down to 1 + 2^-6
+    assert mlp.forward_bf16(net(3 * 2.0 ** -8, 2.0 ** -9), X[:1])[0] == 1.0 + 2.0 ** -6
+    # h1 rounds to 1; h2 = 1 + 2^-8 + 2^-10 is past the midpoint: 1 + 2^-7
+    assert mlp.forward_bf16(net(2.0 ** -9, 2.0 ** -8 + 2.0 ** -10), X[:1])[0] == 1.0 + 2.0 ** -7
+    # h2 = 1 + 2^-8 exactly (a tie) goes to the even neighbour 1.0
+    assert mlp.forward_bf16(net(2.0 ** -9, 2.0 ** -8), X[:1])[0] == 1.0
