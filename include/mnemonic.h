@@ -149,6 +149,9 @@ typedef struct {
  *   key_reads          edge keys gathered for emitted tuples
  *   tuples             embeddings found; tuple_words = tuples x |E_Q| keys
  *   vf_reads           vertex-filter words tested
+ *   vf_rejects         work units and candidates the vertex filter (Section V-A,
+ *                      f2 and f3 as local counts) eliminated: the unit's or
+ *                      candidate's other tests had passed so far
  *   frontier_rows      partial embeddings passed from one level to the next
  *   expand_launches    launches of the expansion kernel
  *   expand_tile        candidates per expansion block in use (autotuned with
@@ -180,6 +183,7 @@ typedef struct {
     double ms_batch;
     uint64_t reruns[2];
     uint64_t rerun_causes[2];
+    uint64_t vf_rejects[2];
 } mnemonic_stats;
 
 /*
@@ -211,7 +215,13 @@ int mnemonic_create(const mnemonic_graph *g, const mnemonic_query *q, uint32_t n
  * created and removed within one snapshot appears in both lists).
  * Validation (endpoint range, label range, timestamps non-decreasing across
  * batches, deletion keys live and distinct) runs on the device before any
- * state changes: a failed batch returns its error and changes nothing.
+ * state changes: a batch it rejects returns VERTEX, LABEL, TS_ORDER or
+ * BAD_DELETE and changes nothing. ARG, and OOM while the batch's buffers are
+ * sized before any kernel runs, also change nothing. An OOM or HIP error
+ * after that (a buffer that must grow while the enumeration runs, or a
+ * failed device call) leaves the batch part way applied: the context is then
+ * unusable, and every later call on it except mnemonic_last_error and
+ * mnemonic_destroy returns MNEMONIC_E_HIP.
  * Blocks until the batch's counts and digests are on the host.
  * Errors: ARG, VERTEX, LABEL, TS_ORDER, BAD_DELETE, OOM, HIP.
  */
@@ -323,6 +333,12 @@ int mnemonic_mlp_predict(const float *w, const float *x, uint64_t n, int bf16, f
 int mnemonic_mlp_grad(const float *w, const float *x, const float *target, const uint32_t *idx, uint64_t off,
                       uint64_t m, float *grad, float *loss, void *hip_stream);
 int mnemonic_mlp_adam(float *w, float *m1, float *m2, float *grad, float lr, uint32_t step, void *hip_stream);
+
+/* Test hook for the error paths above (for callers that check their own
+ * failure handling, not for production use): the n-th device allocation the
+ * library makes from this call on, in any context of the process, fails as
+ * if the device were out of memory; n = 0 disarms it. Not thread-safe. */
+void mnemonic_fail_alloc_after(uint64_t n);
 
 /* Frees every device and host buffer of the context. NULL is ignored. */
 void mnemonic_destroy(mnemonic_ctx *ctx);

@@ -37,7 +37,7 @@ ERRORS = {
 EXPORTS = ["mnemonic_create", "mnemonic_apply_batch", "mnemonic_get_result", "mnemonic_copy_keys",
            "mnemonic_get_stats", "mnemonic_last_error", "mnemonic_destroy", "mnemonic_set_scheduler",
            "mnemonic_query_orders", "mnemonic_set_trace", "mnemonic_get_trace", "mnemonic_mlp_predict",
-           "mnemonic_mlp_grad", "mnemonic_mlp_adam", "mnemonic_set_queries"]
+           "mnemonic_mlp_grad", "mnemonic_mlp_adam", "mnemonic_set_queries", "mnemonic_fail_alloc_after"]
 
 _u8p = C.POINTER(C.c_uint8)
 _u32p = C.POINTER(C.c_uint32)
@@ -78,7 +78,8 @@ class mnemonic_stats(C.Structure):
                 ("tuples", C.c_uint64 * 2), ("tuple_words", C.c_uint64 * 2), ("vf_reads", C.c_uint64 * 2),
                 ("frontier_rows", C.c_uint64 * 2), ("expand_launches", C.c_uint64 * 2),
                 ("expand_tile", C.c_uint64), ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2),
-                ("ms_batch", C.c_double), ("reruns", C.c_uint64 * 2), ("rerun_causes", C.c_uint64 * 2)]
+                ("ms_batch", C.c_double), ("reruns", C.c_uint64 * 2), ("rerun_causes", C.c_uint64 * 2),
+                ("vf_rejects", C.c_uint64 * 2)]
 
 
 class MnemonicError(RuntimeError):
@@ -141,6 +142,8 @@ def load():
     L.mnemonic_mlp_grad.argtypes = [vp, vp, vp, vp, C.c_uint64, C.c_uint64, vp, vp, vp]
     L.mnemonic_mlp_adam.restype = C.c_int
     L.mnemonic_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_float, C.c_uint32, vp]
+    L.mnemonic_fail_alloc_after.restype = None
+    L.mnemonic_fail_alloc_after.argtypes = [C.c_uint64]
     _LIB = L
     return L
 
@@ -312,6 +315,11 @@ def mnemonic_get_trace(ctx, phase, with_x=True):
     _check(L.mnemonic_get_trace(ctx, int(phase), C.byref(n), _ptr(codes, C.c_uint64), _ptr(x, C.c_float),
                                 _ptr(work, C.c_uint64), m), ctx)
     return {"codes": codes, "x": x, "work": work}
+
+
+def mnemonic_fail_alloc_after(n):
+    """Test hook: the n-th device allocation from now fails (0 disarms)."""
+    load().mnemonic_fail_alloc_after(int(n))
 
 
 def _dev(t):

@@ -54,10 +54,18 @@ inline uint32_t ceil_log2(uint64_t x) {
     return b;
 }
 
+// Failure injection for tests (mnemonic_fail_alloc_after): the countdown
+// makes the n-th device allocation from the moment it is armed fail as if the
+// device were out of memory; 0 means disarmed.
+uint64_t g_fail_alloc_in = 0;
+
 template <typename T>
 void dev_alloc(T*& p, size_t n) {
     void* q = nullptr;
     if (n == 0) n = 1;
+    if (g_fail_alloc_in && --g_fail_alloc_in == 0)
+        throw ApiError{MNEMONIC_E_OOM, "device allocation of " + std::to_string(n * sizeof(T)) +
+                                           " bytes failed (injected)"};
     hipError_t e = hipMalloc(&q, n * sizeof(T));
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -265,9 +273,12 @@ struct mnemonic_ctx {
 
     // outputs
     std::vector<OutView> houts;
-    // Set while mnemonic_set_queries rebuilds the query-dependent state; left
-    // set when that fails part way, after which the context only reports it.
+    // Set while mnemonic_set_queries rebuilds the query-dependent state, and
+    // while a batch runs from its first launch that may change the graph
+    // until it is complete; left set when either fails part way, after which
+    // the context only reports why (broken_why).
     bool broken = false;
+    std::string broken_why;
     // Largest tuples per phase edge seen, per (query, phase) (-1: none yet):
     // sizes the output buffers before a batch, so that a batch larger than
     // any before does not re-run a phase to grow them.
@@ -289,21 +300,23 @@ struct mnemonic_ctx {
     uint32_t zr_cursor(int p) const { return 2u + (uint32_t)p; }
     uint32_t zr_count(int p) const { return 4u + (uint32_t)p * n_q; }
     uint32_t zr_digest(int p) const { return 4u + 2u * n_q + (uint32_t)p * MN_SHARDS * 2u * n_q; }
-    uint32_t zr_stats(int p) const { return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + (uint32_t)p * MN_SHARDS * 8u; }
+    uint32_t zr_stats(int p) const {
+        return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + (uint32_t)p * MN_SHARDS * MN_TALLIES;
+    }
     // Overflow notes of the device-sized levels, per phase, four words per
     // level L: [candidates exceeded the launch, largest candidate total, rows
     // of level L + 1 exceeded their buffer, largest row count]; after the
     // levels: [start rows exceeded their buffer, largest count, -, -].
     uint32_t zr_note(int p) const {
-        return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 16u * MN_SHARDS + (uint32_t)p * 4u * (MN_MAXLV + 1);
+        return 4u + 2u * n_q + 4u * MN_SHARDS * n_q + 2u * MN_TALLIES * MN_SHARDS + (uint32_t)p * 4u * (MN_MAXLV + 1);
     }
     uint32_t note_cand(int p, uint32_t L) const { return zr_note(p) + 4u * L; }
     uint32_t note_rows(int p, uint32_t L) const { return zr_note(p) + 4u * L + 2u; }
     uint32_t note_seed(int p) const { return zr_note(p) + 4u * MN_MAXLV; }
     uint32_t zr_words() const { return zr_note(2); }
-    // shard sums of the last readback: digests [p][q][2], tallies [p][8]
+    // shard sums of the last readback: digests [p][q][2], tallies [p][MN_TALLIES]
     std::vector<uint64_t> sum_dig;
-    uint64_t sum_st[2][8] = {{0}};
+    uint64_t sum_st[2][MN_TALLIES] = {{0}};
     void summarize() {
         sum_dig.assign(4 * (size_t)n_q, 0);
         for (int p = 0; p < 2; p++) {
@@ -311,9 +324,9 @@ struct mnemonic_ctx {
                 const unsigned long long* d = h_zr.data() + zr_digest(p) + (size_t)sh * 2 * n_q;
                 for (uint32_t i = 0; i < 2 * n_q; i++) sum_dig[(size_t)p * 2 * n_q + i] += d[i];
             }
-            for (int i = 0; i < 8; i++) {
+            for (int i = 0; i < MN_TALLIES; i++) {
                 uint64_t v = 0;
-                for (uint32_t sh = 0; sh < MN_SHARDS; sh++) v += h_zr[zr_stats(p) + sh * 8 + i];
+                for (uint32_t sh = 0; sh < MN_SHARDS; sh++) v += h_zr[zr_stats(p) + sh * MN_TALLIES + i];
                 sum_st[p][i] = v;
             }
         }
@@ -906,7 +919,7 @@ void reset_phase(mnemonic_ctx* c, int p) {
     // counts, digests, cursor and stats of one phase (err is 0 whenever this runs)
     mn_launch_reset(c->d_err, c->d_zr + c->zr_count(p), c->n_q, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_digest(p), MN_SHARDS * 2 * c->n_q, s);
-    mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), MN_SHARDS * 8, s);
+    mn_launch_reset(c->d_err, c->d_zr + c->zr_stats(p), MN_SHARDS * MN_TALLIES, s);
     mn_launch_reset(c->d_err, c->d_zr + c->zr_note(p), 4 * (MN_MAXLV + 1), s);
     if (c->tr_cap) mn_launch_set_u32(c->d_tr_n + p, 0, s);
 }
@@ -1393,6 +1406,15 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         grow_outputs(c, want);
     }
     GraphView g0 = make_view(c, false);
+    // From the first launch on, a failure other than the validation's leaves
+    // the graph, its index or the results part way through the batch: the
+    // context stays unusable unless the batch completes (or validation
+    // rejects it, which changes nothing: every kernel after the validation
+    // does no work once the error word is set).
+    if (enumerate) {
+        c->broken = true;
+        c->broken_why = "a batch";
+    }
     mn_launch_reset(c->d_err, c->d_zr, c->n_zr, s);
     if (c->tr_cap) {  // the trace holds this batch's start rows only
         mn_launch_set_u32(c->d_tr_n, 0, s);
@@ -1478,6 +1500,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     }
     if (err) {
         swap_in();
+        c->broken = false;  // nothing changed
         switch (err) {
             case MN_ERR_VERTEX: throw ApiError{MNEMONIC_E_VERTEX, "edge endpoint >= n_vertices"};
             case MN_ERR_LABEL: throw ApiError{MNEMONIC_E_LABEL, "edge label >= n_elabels"};
@@ -1619,6 +1642,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             st.tuples[p] = z[5];
             st.vf_reads[p] = z[6];
             st.frontier_rows[p] = z[7];
+            st.vf_rejects[p] = z[8];
             st.expand_launches[p] = c->n_expand[p];
             st.reruns[p] = c->reruns[p];
             st.rerun_causes[p] = c->rerun_causes[p];
@@ -1639,6 +1663,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         }
         c->have_result = true;
     }
+    c->broken = false;
     return MNEMONIC_OK;
 }
 
@@ -1646,7 +1671,7 @@ template <typename F>
 int guarded(mnemonic_ctx* c, F&& f) {
     try {
         if (c && c->broken) {
-            c->err = "context unusable: a query-set change failed part way; destroy it";
+            c->err = "context unusable: " + c->broken_why + " failed part way; destroy it";
             return MNEMONIC_E_HIP;
         }
         if (c) c->err.clear();
@@ -1978,6 +2003,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         hipStream_t s = c->stream;
         HIPCHK(hipStreamSynchronize(s));
         c->broken = true;  // until every query-dependent part is rebuilt below
+        c->broken_why = "a query-set change";
         // query tables
         c->n_q = t.n_q;
         c->n_plans = t.n_plans;
@@ -2157,6 +2183,8 @@ int mnemonic_get_trace(mnemonic_ctx* ctx, int phase, uint64_t* n, uint64_t* code
         return MNEMONIC_OK;
     });
 }
+
+void mnemonic_fail_alloc_after(uint64_t n) { g_fail_alloc_in = n; }
 
 int mnemonic_mlp_predict(const float* w, const float* x, uint64_t n, int bf16, float* y, void* hip_stream) {
     if (n && (!w || !x || !y)) return MNEMONIC_E_ARG;

@@ -51,6 +51,7 @@
 
 #define MN_SEM_ISO 0  // mnemonic_semantics: MNEMONIC_ISO
 #define MN_SHARDS 32  // copies of the per-phase digests and work tallies (summed on the host)
+#define MN_TALLIES 9  // work tallies per phase (EnumStats)
 #define MN_MAXCLOSE 8  // closing edges per start edge (the query's cyclomatic number)
 #define MN_NVAR 4      // matching orders per (query, start position): the static one and alternatives
 

@@ -131,7 +131,7 @@ __device__ inline void wkey(const RowsView& R, uint32_t k, uint32_t r, uint64_t 
 
 // Per-lane work tallies of one launch (32 bits suffice per lane and launch).
 struct Cnt {
-    uint32_t seeds, entries, probes, range_probes, keys, tuples, vf, rows;
+    uint32_t seeds, entries, probes, range_probes, keys, tuples, vf, rows, vfrej;
 };
 
 constexpr uint32_t MAXQ = 256;
@@ -140,7 +140,7 @@ constexpr uint32_t MAXQ = 256;
 // summed here and reach global memory once per block, into shard
 // b % MN_SHARDS, so that no address sees more than a few atomics per launch.
 struct BlockAcc {
-    unsigned long long st[8];
+    unsigned long long st[MN_TALLIES];
     unsigned long long dig[2 * MAXQ];
     uint32_t dead;  // the error word was set before this block started
 };
@@ -149,11 +149,11 @@ __device__ inline uint32_t block_linear() { return blockIdx.x + blockIdx.y * gri
 
 // Zeroes the accumulators and reads the error word once for the whole block.
 __device__ void acc_init(BlockAcc& A, uint32_t n_dig, const uint32_t* err) {
-    for (uint32_t i = threadIdx.x; i < 8 + n_dig; i += MN_BLOCK) {
-        if (i < 8)
+    for (uint32_t i = threadIdx.x; i < MN_TALLIES + n_dig; i += MN_BLOCK) {
+        if (i < MN_TALLIES)
             A.st[i] = 0;
         else
-            A.dig[i - 8] = 0;
+            A.dig[i - MN_TALLIES] = 0;
     }
     if (threadIdx.x == 0) A.dead = failed(err) ? 1u : 0u;
     __syncthreads();
@@ -164,19 +164,19 @@ __device__ void acc_init(BlockAcc& A, uint32_t n_dig, const uint32_t* err) {
 __device__ void acc_flush(BlockAcc& A, const Cnt& K, uint32_t n_dig, EnumStats* stats,
                           unsigned long long* digest) {
     // a lane's tallies of one launch fit in 32 bits, and so do a wave's
-    const uint32_t v[8] = {wave_sum32(K.seeds), wave_sum32(K.entries), wave_sum32(K.probes),
-                           wave_sum32(K.range_probes), wave_sum32(K.keys), wave_sum32(K.tuples),
-                           wave_sum32(K.vf), wave_sum32(K.rows)};
+    const uint32_t v[MN_TALLIES] = {wave_sum32(K.seeds), wave_sum32(K.entries), wave_sum32(K.probes),
+                                    wave_sum32(K.range_probes), wave_sum32(K.keys), wave_sum32(K.tuples),
+                                    wave_sum32(K.vf), wave_sum32(K.rows), wave_sum32(K.vfrej)};
     if (__lane_id() == 0) {
 #pragma unroll
-        for (int i = 0; i < 8; i++)
+        for (int i = 0; i < MN_TALLIES; i++)
             if (v[i]) atomicAdd(&A.st[i], (unsigned long long)v[i]);
     }
     __syncthreads();
     const uint32_t shard = block_linear() % MN_SHARDS;
     unsigned long long* gst = reinterpret_cast<unsigned long long*>(stats + shard);
     unsigned long long* gdig = digest ? digest + (size_t)shard * n_dig : nullptr;
-    if (threadIdx.x < 8 && A.st[threadIdx.x]) atomicAdd(&gst[threadIdx.x], A.st[threadIdx.x]);
+    if (threadIdx.x < MN_TALLIES && A.st[threadIdx.x]) atomicAdd(&gst[threadIdx.x], A.st[threadIdx.x]);
     for (uint32_t i = threadIdx.x; i < n_dig; i += MN_BLOCK)
         if (A.dig[i]) atomicAdd(&gdig[i], A.dig[i]);
 }
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
     }
     __syncthreads();
     const uint32_t m = s_n;
-    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    Cnt K = {};
     constexpr int NA = NC > 0 ? NC : 1;
     // pass 2: the listed pairs, densely
     for (uint32_t k0 = 0; k0 < m; k0 += MN_BLOCK) {  // block-uniform
@@ -654,8 +654,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
             s = g.s_src[pslot];
             d = g.s_dst[pslot];
             K.vf += 2;
-            ok = !(P.sem == MN_SEM_ISO && s == d) && vf_bit(g, s, P.vf_base + P.qa) &&
-                 vf_bit(g, d, P.vf_base + P.qb);
+            const bool loop_ok = !(P.sem == MN_SEM_ISO && s == d);
+            const bool vf_ok = vf_bit(g, s, P.vf_base + P.qa) && vf_bit(g, d, P.vf_base + P.qb);
+            K.vfrej += loop_ok && !vf_ok ? 1u : 0u;
+            ok = loop_ok && vf_ok;
         }
         Bind B;
         B.R = R;
@@ -897,7 +899,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
     if (blockIdx.x * MN_BLOCK >= n) return;  // the grid covers the capacity; the same for the whole block
     acc_init(A, 0, err);
     const uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x;
-    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    Cnt K = {};
     if (r < n && !A.dead) {
         const SeedPlan* P = &g.plans[rcol(R, 0, r)];
         const LevelDesc lv = load_level(P, L);
@@ -1154,7 +1156,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     // go to blocks of one XCD
     const uint32_t tile = xcd_tile(blockIdx.x, nt);
     const uint32_t ncol = 1 + in.wv + in.we + in.trace;
-    Cnt K = {0, 0, 0, 0, 0, 0, 0, 0};
+    Cnt K = {};
     const uint64_t t0 = c0 + (uint64_t)tile * EX_TILE;
     const uint64_t t1 = min(t0 + (uint64_t)EX_TILE, cend);
     const uint32_t rlo = tile_row[tile], rhi = tile_row[tile + 1] + 1;  // rows of this tile lie in [rlo, rhi)
@@ -1210,6 +1212,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
             if (ok && lv.need_vf) {
                 K.vf++;
                 ok = vf_bit(g, w, H.vf_base + lv.vtx);
+                K.vfrej += ok ? 0u : 1u;
             }
             if (ok && H.sem == MN_SEM_ISO) {
                 // the images of the L + 2 mapped query vertices, loaded together

@@ -153,7 +153,9 @@ struct EnumStats {  // per phase, accumulated by the enumeration kernels
     unsigned long long tuples;
     unsigned long long vf_reads;
     unsigned long long rows;          // partial embeddings written between levels
+    unsigned long long vf_rejects;    // work units and candidates the vertex filter eliminated
 };
+static_assert(sizeof(EnumStats) == MN_TALLIES * 8, "tallies");
 
 // Per-phase outputs. Digests and tallies have MN_SHARDS copies so that
 // blocks spread their atomics over many addresses: block b adds into copy

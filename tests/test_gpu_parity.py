@@ -263,6 +263,99 @@ def test_bad_batches_fail_atomically(B):
         o.close()
 
 
+def test_allocation_failures_undo_the_batch_or_retire_the_context(B):
+    # Each device allocation a batch makes fails in turn (the library's test
+    # hook). A failure while the batch's buffers are sized, before any kernel
+    # runs, changes nothing: the same batch applied again matches the oracle.
+    # A later one leaves the batch part way: the context then refuses every
+    # call with MNEMONIC_E_HIP. A wrong result is never returned.
+    # The first batch holds two edges, so the second (the rest of the first
+    # two stream batches) outgrows every buffer sized from the first's rates:
+    # it grows them while it runs, and re-runs phases.
+    case = synth.rmat_case(scale=9, n_init=3000, n_stream=768, batch=256, n_batches=3, n_vlabels=3, n_elabels=4)
+    qs = case["queries"]
+    s0, s1 = case["batches"][0], case["batches"][1]
+    b0 = synth.make_batch(s0["src"][:2], s0["dst"][:2], s0["elabel"][:2], s0["ts"][:2], [])
+    b1 = synth.make_batch(*[np.concatenate([s0[f][2:], s1[f]]) for f in ("src", "dst", "elabel", "ts")],
+                          np.concatenate([s0["del_keys"], s1["del_keys"]]))
+    seen = {}
+    for k in range(1, 41):
+        o = Oracle(case["graph"], qs)
+        m = B.Matcher(case["graph"], qs, flags=B.F_EMIT, out_capacity=64, n_elabels=4)
+        try:
+            o.apply_batch(b0)
+            m.apply_batch(b0)
+            B.mnemonic_fail_alloc_after(k)
+            try:
+                m.apply_batch(b1)
+                outcome = "ok"
+            except B.MnemonicError as e:
+                assert e.name == "MNEMONIC_E_OOM", str(e)
+                outcome = "failed"
+            finally:
+                B.mnemonic_fail_alloc_after(0)
+            o.apply_batch(b1)
+            if outcome == "failed":
+                try:
+                    m.apply_batch(b1)
+                    outcome = "undone"
+                except B.MnemonicError as e:
+                    assert e.name == "MNEMONIC_E_HIP" and "unusable" in str(e), str(e)
+                    for call in (lambda: m.result(0), lambda: m.stats(), lambda: m.apply_batch(case["batches"][2])):
+                        with pytest.raises(B.MnemonicError) as ei:
+                            call()
+                        assert ei.value.name == "MNEMONIC_E_HIP"
+                    outcome = "retired"
+            if outcome != "retired":
+                for qi in range(len(qs)):
+                    r = m.result(qi)
+                    for ph in (False, True):
+                        assert (r["n_expired"] if ph else r["n_new"]) == o.count(qi, ph), (k, qi, ph)
+                        assert (r["dig_expired"] if ph else r["dig_new"]) == o.digest(qi, ph), (k, qi, ph)
+                        np.testing.assert_array_equal(canon(m.keys(qi, ph)), o.result(qi, ph))
+            seen[outcome] = seen.get(outcome, 0) + 1
+        finally:
+            B.mnemonic_fail_alloc_after(0)
+            m.close()
+            o.close()
+    say("allocation failures:", seen)
+    assert seen.get("retired", 0) > 0 and seen.get("undone", 0) > 0 and seen.get("ok", 0) > 0
+
+
+def test_vertex_filter_rejects_exactly_the_units_and_candidates_it_must(B):
+    # Section V-A's local filters (f2: enough edges of each label and
+    # direction; f3: enough neighbours of each vertex label), read as counts:
+    # under isomorphism a data vertex needs at least as many as the query
+    # vertex has, under homomorphism at least one where the query has any.
+    # Query u0 -0-> u1 -0-> u2, u2 -1-> u3, u2 -1-> u4 (labels on the edges,
+    # every vertex a wildcard): u1 needs an in- and an out-edge of label 0; u2
+    # needs an in-edge of label 0 and two (iso) or one (homo) out-edges of
+    # label 1. Graph A=0 .. G=6: B->C, B->F (label 0), C->D, C->E, F->G (1);
+    # the batch inserts A->B (0). Work units of A->B: position 0 passes both
+    # endpoints' filters; position 1 puts A at u1, and A has no in-edge: the
+    # filter rejects it. From (A, B) the first level maps u2 to C or F (B's
+    # label-0 out-neighbours): F has one label-1 out-edge, too few for u2
+    # under isomorphism. So the filter rejects 2 (iso) and 1 (homo), and the
+    # embeddings are the oracle's either way (2 and 5).
+    g = synth.make_graph(7, [1] * 7, [1, 1, 2, 2, 5], [2, 5, 3, 4, 6], [0, 0, 1, 1, 1])
+    edges = [(0, 1, 0), (1, 2, 0), (2, 3, 1), (2, 4, 1)]
+    batch = synth.make_batch([0], [1], [0], [5], [])
+    for sem, rejects, n_emb in ((synth.ISO, 2, 2), (synth.HOMO, 1, 5)):
+        q = synth.make_query(5, [0] * 5, edges, sem)
+        o = Oracle(g, [q])
+        m = B.Matcher(g, [q], flags=B.F_EMIT, n_elabels=2)
+        try:
+            o.apply_batch(batch)
+            m.apply_batch(batch)
+            assert m.stats()["vf_rejects"] == [rejects, 0], (sem, m.stats()["vf_rejects"])
+            assert o.count(0) == n_emb
+            np.testing.assert_array_equal(canon(m.keys(0)), o.result(0))
+            assert m.result(0)["dig_new"] == o.digest(0)
+        finally:
+            m.close()
+            o.close()
+
+
 def test_unsupported_queries_are_rejected(B):
     g = synth.make_graph(3, [1, 1, 1], [0], [1], [0])
     with pytest.raises(B.MnemonicError) as ei:
