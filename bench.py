@@ -54,13 +54,17 @@ HBM_PEAK_GBS = 8000.0
 ENUM_SRC = os.path.join(ROOT, "paper_2206_09983_amd", "csrc", "mn_enum.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_expand_traffic_rmat_s20.txt")
 
-# Algorithmic bytes k_expand must move, per unit of work it counts:
-#   candidate: one 8 B adjacency entry; vertex-filter test: one 4 B word;
-#   closing-edge lookup: one 4 B word per probe (binary search, run walk,
-#   offsets); edge key gathered for a tuple: 8 B; tuple key written: 8 B.
-# Rows of partial embeddings passed between levels are this implementation's
-# choice, not the method's, and are not counted.
-BYTES = {"entries_scanned": 8, "vf_reads": 4, "probe_words": 4, "key_reads": 8, "tuple_words": 8}
+# Algorithmic bytes of the enumerator, per unit of work the library counts
+# (the per-unit figures of the hot-path scope's measurement section):
+#   work unit (seed): 8 B
+#   candidate: its 8 B adjacency entry, plus the 4 B edge-index (edgeMatcher)
+#     word and the 4 B vertex-filter word the method tests per candidate
+#   closing-edge (intersection) lookup: 4 B per probe actually executed
+#   emitted tuple: 8 B per query-edge key written
+# Rows of partial embeddings passed between levels, and the keys gathered from
+# them, are this implementation's choice, not the method's, and are not
+# counted. Each term's total is printed inside the line's roofline object.
+BYTES = {"seeds": 8, "entries_scanned": 8 + 4 + 4, "probe_words": 4, "tuple_words": 8}
 
 
 def log(*a):
@@ -70,8 +74,8 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=16)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--n-init", type=int, default=1 << 24)
     ap.add_argument("--batch", type=int, default=65536)
@@ -97,15 +101,35 @@ def parse():
     return ap.parse_args()
 
 
+def timed_batches(n_total, warmup, steps):
+    """Indices of the timed batches: `steps` batches spread at an equal stride
+    over the stream after the `warmup` first ones (consecutive when the stream
+    is no longer than warmup + steps), so the timing covers the graph as it
+    grows and shrinks over the whole stream."""
+    if steps < 1:
+        raise SystemExit("--steps must be at least 1")
+    if warmup + steps > n_total:
+        raise SystemExit("the stream has %d batches: --warmup + --steps must not exceed it" % n_total)
+    stride = max(1, (n_total - warmup) // steps)
+    return [warmup + i * stride for i in range(steps)]
+
+
+def describe_batches(idx):
+    if len(idx) > 1:
+        return "%d..%d step %d (%d batches)" % (idx[0], idx[-1], idx[1] - idx[0], len(idx))
+    return "%d (1 batch)" % idx[0]
+
+
 def enum_source_hash():
     with open(ENUM_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(workload):
+def read_traffic(workload, steps, warmup):
     """Per-launch HBM bytes of the enumerator from the committed counter
-    summary, or None when absent, taken on a different kernel source, or
-    taken on another workload (the counters cover the default R-MAT stream)."""
+    summary, or None when absent, taken on a different kernel source, on
+    other timed steps, or on another workload (the counters cover the default
+    R-MAT stream)."""
     if workload != "rmat" or not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -115,6 +139,8 @@ def read_traffic(workload):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != enum_source_hash():
+        return None
+    if kv.get("bench_steps_warmup") != "%d %d" % (steps, warmup):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -294,7 +320,6 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     binding.load()  # raises if the HIP library is missing: there is no other path
     torch.cuda.set_device(0)
-    n_batches = args.warmup + args.steps
     t0 = time.perf_counter()
     # the whole 2^23-insertion stream is always drawn, so the graph and every
     # batch are the same whatever --steps and --warmup say
@@ -304,10 +329,14 @@ def main():
         case = synth.multiquery_case(scale=args.scale, n_init=args.n_init, del_frac=args.del_frac, seed=args.seed,
                                      queries=synth.queries_from_json(qdoc["queries"]))
     else:
-        case = synth.rmat_case(scale=args.scale, n_init=args.n_init, n_stream=max(1 << 23, n_batches * args.batch),
+        case = synth.rmat_case(scale=args.scale, n_init=args.n_init,
+                               n_stream=max(1 << 23, (args.warmup + args.steps) * args.batch),
                                batch=args.batch, del_frac=args.del_frac, seed=args.seed, query_seed=7)
     log("generated %s: %d initial edges, %d batches in %.1f s" % (case["name"], len(case["graph"]["src"]),
                                                                    len(case["batches"]), time.perf_counter() - t0))
+    timed = timed_batches(len(case["batches"]), args.warmup, args.steps)
+    n_batches = timed[-1] + 1
+    log("timed batches: %s" % describe_batches(timed))
     stream = torch.cuda.current_stream()
     dev_batches = []
     for b in case["batches"][:n_batches]:
@@ -349,13 +378,17 @@ def main():
         r = {"lat": [], "tot": {k: 0 for k in BYTES}, "expand_ms": 0.0, "launches": 0, "rows": 0, "tuples": 0,
              "edges": 0, "results": []}
         steps = []
+        want = set(timed)
         gc.collect()
         gc.disable()  # no collector pass inside the timed region
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
         for i in range(args.warmup, n_batches):
+            if i not in want:  # between timed steps the stream goes on, untimed
+                m.apply_batch(dev_batches[i])
+                continue
+            torch.cuda.synchronize()
             tb = time.perf_counter()
             m.apply_batch(dev_batches[i])  # returns once the batch's counts and digests are on the host
+            torch.cuda.synchronize()
             r["lat"].append((time.perf_counter() - tb) * 1e3)
             st = m.stats()
             for p in range(2):
@@ -369,9 +402,8 @@ def main():
             res = [m.result(q) for q in range(len(case["queries"]))]
             r["results"].append([(x["n_new"], x["dig_new"], x["n_expired"], x["dig_expired"]) for x in res])
             steps.append((i, r["lat"][-1], st))
-        torch.cuda.synchronize()
-        r["elapsed"] = time.perf_counter() - t_start
         gc.enable()
+        r["elapsed"] = sum(r["lat"]) * 1e-3
         for i, lat, st in steps:  # logged after the timed region
             log("[%s] step %d: %.2f ms (enumerate %.2f + %.2f ms, of which k_expand %.2f + %.2f ms in %s launches), "
                 "seeds %s, rows %s, candidates %s, tuples %s%s" % (
@@ -421,7 +453,7 @@ def main():
     per_launch = alg_bytes / max(launches, 1)
     avg_ms = expand_ms / max(launches, 1)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = read_traffic(args.workload)
+    traffic = read_traffic(args.workload, args.steps, args.warmup)
     lat_s = sorted(lat)
 
     def pct(p):
@@ -446,12 +478,14 @@ def main():
             "vertices": 1 << args.scale, "initial_edges": args.n_init, "batch_insertions": args.batch,
             "batch_deletions": int(args.del_frac * args.batch), "queries": [q["name"] for q in case["queries"]],
             "emit_tuples": not args.count_only, "seed": args.seed,
+            "stream_batches": len(case["batches"]), "timed_batches": describe_batches(timed),
         } if args.workload == "rmat" else {
             "workload": "rmat_s%d_init%d_logbatch1000-262144_del%d%%_64q" % (
                 args.scale, args.n_init, int(round(args.del_frac * 100))),
             "vertices": 1 << args.scale, "initial_edges": args.n_init,
-            "batch_insertions": [len(case["batches"][i]["src"]) for i in range(args.warmup, n_batches)],
+            "batch_insertions": [len(case["batches"][i]["src"]) for i in timed],
             "queries": len(case["queries"]), "emit_tuples": not args.count_only, "seed": args.seed,
+            "stream_batches": len(case["batches"]), "timed_batches": describe_batches(timed),
             "autotune": bool(args.autotune), "expand_tile": m_tile,
         }),
         "embeddings_per_s": tuples / elapsed,
@@ -465,7 +499,9 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_expand", "alg_bytes_per_launch": per_launch, "avg_launch_ms": avg_ms,
-            "launches": launches, "frontier_rows_per_launch": rows / max(launches, 1),
+            "launches": launches, "sum_launch_ms": expand_ms, "frontier_rows_per_launch": rows / max(launches, 1),
+            # each term of the byte model over the timed steps: units counted and bytes per unit
+            "terms": {k: {"units": tot[k], "bytes_per_unit": BYTES[k], "bytes": BYTES[k] * tot[k]} for k in BYTES},
         },
     }
     # the achievable HBM rate on this device (a plain copy), beside the published peak

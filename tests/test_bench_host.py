@@ -41,3 +41,21 @@ def test_cpu_baseline_times_the_oracle_pinned_and_restores_affinity():
 @pytest.mark.skipif(not os.path.exists("/proc/cpuinfo"), reason="no /proc/cpuinfo")
 def test_cpu_model_is_read():
     assert load_bench().cpu_model()
+
+
+def test_timed_batches_spread_over_the_stream():
+    bench = load_bench()
+    t = bench.timed_batches(128, 5, 20)
+    assert len(t) == 20 and t[0] == 5 and t == sorted(set(t)) and t[-1] < 128
+    assert t[1] - t[0] == (128 - 5) // 20  # equal stride over what follows the warm-up
+    assert bench.timed_batches(25, 5, 20) == list(range(5, 25))  # no room for a stride: consecutive
+    assert bench.describe_batches(t) == "5..119 step 6 (20 batches)"
+    with pytest.raises(SystemExit):
+        bench.timed_batches(10, 5, 20)
+
+
+def test_byte_model_terms_follow_the_scope():
+    # per unit: 8 B per work unit, 8 B entry + 4 B edge-index word + 4 B
+    # filter word per candidate, 4 B per closing-edge probe, 8 B per tuple key
+    bench = load_bench()
+    assert bench.BYTES == {"seeds": 8, "entries_scanned": 16, "probe_words": 4, "tuple_words": 8}
