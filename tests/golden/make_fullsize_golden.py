@@ -1,0 +1,88 @@
+"""Writes the full-size golden results: counts and both digests per batch,
+query and phase, computed by the CPU oracle alone.
+
+Test infrastructure, run once offline (it takes minutes of CPU time):
+    python tests/golden/make_fullsize_golden.py rmat        # fullsize_rmat_s20.json
+    python tests/golden/make_fullsize_golden.py multiquery  # fullsize_multiquery_s20.json
+Each file records the workload's parameters and the oracle's results for the
+first batches of its stream: the R-MAT benchmark stream (2^20 vertices, 2^24
+initial edges, batches of 65,536 insertions and 6,553 oldest-key deletions,
+six queries) and the 64-query stream (the same edges in log-uniform
+batches). Only oracle/ and the seeded generators are used: no result here
+comes from the HIP library.
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle.core import Oracle  # noqa: E402
+from paper_2206_09983_amd import synth  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+RMAT = dict(scale=20, n_init=1 << 24, n_stream=1 << 23, batch=65536, del_frac=0.10, seed=7, query_seed=7)
+RMAT_BATCHES = 6
+MULTI = dict(scale=20, n_init=1 << 24, del_frac=0.10, seed=7)
+MULTI_BATCHES = 4
+
+
+def rmat_case():
+    return synth.rmat_case(**RMAT)
+
+
+def multiquery_case():
+    with open(os.path.join(HERE, "multiquery_queries.json")) as f:
+        qdoc = json.load(f)
+    return synth.multiquery_case(queries=synth.queries_from_json(qdoc["queries"]), **MULTI)
+
+
+def oracle_results(case, n_batches):
+    o = Oracle(case["graph"], case["queries"])
+    out = []
+    try:
+        for i in range(n_batches):
+            b = case["batches"][i]
+            t = time.perf_counter()
+            o.apply_batch(b)
+            rec = {"index": i, "n_ins": int(len(b["src"])), "n_del": int(len(b["del_keys"])), "queries": []}
+            for qi, q in enumerate(case["queries"]):
+                rq = {"name": q.get("name", "")}
+                for ph, nm in ((False, "new"), (True, "expired")):
+                    d = o.digest(qi, ph)
+                    rq[nm] = [o.count(qi, ph), d[0], d[1]]
+                rec["queries"].append(rq)
+            out.append(rec)
+            print("batch %d: %.1f s, %d new / %d expired embeddings" % (
+                i, time.perf_counter() - t, sum(r["new"][0] for r in rec["queries"]),
+                sum(r["expired"][0] for r in rec["queries"])), flush=True)
+    finally:
+        o.close()
+    return out
+
+
+def main(which):
+    t = time.perf_counter()
+    if which == "rmat":
+        case, params, n, name = rmat_case(), RMAT, RMAT_BATCHES, "fullsize_rmat_s20.json"
+    elif which == "multiquery":
+        case, params, n, name = multiquery_case(), MULTI, MULTI_BATCHES, "fullsize_multiquery_s20.json"
+    else:
+        raise SystemExit("usage: make_fullsize_golden.py rmat|multiquery")
+    print("generated %s in %.1f s" % (case["name"], time.perf_counter() - t), flush=True)
+    doc = {"workload": case["name"], "params": params, "generator": "paper_2206_09983_amd.synth." + which + "_case",
+           "command": "python tests/golden/make_fullsize_golden.py " + which,
+           "queries": [q.get("name", "") for q in case["queries"]],
+           "result_format": "per query and phase: [count, digest seed A, digest seed B] (digests mod 2^64)",
+           "batches": oracle_results(case, n)}
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(doc, f, indent=1)
+        f.write("\n")
+    print("wrote", name)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "rmat")
