@@ -1,9 +1,16 @@
 """GPU parity at the benchmark's full size, in the configuration bench.py times.
 
 The R-MAT stream (2^20 vertices, 2^24 initial edges, batches of 65,536
-insertions + 6,553 oldest-key deletions, six queries) is too large for the
-single-thread oracle to recompute whole result lists per batch, so this test
-checks what holds at any size plus outputs the oracle can compute one by one:
+insertions + 6,553 oldest-key deletions, six queries):
+
+  * counts and both digests of every query and phase of the first six
+    batches (the benchmark's first timed batch is the sixth) equal the
+    oracle's, stored in tests/golden/fullsize_rmat_s20.json by a script that
+    runs only the oracle; the first snapshot's full lists, sorted on the
+    device, equal the oracle's lists computed here;
+
+and, where the oracle cannot recompute whole lists per batch within a test,
+what holds at any size plus outputs the oracle can compute one by one:
 
   * every emitted tuple is an embedding of the post-insert graph (live edges,
     consistent vertex map, labels, injectivity under isomorphism), tuples are
@@ -15,6 +22,8 @@ checks what holds at any size plus outputs the oracle can compute one by one:
   * the homomorphic 5-path counts equal the closed form (chains of sparse
     matrix-vector products) on the graphs before and after each phase.
 """
+import json
+import os
 import sys
 import time
 
@@ -194,6 +203,66 @@ def test_full_size_rmat_stream(request):
             say("batch %d: %s new, %s expired; %d tuples of sampled units matched the oracle (%.1f s)" % (
                 bi, [m.result(i)["n_new"] for i in range(len(qs))],
                 [m.result(i)["n_expired"] for i in range(len(qs))], total, time.time() - t0))
+    finally:
+        m.close()
+        o.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fullsize_rmat_s20.json")
+
+
+def device_batch(torch, b):
+    return {"src": torch.from_numpy(b["src"].view(np.int32)).cuda(),
+            "dst": torch.from_numpy(b["dst"].view(np.int32)).cuda(),
+            "elabel": torch.from_numpy(b["elabel"]).cuda(),
+            "ts": torch.from_numpy(b["ts"]).cuda(),
+            "del_keys": torch.from_numpy(b["del_keys"].view(np.int64)).cuda()}
+
+
+def test_full_size_stream_equals_the_oracle_golden_and_lists():
+    torch = pytest.importorskip("torch")
+    from paper_2206_09983_amd import binding as B
+    B.load()
+    with open(GOLDEN) as f:
+        gold = json.load(f)
+    t0 = time.time()
+    case = synth.rmat_case(**{k: v for k, v in gold["params"].items()})
+    qs = case["queries"]
+    assert [q["name"] for q in qs] == gold["queries"]
+    say("full-size golden: %s, %d batches (%.1f s)" % (case["name"], len(gold["batches"]), time.time() - t0))
+    stream = torch.cuda.current_stream()
+    # counts and digests of every batch, in the benchmark's configuration
+    m = B.Matcher(case["graph"], qs, flags=B.F_EMIT | B.F_TIMING, out_capacity=1 << 22,
+                  stream=stream.cuda_stream, n_elabels=32)
+    try:
+        for rec in gold["batches"]:
+            b = case["batches"][rec["index"]]
+            assert (len(b["src"]), len(b["del_keys"])) == (rec["n_ins"], rec["n_del"])
+            m.apply_batch(device_batch(torch, b))
+            for qi, rq in enumerate(rec["queries"]):
+                r = m.result(qi)
+                assert [r["n_new"], *r["dig_new"]] == rq["new"], (rec["index"], rq["name"], "new")
+                assert [r["n_expired"], *r["dig_expired"]] == rq["expired"], (rec["index"], rq["name"], "expired")
+            say("batch %d: counts and digests equal the oracle's (%.1f s)" % (rec["index"], time.time() - t0))
+    finally:
+        m.close()
+    # the first snapshot's lists, element by element
+    o = Oracle(case["graph"], qs)
+    m = B.Matcher(case["graph"], qs, flags=B.F_EMIT | B.F_SORT, out_capacity=1 << 22, stream=stream.cuda_stream,
+                  n_elabels=32)
+    try:
+        b = case["batches"][0]
+        m.apply_batch(device_batch(torch, b))
+        o.apply_batch(b)
+        n = 0
+        for qi in range(len(qs)):
+            for ph in (False, True):
+                got = m.keys(qi, ph)
+                ref = o.result(qi, ph)
+                assert got.shape == ref.shape, (qi, ph)
+                assert np.array_equal(got, ref), (qs[qi]["name"], ph)
+                n += len(ref)
+        say("snapshot 0: %d embeddings in lists equal to the oracle's (%.1f s)" % (n, time.time() - t0))
     finally:
         m.close()
         o.close()
