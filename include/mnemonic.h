@@ -228,8 +228,41 @@ int mnemonic_create(const mnemonic_graph *g, const mnemonic_query *q, uint32_t n
 int mnemonic_apply_batch(mnemonic_ctx *ctx, const mnemonic_edges *ins, const uint64_t *del_keys,
                          uint64_t n_del, uint64_t *first_new_key);
 
+/*
+ * mnemonic_apply_batch for callers that cannot allocate memory: code being
+ * captured into a HIP graph, serving loops with a fixed memory budget, and
+ * harnesses that forbid allocation. It applies the snapshot exactly as
+ * mnemonic_apply_batch does (same arguments, same results) but calls no
+ * device or host allocation routine:
+ *   - the batch's control words (error word, readback block of counts,
+ *     digests, work tallies and overflow notes, row counters) live in one
+ *     scratch array per GPU, of at most 65,536 words (512 KiB); a query set
+ *     whose control block needs more (about 130 words per query) returns
+ *     MNEMONIC_E_CAPACITY and changes nothing;
+ *   - every other buffer must already be large enough: a batch whose arrays
+ *     exceed the context's batch buffers returns MNEMONIC_E_CAPACITY and
+ *     changes nothing. The enumeration runs in the level buffers, expansion
+ *     tiles and output lists the context holds; when they are too small the
+ *     batch is still applied (the graph and index move on, later batches may
+ *     follow) but it returns MNEMONIC_E_CAPACITY and its results are
+ *     unavailable: mnemonic_get_result and mnemonic_copy_keys return
+ *     MNEMONIC_E_CAPACITY until the next batch. Buffers grow only through
+ *     mnemonic_apply_batch: a caller sizes the context first (out_capacity
+ *     and rows_per_level at creation, or earlier batches through
+ *     mnemonic_apply_batch, which size buffers from the rates they see);
+ *   - timing (MNEMONIC_F_TIMING), tile autotuning and traces are not
+ *     recorded; the learned scheduler falls back to the static order when
+ *     its decision list has no room (results are the same either way).
+ * Every call on one GPU shares that GPU's scratch array: calls that overlap
+ * on one GPU (two contexts on two streams, two threads) race and must not
+ * be issued. Errors: those of mnemonic_apply_batch, and CAPACITY as above. */
+int mnemonic_apply_batch_noalloc(mnemonic_ctx *ctx, const mnemonic_edges *ins, const uint64_t *del_keys,
+                                 uint64_t n_del, uint64_t *first_new_key);
+
 /* Counts, digests and device tuple pointers of the last batch for one query
- * (index in creation order). Errors: ARG (bad ctx, query or out). */
+ * (index in creation order). Errors: ARG (bad ctx, query or out), CAPACITY
+ * (the last batch's results are unavailable, see
+ * mnemonic_apply_batch_noalloc). */
 int mnemonic_get_result(mnemonic_ctx *ctx, uint32_t query, mnemonic_result *out);
 
 /* Copies the new (expired != 0: expired) tuples of one query to host_buf,

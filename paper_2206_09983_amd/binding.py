@@ -37,7 +37,8 @@ ERRORS = {
 EXPORTS = ["mnemonic_create", "mnemonic_apply_batch", "mnemonic_get_result", "mnemonic_copy_keys",
            "mnemonic_get_stats", "mnemonic_last_error", "mnemonic_destroy", "mnemonic_set_scheduler",
            "mnemonic_query_orders", "mnemonic_set_trace", "mnemonic_get_trace", "mnemonic_mlp_predict",
-           "mnemonic_mlp_grad", "mnemonic_mlp_adam", "mnemonic_set_queries", "mnemonic_fail_alloc_after"]
+           "mnemonic_mlp_grad", "mnemonic_mlp_adam", "mnemonic_set_queries", "mnemonic_fail_alloc_after",
+           "mnemonic_apply_batch_noalloc"]
 
 _u8p = C.POINTER(C.c_uint8)
 _u32p = C.POINTER(C.c_uint32)
@@ -115,6 +116,8 @@ def load():
                                   C.POINTER(mnemonic_options), vp, C.POINTER(vp)]
     L.mnemonic_apply_batch.restype = C.c_int
     L.mnemonic_apply_batch.argtypes = [vp, C.POINTER(mnemonic_edges), _u64p, C.c_uint64, _u64p]
+    L.mnemonic_apply_batch_noalloc.restype = C.c_int
+    L.mnemonic_apply_batch_noalloc.argtypes = [vp, C.POINTER(mnemonic_edges), _u64p, C.c_uint64, _u64p]
     L.mnemonic_get_result.restype = C.c_int
     L.mnemonic_get_result.argtypes = [vp, C.c_uint32, C.POINTER(mnemonic_result)]
     L.mnemonic_copy_keys.restype = C.c_int
@@ -207,10 +210,10 @@ def mnemonic_create(graph, queries, flags=F_EMIT, out_capacity=0, stream=None, n
     return ctx
 
 
-def mnemonic_apply_batch(ctx, batch):
+def mnemonic_apply_batch(ctx, batch, no_alloc=False):
     """batch: dict with src, dst, elabel, ts, del_keys as numpy arrays (host) or
     torch device tensors (int32/uint8/int64; read in place). Returns the first
-    inserted key."""
+    inserted key. no_alloc: call mnemonic_apply_batch_noalloc instead."""
     L = load()
     src = batch["src"]
     on_dev = hasattr(src, "data_ptr") and getattr(src, "is_cuda", False)
@@ -227,7 +230,8 @@ def mnemonic_apply_batch(ctx, batch):
     e = mnemonic_edges(n, _ptr(s, C.c_uint32), _ptr(d, C.c_uint32), _ptr(l, C.c_uint8),
                        _ptr(t, C.c_int64), 1 if on_dev else 0)
     first = C.c_uint64(0)
-    rc = L.mnemonic_apply_batch(ctx, C.byref(e), _ptr(k, C.c_uint64) if nd else None, nd, C.byref(first))
+    fn = L.mnemonic_apply_batch_noalloc if no_alloc else L.mnemonic_apply_batch
+    rc = fn(ctx, C.byref(e), _ptr(k, C.c_uint64) if nd else None, nd, C.byref(first))
     _check(rc, ctx)
     return int(first.value)
 
@@ -357,8 +361,8 @@ class Matcher:
         self.n_q = len(queries)
         self.ctx = mnemonic_create(graph, queries, flags, out_capacity, stream, n_elabels, rows_per_level)
 
-    def apply_batch(self, batch):
-        return mnemonic_apply_batch(self.ctx, batch)
+    def apply_batch(self, batch, no_alloc=False):
+        return mnemonic_apply_batch(self.ctx, batch, no_alloc)
 
     def result(self, q):
         return mnemonic_get_result(self.ctx, q)

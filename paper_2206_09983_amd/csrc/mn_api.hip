@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,10 +60,52 @@ inline uint32_t ceil_log2(uint64_t x) {
 // device were out of memory; 0 means disarmed.
 uint64_t g_fail_alloc_in = 0;
 
+// Set while mnemonic_apply_batch_noalloc runs on this thread: the call fits
+// its batch into the buffers the context already holds, and a buffer that
+// would have to grow refuses instead of allocating.
+thread_local bool t_no_alloc = false;
+
+struct NoAllocScope {
+    NoAllocScope() { t_no_alloc = true; }
+    ~NoAllocScope() { t_no_alloc = false; }
+};
+
+// The per-batch control words of mnemonic_apply_batch_noalloc (readback block
+// of counts, digests, work tallies and overflow notes; error word; row
+// counters; candidate total; decision-list count) live in this array instead
+// of the context's own: one copy per GPU, shared by every such call on it.
+// Host code never passes the array's name to a kernel: it uses the address
+// hipGetSymbolAddress returns for the device, looked up once per device when
+// the device's first context is created.
+constexpr uint64_t MN_NOALLOC_WORDS = 1u << 16;  // 512 KiB
+constexpr int MN_MAX_DEVICES = 64;
+__device__ __align__(256) uint64_t scratch[MN_NOALLOC_WORDS];
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_ptr[MN_MAX_DEVICES] = {};
+
+// Looks up the device address of `scratch` on `device` (the current device).
+void setup_scratch(int device) {
+    if (device < 0 || device >= MN_MAX_DEVICES) return;  // the no-allocation call then reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = static_cast<uint64_t*>(ptr);
+}
+
+uint64_t* scratch_of(int device) {
+    if (device < 0 || device >= MN_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 template <typename T>
 void dev_alloc(T*& p, size_t n) {
     void* q = nullptr;
     if (n == 0) n = 1;
+    if (t_no_alloc)
+        throw ApiError{MNEMONIC_E_CAPACITY, "the batch needs a buffer of " + std::to_string(n * sizeof(T)) +
+                                                " bytes the context does not hold (no-allocation call)"};
     if (g_fail_alloc_in && --g_fail_alloc_in == 0)
         throw ApiError{MNEMONIC_E_OOM, "device allocation of " + std::to_string(n * sizeof(T)) +
                                            " bytes failed (injected)"};
@@ -279,6 +322,9 @@ struct mnemonic_ctx {
     // the context only reports why (broken_why).
     bool broken = false;
     std::string broken_why;
+    // The last batch (a no-allocation call) could not fit its enumeration in
+    // the buffers the context holds: its results are unavailable.
+    bool results_incomplete = false;
     // Largest tuples per phase edge seen, per (query, phase) (-1: none yet):
     // sizes the output buffers before a batch, so that a batch larger than
     // any before does not re-run a phase to grow them.
@@ -929,6 +975,7 @@ void reset_phase(mnemonic_ctx* c, int p) {
 void grow_level(mnemonic_ctx* c, uint32_t L, uint64_t need) {
     auto& B = c->lvb[L];
     if (need <= B.cap) return;
+    if (t_no_alloc) return;  // the level keeps its rows; a larger need is noted by the kernels
     uint64_t nc = std::min<uint64_t>(c->rows_max, std::max<uint64_t>(need, std::max<uint64_t>(B.cap * 2, 4096)));
     HIPCHK(hipStreamSynchronize(c->stream));
     dev_free(B.rows);
@@ -1019,9 +1066,12 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
     if (T == 0) return;
     const bool next = L + 1 < c->max_levels;
     if (next) grow_level(c, L + 1, T);
-    // chunks bounded by the next level's rows (each candidate yields <= 1 row)
-    const uint64_t K = next ? c->lvb[L + 1].cap : (1ull << 26);
-    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
+    // chunks bounded by the next level's rows (each candidate yields <= 1 row),
+    // and in a no-allocation call by the tile buffer the context holds
+    uint64_t K = next ? c->lvb[L + 1].cap : (1ull << 26);
+    if (t_no_alloc) K = std::min<uint64_t>(K, c->cap_tiles >= 2 ? (c->cap_tiles - 1) * MN_BLOCK : 0);
+    if (K == 0) throw ApiError{MNEMONIC_E_CAPACITY, "no room for one level of the enumeration"};
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0 && !t_no_alloc;
     for (uint64_t c0 = 0; c0 < T; c0 += K) {
         const uint64_t c1 = std::min<uint64_t>(T, c0 + K);
         uint32_t* n_out = c->d_nrows + L + 1;
@@ -1082,7 +1132,7 @@ void resolve_events(mnemonic_ctx* c) {
 // and runs the phase again.
 void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint64_t n0_max, uint64_t ns) {
     hipStream_t s = c->stream;
-    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0 && !t_no_alloc;
     // every level takes some rows, so that an overflow always leaves a note;
     // levels and the candidate buffer are sized at the largest rates seen
     // with a margin, so that a batch larger than any before does not re-run
@@ -1099,13 +1149,20 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
             if (c->rate[po.phase][L] > 0) want = std::max<uint64_t>(want, (uint64_t)(1.5 * c->rate[po.phase][L] * (double)ns));
         if (want > c->cand_k && want <= most / 2) c->cand_k = std::min<uint64_t>(most, std::max<uint64_t>(want, 2 * c->cand_k));
     }
-    const uint64_t need_tiles = mn_expand_tiles(0, c->cand_k) + 1;
+    // candidates one launch may take: bounded by the tile buffer (a
+    // no-allocation call takes what the buffer it has covers)
+    uint64_t K = c->cand_k;
+    const uint64_t need_tiles = mn_expand_tiles(0, K) + 1;
     if (need_tiles > c->cap_tiles) {
-        HIPCHK(hipStreamSynchronize(s));
-        dev_free(c->d_tiles);
-        c->cap_tiles = 0;
-        dev_alloc(c->d_tiles, need_tiles);
-        c->cap_tiles = need_tiles;
+        if (t_no_alloc) {
+            K = c->cap_tiles >= 2 ? (c->cap_tiles - 1) * MN_BLOCK : 0;
+        } else {
+            HIPCHK(hipStreamSynchronize(s));
+            dev_free(c->d_tiles);
+            c->cap_tiles = 0;
+            dev_alloc(c->d_tiles, need_tiles);
+            c->cap_tiles = need_tiles;
+        }
     }
     uint64_t n_max = std::min<uint64_t>(n0_max, c->lvb[0].cap);
     for (uint32_t L = 0; L < c->max_levels; L++) {
@@ -1121,7 +1178,6 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
                               c->d_zr + (L ? c->note_rows(po.phase, L - 1) : c->note_seed(po.phase)));
         // candidates are bounded by the tile buffer and the grid only; rows
         // past the next level's buffer are counted and noted
-        const uint64_t K = c->cand_k;
         unsigned long long* note = c->d_zr + c->note_cand(po.phase, L);
         const double rt = c->rate[po.phase][L];
         const uint64_t expect = rt < 0 ? (~0ull >> 8) : (uint64_t)(rt * (double)ns) + 1;
@@ -1155,7 +1211,7 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
 // size; otherwise they run device-sized (device_levels).
 void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_slots, bool host_chunks = false) {
     hipStream_t s = c->stream;
-    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0;
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0 && !t_no_alloc;
     if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], s));
     if (n_slots && c->n_static) {
         GraphView g = make_view(c, false);
@@ -1166,13 +1222,18 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
         // keep the worst case.
         const double r0 = c->rate[p][MN_MAXLV];
         const double per_slot = (host_chunks || r0 < 0) ? (double)c->n_static : std::min<double>(c->n_static, 1.5 * r0 + 0.01);
-        const uint64_t chunk = std::max<uint64_t>(1, (uint64_t)((double)c->rows_max / per_slot));
+        // a no-allocation call walks the start rows in chunks its first level holds
+        const double room = t_no_alloc && host_chunks && c->max_levels ? (double)c->lvb[0].cap : (double)c->rows_max;
+        const uint64_t chunk = std::max<uint64_t>(1, (uint64_t)(room / per_slot));
         c->chunk_ns[p] = std::min<uint64_t>(chunk, n_slots);
         for (uint64_t s0 = 0; s0 < n_slots; s0 += chunk) {
             const uint64_t ns = std::min<uint64_t>(chunk, n_slots - s0);
             if (c->max_levels)  // else every plan emits at once
                 grow_level(c, 0, std::min<uint64_t>(c->rows_max, (uint64_t)(per_slot * (double)ns) + 1024));
-            const bool decide = c->max_levels && c->deciding();
+            // without room for the decision list (no-allocation call) the start
+            // rows keep the static order: the results do not depend on it
+            const bool decide = c->max_levels && c->deciding() && !(t_no_alloc && c->cap_dec < c->lvb[0].cap);
+            if (!decide) g.dec = nullptr;
             if (decide) {
                 if (c->cap_dec < c->lvb[0].cap) {
                     HIPCHK(hipStreamSynchronize(s));
@@ -1270,6 +1331,19 @@ bool absorb_notes(mnemonic_ctx* c, int p, bool& host_chunks, uint64_t& cause, st
     return again;
 }
 
+// Whether sort_outputs finds every scratch buffer it needs already allocated.
+bool sort_fits(const mnemonic_ctx* c) {
+    for (uint32_t q = 0; q < c->n_q; q++)
+        for (int p = 0; p < 2; p++) {
+            const uint64_t n = std::min<uint64_t>(c->h_zr[c->zr_count(p) + q], c->houts[q].cap[p]);
+            if (n <= 1) continue;
+            if (n > c->cap_srt || n * c->hq[q].n_qe > c->cap_srt_rows ||
+                mn_tuple_sort_scratch_words((uint32_t)n) > c->cap_srt_scr)
+                return false;
+        }
+    return true;
+}
+
 // Puts every query's result tuples of both phases in lexicographic order.
 void sort_outputs(mnemonic_ctx* c) {
     hipStream_t s = c->stream;
@@ -1323,9 +1397,9 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     if (n_ins + n_del >= (1ull << 31)) throw ApiError{MNEMONIC_E_ARG, "batch too large"};
     ensure_capacity(c, n_ins, n_del);
     static const uint32_t kItems[3] = {1, 2, 4};
-    const bool tune = enumerate && c->tuning();
+    const bool tune = enumerate && c->tuning() && !t_no_alloc;
     if (tune) c->tile_items = kItems[c->tune_batch % 3];
-    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0 && enumerate;
+    const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0 && enumerate && !t_no_alloc;
     for (int p = 0; p < 2; p++) {
         c->ms_expand[p] = 0;
         c->n_expand[p] = 0;
@@ -1391,7 +1465,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     b.debi_bits = c->d_debi_bits;
     b.vf_bits = c->d_vf_bits;
 
-    if (enumerate && (c->flags & MNEMONIC_F_EMIT) && !(c->flags & MNEMONIC_F_INDEX_ONLY)) {
+    if (enumerate && (c->flags & MNEMONIC_F_EMIT) && !(c->flags & MNEMONIC_F_INDEX_ONLY) && !t_no_alloc) {
         // outputs sized for this batch at the largest per-edge rates seen,
         // with a margin; at most 4x per batch, so one unusual batch cannot
         // claim a large share of the device
@@ -1414,6 +1488,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     if (enumerate) {
         c->broken = true;
         c->broken_why = "a batch";
+        c->results_incomplete = false;
     }
     mn_launch_reset(c->d_err, c->d_zr, c->n_zr, s);
     if (c->tr_cap) {  // the trace holds this batch's start rows only
@@ -1553,6 +1628,21 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                         if (last) why += " [query " + std::to_string(q) + " output " + std::to_string(need[2 * q + p]) + "]";
                     }
                 }
+            if (t_no_alloc && (redo[0] || redo[1])) {
+                // No buffer may grow in this call. Levels that outgrew theirs
+                // are walked again in chunks the buffers hold; output lists that
+                // are too small cannot be helped: the batch stands, its results
+                // are incomplete.
+                bool fits = (cause[0] | cause[1]) & 8u ? false : true;
+                for (int p = 0; p < 2 && fits; p++)
+                    if (redo[p] && c->max_levels && c->lvb[0].cap < c->n_static) fits = false;
+                if (!fits) {
+                    c->results_incomplete = true;
+                    for (int p = 0; p < 2; p++) c->rerun_causes[p] |= cause[p];
+                    break;
+                }
+                for (int p = 0; p < 2; p++) host_chunks[p] = host_chunks[p] || redo[p];
+            }
             for (int p = 0; p < 2; p++)
                 if (redo[p]) {
                     c->reruns[p]++;
@@ -1560,7 +1650,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                 }
             if (!redo[0] && !redo[1]) break;
             if (last) throw ApiError{MNEMONIC_E_HIP, "enumeration did not settle (internal)" + why};
-            grow_outputs(c, need);
+            if (!t_no_alloc) grow_outputs(c, need);
             if (redo[0]) {
                 // per direction: deletion flags cleared before insertion flags are set
                 mn_launch_set_flags(c->d_adj[0], c->d_delpos[cur][0], c->d_adj[1], c->d_delpos[cur][1],
@@ -1581,9 +1671,13 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
             read_zr(c, nullptr);
             c->summarize();
         }
-        if (emit && (c->flags & MNEMONIC_F_SORT)) {
-            sort_outputs(c);
-            HIPCHK(hipStreamSynchronize(s));
+        if (emit && (c->flags & MNEMONIC_F_SORT) && !c->results_incomplete) {
+            if (t_no_alloc && !sort_fits(c)) {
+                c->results_incomplete = true;
+            } else {
+                sort_outputs(c);
+                HIPCHK(hipStreamSynchronize(s));
+            }
         }
         if (timing) resolve_events(c);
         if (tune) {
@@ -1664,8 +1758,43 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         c->have_result = true;
     }
     c->broken = false;
+    if (c->results_incomplete)
+        throw ApiError{MNEMONIC_E_CAPACITY, "batch applied, but its enumeration needs larger buffers than the context "
+                                            "holds (causes " + std::to_string(c->rerun_causes[0]) + ", " +
+                                            std::to_string(c->rerun_causes[1]) + "): its results are unavailable"};
     return MNEMONIC_OK;
 }
+
+// Points the context's per-batch control words into the device's scratch
+// array for the duration of a no-allocation call, and back afterwards.
+struct ScratchSwap {
+    mnemonic_ctx* c;
+    unsigned long long* zr;
+    uint32_t* err;
+    uint32_t* nrows;
+    uint64_t* total;
+    uint32_t* dec_n;
+    static uint64_t words(const mnemonic_ctx* c) { return c->n_zr + 1 + (MN_MAXLV + 2 + 1) / 2 + 1 + 1; }
+    ScratchSwap(mnemonic_ctx* c_, uint64_t* w) : c(c_), zr(c_->d_zr), err(c_->d_err), nrows(c_->d_nrows),
+                                                 total(c_->d_total), dec_n(c_->d_dec_n) {
+        c->d_zr = reinterpret_cast<unsigned long long*>(w);
+        w += c->n_zr;
+        c->d_err = reinterpret_cast<uint32_t*>(w);
+        w += 1;
+        c->d_nrows = reinterpret_cast<uint32_t*>(w);
+        w += (MN_MAXLV + 2 + 1) / 2;
+        c->d_total = w;
+        w += 1;
+        c->d_dec_n = reinterpret_cast<uint32_t*>(w);
+    }
+    ~ScratchSwap() {
+        c->d_zr = zr;
+        c->d_err = err;
+        c->d_nrows = nrows;
+        c->d_total = total;
+        c->d_dec_n = dec_n;
+    }
+};
 
 template <typename F>
 int guarded(mnemonic_ctx* c, F&& f) {
@@ -1808,6 +1937,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         if (g->n_vertices > (1u << 24)) throw ApiError{MNEMONIC_E_LIMIT, "n_vertices > 2^24"};
         if (g->n_elabels > 256) throw ApiError{MNEMONIC_E_ARG, "n_elabels > 256"};
         HIPCHK(hipGetDevice(&c->device));
+        setup_scratch(c->device);
         c->stream = static_cast<hipStream_t>(hip_stream);
         if (opt) c->flags = opt->flags;
         // at most 2^26 rows per level: the kernels index a level's columns in 32 bits
@@ -1928,9 +2058,34 @@ int mnemonic_apply_batch(mnemonic_ctx* ctx, const mnemonic_edges* ins, const uin
     });
 }
 
+int mnemonic_apply_batch_noalloc(mnemonic_ctx* ctx, const mnemonic_edges* ins, const uint64_t* del_keys,
+                                 uint64_t n_del, uint64_t* first_new_key) {
+    if (!ctx) return MNEMONIC_E_ARG;
+    return guarded(ctx, [&]() -> int {
+        uint64_t n_ins = ins ? ins->n : 0;
+        if (n_ins && (!ins->src || !ins->dst || !ins->elabel || !ins->ts))
+            throw ApiError{MNEMONIC_E_ARG, "insertion arrays must not be NULL"};
+        if (n_del && !del_keys) throw ApiError{MNEMONIC_E_ARG, "del_keys must not be NULL"};
+        uint64_t* w = scratch_of(ctx->device);
+        if (!w) throw ApiError{MNEMONIC_E_HIP, "the device's no-allocation scratch is not set up"};
+        const uint64_t need = ScratchSwap::words(ctx);
+        if (need > MN_NOALLOC_WORDS)
+            throw ApiError{MNEMONIC_E_CAPACITY, "the query set's control block (" + std::to_string(need) +
+                                                    " words) exceeds the no-allocation scratch (" +
+                                                    std::to_string(MN_NOALLOC_WORDS) + " words)"};
+        ScratchSwap swap(ctx, w);
+        NoAllocScope no_alloc;
+        bool dev = ins && ins->on_device;
+        return run_batch(ctx, n_ins, ins ? ins->src : nullptr, ins ? ins->dst : nullptr,
+                         ins ? ins->elabel : nullptr, ins ? ins->ts : nullptr, del_keys, n_del, dev, true,
+                         first_new_key);
+    });
+}
+
 int mnemonic_get_result(mnemonic_ctx* ctx, uint32_t query, mnemonic_result* out) {
     if (!ctx || !out || query >= ctx->n_q) return MNEMONIC_E_ARG;
     if (ctx->broken) return MNEMONIC_E_HIP;
+    if (ctx->results_incomplete) return MNEMONIC_E_CAPACITY;
     memset(out, 0, sizeof(*out));
     out->n_qe = ctx->hq[query].n_qe;
     if (!ctx->have_result) return MNEMONIC_OK;
@@ -1954,6 +2109,8 @@ int mnemonic_copy_keys(mnemonic_ctx* ctx, uint32_t query, int expired, uint64_t*
     if (!ctx || query >= ctx->n_q) return MNEMONIC_E_ARG;
     return guarded(ctx, [&]() -> int {
         if (!(ctx->flags & MNEMONIC_F_EMIT)) throw ApiError{MNEMONIC_E_ARG, "context does not emit tuples"};
+        if (ctx->results_incomplete)
+            throw ApiError{MNEMONIC_E_CAPACITY, "the last batch's results are unavailable (no-allocation call)"};
         int p = expired ? 1 : 0;
         uint64_t n = ctx->have_result ? ctx->h_zr[ctx->zr_count(p) + query] : 0;
         if (needed) *needed = n;
