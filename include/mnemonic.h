@@ -184,6 +184,8 @@ typedef struct {
     uint64_t reruns[2];
     uint64_t rerun_causes[2];
     uint64_t vf_rejects[2];
+    uint64_t key_capacity;  /* places in the key-indexed maps (rings over the live key span) */
+    uint64_t key_lo;        /* every key below it is dead */
 } mnemonic_stats;
 
 /*

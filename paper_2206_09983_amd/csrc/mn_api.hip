@@ -196,11 +196,18 @@ struct mnemonic_ctx {
     uint32_t* d_free = nullptr;
     uint64_t cap_debi = 0, cap_free = 0, cap_lab = 0, cap_ts = 0, cap_key = 0, cap_dst = 0;
 
-    // key arrays
+    // key-indexed maps, rings of cap_keys (a power of two) places: key k sits
+    // at k & (cap_keys - 1). Every key below key_lo is dead, and cap_keys
+    // exceeds the span from key_lo to the end of the next batch, so the keys
+    // that may still be met never share a place; the maps' size follows the
+    // live key span (a sliding window's), not the keys ever inserted.
     uint64_t cap_keys = 0, cap_delbits = 0;
     uint32_t* d_key2slot = nullptr;
-    int64_t* d_key_ts = nullptr;  // timestamp by key (kept for retired keys too)
+    int64_t* d_key_ts = nullptr;  // timestamp by key (kept for deleted keys until they fall below key_lo)
     uint32_t* d_delbits = nullptr;
+    uint64_t key_lo = 0;           // host copy, as of the last batch
+    uint64_t key_lo_seen = 0;      // the device's value read back with the batch, committed with it
+    uint64_t* d_key_lo = nullptr;  // advanced on the device after each batch's deletions
 
     // adjacency, double-buffered
     uint64_t cap_E = 0, cap_E2 = 0, cap_E3 = 0, cap_E4 = 0;
@@ -773,6 +780,7 @@ GraphView make_view(const mnemonic_ctx* c, bool next) {
     g.vlab_idx = c->d_vlab_idx;
     g.ext2int = c->d_ext2int;
     g.key_ts = c->d_key_ts;
+    g.key_mask = c->cap_keys ? c->cap_keys - 1 : 0;
     g.n_elab_c = c->n_elab_c;
     g.n_vlab_c = c->n_vlab_c;
     g.n_static = c->n_static;
@@ -812,18 +820,38 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         dev_grow(c->d_debi, dcap, t * c->debi_words, live_slots * c->debi_words, s);
         c->cap_slots = t;
     }
-    uint64_t need_keys = c->next_key + n_ins;
-    if (need_keys > c->cap_keys) {
-        uint64_t cap = c->cap_keys;
-        dev_grow(c->d_key2slot, cap, need_keys, c->next_key, s);
-        uint64_t tcap = c->cap_keys;
-        dev_grow(c->d_key_ts, tcap, need_keys, c->next_key, s);
-        uint64_t bcap = c->cap_delbits;
-        dev_grow(c->d_delbits, bcap, (cap + 31) / 32 + 1, c->cap_delbits, s);
-        if (bcap > c->cap_delbits)
-            HIPCHK(hipMemsetAsync(c->d_delbits + c->cap_delbits, 0, (bcap - c->cap_delbits) * 4, s));
-        c->cap_delbits = bcap;
-        c->cap_keys = cap;
+    // the key rings must place every key from key_lo to the end of this batch
+    // apart; a larger ring takes the entries of the keys that may still be met
+    const uint64_t span = c->next_key + n_ins - c->key_lo;
+    if (span >= c->cap_keys) {
+        uint64_t nc = 1024;
+        while (nc < span + span / 4 + 1) nc *= 2;
+        uint32_t* k2s = nullptr;
+        int64_t* kts = nullptr;
+        uint32_t* bits = nullptr;
+        try {
+            dev_alloc(k2s, nc);
+            dev_alloc(kts, nc);
+            dev_alloc(bits, nc / 32);
+        } catch (...) {
+            dev_free(k2s);
+            dev_free(kts);
+            dev_free(bits);
+            throw;
+        }
+        mn_launch_fill_u32(bits, 0u, nc / 32, s);
+        if (c->cap_keys)
+            mn_launch_ring_copy(c->d_key2slot, c->d_key_ts, c->cap_keys - 1, k2s, kts, nc - 1, c->key_lo,
+                                c->next_key, s);
+        HIPCHK(hipStreamSynchronize(s));
+        dev_free(c->d_key2slot);
+        dev_free(c->d_key_ts);
+        dev_free(c->d_delbits);
+        c->d_key2slot = k2s;
+        c->d_key_ts = kts;
+        c->d_delbits = bits;
+        c->cap_keys = nc;
+        c->cap_delbits = nc / 32;
     }
     uint64_t need_E = c->E - c->n_pending + n_ins;
     c->hb_pos = std::max<uint32_t>(1, ceil_log2(std::max<uint64_t>(c->E, need_E) + 1));
@@ -1018,12 +1046,12 @@ RowsView rows_view(const mnemonic_ctx* c, uint32_t L) {
 
 // Pinned staging of n_zr + 1 words (the readback block and the error word).
 void size_zr_pin(mnemonic_ctx* c) {
-    if (c->cap_zr_pin >= c->n_zr + 1) return;
+    if (c->cap_zr_pin >= c->n_zr + 2) return;
     if (c->h_zr_pin) (void)hipHostFree(c->h_zr_pin);
     c->h_zr_pin = nullptr;
     c->cap_zr_pin = 0;
-    HIPCHK(hipHostMalloc((void**)&c->h_zr_pin, (c->n_zr + 1) * 8, hipHostMallocDefault));
-    c->cap_zr_pin = c->n_zr + 1;
+    HIPCHK(hipHostMalloc((void**)&c->h_zr_pin, (c->n_zr + 2) * 8, hipHostMallocDefault));
+    c->cap_zr_pin = c->n_zr + 2;
 }
 
 // The readback block into h_zr (and the error word into *err when given):
@@ -1034,10 +1062,14 @@ void read_zr(mnemonic_ctx* c, uint32_t* err) {
     if (err) {
         c->h_zr_pin[c->n_zr] = 0;
         HIPCHK(hipMemcpyAsync(c->h_zr_pin + c->n_zr, c->d_err, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c->h_zr_pin + c->n_zr + 1, c->d_key_lo, 8, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
     std::memcpy(c->h_zr.data(), c->h_zr_pin, c->n_zr * 8);
-    if (err) *err = (uint32_t)c->h_zr_pin[c->n_zr];
+    if (err) {
+        *err = (uint32_t)c->h_zr_pin[c->n_zr];
+        c->key_lo_seen = c->h_zr_pin[c->n_zr + 1];
+    }
 }
 
 uint64_t read_u32(mnemonic_ctx* c, const uint32_t* d) {
@@ -1440,6 +1472,8 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     const uint64_t dirbit = 1ull << (c->hb + c->nbr_bits);  // direction bit of the batch sort keys
     b.dirbit = dirbit;
     b.next_key = c->next_key;
+    b.key_lo = c->key_lo;
+    b.key_mask = c->cap_keys - 1;
     b.n_elabels = c->n_elabels;
     b.n_debi_bits = c->n_debi_bits;
     b.n_vf_bits = c->n_vf_bits;
@@ -1566,6 +1600,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         if (enum_on) enumerate_phase(c, 1, c->d_del_slot[cur], n_del);
         uint32_t n_free_after = c->n_free - (uint32_t)std::min<uint64_t>(n_ins, c->n_free);
         mn_launch_finalize(b, n_free_after, s);
+        mn_launch_advance_lo(c->d_key2slot, c->cap_keys - 1, c->d_key_lo, c->next_key + n_ins, c->d_err, s);
         if (timing) HIPCHK(hipEventRecord(c->ev[5], s));
         read_zr(c, &err);
         c->summarize();
@@ -1590,6 +1625,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     c->fresh += (uint32_t)(n_ins - took);
     c->n_free = c->n_free - took + (uint32_t)n_del;
     c->next_key += n_ins;
+    c->key_lo = c->key_lo_seen;
     c->n_live = c->n_live + n_ins - n_del;
     c->E = E_new;
     c->n_pending = n_del;
@@ -1844,6 +1880,7 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_key2slot);
     dev_free(c->d_key_ts);
     dev_free(c->d_delbits);
+    dev_free(c->d_key_lo);
     for (int k = 0; k < 2; k++) {
         dev_free(c->d_skey[k]);
         dev_free(c->d_sval[k]);
@@ -2010,6 +2047,8 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         }
         dev_alloc(c->d_err, 1);
         dev_alloc(c->d_last_ts, 1);
+        dev_alloc(c->d_key_lo, 1);
+        HIPCHK(hipMemsetAsync(c->d_key_lo, 0, 8, s));
         int64_t mn = INT64_MIN;
         HIPCHK(hipMemcpyAsync(c->d_last_ts, &mn, 8, hipMemcpyHostToDevice, s));
         c->n_zr = c->zr_words();
@@ -2131,6 +2170,8 @@ int mnemonic_get_stats(mnemonic_ctx* ctx, mnemonic_stats* out) {
     *out = ctx->stats;
     out->n_live_edges = ctx->n_live;
     out->slot_high_water = ctx->fresh;
+    out->key_capacity = ctx->cap_keys;
+    out->key_lo = ctx->key_lo;
     return MNEMONIC_OK;
 }
 
@@ -2212,7 +2253,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         }
         GraphView g = make_view(c, false);
         mn_launch_reset(c->d_err, nullptr, 0, s);  // a failed batch may have left its error word set
-        mn_launch_reindex(g, c->d_debi_bits, c->n_debi_bits, c->fresh, c->d_key2slot, c->d_del_slot[c->pend],
+        mn_launch_reindex(g, c->d_debi_bits, c->n_debi_bits, c->fresh, c->d_key2slot, c->key_lo, c->d_del_slot[c->pend],
                           (uint32_t)c->n_pending, s);
         mn_launch_vf_refresh(g, c->d_vf_bits, c->n_vf_bits, nullptr, c->nV, c->d_err, s);
         // outputs and per-phase tallies for the new count of queries

@@ -224,6 +224,7 @@ struct GraphView {
     __device__ const uint32_t* offs(uint32_t d) const { return d ? off[1] : off[0]; }
     __device__ const uint64_t* adjs(uint32_t d) const { return d ? adj[1] : adj[0]; }
     __device__ const uint64_t* keys(uint32_t d) const { return d ? adjk[1] : adjk[0]; }
+    uint64_t key_mask;         // key-indexed maps are rings: key k sits at k & key_mask
     int64_t* key_ts;           // key -> timestamp of every edge ever inserted (never invalidated:
                                // a re-run of a phase may still meet edges its batch deleted)
     uint32_t n_elab_c;         // compact edge labels

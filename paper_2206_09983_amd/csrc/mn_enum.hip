@@ -414,10 +414,10 @@ template <int NC>
 __device__ inline int64_t edge_ts(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
                                   const uint32_t* dig, uint32_t k, uint32_t aqe, uint64_t akey) {
     const uint32_t ci = P.close_idx[k];
-    if (k == aqe || ci == TREE_EDGE) return g.key_ts[k == aqe ? akey : B.tree_key(k)];
+    if (k == aqe || ci == TREE_EDGE) return g.key_ts[(k == aqe ? akey : B.tree_key(k)) & g.key_mask];
     RunIt it;
     const uint32_t p = close_instance<NC>(g, P, B, st, dig, ci, it);
-    return g.key_ts[it.adjk[p]];  // p < end: the combination's instances were counted
+    return g.key_ts[it.adjk[p] & g.key_mask];  // p < end: the combination's instances were counted
 }
 
 // Temporal order of one complete embedding: walking the ranked edges by

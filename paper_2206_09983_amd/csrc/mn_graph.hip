@@ -89,13 +89,14 @@ __global__ __launch_bounds__(MN_BLOCK) void k_validate(GraphView g, BatchView b)
     } else if (i < b.n_ins + b.n_del) {
         uint64_t k = b.del_keys[i - b.n_ins];
         uint64_t lim = b.next_key + b.n_ins;
-        if (k >= lim) {
+        if (k >= lim || k < b.key_lo) {  // never inserted, or long dead
             set_err(b.err, MN_ERR_DELETE);
-        } else if (k < b.next_key && b.key2slot[k] == MN_INVALID) {
+        } else if (k < b.next_key && b.key2slot[k & b.key_mask] == MN_INVALID) {
             set_err(b.err, MN_ERR_DELETE);
         } else {
-            uint32_t bit = 1u << (uint32_t)(k & 31);
-            uint32_t old = atomicOr(&b.delbits[k >> 5], bit);
+            const uint64_t rk = k & b.key_mask;
+            uint32_t bit = 1u << (uint32_t)(rk & 31);
+            uint32_t old = atomicOr(&b.delbits[rk >> 5], bit);
             if (old & bit) set_err(b.err, MN_ERR_DELETE);
         }
     }
@@ -122,9 +123,9 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
     g.s_dst[slot] = d;
     g.s_lab[slot] = (uint8_t)l;
     g.s_ts[slot] = b.in_ts[i];
-    g.key_ts[key] = b.in_ts[i];
+    g.key_ts[key & b.key_mask] = b.in_ts[i];
     g.s_key[slot] = key;
-    b.key2slot[key] = slot;
+    b.key2slot[key & b.key_mask] = slot;
     match_edge(g, b.debi_bits, b.n_debi_bits, slot, s, d, l);
     count_edge(g, s, d, l, 1u);
     uint64_t hs = ((uint64_t)l << g.nbr_bits) | d;  // out-entry high word
@@ -143,11 +144,15 @@ __global__ __launch_bounds__(MN_BLOCK) void k_ingest(GraphView g, BatchView b) {
 // those deleted by the last batch (the next batch decrements them).
 __global__ __launch_bounds__(MN_BLOCK) void k_reindex(GraphView g, const DebiBit* __restrict__ bits, uint32_t n_bits,
                                                       uint32_t n_slots, const uint32_t* __restrict__ key2slot,
-                                                      const uint32_t* __restrict__ pend, uint32_t n_pend) {
+                                                      uint64_t key_lo, const uint32_t* __restrict__ pend,
+                                                      uint32_t n_pend) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_slots) {
         const uint32_t slot = i;
-        if (key2slot[g.s_key[slot]] != slot) return;  // retired (or recycled under another key)
+        const uint64_t key = g.s_key[slot];
+        // retired (a key below key_lo is dead, and another key may hold its
+        // ring place), or recycled under another key
+        if (key < key_lo || key2slot[key & g.key_mask] != slot) return;
         const uint32_t s = g.s_src[slot], d = g.s_dst[slot], l = g.s_lab[slot];
         match_edge(g, bits, n_bits, slot, s, d, l);
         count_edge(g, s, d, l, 1u);
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_flag_del(GraphView g, uint64_t* ad
     const uint32_t dir = blockIdx.y;
     if (i >= b.n_del || failed(b.err)) return;
     const uint64_t k = b.del_keys[i];
-    const uint32_t slot = b.key2slot[k];
+    const uint32_t slot = b.key2slot[k & b.key_mask];
     if (dir == 0) b.del_slot[i] = slot;
     const uint32_t s = g.s_src[slot], d = g.s_dst[slot], l = g.s_lab[slot];
     const uint32_t v = dir ? d : s;
@@ -465,9 +470,12 @@ __global__ __launch_bounds__(MN_BLOCK) void k_finalize(BatchView b, uint32_t n_f
     bool ok = !failed(b.err);
     if (i < b.n_del) {
         uint64_t k = b.del_keys[i];
-        if (k < b.next_key + b.n_ins) atomicAnd(&b.delbits[k >> 5], ~(1u << (uint32_t)(k & 31)));
+        if (k < b.next_key + b.n_ins && k >= b.key_lo) {
+            const uint64_t rk = k & b.key_mask;
+            atomicAnd(&b.delbits[rk >> 5], ~(1u << (uint32_t)(rk & 31)));
+        }
         if (ok) {
-            b.key2slot[k] = MN_INVALID;
+            b.key2slot[k & b.key_mask] = MN_INVALID;
             b.free_stack[n_free_after + i] = b.del_slot[i];
         }
     }
@@ -544,9 +552,10 @@ void mn_launch_merge(const MergeSide* side, uint32_t n_vertices, uint32_t e_old,
 uint64_t mn_merge_limit_words(uint64_t e_old) { return 2 * ((e_old + MG_TILE - 1) / MG_TILE + 1); }
 
 void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits, uint32_t n_slots,
-                       const uint32_t* key2slot, const uint32_t* pend, uint32_t n_pend, hipStream_t s) {
+                       const uint32_t* key2slot, uint64_t key_lo, const uint32_t* pend, uint32_t n_pend,
+                       hipStream_t s) {
     const uint64_t n = (uint64_t)n_slots + n_pend;
-    if (n) k_reindex<<<nblocks(n), MN_BLOCK, 0, s>>>(g, bits, n_bits, n_slots, key2slot, pend, n_pend);
+    if (n) k_reindex<<<nblocks(n), MN_BLOCK, 0, s>>>(g, bits, n_bits, n_slots, key2slot, key_lo, pend, n_pend);
 }
 
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
@@ -570,6 +579,66 @@ void mn_launch_flag_del(const GraphView& g, uint64_t* adj_out, uint64_t* adj_in,
 void mn_launch_finalize(const BatchView& b, uint32_t n_free_after, hipStream_t s) {
     uint32_t n = b.n_del ? b.n_del : 1;
     k_finalize<<<nblocks(n), MN_BLOCK, 0, s>>>(b, n_free_after);
+}
+
+// One block moves *lo past dead keys: 4,096 keys per step (16 per thread),
+// stopping at the first live one or at `end`. A windowed stream retires its
+// oldest keys each batch, so a step or two suffice.
+__global__ __launch_bounds__(MN_BLOCK) void k_advance_lo(const uint32_t* __restrict__ key2slot, uint64_t key_mask,
+                                                         uint64_t* lo_dev, uint64_t end, const uint32_t* err) {
+    __shared__ uint32_t s_first;
+    if (failed(err)) return;  // the same for the whole block
+    uint64_t lo = *lo_dev;
+    constexpr uint32_t PER = 16, STEP = PER * MN_BLOCK;
+    while (lo < end) {  // uniform: every thread holds the same lo
+        if (threadIdx.x == 0) s_first = STEP;
+        __syncthreads();
+        for (uint32_t j = 0; j < PER; j++) {
+            const uint32_t o = j * MN_BLOCK + threadIdx.x;
+            const uint64_t k = lo + o;
+            if (k < end && key2slot[k & key_mask] != MN_INVALID) atomicMin(&s_first, o);
+        }
+        __syncthreads();
+        const uint32_t f = s_first;
+        __syncthreads();
+        if (f < STEP) {
+            lo += f;
+            break;
+        }
+        lo = min(end, lo + STEP);
+    }
+    if (threadIdx.x == 0) *lo_dev = lo;
+}
+
+void mn_launch_advance_lo(const uint32_t* key2slot, uint64_t key_mask, uint64_t* lo, uint64_t end,
+                          const uint32_t* err, hipStream_t s) {
+    k_advance_lo<<<1, MN_BLOCK, 0, s>>>(key2slot, key_mask, lo, end, err);
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_ring_copy(const uint32_t* __restrict__ k2s_old,
+                                                        const int64_t* __restrict__ ts_old, uint64_t m_old,
+                                                        uint32_t* __restrict__ k2s_new, int64_t* __restrict__ ts_new,
+                                                        uint64_t m_new, uint64_t lo, uint64_t hi) {
+    const uint64_t k = lo + (uint64_t)blockIdx.x * MN_BLOCK + threadIdx.x;
+    if (k >= hi) return;
+    k2s_new[k & m_new] = k2s_old[k & m_old];
+    ts_new[k & m_new] = ts_old[k & m_old];
+}
+
+void mn_launch_ring_copy(const uint32_t* k2s_old, const int64_t* ts_old, uint64_t m_old, uint32_t* k2s_new,
+                         int64_t* ts_new, uint64_t m_new, uint64_t lo, uint64_t hi, hipStream_t s) {
+    if (hi <= lo) return;
+    k_ring_copy<<<(uint32_t)((hi - lo + MN_BLOCK - 1) / MN_BLOCK), MN_BLOCK, 0, s>>>(k2s_old, ts_old, m_old,
+                                                                                       k2s_new, ts_new, m_new, lo, hi);
+}
+
+__global__ __launch_bounds__(MN_BLOCK) void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * MN_BLOCK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void mn_launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n) k_fill_u32<<<(uint32_t)((n + MN_BLOCK - 1) / MN_BLOCK), MN_BLOCK, 0, s>>>(p, v, n);
 }
 
 void mn_launch_init_vertices(uint32_t* vf, uint32_t* cnt, uint32_t n_vertices, uint32_t vf_words,

@@ -61,6 +61,9 @@ struct BatchView {
     uint32_t hb;            // composite sort key = (vertex << hb) | high word
     uint64_t dirbit;        // direction bit of in-list sort keys (above every vertex/high-word bit)
     uint64_t next_key;      // key of the first inserted edge
+    uint64_t key_lo;        // every key below it is dead (deleted)
+    uint64_t key_mask;      // ring mask of the key-indexed maps (capacity - 1; the capacity exceeds the
+                            // span of keys from key_lo to the end of the batch)
     uint32_t n_elabels;
     uint32_t n_debi_bits;
     uint32_t n_vf_bits;
@@ -125,7 +128,8 @@ uint64_t mn_merge_limit_words(uint64_t e_old);
 // increments for them and for the n_pend slots deleted by the last batch.
 // The counters must be zero before.
 void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits, uint32_t n_slots,
-                       const uint32_t* key2slot, const uint32_t* pend, uint32_t n_pend, hipStream_t s);
+                       const uint32_t* key2slot, uint64_t key_lo, const uint32_t* pend, uint32_t n_pend,
+                       hipStream_t s);
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
 // Sets (set != 0) or clears the flag bit of the entries at pos0[i] of adj0
@@ -135,6 +139,16 @@ void mn_launch_set_flags(uint64_t* adj0, const uint32_t* pos0, uint64_t* adj1, c
 void mn_launch_flag_del(const GraphView& g, uint64_t* adj_out, uint64_t* adj_in, const BatchView& b,
                         hipStream_t s);
 void mn_launch_finalize(const BatchView& b, uint32_t n_free_after, hipStream_t s);
+// Moves *lo past the dead keys (key2slot INVALID) below the first live one,
+// at most up to `end` (one block; no-op once err is set).
+void mn_launch_advance_lo(const uint32_t* key2slot, uint64_t key_mask, uint64_t* lo, uint64_t end,
+                          const uint32_t* err, hipStream_t s);
+// Key-map ring growth: copies the entries of keys [lo, hi) from the rings of
+// mask m_old to those of mask m_new.
+void mn_launch_ring_copy(const uint32_t* k2s_old, const int64_t* ts_old, uint64_t m_old, uint32_t* k2s_new,
+                         int64_t* ts_new, uint64_t m_new, uint64_t lo, uint64_t hi, hipStream_t s);
+// p[i] = v for i < n.
+void mn_launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void mn_launch_init_vertices(uint32_t* vf, uint32_t* cnt, uint32_t n_vertices, uint32_t vf_words,
                              uint32_t n_cnt, hipStream_t s);
 

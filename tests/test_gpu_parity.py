@@ -356,6 +356,52 @@ def test_vertex_filter_rejects_exactly_the_units_and_candidates_it_must(B):
             o.close()
 
 
+def test_sliding_window_wraps_the_key_rings_with_flat_memory(B):
+    # A window of 6,000 edges slides over 120 batches of 500 insertions, each
+    # deleting the 500 oldest live edges (edges leave from the tail of the
+    # window, Section VII-A). The key-indexed maps are rings over the live key
+    # span: 66,000 keys pass through them several times over, their size
+    # stays put once the window is full, and every batch matches the oracle,
+    # a temporally ordered query included (it reads timestamps by key).
+    rng = np.random.default_rng(31)
+    n_init, bs, nb = 6000, 500, 120
+    src, dst = synth.rmat_pairs(rng, 9, n_init + bs * nb)
+    n = 1 << 9
+    vl = rng.integers(0, 3, size=n)
+    el = rng.integers(0, 4, size=len(src)).astype(np.uint8)
+    vmask = (np.uint64(1) << vl.astype(np.uint64)).astype(np.uint64)
+    g, batches = synth.split_stream(n, vmask, src, dst, el, n_init, [bs] * nb, del_frac=1.0)
+    qs = synth.rmat_queries(seed=5, n_vlabels=3, n_elabels=4, s=1.2)
+    qs.append(synth.with_ranks(qs[4], np.arange(len(qs[4]["qsrc"]))))  # the 5-path, ordered in time
+    o = Oracle(g, qs)
+    m = B.Matcher(g, qs, flags=B.F_EMIT, n_elabels=4)
+    caps = []
+    try:
+        for bi, b in enumerate(batches):
+            o.apply_batch(b)
+            m.apply_batch(b)
+            st = m.stats()
+            assert st["key_lo"] == (bi + 1) * bs  # the deleted oldest keys fall below it
+            caps.append(st["key_capacity"])
+            for qi in range(len(qs)):
+                r = m.result(qi)
+                for ph, cnt, dig in ((False, "n_new", "dig_new"), (True, "n_expired", "dig_expired")):
+                    assert r[cnt] == o.count(qi, ph), (bi, qi, ph)
+                    assert r[dig] == o.digest(qi, ph), (bi, qi, ph)
+                    if bi % 20 == 0:
+                        np.testing.assert_array_equal(canon(m.keys(qi, ph)), o.result(qi, ph))
+        assert max(caps) < n_init + bs * nb  # fewer places than keys inserted: the rings wrapped
+        assert len(set(caps[5:])) == 1  # and their size stayed put
+        # a key long below the window is dead; so is one beyond the last
+        for dead in (7, o.n_keys):
+            with pytest.raises(B.MnemonicError) as ei:
+                m.apply_batch(synth.make_batch([], [], [], [], [dead]))
+            assert ei.value.name == "MNEMONIC_E_BAD_DELETE"
+    finally:
+        m.close()
+        o.close()
+
+
 def test_unsupported_queries_are_rejected(B):
     g = synth.make_graph(3, [1, 1, 1], [0], [1], [0])
     with pytest.raises(B.MnemonicError) as ei:
