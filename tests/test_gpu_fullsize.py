@@ -21,6 +21,11 @@ what holds at any size plus outputs the oracle can compute one by one:
     bit-exact with the oracle's per-unit enumeration;
   * the homomorphic 5-path counts equal the closed form (chains of sparse
     matrix-vector products) on the graphs before and after each phase.
+
+The 64-query stream (the same edges in log-uniform batches, 64 random
+queries): counts and both digests of every query and phase of its first four
+batches equal the oracle's, stored in tests/golden/fullsize_multiquery_s20.json
+by the same oracle-only script.
 """
 import json
 import os
@@ -266,3 +271,41 @@ def test_full_size_stream_equals_the_oracle_golden_and_lists():
     finally:
         m.close()
         o.close()
+
+
+MULTI_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fullsize_multiquery_s20.json")
+
+
+def test_full_size_multiquery_stream_equals_the_oracle_golden():
+    # The 64-query stream: the same 2^24 initial edges, log-uniform batches,
+    # the 64 queries of multiquery_queries.json, in the benchmark's
+    # configuration for that workload (emitting, output buffers grown on
+    # demand from 2^16 tuples per query).
+    torch = pytest.importorskip("torch")
+    from paper_2206_09983_amd import binding as B
+    B.load()
+    with open(MULTI_GOLDEN) as f:
+        gold = json.load(f)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "multiquery_queries.json")) as f:
+        qdoc = json.load(f)
+    t0 = time.time()
+    case = synth.multiquery_case(queries=synth.queries_from_json(qdoc["queries"]), **gold["params"])
+    qs = case["queries"]
+    assert [q["name"] for q in qs] == gold["queries"]
+    say("full-size golden: %s, %d batches (%.1f s)" % (case["name"], len(gold["batches"]), time.time() - t0))
+    stream = torch.cuda.current_stream()
+    m = B.Matcher(case["graph"], qs, flags=B.F_EMIT | B.F_TIMING, out_capacity=1 << 16,
+                  stream=stream.cuda_stream, n_elabels=32)
+    try:
+        for rec in gold["batches"]:
+            b = case["batches"][rec["index"]]
+            assert (len(b["src"]), len(b["del_keys"])) == (rec["n_ins"], rec["n_del"])
+            m.apply_batch(device_batch(torch, b))
+            for qi, rq in enumerate(rec["queries"]):
+                r = m.result(qi)
+                assert [r["n_new"], *r["dig_new"]] == rq["new"], (rec["index"], rq["name"], "new")
+                assert [r["n_expired"], *r["dig_expired"]] == rq["expired"], (rec["index"], rq["name"], "expired")
+            say("batch %d (%d insertions, %d deletions): 64 queries' counts and digests equal the oracle's (%.1f s)"
+                % (rec["index"], rec["n_ins"], rec["n_del"], time.time() - t0))
+    finally:
+        m.close()
