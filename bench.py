@@ -410,7 +410,8 @@ def main():
                     tag, i, lat, st["ms_enumerate"][0], st["ms_enumerate"][1], st["ms_expand"][0],
                     st["ms_expand"][1], st["expand_launches"], st["seeds"], st["frontier_rows"],
                     st["entries_scanned"], st["tuples"],
-                    ", re-runs %s (causes %s)" % (st["reruns"], st["rerun_causes"]) if any(st["reruns"]) else ""))
+                    (", re-runs %s (causes %s)" % (st["reruns"], st["rerun_causes"]) if any(st["reruns"]) else "") +
+                    (", %d allocations in %.2f ms" % (st["allocations"], st["ms_alloc"]) if st["allocations"] else "")))
         r["tile"] = m.stats()["expand_tile"]
         m.close()
         return r

@@ -186,6 +186,8 @@ typedef struct {
     uint64_t vf_rejects[2];
     uint64_t key_capacity;  /* places in the key-indexed maps (rings over the live key span) */
     uint64_t key_lo;        /* every key below it is dead */
+    uint64_t allocations;   /* device allocations the batch made (buffers that grew) */
+    double ms_alloc;        /* host time of those allocations and of the frees they replaced */
 } mnemonic_stats;
 
 /*

@@ -80,7 +80,8 @@ class mnemonic_stats(C.Structure):
                 ("frontier_rows", C.c_uint64 * 2), ("expand_launches", C.c_uint64 * 2),
                 ("expand_tile", C.c_uint64), ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2),
                 ("ms_batch", C.c_double), ("reruns", C.c_uint64 * 2), ("rerun_causes", C.c_uint64 * 2),
-                ("vf_rejects", C.c_uint64 * 2), ("key_capacity", C.c_uint64), ("key_lo", C.c_uint64)]
+                ("vf_rejects", C.c_uint64 * 2), ("key_capacity", C.c_uint64), ("key_lo", C.c_uint64),
+                ("allocations", C.c_uint64), ("ms_alloc", C.c_double)]
 
 
 class MnemonicError(RuntimeError):

@@ -18,6 +18,7 @@
 // superset), and an enumeration can be re-run on exactly the same state when
 // an output buffer was too small.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -64,6 +65,10 @@ uint64_t g_fail_alloc_in = 0;
 // its batch into the buffers the context already holds, and a buffer that
 // would have to grow refuses instead of allocating.
 thread_local bool t_no_alloc = false;
+// Device allocations and frees of the calling thread, and the host time they
+// took (with the stream waits that precede a regrowth): reported per batch.
+thread_local uint64_t t_alloc_n = 0;
+thread_local double t_alloc_ms = 0;
 
 struct NoAllocScope {
     NoAllocScope() { t_no_alloc = true; }
@@ -109,7 +114,10 @@ void dev_alloc(T*& p, size_t n) {
     if (g_fail_alloc_in && --g_fail_alloc_in == 0)
         throw ApiError{MNEMONIC_E_OOM, "device allocation of " + std::to_string(n * sizeof(T)) +
                                            " bytes failed (injected)"};
+    const auto t0 = std::chrono::steady_clock::now();
     hipError_t e = hipMalloc(&q, n * sizeof(T));
+    t_alloc_n++;
+    t_alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (e != hipSuccess) {
         (void)hipGetLastError();
         throw ApiError{MNEMONIC_E_OOM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed"};
@@ -119,7 +127,11 @@ void dev_alloc(T*& p, size_t n) {
 
 template <typename T>
 void dev_free(T*& p) {
-    if (p) (void)hipFree(p);
+    if (p) {
+        const auto t0 = std::chrono::steady_clock::now();
+        (void)hipFree(p);
+        t_alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
     p = nullptr;
 }
 
@@ -1427,6 +1439,8 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
               bool on_device, bool enumerate, uint64_t* first_new_key) {
     hipStream_t s = c->stream;
     if (n_ins + n_del >= (1ull << 31)) throw ApiError{MNEMONIC_E_ARG, "batch too large"};
+    t_alloc_n = 0;
+    t_alloc_ms = 0;
     ensure_capacity(c, n_ins, n_del);
     static const uint32_t kItems[3] = {1, 2, 4};
     const bool tune = enumerate && c->tuning() && !t_no_alloc;
@@ -1793,6 +1807,8 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
         }
         c->have_result = true;
     }
+    c->stats.allocations = t_alloc_n;
+    c->stats.ms_alloc = t_alloc_ms;
     c->broken = false;
     if (c->results_incomplete)
         throw ApiError{MNEMONIC_E_CAPACITY, "batch applied, but its enumeration needs larger buffers than the context "

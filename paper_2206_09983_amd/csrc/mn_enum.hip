@@ -253,10 +253,11 @@ struct Bind {
 };
 
 // Instances of closing edge c between f(other) = fo and f(nv) = fn: searches
-// the shorter of the two adjacency lists that hold them. Returns the start of
-// the instance run (labelled edge: the (label, neighbour) run; unlabelled
-// edge: the first accepted entry of the list), with RUN_SWAP set when the
-// list of fn was used, or NO_RUN when no instance passes the mask.
+// the shorter of the two adjacency lists that hold them. Returns the first
+// accepted instance (labelled edge: in the (label, neighbour) run;
+// unlabelled edge: in the whole list), with RUN_SWAP set when the list of fn
+// was used, or NO_RUN when no instance passes the mask. Walks over the
+// instances start there.
 __device__ uint32_t close_find(const GraphView& g, const CloseDesc& c, uint32_t fo, uint32_t fn,
                                uint32_t& probes) {
     const uint32_t d0 = c.dir, d1 = 1u - c.dir;
@@ -277,7 +278,7 @@ __device__ uint32_t close_find(const GraphView& g, const CloseDesc& c, uint32_t 
             const uint64_t e = adj[p];
             probes += 2;
             if (ent_hi(e) != key) break;
-            if (!(c.masked && (ent_lo(e) & MN_FLAG))) return lb | flag;
+            if (!(c.masked && (ent_lo(e) & MN_FLAG))) return p | flag;
         }
         return NO_RUN;
     }
@@ -330,6 +331,30 @@ __device__ inline uint32_t run_next(const RunIt& it, uint32_t p, uint32_t& probe
     }
     return it.end;
 }
+
+// A closing edge's instances as a row keeps them once the edge is resolved:
+// the key of the instance when there is exactly one, else CK_MULTI | their
+// number (edge keys stay below 2^63). st is the first accepted instance, as
+// close_find returns it. Later levels then need no walk over the instances
+// for a mapping whose closing edges each have one.
+constexpr uint64_t CK_MULTI = 1ull << 63;
+
+__device__ inline uint64_t close_word(const GraphView& g, const CloseDesc& c, uint32_t st, uint32_t fo, uint32_t fn,
+                                      uint32_t& probes) {
+    const RunIt it = run_open(g, c, st, fo, fn);
+    const uint32_t q = run_next(it, it.p + 1, probes);
+    if (q >= it.end) return it.adjk[it.p];
+    uint32_t n = 2;
+    for (uint32_t x = run_next(it, q + 1, probes); x < it.end; x = run_next(it, x + 1, probes)) n++;
+    return CK_MULTI | n;
+}
+
+// Set on a candidate's neighbour (vertices stay below 2^24) between the two
+// passes of an expansion: its mapping's closing edges each have one instance.
+constexpr uint32_t CK_ONE = 0x80000000u;
+
+// Instances of a closing edge from the row's word (close_word).
+__device__ inline uint32_t close_word_count(uint64_t w) { return (w & CK_MULTI) ? (uint32_t)w : 1u; }
 
 // Lanes with `active` set reserve v consecutive places in the per-query
 // counters[q]; lanes with the same q share one atomic. All lanes of the wave
@@ -704,7 +729,11 @@ __global__ __launch_bounds__(MN_BLOCK) void k_seed_rows(GraphView g, const uint3
                 wkey(R, P.j, r, B.skey);
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
-                    if (c < (uint32_t)NC && c < P.c0_end) wcol(R, 1 + R.wv + P.close[c].qe, r, st[c]);
+                    if (c < (uint32_t)NC && c < P.c0_end) {
+                        const CloseDesc cd = P.close[c];
+                        wcol(R, 1 + R.wv + cd.qe, r, st[c]);
+                        wkey(R, cd.qe, r, close_word(g, cd, st[c], B.f(cd.other), B.f(cd.nv), K.probes));
+                    }
                 if (R.trace) wcol(R, 1 + R.wv + R.we, r, MN_INVALID);
                 K.rows++;
             } else {
@@ -1114,6 +1143,86 @@ __device__ inline void emit_tree_tuple(const RowsView& R, uint32_t r, uint32_t n
     dB += hB;
 }
 
+// Embeddings of a complete mapping at the last level of a plan with closing
+// edges and no temporal order: the product of each closing edge's instances,
+// from the row's words for edges resolved at earlier levels (close_word) and
+// by a walk for those this level resolves (st[c], its new vertex mapped to w).
+template <int NC>
+__device__ inline uint64_t closed_mult(const GraphView& g, const SeedPlan* P, const RowsView& R, uint32_t r,
+                                       const LevelDesc& lv, uint32_t n_close, const uint32_t* st, uint32_t w,
+                                       uint32_t& probes) {
+    constexpr int NA = NC > 0 ? NC : 1;
+    uint64_t mult = 1;
+#pragma unroll
+    for (uint32_t c = 0; c < NA; c++) {
+        if (c < (uint32_t)NC && c < n_close) {
+            const CloseDesc cd = P->close[c];
+            uint32_t n;
+            if (c >= lv.c_begin && c < lv.c_end) {
+                const RunIt it = run_open(g, cd, st[c], rcol(R, 1 + cd.other, r), w);
+                n = 1;
+                for (uint32_t x = run_next(it, it.p + 1, probes); x < it.end; x = run_next(it, x + 1, probes)) n++;
+            } else {
+                n = close_word_count(rkey(R, cd.qe, r));
+            }
+            mult *= n;
+        }
+    }
+    return mult;
+}
+
+// The one embedding of a complete mapping whose closing edges each have one
+// instance (no temporal order): the row's keys, the closing edges this level
+// resolves at their first accepted instances and akey at the anchor aqe;
+// both digest chains from query q's seeds. Written at `row` when emitting.
+template <int NC>
+__device__ inline void emit_closed_tuple(const GraphView& g, const SeedPlan* P, const RowsView& R, uint32_t r,
+                                         uint32_t q, uint32_t nqe, const LevelDesc& lv, const uint32_t* st,
+                                         uint64_t akey, uint64_t* row, bool write, Cnt& K, uint64_t& dA,
+                                         uint64_t& dB) {
+    constexpr int NA = NC > 0 ? NC : 1;
+    uint32_t hq[NA];
+    uint64_t hk[NA];
+#pragma unroll
+    for (uint32_t c = 0; c < NA; c++) {
+        hq[c] = 0xFFu;
+        hk[c] = 0;
+        if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
+            const CloseDesc cd = P->close[c];
+            const bool sw = (st[c] & RUN_SWAP) != 0;
+            hq[c] = cd.qe;
+            hk[c] = g.keys(sw ? 1u - cd.dir : (uint32_t)cd.dir)[st[c] & ~RUN_SWAP];
+        }
+    }
+    uint64_t hA = mn_mix64(MN_SEED_A ^ (uint64_t)q), hB = mn_mix64(MN_SEED_B ^ (uint64_t)q);
+    for (uint32_t k0 = 0; k0 < nqe; k0 += 8) {  // one pass for up to 8 edges
+        uint64_t kv[8];
+#pragma unroll
+        for (uint32_t i = 0; i < 8; i++) {
+            const uint32_t k = k0 + i;
+            kv[i] = k < nqe && k != lv.qe ? rkey(R, k, r) : akey;
+#pragma unroll
+            for (uint32_t c = 0; c < NA; c++)
+                if (hq[c] == k) kv[i] = hk[c];
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < 8; i++)
+            if (k0 + i < nqe) {
+                hA = mn_mix64(hA + kv[i]);
+                hB = mn_mix64(hB + kv[i]);
+            }
+        if (write) {
+#pragma unroll
+            for (uint32_t i = 0; i < 8; i++)
+                if (k0 + i < nqe) store_key(row + k0 + i, kv[i]);
+        }
+    }
+    K.keys += nqe;
+    K.tuples++;
+    dA += hA;
+    dB += hB;
+}
+
 // One block tests a tile of 256 x ITEMS candidates in two passes. Pass 1 runs
 // the filters and gives every survivor a place inside the block (LDS counters
 // per query for embeddings, one for new rows); one global atomic per query
@@ -1267,6 +1376,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
             if (last) {
                 if (!H.temporal && (NC == 0 || H.n_close == 0)) {
                     mult = 1;
+                } else if (NC <= 4 && !H.temporal) {
+                    // (plans with more closing edges keep the general path's registers)
+                    mult = closed_mult<NC>(g, P, in, r, lv, H.n_close, st, w, K.probes);
+                    if (mult == 1) w |= CK_ONE;  // pass 2 writes the one embedding from the row
                 } else {
                     Bind B;
                     B.R = in;
@@ -1363,8 +1476,11 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                 K.keys++;
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
-                    if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end)
-                        wcol(out, 1 + out.wv + P->close[c].qe, dst, st[c]);
+                    if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
+                        const CloseDesc cd = P->close[c];
+                        wcol(out, 1 + out.wv + cd.qe, dst, st[c]);
+                        wkey(out, cd.qe, dst, close_word(g, cd, st[c], rcol(in, 1 + cd.other, r), w, K.probes));
+                    }
                 K.rows++;
             }  // rows past the buffer are counted, not written: the host grows it and runs again
         }
@@ -1383,6 +1499,11 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                 const OutView& ov = po.outs[q];
                 const bool write = po.emit && pos < ov.cap[po.phase];
                 emit_tree_tuple(in, r, H.n_qe, lv.qe, akey, ov.keys[po.phase] + pos * H.n_qe, write, K, dA, dB);
+            } else if (NC > 0 && NC <= 4 && (w & CK_ONE)) {
+                const OutView& ov = po.outs[q];
+                const bool write = po.emit && pos < ov.cap[po.phase];
+                emit_closed_tuple<NC>(g, P, in, r, q, H.n_qe, lv, st, akey, ov.keys[po.phase] + pos * H.n_qe, write, K,
+                                      dA, dB);
             } else {
                 Bind B;
                 B.R = in;
