@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--serve-scale", type=int, default=22, help="serving: R-MAT scale")
     ap.add_argument("--serve-window", type=int, default=1 << 26, help="serving: edges in the initial window")
     ap.add_argument("--autotune", action="store_true", help="let the library choose its expansion tile")
+    ap.add_argument("--tree-filter", action="store_true",
+                    help="strengthen the vertex filter with the spanning-tree propagation before each batch")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     ap.add_argument("--scheduler", choices=("both", "static", "learned"), default="both",
@@ -347,6 +349,8 @@ def main():
                             "del_keys": torch.from_numpy(b["del_keys"].view(np.int64)).cuda()})
     torch.cuda.synchronize()
     flags = binding.F_TIMING | (0 if args.count_only else binding.F_EMIT) | (binding.F_AUTOTUNE if args.autotune else 0)
+    if args.tree_filter:
+        flags |= binding.F_TREE_FILTER
     if args.workload == "multiquery":
         args.out_capacity = min(args.out_capacity, 1 << 16)  # 64 queries: buffers grow on demand
     weights = None
@@ -487,7 +491,7 @@ def main():
             "batch_insertions": [len(case["batches"][i]["src"]) for i in timed],
             "queries": len(case["queries"]), "emit_tuples": not args.count_only, "seed": args.seed,
             "stream_batches": len(case["batches"]), "timed_batches": describe_batches(timed),
-            "autotune": bool(args.autotune), "expand_tile": m_tile,
+            "autotune": bool(args.autotune), "expand_tile": m_tile, "tree_filter": bool(args.tree_filter),
         }),
         "embeddings_per_s": tuples / elapsed,
         "p50_batch_ms": pct(50),

@@ -108,6 +108,13 @@ typedef struct {
 #define MNEMONIC_F_INDEX_ONLY 8u /* maintain the graph and its index (Algorithm 2's updates,
                                     edgeMatcher, filters) but enumerate nothing: results stay
                                     empty; measures the update path alone */
+#define MNEMONIC_F_TREE_FILTER 32u /* before each batch's enumeration, strengthen the vertex
+                                      filter with the spanning-tree propagation of Section V-B
+                                      (f4 bottom-up, then f1 top-down, over each query's BFS tree
+                                      from query vertex 0), recomputed on the graph with the
+                                      batch's insertions; every level then tests it. Results do
+                                      not depend on it: it only prunes candidates no embedding
+                                      uses. */
 
 typedef struct {
     uint32_t flags;          /* MNEMONIC_F_* */
@@ -188,6 +195,8 @@ typedef struct {
     uint64_t key_lo;        /* every key below it is dead */
     uint64_t allocations;   /* device allocations the batch made (buffers that grew) */
     double ms_alloc;        /* host time of those allocations and of the frees they replaced */
+    uint64_t tree_cleared;  /* MNEMONIC_F_TREE_FILTER: (vertex, query vertex) filter bits the
+                               spanning-tree rounds cleared this batch */
 } mnemonic_stats;
 
 /*

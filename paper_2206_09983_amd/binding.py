@@ -21,6 +21,7 @@ F_TIMING = 2
 F_AUTOTUNE = 4
 F_INDEX_ONLY = 8
 F_SORT = 16
+F_TREE_FILTER = 32
 SCHED_STATIC = 0
 SCHED_LEARNED = 1
 SCHED_FIXED = 2
@@ -81,7 +82,7 @@ class mnemonic_stats(C.Structure):
                 ("expand_tile", C.c_uint64), ("ms_expand", C.c_double * 2), ("ms_enumerate", C.c_double * 2),
                 ("ms_batch", C.c_double), ("reruns", C.c_uint64 * 2), ("rerun_causes", C.c_uint64 * 2),
                 ("vf_rejects", C.c_uint64 * 2), ("key_capacity", C.c_uint64), ("key_lo", C.c_uint64),
-                ("allocations", C.c_uint64), ("ms_alloc", C.c_double)]
+                ("allocations", C.c_uint64), ("ms_alloc", C.c_double), ("tree_cleared", C.c_uint64)]
 
 
 class MnemonicError(RuntimeError):

@@ -195,6 +195,13 @@ struct mnemonic_ctx {
     int16_t* d_vlab_idx = nullptr;
     uint32_t* d_vf = nullptr;
     uint32_t* d_cnt = nullptr;
+    // spanning-tree filter (MNEMONIC_F_TREE_FILTER): its steps round by round
+    // (round i = steps [tree_round[i], tree_round[i + 1])) and the filter
+    // bits the enumerator then reads: VF with the tree's conditions applied
+    std::vector<TreeStep> htree;
+    std::vector<uint32_t> tree_round;
+    TreeStep* d_tree = nullptr;
+    uint32_t* d_vfp = nullptr;
     uint4* d_meta[2] = {nullptr, nullptr};
 
     // slot arrays
@@ -360,6 +367,7 @@ struct mnemonic_ctx {
     std::string err;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
+    bool tree_on() const { return (flags & MNEMONIC_F_TREE_FILTER) != 0; }
     // zero-region layout
     uint32_t zr_nseeds(int p) const { return (uint32_t)p; }
     uint32_t zr_cursor(int p) const { return 2u + (uint32_t)p; }
@@ -378,7 +386,8 @@ struct mnemonic_ctx {
     uint32_t note_cand(int p, uint32_t L) const { return zr_note(p) + 4u * L; }
     uint32_t note_rows(int p, uint32_t L) const { return zr_note(p) + 4u * L + 2u; }
     uint32_t note_seed(int p) const { return zr_note(p) + 4u * MN_MAXLV; }
-    uint32_t zr_words() const { return zr_note(2); }
+    uint32_t zr_tree() const { return zr_note(2); }  // filter bits the spanning-tree rounds cleared
+    uint32_t zr_words() const { return zr_note(2) + 1u; }
     // shard sums of the last readback: digests [p][q][2], tallies [p][MN_TALLIES]
     std::vector<uint64_t> sum_dig;
     uint64_t sum_st[2][MN_TALLIES] = {{0}};
@@ -561,10 +570,12 @@ void build_plan(const mnemonic_ctx* c, const QueryDev& Q, uint32_t qi, uint32_t 
     }
     P.n_levels = (uint8_t)L;
     P.n_close = (uint8_t)nc;
-    // Below the last level the filter bit can also prune by degree.
-    for (uint32_t l = 0; l + 1 < L; l++) {
+    // Below the last level the filter bit can also prune by degree; with the
+    // spanning-tree filter it can prune at every level.
+    for (uint32_t l = 0; l < L; l++) {
         LevelDesc& lv = P.lv[l];
-        if (!lv.need_vf && !filters_trivial(c, Q, lv.vtx, lv.qe, lv.from, lv.dir)) lv.need_vf = 1;
+        if (c->tree_on() || (l + 1 < L && !lv.need_vf && !filters_trivial(c, Q, lv.vtx, lv.qe, lv.from, lv.dir)))
+            lv.need_vf = 1;
     }
 }
 
@@ -609,6 +620,86 @@ void check_query(const mnemonic_query& q) {
             if (seen[q.qsrc[i]] || seen[q.qdst[i]]) seen[q.qsrc[i]] = seen[q.qdst[i]] = true;
     for (uint32_t v = 0; v < q.n_qv; v++)
         if (!seen[v]) bad("query not weakly connected");
+}
+
+// The spanning-tree filter of Section V-B over each query's BFS tree from
+// query vertex 0 (its root; edges taken in index order). Bottom-up (f4), by
+// decreasing depth: a vertex keeps its bit for u only with a neighbour, over
+// the tree edge to each child c, that keeps its bit for c. Top-down (f1), by
+// increasing depth: a vertex keeps its bit for c only with a neighbour over
+// the tree edge from the parent u that keeps its bit for u. Each depth is one
+// round: its steps test and need disjoint bits.
+void build_tree_steps(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
+    struct Edge {
+        uint32_t depth;
+        TreeStep up, down;
+    };
+    std::vector<Edge> edges;
+    uint32_t maxd = 0;
+    auto range = [&](TreeStep& st, int32_t lab, uint64_t req) {
+        uint32_t lo = 0, hi = 0;
+        bool exact = false;
+        const bool some = class_hull(c, req, lo, hi, exact);
+        st.whole = lab < 0 ? 1u : 0u;
+        st.empty = some ? 0u : 1u;
+        st.key_lo = st.key_hi = 0;
+        if (lab >= 0 && some) {
+            st.key_lo = ((uint32_t)lab << c->nbr_bits) | lo;
+            st.key_hi = ((uint32_t)lab << c->nbr_bits) | (hi - 1);
+        }
+    };
+    for (uint32_t i = 0; i < n_q; i++) {
+        const mnemonic_query& q = qs[i];
+        const uint32_t base = c->hq[i].vf_base;
+        int depth[MN_MAXQV];
+        for (auto& d : depth) d = -1;
+        uint32_t queue[MN_MAXQV], head = 0, tail = 0;
+        depth[0] = 0;
+        queue[tail++] = 0;
+        while (head < tail) {
+            const uint32_t u = queue[head++];
+            for (uint32_t k = 0; k < q.n_qe; k++) {
+                uint32_t ch;
+                bool out;
+                if (q.qsrc[k] == u && depth[q.qdst[k]] < 0) {
+                    ch = q.qdst[k];
+                    out = true;
+                } else if (q.qdst[k] == u && depth[q.qsrc[k]] < 0) {
+                    ch = q.qsrc[k];
+                    out = false;
+                } else {
+                    continue;
+                }
+                depth[ch] = depth[u] + 1;
+                queue[tail++] = ch;
+                Edge e;
+                memset(&e, 0, sizeof(e));
+                e.depth = (uint32_t)depth[ch];
+                maxd = std::max(maxd, e.depth);
+                e.up.test = (uint16_t)(base + u);
+                e.up.need = (uint16_t)(base + ch);
+                e.up.dir = out ? 0u : 1u;  // from f(u): out-list when the query edge leaves u
+                range(e.up, q.qelabel[k], q.qv_require[ch]);
+                e.down.test = (uint16_t)(base + ch);
+                e.down.need = (uint16_t)(base + u);
+                e.down.dir = out ? 1u : 0u;
+                range(e.down, q.qelabel[k], q.qv_require[u]);
+                edges.push_back(e);
+            }
+        }
+    }
+    c->htree.clear();
+    c->tree_round.assign(1, 0);
+    for (uint32_t d = maxd; d >= 1; d--) {
+        for (const Edge& e : edges)
+            if (e.depth == d) c->htree.push_back(e.up);
+        c->tree_round.push_back((uint32_t)c->htree.size());
+    }
+    for (uint32_t d = 1; d <= maxd; d++) {
+        for (const Edge& e : edges)
+            if (e.depth == d) c->htree.push_back(e.down);
+        c->tree_round.push_back((uint32_t)c->htree.size());
+    }
 }
 
 void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
@@ -752,6 +843,7 @@ void prepare_queries(mnemonic_ctx* c, const mnemonic_query* qs, uint32_t n_q) {
     c->total_qe = debi_base;
     c->vf_words = (vf_base + 31) / 32;
     c->debi_words = (debi_base + 31) / 32;
+    build_tree_steps(c, qs, n_q);
 }
 
 template <typename T>
@@ -1259,6 +1351,7 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
     if (timing) HIPCHK(hipEventRecord(c->ev[2 * p], s));
     if (n_slots && c->n_static) {
         GraphView g = make_view(c, false);
+        if (c->tree_on()) g.vf = c->d_vfp;
         PhaseOut po = phase_out(c, p);
         // Start rows per slot: the last batches' rate with a margin when known
         // (the seed kernel counts past the buffer and the phase is re-run if
@@ -1593,6 +1686,14 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     GraphView g1 = make_view(c, merge);
     mn_launch_vf_refresh(g1, c->d_vf_bits, c->n_vf_bits, enumerate ? c->d_touched : nullptr,
                          enumerate ? (uint32_t)(2 * (n_prev + n_ins)) : c->nV, c->d_err, s);
+    if (enumerate && c->tree_on() && !(c->flags & MNEMONIC_F_INDEX_ONLY)) {
+        // the spanning-tree filter on G with the batch's insertions (both
+        // phases enumerate on it): VF, then the rounds
+        HIPCHK(hipMemcpyAsync(c->d_vfp, c->d_vf, (size_t)c->nV * c->vf_words * 4, hipMemcpyDeviceToDevice, s));
+        for (size_t i = 0; i + 1 < c->tree_round.size(); i++)
+            mn_launch_tree_step(g1, c->d_vfp, c->d_tree + c->tree_round[i], c->tree_round[i + 1] - c->tree_round[i],
+                                c->nV, c->d_zr + c->zr_tree(), c->d_err, s);
+    }
     uint64_t* adjn[2] = {merge ? c->d_adj2[0] : c->d_adj[0], merge ? c->d_adj2[1] : c->d_adj[1]};
     // the enumerator reads the current view; point it at the merged arrays
     auto swap_in = [&]() {
@@ -1809,6 +1910,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     }
     c->stats.allocations = t_alloc_n;
     c->stats.ms_alloc = t_alloc_ms;
+    c->stats.tree_cleared = c->h_zr[c->zr_tree()];
     c->broken = false;
     if (c->results_incomplete)
         throw ApiError{MNEMONIC_E_CAPACITY, "batch applied, but its enumeration needs larger buffers than the context "
@@ -1883,6 +1985,8 @@ void free_all(mnemonic_ctx* c) {
     dev_free(c->d_elab_idx);
     dev_free(c->d_vlab_idx);
     dev_free(c->d_vf);
+    dev_free(c->d_vfp);
+    dev_free(c->d_tree);
     dev_free(c->d_cnt);
     dev_free(c->d_meta[0]);
     dev_free(c->d_meta[1]);
@@ -2054,6 +2158,10 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         dev_alloc(c->d_vf, (size_t)c->nV * c->vf_words);
         dev_alloc(c->d_cnt, (size_t)c->nV * c->n_cnt);
         mn_launch_init_vertices(c->d_vf, c->d_cnt, c->nV, c->vf_words, c->n_cnt, s);
+        if (c->tree_on()) {
+            upload(c->d_tree, c->htree, s);
+            dev_alloc(c->d_vfp, (size_t)c->nV * c->vf_words);
+        }
         dev_alloc(c->d_meta[0], c->nV);
         dev_alloc(c->d_meta[1], c->nV);
         for (int d = 0; d < 2; d++) {
@@ -2202,6 +2310,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         mnemonic_ctx* c = ctx;
         // plan the new set on a scratch context first: a bad query changes nothing
         mnemonic_ctx t;
+        t.flags = c->flags;
         t.nV = c->nV;
         t.n_elabels = c->n_elabels;
         t.nbr_bits = c->nbr_bits;
@@ -2233,6 +2342,8 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         c->hdebi.swap(t.hdebi);
         c->hvf.swap(t.hvf);
         c->hreq.swap(t.hreq);
+        c->htree.swap(t.htree);
+        c->tree_round.swap(t.tree_round);
         memcpy(c->elab_idx, t.elab_idx, sizeof(c->elab_idx));
         memcpy(c->vlab_idx, t.vlab_idx, sizeof(c->vlab_idx));
         c->n_elab_c = t.n_elab_c;
@@ -2263,6 +2374,12 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         dev_alloc(c->d_vf, (size_t)c->nV * c->vf_words);
         dev_alloc(c->d_cnt, (size_t)c->nV * c->n_cnt);
         mn_launch_init_vertices(c->d_vf, c->d_cnt, c->nV, c->vf_words, c->n_cnt, s);
+        if (c->tree_on()) {
+            dev_free(c->d_tree);
+            dev_free(c->d_vfp);
+            upload(c->d_tree, c->htree, s);
+            dev_alloc(c->d_vfp, (size_t)c->nV * c->vf_words);
+        }
         if (c->debi_words != old_words && c->cap_slots) {
             dev_free(c->d_debi);
             dev_alloc(c->d_debi, c->cap_slots * c->debi_words);

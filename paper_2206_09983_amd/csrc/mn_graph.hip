@@ -375,6 +375,62 @@ __global__ __launch_bounds__(MN_BLOCK) void k_merge_old(MergeSide m0, MergeSide 
     }
 }
 
+// Spanning-tree filter step (Section V-B): f4 bottom-up, a vertex stays a
+// candidate for query vertex u only if, for the tree child c, some
+// neighbour over the tree edge's label and direction is still a candidate
+// for c; f1 top-down, a candidate for c needs a neighbour that is still a
+// candidate for its tree parent. Both are the one rule of TreeStep, applied
+// to bit `test` with `need` on the other side. Block row y takes step y; the
+// grid strides over the vertices. The first entry of the range is found by
+// binary search and the run is walked until a supporting neighbour turns up.
+__global__ __launch_bounds__(MN_BLOCK) void k_tree_step(GraphView g, uint32_t* vf, const TreeStep* __restrict__ steps,
+                                                        uint32_t n_v, unsigned long long* cleared,
+                                                        const uint32_t* err) {
+    if (failed(err)) return;
+    const TreeStep st = steps[blockIdx.y];
+    const uint32_t W = g.vf_words;
+    const uint32_t tw = st.test >> 5, tb = 1u << (st.test & 31);
+    const uint32_t nw = st.need >> 5, nb = 1u << (st.need & 31);
+    uint32_t n_clear = 0;
+    for (uint32_t v = blockIdx.x * MN_BLOCK + threadIdx.x; v < n_v; v += gridDim.x * MN_BLOCK) {
+        uint32_t* word = vf + (size_t)v * W + tw;
+        if (!(*word & tb)) continue;
+        bool found = false;
+        if (!st.empty) {
+            const uint32_t* of = st.dir ? g.off[1] : g.off[0];
+            const uint64_t* adj = st.dir ? g.adj[1] : g.adj[0];
+            const uint32_t* w32 = reinterpret_cast<const uint32_t*>(adj);
+            uint32_t a = of[v], b = of[v + 1];
+            if (!st.whole) {
+                while (a < b) {  // first entry with high word >= key_lo
+                    const uint32_t m = (a + b) >> 1;
+                    if (w32[2 * (size_t)m + 1] < st.key_lo)
+                        a = m + 1;
+                    else
+                        b = m;
+                }
+                b = of[v + 1];
+            }
+            for (uint32_t p = a; p < b && !found; p++) {
+                const uint32_t hi = w32[2 * (size_t)p + 1];
+                if (!st.whole && hi > st.key_hi) break;
+                const uint32_t x = hi & g.nbr_mask;
+                found = (vf[(size_t)x * W + nw] & nb) != 0u;
+            }
+        }
+        if (!found) {
+            atomicAnd(word, ~tb);
+            n_clear++;
+        }
+    }
+    if (cleared) {
+        uint32_t tot = n_clear;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, 64);
+        if (__lane_id() == 0 && tot) atomicAdd(cleared, (unsigned long long)tot);
+    }
+}
+
 // VF bit of (query, vertex u) at data vertex v: label requirement plus the
 // counting filters of Section V-A (f2: edges per direction and label; f3:
 // edges per direction towards each neighbour label), thresholds prepared on
@@ -564,6 +620,15 @@ void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits
     constexpr uint32_t VPB = 2 * (MN_BLOCK / 64);
     const uint32_t blocks = (uint32_t)std::min<uint64_t>(65536, ((uint64_t)n + VPB - 1) / VPB);
     if (n) k_vf_refresh<<<blocks, MN_BLOCK, 0, s>>>(g, bits, n_bits, list, n, err);
+}
+
+void mn_launch_tree_step(const GraphView& g, uint32_t* vf, const TreeStep* steps, uint32_t n, uint32_t n_v,
+                         unsigned long long* cleared, const uint32_t* err, hipStream_t s) {
+    if (!n || !n_v) return;
+    const uint32_t bx = (uint32_t)std::min<uint64_t>(4096, nblocks(n_v));
+    for (uint32_t s0 = 0; s0 < n; s0 += 65535)
+        k_tree_step<<<dim3(bx, std::min<uint32_t>(65535, n - s0)), MN_BLOCK, 0, s>>>(g, vf, steps + s0, n_v, cleared,
+                                                                                  err);
 }
 
 void mn_launch_set_flags(uint64_t* adj0, const uint32_t* pos0, uint64_t* adj1, const uint32_t* pos1, uint32_t n,

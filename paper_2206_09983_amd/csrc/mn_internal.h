@@ -54,6 +54,21 @@ struct VfBit {  // one vertex-filter bit: label requirement and count requiremen
     uint32_t req_end;
 };
 
+// One step of the spanning-tree filter (Section V-B, f1 top-down and f4
+// bottom-up) for one query tree edge: a vertex keeps bit `test` only if its
+// adjacency in direction `dir` holds, inside the high-word range [key_lo,
+// key_hi] (the tree edge's label and the other end's vertex classes; every
+// entry when `whole`), a neighbour with bit `need`.
+struct TreeStep {
+    uint16_t test;
+    uint16_t need;
+    uint32_t dir;
+    uint32_t key_lo;
+    uint32_t key_hi;
+    uint32_t whole;
+    uint32_t empty;  // no vertex class can carry the other end: the bit is cleared everywhere
+};
+
 struct BatchView {
     uint32_t n_ins, n_del, n_prev_del;
     uint32_t n_free;        // free-slot stack height before this batch
@@ -132,6 +147,13 @@ void mn_launch_reindex(const GraphView& g, const DebiBit* bits, uint32_t n_bits,
                        hipStream_t s);
 void mn_launch_vf_refresh(const GraphView& g, const VfBit* bits, uint32_t n_bits,
                           const uint32_t* list, uint32_t n, const uint32_t* err, hipStream_t s);
+// One round of the spanning-tree filter over the n_v vertices of g: for each
+// of the n steps, vertices whose bit `test` lacks a neighbour with bit `need`
+// (TreeStep) lose it in vf (n_v x g.vf_words words). Steps of one launch
+// must not test a bit another of them needs. cleared (optional) counts the
+// bits cleared.
+void mn_launch_tree_step(const GraphView& g, uint32_t* vf, const TreeStep* steps, uint32_t n, uint32_t n_v,
+                         unsigned long long* cleared, const uint32_t* err, hipStream_t s);
 // Sets (set != 0) or clears the flag bit of the entries at pos0[i] of adj0
 // and pos1[i] of adj1 (both directions, i < n) in one launch.
 void mn_launch_set_flags(uint64_t* adj0, const uint32_t* pos0, uint64_t* adj1, const uint32_t* pos1, uint32_t n,
