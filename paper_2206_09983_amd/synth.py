@@ -308,6 +308,27 @@ def serving_times(edges, window_ticks=1 << 24, rate=1e6, tick_s=1e-6, seed=7):
     return graph, (edges["src"][nw:], edges["dst"][nw:], edges["elabel"][nw:], ts)
 
 
+def serving_case(queries, scale=22, n_window=1 << 26, rate=2e7, batch=65536, n_batches=2,
+                 window_ticks=1 << 24, seed=7):
+    """A fixed slice of the serving stream: the initial window of
+    serving_times at ``rate``, then ``n_batches`` batches of ``batch``
+    consecutive arrivals. Each batch deletes the live keys whose timestamp is
+    at most (the batch's last arrival timestamp - window_ticks), as a server
+    flushing full batches would. ``queries`` are used as given."""
+    edges = serving_edges(scale=scale, n_window=n_window, n_arrivals=batch * n_batches, seed=seed)
+    graph, (s, d, l, ts) = serving_times(edges, window_ticks=window_ticks, rate=rate, seed=seed)
+    all_ts = np.concatenate([graph["ts"], ts])
+    batches, oldest = [], 0
+    for i in range(n_batches):
+        a, b = i * batch, (i + 1) * batch
+        now = int(ts[b - 1])
+        cut = max(oldest, int(np.searchsorted(all_ts, now - window_ticks, side="right")))
+        batches.append(make_batch(s[a:b], d[a:b], l[a:b], ts[a:b], np.arange(oldest, cut, dtype=np.uint64)))
+        oldest = cut
+    return {"name": "serving_rmat_s%d_window%d_ticks%d_rate%.0e_b%d" % (scale, n_window, window_ticks, rate, batch),
+            "graph": graph, "batches": batches, "queries": list(queries)}
+
+
 def random_connected_query(rng, nv, n_extra, n_vlabels, n_elabels, wild_p, sem):
     """Random weakly connected simple digraph query (no self-loops, at most one
     edge per ordered pair)."""

@@ -4,17 +4,22 @@ query and phase, computed by the CPU oracle alone.
 Test infrastructure, run once offline (it takes minutes of CPU time):
     python tests/golden/make_fullsize_golden.py rmat        # fullsize_rmat_s20.json
     python tests/golden/make_fullsize_golden.py multiquery  # fullsize_multiquery_s20.json
+    python tests/golden/make_fullsize_golden.py serving     # fullsize_serving_s22.json
 Each file records the workload's parameters and the oracle's results for the
 first batches of its stream: the R-MAT benchmark stream (2^20 vertices, 2^24
 initial edges, batches of 65,536 insertions and 6,553 oldest-key deletions,
-six queries) and the 64-query stream (the same edges in log-uniform
-batches). Only oracle/ and the seeded generators are used: no result here
-comes from the HIP library.
+six queries), the 64-query stream (the same edges in log-uniform batches)
+and a slice of the serving stream (2^22 vertices, a 2^26-edge window over
+2^24 ticks, arrivals at 2e7 edges/s in batches of 65,536, each deleting what
+left the window, 16 temporally ordered queries). Only oracle/ and the seeded
+generators are used: no result here comes from the HIP library.
 """
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -28,6 +33,12 @@ RMAT = dict(scale=20, n_init=1 << 24, n_stream=1 << 23, batch=65536, del_frac=0.
 RMAT_BATCHES = 6
 MULTI = dict(scale=20, n_init=1 << 24, del_frac=0.10, seed=7)
 MULTI_BATCHES = 4
+SERVING = dict(scale=22, n_window=1 << 26, rate=2e7, batch=65536, n_batches=2, window_ticks=1 << 24, seed=7)
+
+
+def multiquery_queries():
+    with open(os.path.join(HERE, "multiquery_queries.json")) as f:
+        return synth.queries_from_json(json.load(f)["queries"])
 
 
 def rmat_case():
@@ -35,9 +46,13 @@ def rmat_case():
 
 
 def multiquery_case():
-    with open(os.path.join(HERE, "multiquery_queries.json")) as f:
-        qdoc = json.load(f)
-    return synth.multiquery_case(queries=synth.queries_from_json(qdoc["queries"]), **MULTI)
+    return synth.multiquery_case(queries=multiquery_queries(), **MULTI)
+
+
+def serving_case():
+    # the serving workload's 16 queries, each ordered in time along its edges
+    qs = [synth.with_ranks(q, np.arange(len(q["qsrc"]))) for q in multiquery_queries()[:16]]
+    return synth.serving_case(qs, **SERVING)
 
 
 def oracle_results(case, n_batches):
@@ -70,8 +85,10 @@ def main(which):
         case, params, n, name = rmat_case(), RMAT, RMAT_BATCHES, "fullsize_rmat_s20.json"
     elif which == "multiquery":
         case, params, n, name = multiquery_case(), MULTI, MULTI_BATCHES, "fullsize_multiquery_s20.json"
+    elif which == "serving":
+        case, params, n, name = serving_case(), SERVING, SERVING["n_batches"], "fullsize_serving_s22.json"
     else:
-        raise SystemExit("usage: make_fullsize_golden.py rmat|multiquery")
+        raise SystemExit("usage: make_fullsize_golden.py rmat|multiquery|serving")
     print("generated %s in %.1f s" % (case["name"], time.perf_counter() - t), flush=True)
     doc = {"workload": case["name"], "params": params, "generator": "paper_2206_09983_amd.synth." + which + "_case",
            "command": "python tests/golden/make_fullsize_golden.py " + which,

@@ -25,7 +25,10 @@ what holds at any size plus outputs the oracle can compute one by one:
 The 64-query stream (the same edges in log-uniform batches, 64 random
 queries): counts and both digests of every query and phase of its first four
 batches equal the oracle's, stored in tests/golden/fullsize_multiquery_s20.json
-by the same oracle-only script.
+by the same oracle-only script. The serving stream's window (2^22 vertices,
+2^26 edges, 16 temporally ordered queries): counts and digests of two
+batches of 65,536 arrivals with the deletions of the keys that left the
+window, likewise from the oracle (tests/golden/fullsize_serving_s22.json).
 """
 import json
 import os
@@ -306,6 +309,44 @@ def test_full_size_multiquery_stream_equals_the_oracle_golden():
                 assert [r["n_new"], *r["dig_new"]] == rq["new"], (rec["index"], rq["name"], "new")
                 assert [r["n_expired"], *r["dig_expired"]] == rq["expired"], (rec["index"], rq["name"], "expired")
             say("batch %d (%d insertions, %d deletions): 64 queries' counts and digests equal the oracle's (%.1f s)"
+                % (rec["index"], rec["n_ins"], rec["n_del"], time.time() - t0))
+    finally:
+        m.close()
+
+
+SERVING_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fullsize_serving_s22.json")
+
+
+def test_full_size_serving_window_equals_the_oracle_golden():
+    # A slice of the serving stream: 2^22 vertices, a 2^26-edge window over
+    # 2^24 ticks, arrivals at 2e7 edges/s in batches of 65,536, each deleting
+    # the keys that left the window, and the serving workload's 16 queries,
+    # each ordered in time along its edges.
+    torch = pytest.importorskip("torch")
+    from paper_2206_09983_amd import binding as B
+    B.load()
+    with open(SERVING_GOLDEN) as f:
+        gold = json.load(f)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "multiquery_queries.json")) as f:
+        qdoc = json.load(f)
+    t0 = time.time()
+    qs = [synth.with_ranks(q, np.arange(len(q["qsrc"]))) for q in synth.queries_from_json(qdoc["queries"][:16])]
+    case = synth.serving_case(qs, **gold["params"])
+    assert [q["name"] for q in qs] == gold["queries"]
+    say("full-size golden: %s, %d batches (%.1f s)" % (case["name"], len(gold["batches"]), time.time() - t0))
+    stream = torch.cuda.current_stream()
+    m = B.Matcher(case["graph"], qs, flags=B.F_EMIT | B.F_TIMING, out_capacity=1 << 16, stream=stream.cuda_stream,
+                  n_elabels=32)
+    try:
+        for rec in gold["batches"]:
+            b = case["batches"][rec["index"]]
+            assert (len(b["src"]), len(b["del_keys"])) == (rec["n_ins"], rec["n_del"])
+            m.apply_batch(device_batch(torch, b))
+            for qi, rq in enumerate(rec["queries"]):
+                r = m.result(qi)
+                assert [r["n_new"], *r["dig_new"]] == rq["new"], (rec["index"], rq["name"], "new")
+                assert [r["n_expired"], *r["dig_expired"]] == rq["expired"], (rec["index"], rq["name"], "expired")
+            say("batch %d (%d insertions, %d deletions): 16 temporal queries equal the oracle (%.1f s)"
                 % (rec["index"], rec["n_ins"], rec["n_del"], time.time() - t0))
     finally:
         m.close()
