@@ -282,11 +282,14 @@ def serving_bench(args):
         nb = len(srv.batches)
         ins = sum(b["n_ins"] for b in srv.batches)
         st = srv.m.stats()
+        host = {k: v / max(1, nb) for k, v in srv.host_ms.items()}
         out.append({"rate": rate, "edges_per_s": eps, "insertions": ins, "batches": nb,
                     "mean_batch": ins / max(1, nb), "p50_ms": p50, "p99_ms": p99,
-                    "slot_high_water": st["slot_high_water"]})
-        log("rate %.0f: %.3gM edges/s processed, %d batches (mean %d insertions), p50 %.2f ms p99 %.2f ms" % (
-            rate, eps / 1e6, nb, ins / max(1, nb), p50 or 0, p99 or 0))
+                    "slot_high_water": st["slot_high_water"], "host_ms_per_batch": host})
+        log("rate %.0f: %.3gM edges/s processed, %d batches (mean %d insertions), p50 %.2f ms p99 %.2f ms; "
+            "host ms per batch: form %.2f, apply %.2f (device %.2f), results %.2f" % (
+                rate, eps / 1e6, nb, ins / max(1, nb), p50 or 0, p99 or 0, host["form"], host["apply"],
+                host["device"], host["results"]))
         srv.close()
     top = out[-1]
     line = {"metric": METRIC, "value": top["edges_per_s"], "unit": "matched data edges/s", "n_gpus": 1,

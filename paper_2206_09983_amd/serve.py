@@ -64,6 +64,7 @@ class Server:
         self.out_capacity = int(out_capacity)
         self.keep_lists = keep_lists
         self.emit = bool(flags & B.F_EMIT)
+        self.timing = bool(flags & B.F_TIMING) and backend is None
         self.n_vertices = int(graph["n_vertices"])
         self.device_inputs = device_inputs
         self.stream = stream
@@ -99,6 +100,9 @@ class Server:
             self.m = backend(graph, act)
         self.batches = []   # per batch: dict(now, n_ins, n_del, active, results, latency_ms)
         self.n_edges = 0
+        # host time of the batch steps (ms, summed): forming batches, the
+        # library call, reading results
+        self.host_ms = {"form": 0.0, "apply": 0.0, "results": 0.0, "device": 0.0}
 
     # ------------------------------------------------------------ queries
     def submit(self, query, lifetime=None):
@@ -191,6 +195,7 @@ class Server:
         """Runs one batch if due at time `now` (ticks). Returns its record or None."""
         if not self.due(now):
             return None
+        t_form = time.perf_counter()
         (src, dst, lab, ts), wall0 = self._take(self.flush)
         if int(ts[0]) < self.last_ts:
             raise ValueError("arrival timestamps must not decrease")
@@ -208,6 +213,7 @@ class Server:
                      "del_keys": torch.from_numpy(del_keys.view(np.int64)).cuda()}
             if self.stream is None:
                 torch.cuda.current_stream().synchronize()
+        t_apply = time.perf_counter()
         first = self.m.apply_batch(batch)
         done = time.perf_counter()
         assert first == self.next_key, (first, self.next_key)
@@ -224,6 +230,12 @@ class Server:
                 rec["expired"] = self.m.keys(pos, expired=True)
             res[qid] = rec
             self.info[qid]["batches"] += 1
+        if self.timing:
+            self.host_ms["device"] += self.m.stats()["ms_batch"]
+        t_end = time.perf_counter()
+        self.host_ms["form"] += (t_apply - t_form) * 1e3
+        self.host_ms["apply"] += (done - t_apply) * 1e3
+        self.host_ms["results"] += (t_end - done) * 1e3
         rec = {"now": int(now), "n_ins": len(ts), "n_del": len(del_keys), "del_range": (lo, cut), "first_key": first,
                "active": list(self.active), "results": res,
                "latency_ms": (done - wall0) * 1e3 if wall0 is not None else None}
@@ -286,6 +298,11 @@ def run_realtime(server, src, dst, lab, ts, tick_s=1e-6, duration_s=None):
     stop = threading.Event()
 
     def intake():
+        # arrivals are pushed in slices of at most `poll` seconds; the thread
+        # sleeps between slices, as a network reader blocks on its socket,
+        # so the batch loop gets the interpreter back as soon as its library
+        # call returns
+        poll = 0.0002
         i = 0
         while i < n and not stop.is_set():
             now = (time.perf_counter() - t0) / tick_s + base
@@ -293,8 +310,9 @@ def run_realtime(server, src, dst, lab, ts, tick_s=1e-6, duration_s=None):
             if j > i:
                 server.push(src[i:j], dst[i:j], lab[i:j], ts[i:j], wall=t0 + (int(ts[i]) - base) * tick_s)
                 i = j
+                time.sleep(poll)
             else:
-                time.sleep(min(0.0002, max(0.0, (int(ts[i]) - now) * tick_s)))
+                time.sleep(min(poll, max(0.0, (int(ts[i]) - now) * tick_s)))
         stop.set()
 
     th = threading.Thread(target=intake, daemon=True)
