@@ -925,11 +925,12 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
         n = min(n, nd);
     }
     if (zero_next && blockIdx.x == 0 && threadIdx.x == 0) *zero_next = 0u;
-    if (blockIdx.x * MN_BLOCK >= n) return;  // the grid covers the capacity; the same for the whole block
+    if (blockIdx.x * MN_BLOCK >= n) return;  // the same for the whole block
     acc_init(A, 0, err);
-    const uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x;
     Cnt K = {};
-    if (r < n && !A.dead) {
+    // the grid is bounded (the row count may be known on the device only):
+    // it strides over the rows
+    for (uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x; r < n && !A.dead; r += gridDim.x * MN_BLOCK) {
         const SeedPlan* P = &g.plans[rcol(R, 0, r)];
         const LevelDesc lv = load_level(P, L);
         if (R.hpre) {
@@ -1576,7 +1577,10 @@ void mn_launch_note_count(const uint32_t* count, uint64_t cap, unsigned long lon
 void mn_launch_level_range(const GraphView& g, RowsView rows, uint32_t n, const uint32_t* n_dev, uint32_t L,
                            uint32_t* lo, uint32_t* cnt, EnumStats* st, const uint32_t* err, hipStream_t s,
                            uint32_t* zero_next, unsigned long long* note) {
-    k_level_range<<<nblocks(n ? n : 1), MN_BLOCK, 0, s>>>(g, rows, n, n_dev, L, lo, cnt, st, zero_next, note, err);
+    // at most 16 blocks per CU: a device-sized level passes its buffer's
+    // capacity as n, most of it unused
+    const uint32_t blocks = std::min<uint32_t>(nblocks(n ? n : 1), 4096u);
+    k_level_range<<<blocks, MN_BLOCK, 0, s>>>(g, rows, n, n_dev, L, lo, cnt, st, zero_next, note, err);
 }
 
 uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return expand_tiles(c0, c1, EX_TILE_MIN); }
