@@ -207,13 +207,15 @@ def load_weights(path=None):
 def time_stream(graph, queries, batches, mode, weights=None, flags=B.F_EMIT, n_elabels=32, warmup=2,
                 out_capacity=1 << 22):
     """Runs the stream under one scheduler mode; returns ms per batch (timed
-    batches), per-batch (count, digest) results and enumeration work."""
+    batches, wall clock), the expansion kernels' summed device time over the
+    timed batches (expand_ms), per-batch (count, digest) results and
+    enumeration work."""
     import torch
     stream = torch.cuda.current_stream()
     dev = [_device_batch(torch, b) for b in batches]
-    m = B.Matcher(graph, queries, flags=flags, stream=stream.cuda_stream, n_elabels=n_elabels,
+    m = B.Matcher(graph, queries, flags=flags | B.F_TIMING, stream=stream.cuda_stream, n_elabels=n_elabels,
                   out_capacity=out_capacity)
-    res, ms, work = [], [], 0
+    res, ms, work, expand_ms = [], [], 0, 0.0
     try:
         m.set_scheduler(mode, weights)
         for bi, db in enumerate(dev):
@@ -224,12 +226,14 @@ def time_stream(graph, queries, batches, mode, weights=None, flags=B.F_EMIT, n_e
             if bi >= warmup:
                 ms.append(dt)
             st = m.stats()
+            if bi >= warmup:
+                expand_ms += sum(st["ms_expand"])
             work += sum(st["entries_scanned"]) + sum(st["seeds"])
             res.append([(r["n_new"], r["dig_new"], r["n_expired"], r["dig_expired"])
                         for r in (m.result(q) for q in range(len(queries)))])
     finally:
         m.close()
-    return {"ms": float(np.mean(ms)) if ms else 0.0, "results": res, "work": int(work)}
+    return {"ms": float(np.mean(ms)) if ms else 0.0, "expand_ms": expand_ms, "results": res, "work": int(work)}
 
 
 def workload(name, seed, scale=20):

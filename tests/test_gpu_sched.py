@@ -233,13 +233,28 @@ def test_committed_network_cuts_the_64_query_streams_work_at_least_in_half(B):
     # The 64-query stream is where matching orders matter (cycles and
     # cliques). On its first batches (stream seed 7; the network was trained
     # on seed 9) the learned choice must at least halve the candidates
-    # examined, with identical counts and digests.
+    # examined, with identical counts and digests, and take less time per
+    # batch: the better of two alternating runs per mode (the expansion
+    # kernels' summed device time is reported beside it; the order saves
+    # time in the levels' bookkeeping as much as in the expansion itself).
     from paper_2206_09983_amd import sched
     w = sched.load_weights()
     case = sched.workload("multiquery", 7)
     batches = case["batches"][:6]
-    st = sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_STATIC, flags=0, warmup=0)
-    le = sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_LEARNED, w, flags=0, warmup=0)
-    say("64-query work: static %d learned %d (%.2fx)" % (st["work"], le["work"], st["work"] / max(1, le["work"])))
-    assert st["results"] == le["results"]
+    runs = {"static": [], "learned": []}
+    for _ in range(2):
+        runs["static"].append(sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_STATIC, flags=0,
+                                                warmup=0))
+        runs["learned"].append(sched.time_stream(case["graph"], case["queries"], batches, B.SCHED_LEARNED, w,
+                                                 flags=0, warmup=0))
+    st, le = runs["static"][0], runs["learned"][0]
+    ex_st = min(r["expand_ms"] for r in runs["static"])
+    ex_le = min(r["expand_ms"] for r in runs["learned"])
+    wall_st = min(r["ms"] for r in runs["static"])
+    wall_le = min(r["ms"] for r in runs["learned"])
+    say("64-query work: static %d learned %d (%.2fx); expansion %.2f vs %.2f ms (%.2fx); batch %.2f vs %.2f ms "
+        "(%.2fx)" % (st["work"], le["work"], st["work"] / max(1, le["work"]), ex_st, ex_le, ex_st / ex_le, wall_st,
+                     wall_le, wall_st / wall_le))
+    assert all(r["results"] == st["results"] for rs in runs.values() for r in rs)
     assert le["work"] * 2 <= st["work"]
+    assert wall_le * 1.05 <= wall_st
