@@ -399,50 +399,75 @@ __device__ void grouped_digest(bool active, uint32_t q, uint64_t a, uint64_t b, 
     }
 }
 
-// Combination t of the closing edges' instances: digit i = which accepted
-// instance of close[i] (mixed radix over cnt[]).
+// The combinations of the closing edges' instances, stepped through like an
+// odometer: digit i is the position of close[i]'s current accepted instance
+// in its run, digit 0 moves fastest. A step walks only the digits that move
+// (one run step each, plus a wrap to the run's first instance on a carry),
+// so a combination costs O(1) run steps on average instead of a walk from
+// every run's start. st[i] is close[i]'s first accepted instance (as
+// close_find returns it), RUN_SWAP marking the list of f(nv).
 template <int NC>
-__device__ inline void combo_digits(uint64_t t, const uint32_t* cnt, uint32_t* dig) {
+__device__ inline void odo_first(const SeedPlan& P, const uint32_t* st, uint32_t* pos) {
     constexpr int NA = NC > 0 ? NC : 1;
 #pragma unroll
-    for (uint32_t i = 0; i < NA; i++) {
-        dig[i] = 0;
-        if (t) {  // t = 0 (the only tuple when every run holds one instance) has all digits 0
-            dig[i] = (uint32_t)(t % cnt[i]);
-            t /= cnt[i];
-        }
-    }
+    for (uint32_t i = 0; i < NA; i++) pos[i] = st[i] & ~RUN_SWAP;
 }
 
-// Position of the dig-th accepted instance of closing edge ci in its run.
+// Advances to the next combination; false after the last one (every digit
+// back at its first instance).
 template <int NC>
-__device__ inline uint32_t close_instance(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                                          const uint32_t* dig, uint32_t ci, RunIt& it) {
+__device__ inline bool odo_next(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                                uint32_t* pos) {
     constexpr int NA = NC > 0 ? NC : 1;
-    uint32_t s_st = 0, s_dig = 0;
+    // one digit per step of a rolled loop: the run walk is compiled once,
+    // and the digit's state is picked from and put back into the arrays
+#pragma unroll 1
+    for (uint32_t i = 0; i < (uint32_t)NC && i < P.n_close; i++) {
+        uint32_t s_st = 0, s_pos = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < NA; k++)
+            if (k == i) {
+                s_st = st[k];
+                s_pos = pos[k];
+            }
+        const CloseDesc c = P.close[i];
+        const RunIt it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
+        uint32_t unused = 0;
+        const uint32_t q = run_next(it, s_pos + 1, unused);
+        const bool moved = q < it.end;
+        const uint32_t v = moved ? q : it.p;  // a carry puts the digit back at its first instance
+#pragma unroll
+        for (uint32_t k = 0; k < NA; k++)
+            if (k == i) pos[k] = v;
+        if (moved) return true;
+    }
+    return false;
+}
+
+// Key of close[ci]'s current instance (pos[ci] in the list st[ci] names).
+template <int NC>
+__device__ inline uint64_t odo_key(const GraphView& g, const SeedPlan& P, const uint32_t* st, const uint32_t* pos,
+                                   uint32_t ci) {
+    constexpr int NA = NC > 0 ? NC : 1;
+    uint32_t s_st = 0, s_pos = 0;
 #pragma unroll
     for (uint32_t i = 0; i < NA; i++)
         if (i == ci) {
             s_st = st[i];
-            s_dig = dig[i];
+            s_pos = pos[i];
         }
     const CloseDesc c = P.close[ci];
-    it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
-    uint32_t unused = 0;
-    uint32_t p = run_next(it, it.p, unused);
-    for (uint32_t n = 0; n < s_dig; n++) p = run_next(it, p + 1, unused);
-    return p;
+    const uint32_t dir = (s_st & RUN_SWAP) ? 1u - c.dir : (uint32_t)c.dir;
+    return g.keys(dir)[s_pos];
 }
 
-// Timestamp of the edge that query edge k maps to in combination dig.
+// Timestamp of the edge that query edge k maps to in the current combination.
 template <int NC>
 __device__ inline int64_t edge_ts(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                                  const uint32_t* dig, uint32_t k, uint32_t aqe, uint64_t akey) {
+                                  const uint32_t* pos, uint32_t k, uint32_t aqe, uint64_t akey) {
     const uint32_t ci = P.close_idx[k];
     if (k == aqe || ci == TREE_EDGE) return g.key_ts[(k == aqe ? akey : B.tree_key(k)) & g.key_mask];
-    RunIt it;
-    const uint32_t p = close_instance<NC>(g, P, B, st, dig, ci, it);
-    return g.key_ts[it.adjk[p] & g.key_mask];  // p < end: the combination's instances were counted
+    return g.key_ts[odo_key<NC>(g, P, st, pos, ci) & g.key_mask];
 }
 
 // Temporal order of one complete embedding: walking the ranked edges by
@@ -450,7 +475,7 @@ __device__ inline int64_t edge_ts(const GraphView& g, const SeedPlan& P, const B
 // all lower ranks.
 template <int NC>
 __device__ bool in_time_order(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                              const uint32_t* dig, uint32_t aqe, uint64_t akey) {
+                              const uint32_t* pos, uint32_t aqe, uint64_t akey) {
     int64_t below = INT64_MIN, level = INT64_MIN;
     int cur = -1;
     for (uint32_t x = 0; x < P.n_ranked; x++) {
@@ -460,41 +485,49 @@ __device__ bool in_time_order(const GraphView& g, const SeedPlan& P, const Bind&
             level = INT64_MIN;
             cur = P.rank[k];
         }
-        const int64_t t = edge_ts<NC>(g, P, B, st, dig, k, aqe, akey);
+        const int64_t t = edge_ts<NC>(g, P, B, st, pos, k, aqe, akey);
         if (!(below < t)) return false;
         level = max(level, t);
     }
     return true;
 }
 
-// Number of embeddings of a complete vertex mapping: the product over the
-// closing edges of their accepted instances (st[i] is the run start of
-// close[i]; cnt[i] receives each factor), or, for a plan with a temporal
-// order, the combinations of instances that satisfy it. aqe/akey: the anchor
-// query edge of the level and its edge (0xFF: none).
+// Number of embeddings of a complete mapping: the product over the
+// closing edges of their accepted instances (st[i] is the first accepted
+// instance of close[i]), or, for a plan with a temporal order, the
+// combinations of instances that satisfy it. aqe/akey: the anchor query edge
+// of the level and its edge (0xFF: none).
 template <int NC>
 __device__ uint64_t close_mult(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                               uint32_t* cnt, uint32_t& probes, uint32_t aqe, uint64_t akey) {
+                               uint32_t& probes, uint32_t aqe, uint64_t akey) {
     constexpr int NA = NC > 0 ? NC : 1;
     uint64_t mult = 1;
 #pragma unroll
     for (uint32_t i = 0; i < NA; i++) {
-        cnt[i] = 1;
         if (i < (uint32_t)NC && i < P.n_close) {
             const CloseDesc c = P.close[i];
             const RunIt it = run_open(g, c, st[i], B.f(c.other), B.f(c.nv));
             uint32_t n = 0;
             for (uint32_t p = run_next(it, it.p, probes); p < it.end; p = run_next(it, p + 1, probes)) n++;
-            cnt[i] = n;
             mult *= n;
         }
     }
     if (P.temporal && mult) {
+        uint32_t pos[NA];
+        odo_first<NC>(P, st, pos);
         uint64_t ok = 0;
-        for (uint64_t t = 0; t < mult; t++) {
-            uint32_t dig[NA];
-            combo_digits<NC>(t, cnt, dig);
-            ok += in_time_order<NC>(g, P, B, st, dig, aqe, akey) ? 1u : 0u;
+        if constexpr (NC == 1) {  // one closing edge: a plain walk over its run
+            const CloseDesc c = P.close[0];
+            const RunIt it = run_open(g, c, st[0], B.f(c.other), B.f(c.nv));
+            uint32_t unused = 0;
+            for (uint32_t p = it.p; p < it.end; p = run_next(it, p + 1, unused)) {
+                pos[0] = p;
+                ok += in_time_order<NC>(g, P, B, st, pos, aqe, akey) ? 1u : 0u;
+            }
+        } else {
+            do {
+                ok += in_time_order<NC>(g, P, B, st, pos, aqe, akey) ? 1u : 0u;
+            } while (odo_next<NC>(g, P, B, st, pos));
         }
         mult = ok;
     }
@@ -506,11 +539,12 @@ __device__ uint64_t close_mult(const GraphView& g, const SeedPlan& P, const Bind
 // lists its edges' keys in query-edge order, the anchor query edge aqe
 // (0xFF: none) mapping to the edge with key akey, and is folded as
 // h_s = mix(...mix(mix(s ^ q) + k_0)... + k_{m-1}), mix = SplitMix64's
-// finaliser.
+// finaliser. Combinations come in odometer order; under a temporal order
+// only those that satisfy it (close_mult counted exactly those: mult).
 template <int NC>
 __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                            const uint32_t* cnt, uint64_t mult, uint32_t aqe, uint64_t akey, uint64_t pos,
-                            const PhaseOut& po, Cnt& K, uint64_t& dA, uint64_t& dB) {
+                            uint64_t mult, uint32_t aqe, uint64_t akey, uint64_t pos0, const PhaseOut& po, Cnt& K,
+                            uint64_t& dA, uint64_t& dB) {
     constexpr int NA = NC > 0 ? NC : 1;
     const uint32_t q = P.q;
     const OutView& ov = po.outs[q];
@@ -519,22 +553,14 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
     const uint32_t nqe = P.n_qe;
     const uint64_t s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
     const uint64_t s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
-    // every combination of instances; under a temporal order only those
-    // that satisfy it (close_mult counted exactly those: mult of them)
-    uint64_t total = mult;
-    if (P.temporal) {
-        total = 1;
-#pragma unroll
-        for (uint32_t i = 0; i < NA; i++) total *= cnt[i];
-    }
+    uint32_t pos[NA];
+    odo_first<NC>(P, st, pos);
     uint64_t j = 0;
-    for (uint64_t t = 0; t < total && j < mult; t++) {
-        uint32_t dig[NA];
-        combo_digits<NC>(t, cnt, dig);
-        if (P.temporal && !in_time_order<NC>(g, P, B, st, dig, aqe, akey)) continue;
+    auto one = [&]() {  // the current combination, when it is an embedding
+        if (P.temporal && !in_time_order<NC>(g, P, B, st, pos, aqe, akey)) return;
         uint64_t hA = s0A, hB = s0B;
-        const bool write = po.emit && (pos + j) < cap;
-        uint64_t* row = out + (pos + j) * nqe;
+        const bool write = po.emit && (pos0 + j) < cap;
+        uint64_t* row = out + (pos0 + j) * nqe;
         j++;
         for (uint32_t k = 0; k < nqe; k++) {
             uint64_t key;
@@ -544,9 +570,7 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
             } else if (ci == TREE_EDGE) {
                 key = B.tree_key(k);
             } else {
-                RunIt it;
-                const uint32_t p = close_instance<NC>(g, P, B, st, dig, ci, it);  // walks runs counted by close_mult
-                key = p < it.end ? it.adjk[p] : 0ull;  // p < end: the instances were counted
+                key = odo_key<NC>(g, P, st, pos, ci);
             }
             K.keys++;
             hA = mn_mix64(hA + key);
@@ -556,6 +580,23 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
         dA += hA;
         dB += hB;
         K.tuples++;
+    };
+    if constexpr (NC <= 1) {  // at most one closing edge: a plain walk over its run
+        if (NC == 0 || P.n_close == 0) {
+            one();
+        } else {
+            const CloseDesc c = P.close[0];
+            const RunIt it = run_open(g, c, st[0], B.f(c.other), B.f(c.nv));
+            uint32_t unused = 0;
+            for (uint32_t p = it.p; p < it.end && j < mult; p = run_next(it, p + 1, unused)) {
+                pos[0] = p;
+                one();
+            }
+        }
+    } else {
+        do {
+            one();
+        } while (j < mult && odo_next<NC>(g, P, B, st, pos));
     }
 }
 
@@ -566,13 +607,11 @@ template <int NC>
 __device__ void emit_complete(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
                               uint32_t aqe, uint64_t akey, bool active, const PhaseOut& po, BlockAcc& A,
                               Cnt& K) {
-    constexpr int NA = NC > 0 ? NC : 1;
-    uint32_t cnt[NA];
-    const uint64_t mult = active ? close_mult<NC>(g, P, B, st, cnt, K.probes, aqe, akey) : 0u;
+    const uint64_t mult = active ? close_mult<NC>(g, P, B, st, K.probes, aqe, akey) : 0u;
     const uint32_t q = P.q;
     const uint64_t pos = grouped_reserve(mult != 0, q, mult, po.count);
     uint64_t dA = 0, dB = 0;
-    if (mult) emit_tuples<NC>(g, P, B, st, cnt, mult, aqe, akey, pos, po, K, dA, dB);
+    if (mult) emit_tuples<NC>(g, P, B, st, mult, aqe, akey, pos, po, K, dA, dB);
     grouped_digest(mult != 0, q, dA, dB, A.dig);
 }
 
@@ -1394,9 +1433,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                     for (uint32_t c = 0; c < NA; c++)
                         if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
                             st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
-                    uint32_t cnt[NA];
-                    mult = close_mult<NC>(g, *P, B, st, cnt, K.probes, lv.qe,
-                                          H.temporal ? g.keys(lv.dir)[p] : 0ull);
+                    mult = close_mult<NC>(g, *P, B, st, K.probes, lv.qe, H.temporal ? g.keys(lv.dir)[p] : 0ull);
                 }
             }
             const bool has = mult != 0;
@@ -1518,10 +1555,9 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                 for (uint32_t c = 0; c < NA; c++)
                     if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
                         st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
-                uint32_t cnt[NA];
                 uint32_t unused = 0;
-                const uint64_t mult = close_mult<NC>(g, *P, B, st, cnt, unused, lv.qe, akey);
-                emit_tuples<NC>(g, *P, B, st, cnt, mult, lv.qe, akey, pos, po, K, dA, dB);
+                const uint64_t mult = close_mult<NC>(g, *P, B, st, unused, lv.qe, akey);
+                emit_tuples<NC>(g, *P, B, st, mult, lv.qe, akey, pos, po, K, dA, dB);
             }
         }
     }
