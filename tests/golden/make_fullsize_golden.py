@@ -2,7 +2,7 @@
 query and phase, computed by the CPU oracle alone.
 
 Test infrastructure, run once offline (it takes minutes of CPU time):
-    python tests/golden/make_fullsize_golden.py rmat        # fullsize_rmat_s20.json
+    python tests/golden/make_fullsize_golden.py rmat [W]    # fullsize_rmat_s20.json (W worker processes)
     python tests/golden/make_fullsize_golden.py multiquery  # fullsize_multiquery_s20.json
     python tests/golden/make_fullsize_golden.py serving     # fullsize_serving_s22.json
 Each file records the workload's parameters and the oracle's results for the
@@ -30,7 +30,7 @@ from paper_2206_09983_amd import synth  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 RMAT = dict(scale=20, n_init=1 << 24, n_stream=1 << 23, batch=65536, del_frac=0.10, seed=7, query_seed=7)
-RMAT_BATCHES = 6
+RMAT_BATCHES = 120  # through the benchmark's last timed batch (5 warm-up, then every 6th up to 119)
 MULTI = dict(scale=20, n_init=1 << 24, del_frac=0.10, seed=7)
 MULTI_BATCHES = 4
 SERVING = dict(scale=22, n_window=1 << 26, rate=2e7, batch=65536, n_batches=2, window_ticks=1 << 24, seed=7)
@@ -55,11 +55,17 @@ def serving_case():
     return synth.serving_case(qs, **SERVING)
 
 
-def oracle_results(case, n_batches):
+def oracle_results(case, n_batches, first=0):
+    """Results of batches [first, n_batches): the batches before `first` are
+    applied without enumeration (the graph after them is the same)."""
     o = Oracle(case["graph"], case["queries"])
     out = []
     try:
-        for i in range(n_batches):
+        for i in range(first):
+            b = case["batches"][i]
+            o.insert(b, enumerate=False)
+            o.delete(b["del_keys"], enumerate=False)
+        for i in range(first, n_batches):
             b = case["batches"][i]
             t = time.perf_counter()
             o.apply_batch(b)
@@ -79,7 +85,24 @@ def oracle_results(case, n_batches):
     return out
 
 
-def main(which):
+def _chunk(args):
+    which, lo, hi = args
+    case = {"rmat": rmat_case, "multiquery": multiquery_case, "serving": serving_case}[which]()
+    return oracle_results(case, hi, first=lo)
+
+
+def parallel_results(which, n, workers):
+    """Batches cut into `workers` consecutive ranges, each computed by its own
+    oracle process that first replays the batches before its range."""
+    import multiprocessing as mp
+    bounds = [round(n * k / workers) for k in range(workers + 1)]
+    jobs = [(which, bounds[k], bounds[k + 1]) for k in range(workers) if bounds[k] < bounds[k + 1]]
+    with mp.get_context("fork").Pool(len(jobs)) as pool:
+        parts = pool.map(_chunk, jobs)
+    return [rec for part in parts for rec in part]
+
+
+def main(which, workers=1):
     t = time.perf_counter()
     if which == "rmat":
         case, params, n, name = rmat_case(), RMAT, RMAT_BATCHES, "fullsize_rmat_s20.json"
@@ -94,7 +117,7 @@ def main(which):
            "command": "python tests/golden/make_fullsize_golden.py " + which,
            "queries": [q.get("name", "") for q in case["queries"]],
            "result_format": "per query and phase: [count, digest seed A, digest seed B] (digests mod 2^64)",
-           "batches": oracle_results(case, n)}
+           "batches": oracle_results(case, n) if workers <= 1 else parallel_results(which, n, workers)}
     with open(os.path.join(HERE, name), "w") as f:
         json.dump(doc, f, indent=1)
         f.write("\n")
@@ -102,4 +125,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "rmat")
+    main(sys.argv[1] if len(sys.argv) > 1 else "rmat", int(sys.argv[2]) if len(sys.argv) > 2 else 1)
