@@ -98,6 +98,27 @@ void setup_scratch(int device) {
     g_scratch_ptr[device] = static_cast<uint64_t*>(ptr);
 }
 
+// Device memory comes from the device's stream-ordered pool, and the pool
+// keeps what is freed: a buffer that grows is replaced without a stream
+// synchronisation, and a later allocation (in this context or another) reuses
+// the pool's memory instead of mapping new pages, which a plain allocation
+// after a large free can take tens of milliseconds to do. Set up once per
+// device. t_stream is the calling context's stream: allocations and frees
+// are ordered on it.
+bool g_pool_ready[MN_MAX_DEVICES] = {};
+thread_local hipStream_t t_stream = nullptr;
+
+void setup_pool(int device) {
+    if (device < 0 || device >= MN_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_pool_ready[device]) return;
+    hipMemPool_t pool = nullptr;
+    HIPCHK(hipDeviceGetDefaultMemPool(&pool, device));
+    uint64_t keep = ~0ull;
+    HIPCHK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    g_pool_ready[device] = true;
+}
+
 uint64_t* scratch_of(int device) {
     if (device < 0 || device >= MN_MAX_DEVICES) return nullptr;
     std::lock_guard<std::mutex> lock(g_scratch_mu);
@@ -115,7 +136,17 @@ void dev_alloc(T*& p, size_t n) {
         throw ApiError{MNEMONIC_E_OOM, "device allocation of " + std::to_string(n * sizeof(T)) +
                                            " bytes failed (injected)"};
     const auto t0 = std::chrono::steady_clock::now();
-    hipError_t e = hipMalloc(&q, n * sizeof(T));
+    hipError_t e = hipMallocAsync(&q, n * sizeof(T), t_stream);
+    if (e != hipSuccess) {
+        // the pool may hold freed memory the request needs: hand it back to
+        // the device once the stream's pending frees are done, and try again
+        (void)hipGetLastError();
+        int dev = 0;
+        hipMemPool_t pool = nullptr;
+        if (hipStreamSynchronize(t_stream) == hipSuccess && hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && hipMemPoolTrimTo(pool, 0) == hipSuccess)
+            e = hipMallocAsync(&q, n * sizeof(T), t_stream);
+    }
     t_alloc_n++;
     t_alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (e != hipSuccess) {
@@ -127,9 +158,9 @@ void dev_alloc(T*& p, size_t n) {
 
 template <typename T>
 void dev_free(T*& p) {
-    if (p) {
+    if (p) {  // after the work already queued on the stream, which may still use it
         const auto t0 = std::chrono::steady_clock::now();
-        (void)hipFree(p);
+        (void)hipFreeAsync(p, t_stream);
         t_alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     p = nullptr;
@@ -139,15 +170,14 @@ void dev_free(T*& p) {
 template <typename T>
 void dev_grow(T*& p, uint64_t& cap, uint64_t need, uint64_t keep, hipStream_t s) {
     if (need <= cap && p) return;
-    // twice the need: a regrowth stalls the stream (allocation, copy, free),
-    // and the device has memory to spare for a stream that keeps growing
+    // twice the need: a stream that keeps growing regrows rarely, and the
+    // device has memory to spare
     uint64_t nc = std::max<uint64_t>(2 * need, 2 * cap);
     nc = std::max<uint64_t>(nc, 256);
     T* np = nullptr;
     dev_alloc(np, nc);
     if (p && keep) HIPCHK(hipMemcpyAsync(np, p, keep * sizeof(T), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    dev_free(p);
+    dev_free(p);  // stream-ordered: after the copy
     p = np;
     cap = nc;
 }
@@ -355,6 +385,9 @@ struct mnemonic_ctx {
     // sizes the output buffers before a batch, so that a batch larger than
     // any before does not re-run a phase to grow them.
     std::vector<double> out_rate;
+    // Largest tuple count seen per (query, phase): bounds that sizing, since a
+    // rate taken on a small batch can overstate a large one by far.
+    std::vector<uint64_t> out_max;
     OutView* d_outs = nullptr;
 
     // host mirrors
@@ -947,8 +980,7 @@ void ensure_capacity(mnemonic_ctx* c, uint64_t n_ins, uint64_t n_del) {
         if (c->cap_keys)
             mn_launch_ring_copy(c->d_key2slot, c->d_key_ts, c->cap_keys - 1, k2s, kts, nc - 1, c->key_lo,
                                 c->next_key, s);
-        HIPCHK(hipStreamSynchronize(s));
-        dev_free(c->d_key2slot);
+        dev_free(c->d_key2slot);  // stream-ordered: after the copy
         dev_free(c->d_key_ts);
         dev_free(c->d_delbits);
         c->d_key2slot = k2s;
@@ -1064,11 +1096,12 @@ void grow_outputs(mnemonic_ctx* c, const std::vector<uint64_t>& need) {
             for (int p = 0; p < 2; p++) {
                 uint64_t n = need[2 * q + p];
                 if (n <= c->houts[q].cap[p]) continue;
-                uint64_t nc = std::max<uint64_t>(n + n / 4, c->houts[q].cap[p] * 2);
+                // a quarter above the need, or up to twice it for a buffer that
+                // keeps growing
+                uint64_t nc = std::max<uint64_t>(n + n / 4, std::min<uint64_t>(c->houts[q].cap[p] * 2, 2 * n));
                 uint64_t* fresh = nullptr;
                 dev_alloc(fresh, nc * c->hq[q].n_qe);
-                HIPCHK(hipStreamSynchronize(c->stream));  // no launch still writes the old buffer
-                dev_free(c->houts[q].keys[p]);
+                dev_free(c->houts[q].keys[p]);  // stream-ordered: after the launches that wrote it
                 c->houts[q].keys[p] = fresh;
                 c->houts[q].cap[p] = nc;
                 changed = true;
@@ -1109,8 +1142,7 @@ void grow_level(mnemonic_ctx* c, uint32_t L, uint64_t need) {
     if (need <= B.cap) return;
     if (t_no_alloc) return;  // the level keeps its rows; a larger need is noted by the kernels
     uint64_t nc = std::min<uint64_t>(c->rows_max, std::max<uint64_t>(need, std::max<uint64_t>(B.cap * 2, 4096)));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    dev_free(B.rows);
+    dev_free(B.rows);  // stream-ordered: after the launches that used them
     dev_free(B.keys);
     dev_free(B.lo);
     dev_free(B.cnt);
@@ -1214,7 +1246,6 @@ void process_level(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         mn_launch_set_u32(n_out, 0, s);
         const uint64_t need_tiles = mn_expand_tiles(c0, c1) + 1;
         if (need_tiles > c->cap_tiles) {
-            HIPCHK(hipStreamSynchronize(s));
             dev_free(c->d_tiles);
             c->cap_tiles = 0;
             dev_alloc(c->d_tiles, need_tiles);
@@ -1293,7 +1324,6 @@ void device_levels(mnemonic_ctx* c, const GraphView& g, const PhaseOut& po, uint
         if (t_no_alloc) {
             K = c->cap_tiles >= 2 ? (c->cap_tiles - 1) * MN_BLOCK : 0;
         } else {
-            HIPCHK(hipStreamSynchronize(s));
             dev_free(c->d_tiles);
             c->cap_tiles = 0;
             dev_alloc(c->d_tiles, need_tiles);
@@ -1373,7 +1403,6 @@ void enumerate_phase(mnemonic_ctx* c, int p, const uint32_t* slots, uint64_t n_s
             if (!decide) g.dec = nullptr;
             if (decide) {
                 if (c->cap_dec < c->lvb[0].cap) {
-                    HIPCHK(hipStreamSynchronize(s));
                     dev_free(c->d_dec);
                     c->cap_dec = 0;
                     dev_alloc(c->d_dec, c->lvb[0].cap);
@@ -1492,7 +1521,6 @@ void sort_outputs(mnemonic_ctx* c) {
             if (n >= (1ull << 32)) throw ApiError{MNEMONIC_E_LIMIT, "more than 2^32 tuples to sort"};
             const uint32_t m = c->hq[q].n_qe;
             if (n > c->cap_srt) {
-                HIPCHK(hipStreamSynchronize(s));
                 for (int k = 0; k < 2; k++) {
                     dev_free(c->d_srt_k[k]);
                     dev_free(c->d_srt_v[k]);
@@ -1506,7 +1534,6 @@ void sort_outputs(mnemonic_ctx* c) {
                 c->cap_srt = nc;
             }
             if (n * m > c->cap_srt_rows) {
-                HIPCHK(hipStreamSynchronize(s));
                 dev_free(c->d_srt_rows);
                 c->cap_srt_rows = 0;
                 dev_alloc(c->d_srt_rows, 2 * n * m);
@@ -1514,7 +1541,6 @@ void sort_outputs(mnemonic_ctx* c) {
             }
             const uint64_t sw = mn_tuple_sort_scratch_words((uint32_t)n);
             if (sw > c->cap_srt_scr) {
-                HIPCHK(hipStreamSynchronize(s));
                 dev_free(c->d_srt_scr);
                 c->cap_srt_scr = 0;
                 dev_alloc(c->d_srt_scr, 2 * sw);
@@ -1616,7 +1642,9 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                 const double r = c->out_rate[2 * (size_t)q + p];
                 if (r <= 0) continue;
                 const double est = 1.5 * r * (double)(p ? n_del : n_ins);
-                want[2 * (size_t)q + p] = (uint64_t)std::min<double>(est, 4.0 * (double)c->houts[q].cap[p]);
+                const double most = 2.0 * (double)c->out_max[2 * (size_t)q + p] + 65536.0;
+                want[2 * (size_t)q + p] =
+                    (uint64_t)std::min<double>(std::min<double>(est, most), 4.0 * (double)c->houts[q].cap[p]);
             }
         grow_outputs(c, want);
     }
@@ -1855,6 +1883,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
                 const uint64_t n = c->h_zr[c->zr_count(p) + q];
                 double& r = c->out_rate[2 * (size_t)q + p];
                 if (ne) r = std::max<double>(r, (double)n / (double)ne);
+                c->out_max[2 * (size_t)q + p] = std::max<uint64_t>(c->out_max[2 * (size_t)q + p], n);
             }
         // rates of this batch for the next one (levels that saw candidates)
         for (int p = 0; p < 2; p++) {
@@ -1957,7 +1986,10 @@ int guarded(mnemonic_ctx* c, F&& f) {
             c->err = "context unusable: " + c->broken_why + " failed part way; destroy it";
             return MNEMONIC_E_HIP;
         }
-        if (c) c->err.clear();
+        if (c) {
+            c->err.clear();
+            t_stream = c->stream;
+        }
         return f();
     } catch (const ApiError& e) {
         if (c) c->err = e.msg;
@@ -2095,7 +2127,9 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         if (g->n_elabels > 256) throw ApiError{MNEMONIC_E_ARG, "n_elabels > 256"};
         HIPCHK(hipGetDevice(&c->device));
         setup_scratch(c->device);
+        setup_pool(c->device);
         c->stream = static_cast<hipStream_t>(hip_stream);
+        t_stream = c->stream;
         if (opt) c->flags = opt->flags;
         // at most 2^26 rows per level: the kernels index a level's columns in 32 bits
         if (opt && opt->rows_per_level)
@@ -2184,6 +2218,7 @@ int mnemonic_create(const mnemonic_graph* g, const mnemonic_query* q, uint32_t n
         c->out_cap0 = cap;
         c->houts.resize(n_q);
         c->out_rate.assign(2 * (size_t)n_q, -1.0);
+        c->out_max.assign(2 * (size_t)n_q, 0);
         for (uint32_t i = 0; i < n_q; i++)
             for (int p = 0; p < 2; p++) {
                 c->houts[i].cap[p] = (c->flags & MNEMONIC_F_EMIT) ? cap : 0;
@@ -2395,6 +2430,7 @@ int mnemonic_set_queries(mnemonic_ctx* ctx, const mnemonic_query* q, uint32_t n_
         dev_free(c->d_outs);
         c->houts.assign(n_q, OutView{});
         c->out_rate.assign(2 * (size_t)n_q, -1.0);
+        c->out_max.assign(2 * (size_t)n_q, 0);
         for (uint32_t i = 0; i < n_q; i++)
             for (int p = 0; p < 2; p++) {
                 c->houts[i].cap[p] = (c->flags & MNEMONIC_F_EMIT) ? c->out_cap0 : 0;
@@ -2539,7 +2575,9 @@ int mnemonic_mlp_adam(float* w, float* m1, float* m2, float* grad, float lr, uin
 void mnemonic_destroy(mnemonic_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    t_stream = ctx->stream;
     free_all(ctx);
+    (void)hipStreamSynchronize(ctx->stream);  // the frees are ordered on the caller's stream
     delete ctx;
 }
 

@@ -399,25 +399,78 @@ __device__ void grouped_digest(bool active, uint32_t q, uint64_t a, uint64_t b, 
     }
 }
 
+// Whether instance `key` of closing edge ci can take part in a temporally
+// ordered embedding with the mapping's fixed edges (tree edges and the
+// anchor aqe, whose key is akey): its timestamp must exceed theirs of lower
+// rank and stay below theirs of higher rank. Always true for an unranked
+// edge; the other closing edges are checked per combination.
+__device__ inline bool inst_in_window(const GraphView& g, const SeedPlan& P, const Bind& B, uint32_t ci, uint64_t key,
+                                      uint32_t aqe, uint64_t akey) {
+    const int r = P.rank[P.close[ci].qe];
+    if (r < 0) return true;
+    const int64_t t = g.key_ts[key & g.key_mask];
+    for (uint32_t x = 0; x < P.n_ranked; x++) {
+        const uint32_t k = P.rorder[x];
+        const int rk = P.rank[k];
+        if (rk == r || (k != aqe && P.close_idx[k] != TREE_EDGE)) continue;
+        const int64_t tk = g.key_ts[(k == aqe ? akey : B.tree_key(k)) & g.key_mask];
+        if (rk < r ? !(tk < t) : !(t < tk)) return false;
+    }
+    return true;
+}
+
 // The combinations of the closing edges' instances, stepped through like an
 // odometer: digit i is the position of close[i]'s current accepted instance
 // in its run, digit 0 moves fastest. A step walks only the digits that move
 // (one run step each, plus a wrap to the run's first instance on a carry),
 // so a combination costs O(1) run steps on average instead of a walk from
 // every run's start. st[i] is close[i]'s first accepted instance (as
-// close_find returns it), RUN_SWAP marking the list of f(nv).
+// close_find returns it), RUN_SWAP marking the list of f(nv). Under a
+// temporal order (`win`) each digit runs only over the instances that fit
+// the fixed edges' timestamps (inst_in_window): combinations outside those
+// windows cannot be embeddings, and only the windows' product is visited.
+
+// Digit i's first instance at or after p (in its window when `win`), or the
+// run's end.
+__device__ inline uint32_t odo_seek(const GraphView& g, const SeedPlan& P, const Bind& B, const RunIt& it, uint32_t i,
+                                    uint32_t p, bool win, uint32_t aqe, uint64_t akey) {
+    uint32_t unused = 0;
+    uint32_t q = run_next(it, p, unused);
+    while (win && q < it.end && !inst_in_window(g, P, B, i, it.adjk[q], aqe, akey)) q = run_next(it, q + 1, unused);
+    return q;
+}
+
+// Puts every digit at its first instance; false when some digit has none (no
+// combination).
 template <int NC>
-__device__ inline void odo_first(const SeedPlan& P, const uint32_t* st, uint32_t* pos) {
+__device__ inline bool odo_first(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
+                                 uint32_t* pos, bool win, uint32_t aqe, uint64_t akey) {
     constexpr int NA = NC > 0 ? NC : 1;
 #pragma unroll
     for (uint32_t i = 0; i < NA; i++) pos[i] = st[i] & ~RUN_SWAP;
+    if (!win) return true;
+#pragma unroll 1
+    for (uint32_t i = 0; i < (uint32_t)NC && i < P.n_close; i++) {
+        uint32_t s_st = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < NA; k++)
+            if (k == i) s_st = st[k];
+        const CloseDesc c = P.close[i];
+        const RunIt it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
+        const uint32_t q = odo_seek(g, P, B, it, i, it.p, true, aqe, akey);
+        if (q >= it.end) return false;
+#pragma unroll
+        for (uint32_t k = 0; k < NA; k++)
+            if (k == i) pos[k] = q;
+    }
+    return true;
 }
 
 // Advances to the next combination; false after the last one (every digit
 // back at its first instance).
 template <int NC>
 __device__ inline bool odo_next(const GraphView& g, const SeedPlan& P, const Bind& B, const uint32_t* st,
-                                uint32_t* pos) {
+                                uint32_t* pos, bool win, uint32_t aqe, uint64_t akey) {
     constexpr int NA = NC > 0 ? NC : 1;
     // one digit per step of a rolled loop: the run walk is compiled once,
     // and the digit's state is picked from and put back into the arrays
@@ -432,10 +485,17 @@ __device__ inline bool odo_next(const GraphView& g, const SeedPlan& P, const Bin
             }
         const CloseDesc c = P.close[i];
         const RunIt it = run_open(g, c, s_st, B.f(c.other), B.f(c.nv));
-        uint32_t unused = 0;
-        const uint32_t q = run_next(it, s_pos + 1, unused);
-        const bool moved = q < it.end;
-        const uint32_t v = moved ? q : it.p;  // a carry puts the digit back at its first instance
+        // the next instance; past the last one, a carry puts the digit back at
+        // its first instance (one exists: odo_first found it)
+        uint32_t from = s_pos + 1, v = it.end;
+        bool moved = true;
+#pragma unroll 1
+        for (int pass = 0; pass < 2; pass++) {
+            v = odo_seek(g, P, B, it, i, from, win, aqe, akey);
+            if (v < it.end) break;
+            moved = false;
+            from = it.p;
+        }
 #pragma unroll
         for (uint32_t k = 0; k < NA; k++)
             if (k == i) pos[k] = v;
@@ -514,7 +574,6 @@ __device__ uint64_t close_mult(const GraphView& g, const SeedPlan& P, const Bind
     }
     if (P.temporal && mult) {
         uint32_t pos[NA];
-        odo_first<NC>(P, st, pos);
         uint64_t ok = 0;
         if constexpr (NC == 1) {  // one closing edge: a plain walk over its run
             const CloseDesc c = P.close[0];
@@ -524,10 +583,10 @@ __device__ uint64_t close_mult(const GraphView& g, const SeedPlan& P, const Bind
                 pos[0] = p;
                 ok += in_time_order<NC>(g, P, B, st, pos, aqe, akey) ? 1u : 0u;
             }
-        } else {
+        } else if (odo_first<NC>(g, P, B, st, pos, true, aqe, akey)) {
             do {
                 ok += in_time_order<NC>(g, P, B, st, pos, aqe, akey) ? 1u : 0u;
-            } while (odo_next<NC>(g, P, B, st, pos));
+            } while (odo_next<NC>(g, P, B, st, pos, true, aqe, akey));
         }
         mult = ok;
     }
@@ -554,7 +613,6 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
     const uint64_t s0A = mn_mix64(MN_SEED_A ^ (uint64_t)q);
     const uint64_t s0B = mn_mix64(MN_SEED_B ^ (uint64_t)q);
     uint32_t pos[NA];
-    odo_first<NC>(P, st, pos);
     uint64_t j = 0;
     auto one = [&]() {  // the current combination, when it is an embedding
         if (P.temporal && !in_time_order<NC>(g, P, B, st, pos, aqe, akey)) return;
@@ -582,6 +640,7 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
         K.tuples++;
     };
     if constexpr (NC <= 1) {  // at most one closing edge: a plain walk over its run
+        pos[0] = 0;
         if (NC == 0 || P.n_close == 0) {
             one();
         } else {
@@ -593,10 +652,13 @@ __device__ void emit_tuples(const GraphView& g, const SeedPlan& P, const Bind& B
                 one();
             }
         }
-    } else {
+    } else if (odo_first<NC>(g, P, B, st, pos, false, aqe, akey)) {
+        // every combination, in_time_order deciding: the windows pay off in
+        // close_mult, which meets every complete mapping, while only mappings
+        // with embeddings get here
         do {
             one();
-        } while (j < mult && odo_next<NC>(g, P, B, st, pos));
+        } while (j < mult && odo_next<NC>(g, P, B, st, pos, false, aqe, akey));
     }
 }
 
