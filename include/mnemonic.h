@@ -209,6 +209,10 @@ typedef struct {
  *     opt may be NULL (defaults: emit on, no timing).
  *   hip_stream: the hipStream_t every kernel and copy of this context runs on
  *     (NULL = the default stream). The current HIP device at creation is used.
+ *     The context's device buffers come from that device's default memory
+ *     pool, allocated and freed in order on this stream; the library raises
+ *     the pool's release threshold, so memory it frees stays in the pool for
+ *     later allocations (hipMemPoolTrimTo returns it to the device).
  *   out: receives the context; unchanged on failure.
  * Errors: ARG, QUERY, VERTEX, LABEL, TS_ORDER, LIMIT, OOM, HIP.
  */
