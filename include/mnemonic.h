@@ -98,8 +98,8 @@ typedef struct {
 
 #define MNEMONIC_F_EMIT 1u   /* write the embedding tuples (else counts and digests only) */
 #define MNEMONIC_F_TIMING 2u /* record HIP events around the enumeration kernels */
-#define MNEMONIC_F_AUTOTUNE 4u /* the first batches try each expansion tile size (256, 512,
-                                  1024 candidates per block) twice and keep the fastest per
+#define MNEMONIC_F_AUTOTUNE 4u /* the first batches try each expansion tile size (512, 1024,
+                                  2048 candidates per block) twice and keep the fastest per
                                   candidate; results do not depend on the choice */
 #define MNEMONIC_F_SORT 16u /* with MNEMONIC_F_EMIT: each result list is sorted on the device into
                                lexicographic order of its key tuples before the call returns
@@ -162,7 +162,7 @@ typedef struct {
  *   frontier_rows      partial embeddings passed from one level to the next
  *   expand_launches    launches of the expansion kernel
  *   expand_tile        candidates per expansion block in use (autotuned with
- *                      MNEMONIC_F_AUTOTUNE, else 512)
+ *                      MNEMONIC_F_AUTOTUNE, else 1024)
  *   reruns             times the phase ran again after a buffer proved too
  *                      small (the buffers grow; results are unaffected)
  *   rerun_causes       what was too small, OR-ed over the re-runs: 1 start

@@ -326,7 +326,7 @@ struct mnemonic_ctx {
     double row_rate[2][MN_MAXLV + 1];  // largest rows of level L per start slot seen (-1: none yet)
     uint64_t chunk_ns[2] = {1, 1};  // slots of the largest start chunk of the last run of each phase
     uint64_t cover[2][MN_MAXLV];    // candidates each level's launch covered in the last device-sized run
-    uint32_t tile_items = 2;       // expansion tile = 256 x tile_items candidates
+    uint32_t tile_items = 4;       // expansion tile = 256 x tile_items candidates
     // autotuning of tile_items: trial batches per setting, time and candidates
     static constexpr uint32_t TUNE_TRIALS = 2;
     uint32_t tune_batch = 0;
@@ -1561,7 +1561,7 @@ int run_batch(mnemonic_ctx* c, uint64_t n_ins, const uint32_t* src, const uint32
     t_alloc_n = 0;
     t_alloc_ms = 0;
     ensure_capacity(c, n_ins, n_del);
-    static const uint32_t kItems[3] = {1, 2, 4};
+    static const uint32_t kItems[3] = {2, 4, 8};
     const bool tune = enumerate && c->tuning() && !t_no_alloc;
     if (tune) c->tile_items = kItems[c->tune_batch % 3];
     const bool timing = (c->flags & (MNEMONIC_F_TIMING | MNEMONIC_F_AUTOTUNE)) != 0 && enumerate && !t_no_alloc;

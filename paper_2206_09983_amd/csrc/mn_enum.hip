@@ -46,6 +46,15 @@ namespace {
 // candidates per lane in one expansion tile (tile = 256 x items): 1, 2 or 4
 constexpr uint32_t EX_TILE_MIN = MN_BLOCK;  // the smallest tile sizes the tile_row buffer
 constexpr uint64_t EX_SPARE_TILES = 8192;   // grid margin of a device-sized expansion past the expected tiles
+// Waves per SIMD the expansion kernels' registers must allow in blocks of
+// 512 and more threads (two or more waves per SIMD each): with no or one
+// closing edge, full occupancy (64 VGPRs, a few spill in the emitting
+// variants: measured faster than losing a block), with more, as many blocks
+// as their larger arrays leave room for. Blocks of 256 keep the compiler's
+// choice.
+constexpr uint32_t ex_min_waves(uint32_t threads, int nc) {
+    return threads < 512 ? 1u : nc <= 1 ? 8u : nc <= 4 ? 6u : 4u;
+}
 constexpr uint32_t NO_RUN = 0xFFFFFFFFu;
 constexpr uint32_t RUN_SWAP = 0x80000000u;
 constexpr uint8_t TREE_EDGE = 0xFF;
@@ -149,7 +158,7 @@ __device__ inline uint32_t block_linear() { return blockIdx.x + blockIdx.y * gri
 
 // Zeroes the accumulators and reads the error word once for the whole block.
 __device__ void acc_init(BlockAcc& A, uint32_t n_dig, const uint32_t* err) {
-    for (uint32_t i = threadIdx.x; i < MN_TALLIES + n_dig; i += MN_BLOCK) {
+    for (uint32_t i = threadIdx.x; i < MN_TALLIES + n_dig; i += blockDim.x) {
         if (i < MN_TALLIES)
             A.st[i] = 0;
         else
@@ -177,7 +186,7 @@ __device__ void acc_flush(BlockAcc& A, const Cnt& K, uint32_t n_dig, EnumStats* 
     unsigned long long* gst = reinterpret_cast<unsigned long long*>(stats + shard);
     unsigned long long* gdig = digest ? digest + (size_t)shard * n_dig : nullptr;
     if (threadIdx.x < MN_TALLIES && A.st[threadIdx.x]) atomicAdd(&gst[threadIdx.x], A.st[threadIdx.x]);
-    for (uint32_t i = threadIdx.x; i < n_dig; i += MN_BLOCK)
+    for (uint32_t i = threadIdx.x; i < n_dig; i += blockDim.x)
         if (A.dig[i]) atomicAdd(&gdig[i], A.dig[i]);
 }
 
@@ -1325,19 +1334,19 @@ __device__ inline void emit_closed_tuple(const GraphView& g, const SeedPlan* P, 
     dB += hB;
 }
 
-// One block tests a tile of 256 x ITEMS candidates in two passes. Pass 1 runs
-// the filters and gives every survivor a place inside the block (LDS counters
-// per query for embeddings, one for new rows); one global atomic per query
-// and block then reserves the block's places; pass 2 writes rows and
-// embeddings. Contended device-scope atomics (they serialise across the XCDs)
-// drop from one per wave and item to one per block.
+// One block of BT threads tests a tile of BT x ITEMS candidates in two
+// passes. Pass 1 runs the filters and gives every survivor a place inside the
+// block (LDS counters per query for embeddings, one for new rows); one global
+// atomic per query and block then reserves the block's places; pass 2 writes
+// rows and embeddings. Contended device-scope atomics (they serialise across
+// the XCDs) drop from one per wave and item to one per block.
 // What pass 1 learns about a candidate (its row, entry position, neighbour
 // and closing-run starts) waits in LDS for pass 2. Each lane keeps the
 // digests of the embeddings it emits in registers and the block reduces them
 // once; waves whose survivors each have one embedding of one query take their
 // places with a ballot count instead of a scan.
-template <int NC, bool ROWS, bool EMIT, uint32_t ITEMS>
-__global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, uint32_t n_in,
+template <int NC, bool ROWS, bool EMIT, uint32_t ITEMS, uint32_t BT>
+__global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g, RowsView in, uint32_t n_in,
                                                      const uint32_t* __restrict__ lo,
                                                      const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ tile_row, uint64_t c0,
@@ -1345,7 +1354,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
                                                      RowsView out, uint32_t* n_out, PhaseOut po,
                                                      const uint32_t* err) {
     constexpr int NA = NC > 0 ? NC : 1;
-    constexpr uint32_t EX_TILE = MN_BLOCK * ITEMS;
+    constexpr uint32_t EX_TILE = BT * ITEMS;
     constexpr uint32_t EX_LDS_ROWS = EX_TILE + 1;
     // the tile's rows when they fit: first candidate relative to the tile's
     // (the first row's is 0; d0 = how far it starts before the tile), first
@@ -1375,7 +1384,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     const bool staged = span <= EX_LDS_ROWS;
     const uint32_t d0 = (uint32_t)(t0 - off[rlo]);  // the runs' positions fit in 32 bits
     if (staged)
-        for (uint32_t x = threadIdx.x; x < span; x += MN_BLOCK) {
+        for (uint32_t x = threadIdx.x; x < span; x += BT) {
             const uint32_t rr = rlo + x;
             const uint64_t o = off[rr];
             s_rel[x] = x ? (uint32_t)(o - t0) : 0u;  // rows after the first start inside the tile or past it
@@ -1383,13 +1392,13 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
             s_pl[x] = (uint16_t)rcol(in, 0, rr);
         }
     if (EMIT)
-        for (uint32_t x = threadIdx.x; x < po.n_q; x += MN_BLOCK) s_qn[x] = 0;
+        for (uint32_t x = threadIdx.x; x < po.n_q; x += BT) s_qn[x] = 0;
     if (threadIdx.x == 0) s_nrows = 0;
     __syncthreads();
 
     // ---- pass 1: filters and places inside the block
     for (uint32_t it = 0; it < ITEMS; it++) {
-        const uint32_t idx = it * MN_BLOCK + threadIdx.x;
+        const uint32_t idx = it * BT + threadIdx.x;
         const uint64_t t = t0 + idx;
         bool ok = t < t1 && !A.dead;
         uint32_t r = 0, w = 0, p = 0;
@@ -1530,7 +1539,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     // ---- one global reservation per query (and one for rows) per block
     if (ROWS && threadIdx.x == 0 && s_nrows) s_rbase = atomicAdd(n_out, s_nrows);
     if (EMIT)
-        for (uint32_t x = threadIdx.x; x < po.n_q; x += MN_BLOCK)
+        for (uint32_t x = threadIdx.x; x < po.n_q; x += BT)
             if (s_qn[x]) s_qn[x] = atomicAdd(&po.count[x], s_qn[x]);
     __syncthreads();
 
@@ -1538,7 +1547,7 @@ __global__ __launch_bounds__(MN_BLOCK) void k_expand(GraphView g, RowsView in, u
     uint32_t dq = MAXQ;  // query of the lane's digest sums
     uint64_t dA = 0, dB = 0;
     for (uint32_t it = 0; it < ITEMS; it++) {
-        const uint32_t idx = it * MN_BLOCK + threadIdx.x;
+        const uint32_t idx = it * BT + threadIdx.x;
         const uint64_t t = t0 + idx;
         const uint32_t loc = t < t1 ? s_loc[idx] : NO_LOC;
         if (loc == NO_LOC) continue;
@@ -1686,34 +1695,40 @@ uint64_t mn_expand_tiles(uint64_t c0, uint64_t c1) { return expand_tiles(c0, c1,
 // k_expand launches go through hipExtLaunchKernel so that the optional
 // events are stamped by the dispatch itself: they time the kernel, not the
 // queue around it.
-template <int NC, uint32_t ITEMS>
+template <int NC, uint32_t ITEMS, uint32_t BT>
 void launch_expand_nc(bool rows, bool emit, dim3 grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
                       const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo, const uint64_t* off,
                       const uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev, uint32_t L,
                       RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err) {
-    auto k = rows && emit ? k_expand<NC, true, true, ITEMS>
-                          : rows ? k_expand<NC, true, false, ITEMS> : k_expand<NC, false, true, ITEMS>;
-    hipExtLaunchKernelGGL(k, grid, dim3(MN_BLOCK), 0, s, ev0, ev1, 0, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L,
+    auto k = rows && emit ? k_expand<NC, true, true, ITEMS, BT>
+                          : rows ? k_expand<NC, true, false, ITEMS, BT> : k_expand<NC, false, true, ITEMS, BT>;
+    hipExtLaunchKernelGGL(k, grid, dim3(BT), 0, s, ev0, ev1, 0, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L,
                           out, n_out, po, err);
 }
 
-template <uint32_t ITEMS>
+// Tiles of 256 x T candidates: two per thread, in blocks of 128 x T threads
+// (T = 2, 4, 8). Larger blocks take their places in the output with fewer
+// device atomics on the shared counters, whose memory-side throughput (about
+// one per 12 ns and word) bounds the expansion's largest launches; their LDS
+// per wave, and so the occupancy, stay the same.
+template <uint32_t T>
 void launch_expand_items(uint32_t max_close, bool rows, bool emit, dim3 grid, hipStream_t s, hipEvent_t ev0,
                          hipEvent_t ev1, const GraphView& g, RowsView in, uint32_t n_in, const uint32_t* lo,
                          const uint64_t* off, const uint32_t* tile_row, uint64_t c0, uint64_t c1, const uint64_t* T_dev,
                          uint32_t L, RowsView out, uint32_t* n_out, PhaseOut po, const uint32_t* err) {
 #define MN_EXPAND_ARGS rows, emit, grid, s, ev0, ev1, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err
+    constexpr uint32_t BT = 128 * T, ITEMS = 2;
     switch (nc_bucket(max_close)) {
-        case 0: launch_expand_nc<0, ITEMS>(MN_EXPAND_ARGS); break;
-        case 1: launch_expand_nc<1, ITEMS>(MN_EXPAND_ARGS); break;
-        case 2: launch_expand_nc<2, ITEMS>(MN_EXPAND_ARGS); break;
-        case 4: launch_expand_nc<4, ITEMS>(MN_EXPAND_ARGS); break;
-        default: launch_expand_nc<8, ITEMS>(MN_EXPAND_ARGS); break;
+        case 0: launch_expand_nc<0, ITEMS, BT>(MN_EXPAND_ARGS); break;
+        case 1: launch_expand_nc<1, ITEMS, BT>(MN_EXPAND_ARGS); break;
+        case 2: launch_expand_nc<2, ITEMS, BT>(MN_EXPAND_ARGS); break;
+        case 4: launch_expand_nc<4, ITEMS, BT>(MN_EXPAND_ARGS); break;
+        default: launch_expand_nc<8, ITEMS, BT>(MN_EXPAND_ARGS); break;
     }
 #undef MN_EXPAND_ARGS
 }
 
-inline uint32_t expand_items(uint32_t items) { return items == 1 || items == 4 ? items : 2u; }
+inline uint32_t expand_items(uint32_t items) { return items == 4 || items == 8 ? items : 2u; }
 
 uint64_t mn_expand_end(uint64_t c0, uint64_t c1, uint64_t expect, uint32_t items) {
     const uint32_t tile = MN_BLOCK * expand_items(items);
@@ -1758,8 +1773,8 @@ uint64_t mn_launch_expand(const GraphView& g, RowsView in, uint32_t n_in, const 
                                                             note);
     const dim3 grid((uint32_t)tiles);
 #define MN_ITEMS_ARGS max_close, rows, emit, grid, s, ev0, ev1, g, in, n_in, lo, off, tile_row, c0, c1, T_dev, L, out, n_out, po, err
-    if (items == 1)
-        launch_expand_items<1>(MN_ITEMS_ARGS);
+    if (items == 8)
+        launch_expand_items<8>(MN_ITEMS_ARGS);
     else if (items == 4)
         launch_expand_items<4>(MN_ITEMS_ARGS);
     else
