@@ -5,6 +5,7 @@ Test infrastructure, run once offline (it takes minutes of CPU time):
     python tests/golden/make_fullsize_golden.py rmat [W]    # fullsize_rmat_s20.json (W worker processes)
     python tests/golden/make_fullsize_golden.py multiquery  # fullsize_multiquery_s20.json
     python tests/golden/make_fullsize_golden.py serving     # fullsize_serving_s22.json
+    python tests/golden/make_fullsize_golden.py multiquery_timed W  # fullsize_multiquery_timed_s20.json
 Each file records the workload's parameters and the oracle's results for the
 first batches of its stream: the R-MAT benchmark stream (2^20 vertices, 2^24
 initial edges, batches of 65,536 insertions and 6,553 oldest-key deletions,
@@ -91,6 +92,19 @@ def _chunk(args):
     return oracle_results(case, hi, first=lo)
 
 
+def _one(args):
+    which, i = args
+    case = {"rmat": rmat_case, "multiquery": multiquery_case, "serving": serving_case}[which]()
+    return oracle_results(case, i + 1, first=i)[0]
+
+
+def timed_indices(n_total, warmup, steps):
+    """The batches the benchmark times: `steps` at an equal stride after the
+    `warmup` first ones."""
+    stride = max(1, (n_total - warmup) // steps)
+    return [warmup + k * stride for k in range(steps)]
+
+
 def parallel_results(which, n, workers):
     """Batches cut into `workers` consecutive ranges, each computed by its own
     oracle process that first replays the batches before its range."""
@@ -102,7 +116,33 @@ def parallel_results(which, n, workers):
     return [rec for part in parts for rec in part]
 
 
+def main_timed(workers):
+    """The 64-query stream's 20 timed batches (5 warm-up, 20 steps), each by
+    its own oracle process after replaying the batches before it."""
+    import multiprocessing as mp
+    t = time.perf_counter()
+    case = multiquery_case()
+    idx = timed_indices(len(case["batches"]), 5, 20)
+    print("generated %s in %.1f s; batches %s" % (case["name"], time.perf_counter() - t, idx), flush=True)
+    # the largest batches first, so that the pool's last jobs are short
+    order = sorted(idx, key=lambda i: -len(case["batches"][i]["src"]))
+    with mp.get_context("fork").Pool(workers) as pool:
+        recs = pool.map(_one, [("multiquery", i) for i in order], chunksize=1)
+    recs.sort(key=lambda r: r["index"])
+    doc = {"workload": case["name"], "params": MULTI, "generator": "paper_2206_09983_amd.synth.multiquery_case",
+           "command": "python tests/golden/make_fullsize_golden.py multiquery_timed %d" % workers,
+           "queries": [q.get("name", "") for q in case["queries"]],
+           "result_format": "per query and phase: [count, digest seed A, digest seed B] (digests mod 2^64)",
+           "timed": {"warmup": 5, "steps": 20}, "batches": recs}
+    with open(os.path.join(HERE, "fullsize_multiquery_timed_s20.json"), "w") as f:
+        json.dump(doc, f, indent=1)
+        f.write("\n")
+    print("wrote fullsize_multiquery_timed_s20.json", flush=True)
+
+
 def main(which, workers=1):
+    if which == "multiquery_timed":
+        return main_timed(workers)
     t = time.perf_counter()
     if which == "rmat":
         case, params, n, name = rmat_case(), RMAT, RMAT_BATCHES, "fullsize_rmat_s20.json"

@@ -350,3 +350,49 @@ def test_full_size_serving_window_equals_the_oracle_golden():
                 % (rec["index"], rec["n_ins"], rec["n_del"], time.time() - t0))
     finally:
         m.close()
+
+
+MULTI_TIMED_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fullsize_multiquery_timed_s20.json")
+
+
+@pytest.mark.skipif(not os.path.exists(MULTI_TIMED_GOLDEN), reason="the timed batches' golden file is not written")
+def test_full_size_multiquery_timed_batches_equal_the_oracle_golden():
+    # The 64-query stream's batches that bench.py times (5 warm-up, then 20
+    # at a stride): the whole stream is replayed up to the last of them in
+    # the benchmark's configuration, and each timed batch's counts and
+    # digests are compared with the oracle's.
+    torch = pytest.importorskip("torch")
+    from paper_2206_09983_amd import binding as B
+    import bench
+    B.load()
+    with open(MULTI_TIMED_GOLDEN) as f:
+        gold = json.load(f)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "multiquery_queries.json")) as f:
+        qdoc = json.load(f)
+    t0 = time.time()
+    case = synth.multiquery_case(queries=synth.queries_from_json(qdoc["queries"]), **gold["params"])
+    qs = case["queries"]
+    assert [q["name"] for q in qs] == gold["queries"]
+    idx = [rec["index"] for rec in gold["batches"]]
+    assert idx == bench.timed_batches(len(case["batches"]), gold["timed"]["warmup"], gold["timed"]["steps"])
+    by_index = {rec["index"]: rec for rec in gold["batches"]}
+    say("full-size golden: %s, timed batches %s (%.1f s)" % (case["name"], idx, time.time() - t0))
+    stream = torch.cuda.current_stream()
+    m = B.Matcher(case["graph"], qs, flags=B.F_EMIT | B.F_TIMING, out_capacity=1 << 16,
+                  stream=stream.cuda_stream, n_elabels=32)
+    try:
+        for i in range(idx[-1] + 1):
+            b = case["batches"][i]
+            m.apply_batch(device_batch(torch, b))
+            rec = by_index.get(i)
+            if rec is None:
+                continue
+            assert (len(b["src"]), len(b["del_keys"])) == (rec["n_ins"], rec["n_del"])
+            for qi, rq in enumerate(rec["queries"]):
+                r = m.result(qi)
+                assert [r["n_new"], *r["dig_new"]] == rq["new"], (i, rq["name"], "new")
+                assert [r["n_expired"], *r["dig_expired"]] == rq["expired"], (i, rq["name"], "expired")
+            say("batch %d (%d insertions): 64 queries' counts and digests equal the oracle's (%.1f s)"
+                % (i, rec["n_ins"], time.time() - t0))
+    finally:
+        m.close()
