@@ -162,7 +162,8 @@ typedef struct {
  *   frontier_rows      partial embeddings passed from one level to the next
  *   expand_launches    launches of the expansion kernel
  *   expand_tile        candidates per expansion block in use (autotuned with
- *                      MNEMONIC_F_AUTOTUNE, else 1024)
+ *                      MNEMONIC_F_AUTOTUNE, else 1024 when no query's plans
+ *                      have more than one closing edge, 512 otherwise)
  *   reruns             times the phase ran again after a buffer proved too
  *                      small (the buffers grow; results are unaffected)
  *   rerun_causes       what was too small, OR-ed over the re-runs: 1 start
