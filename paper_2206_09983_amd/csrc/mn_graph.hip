@@ -219,7 +219,9 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(MergeSide m0, MergeSid
         lower_bounds2(bk, s_w[0], s_w[1], kbase + ((uint64_t)v << hb), kbase + ((uint64_t)(v + 1) << hb), bs, be);
     if (s_w[2] < s_w[3]) lower_bounds2(dpos, s_w[2], s_w[3], dbase + o0, dbase + o1, ds, de);
     m.newoff[v] = o0 - ds + bs;
-    m.meta[v] = make_uint4(bs, be - bs, ds, de - ds);
+    // k_merge_new reads meta only for vertices with batch entries: most
+    // vertices write none (16 of the 20 bytes a vertex would write)
+    if (be > bs) m.meta[v] = make_uint4(bs, be - bs, ds, de - ds);
     if (v == nv - 1) m.newoff[nv] = e_old - n_d + n_b;
 }
 
