@@ -192,6 +192,26 @@ __device__ inline void lower_bounds2(const uint64_t* __restrict__ a, uint32_t lo
 // [ds, de) in dpos, and its offset in the merged adjacency. Four threads first
 // bound the block's 256 vertices in both sorted arrays, so that every
 // vertex searches only its block's window. blockIdx.y is the direction.
+// First i in [lo, hi) with a[i] >= key (hi if none), by a whole wave (all
+// lanes call it with the same arguments): each round the 64 lanes probe 64
+// evenly spaced places of the range and keep the 1/65 between the last probe
+// below key and the first not below it, so 2^18 values take three rounds of
+// dependent loads instead of eighteen.
+template <typename T>
+__device__ uint32_t wave_lower_bound(const T* __restrict__ a, uint32_t lo, uint32_t hi, T key) {
+    const uint32_t lane = __lane_id();
+    while (hi - lo > MN_WAVE) {  // the answer lies in [lo, hi]
+        const uint64_t n = hi - lo;
+        const uint32_t c = (uint32_t)__popcll(__ballot(a[lo + (uint32_t)(n * (lane + 1) / 65)] < key));
+        // a is sorted, so the c probes below key are the first c
+        const uint32_t nlo = c ? lo + (uint32_t)(n * c / 65) + 1 : lo;
+        hi = c < MN_WAVE ? lo + (uint32_t)(n * (c + 1) / 65) : hi;
+        lo = nlo;
+    }
+    const uint32_t p = lo + lane;
+    return lo + (uint32_t)__popcll(__ballot(p < hi && a[p] < key));
+}
+
 __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(MergeSide m0, MergeSide m1, uint32_t nv, uint32_t e_old,
                                                           uint32_t n_b, uint32_t n_d, uint32_t hb,
                                                           const uint32_t* err) {
@@ -203,12 +223,15 @@ __global__ __launch_bounds__(MN_BLOCK) void k_vertex_meta(MergeSide m0, MergeSid
     __shared__ uint32_t s_w[4];
     const uint32_t v0 = blockIdx.x * MN_BLOCK, v1 = min(v0 + MN_BLOCK, nv);
     const uint32_t tid = threadIdx.x;
-    if (tid < 2) {
-        const uint32_t u = tid ? v1 : v0;
-        s_w[tid] = n_b ? lower_bound_dev<uint64_t>(bk, 0, n_b, kbase + ((uint64_t)u << hb)) : 0u;
-    } else if (tid < 4) {
-        const uint32_t u = tid == 3 ? v1 : v0;
-        s_w[tid] = n_d ? lower_bound_dev<uint64_t>(dpos, 0, n_d, dbase + off[u]) : 0u;
+    // the block's windows of the sorted batch entries and deletion positions,
+    // one wave per bound
+    static_assert(MN_BLOCK / MN_WAVE == 4, "one wave per window bound");
+    {
+        const uint32_t wv = tid / MN_WAVE;
+        const uint32_t u = wv & 1u ? v1 : v0;
+        const uint32_t x = wv < 2 ? wave_lower_bound<uint64_t>(bk, 0, n_b, kbase + ((uint64_t)u << hb))
+                                  : wave_lower_bound<uint64_t>(dpos, 0, n_d, dbase + off[u]);
+        if (__lane_id() == 0) s_w[wv] = x;
     }
     __syncthreads();
     const uint32_t v = v0 + tid;
