@@ -679,14 +679,17 @@ __global__ __launch_bounds__(MN_BLOCK) void k_advance_lo(const uint32_t* __restr
     __shared__ uint32_t s_first;
     if (failed(err)) return;  // the same for the whole block
     uint64_t lo = *lo_dev;
-    constexpr uint32_t PER = 16, STEP = PER * MN_BLOCK;
+    constexpr uint32_t PER = 32, STEP = PER * MN_BLOCK;
     while (lo < end) {  // uniform: every thread holds the same lo
         if (threadIdx.x == 0) s_first = STEP;
         __syncthreads();
         for (uint32_t j = 0; j < PER; j++) {
             const uint32_t o = j * MN_BLOCK + threadIdx.x;
             const uint64_t k = lo + o;
-            if (k < end && key2slot[k & key_mask] != MN_INVALID) atomicMin(&s_first, o);
+            // one LDS atomic per wave: its first live key (past the first one
+            // most keys are live, and an atomic each serialised on one word)
+            const uint64_t live = __ballot(k < end && key2slot[k & key_mask] != MN_INVALID);
+            if (live && __lane_id() == (uint32_t)__ffsll((unsigned long long)live) - 1) atomicMin(&s_first, o);
         }
         __syncthreads();
         const uint32_t f = s_first;
