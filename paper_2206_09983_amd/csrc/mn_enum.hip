@@ -1145,8 +1145,12 @@ __global__ __launch_bounds__(MN_BLOCK) void k_offsets_partition(const uint32_t* 
                                                                 unsigned long long* note) {
     __shared__ uint64_t s_pre[MN_BLOCK / MN_WAVE], s_tot[MN_BLOCK / MN_WAVE];
     if (n_dev) n = min(n, *n_dev);
+    // the grid follows the buffer's capacity; only tiles that hold rows count,
+    // and blocks past them leave (block 0 stores the total)
+    const uint32_t nbu = min(nb, (uint32_t)(((uint64_t)n + MN_SCAN_TILE - 1) / MN_SCAN_TILE));
+    if (blockIdx.x > 0 && blockIdx.x >= nbu) return;  // the same for the whole block
     uint64_t pre = 0, tot = 0;
-    for (uint32_t i = threadIdx.x; i < nb; i += MN_BLOCK) {
+    for (uint32_t i = threadIdx.x; i < nbu; i += MN_BLOCK) {
         const uint64_t v = sums[i];
         tot += v;
         if (i < blockIdx.x) pre += v;
