@@ -228,6 +228,10 @@ __global__ __launch_bounds__(MN_BLOCK) void k_scan64_local(const TI* in, uint64_
     __shared__ uint64_t wsum[RS_WAVES];
     if (n_dev) n = min(n, *n_dev);
     uint32_t tid = threadIdx.x;
+    if ((size_t)blockIdx.x * SC_TILE >= n) {  // the same for the whole block: a tile past the values
+        if (tid == 0) sums[blockIdx.x] = 0;
+        return;
+    }
     size_t base = (size_t)blockIdx.x * SC_TILE + (size_t)tid * SC_ITEMS;
     uint64_t v[SC_ITEMS];
     uint64_t tsum = 0;
