@@ -207,6 +207,40 @@ def test_candidate_spike_is_covered_without_a_rerun(B):
     assert not rr.get("causes", 0) & 2, rr
 
 
+def test_expansion_tile_follows_the_query_sets_closing_edges(B):
+    # Query sets whose plans have at most one closing edge expand in tiles of
+    # 1024 candidates (blocks of 512 threads), others in tiles of 512; a
+    # query-set change picks the tile again. Results stay the oracle's.
+    case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
+    # (labelled edges keep the oracle's work small: wildcard 4-cliques here
+    # have hundreds of millions of embeddings)
+    tri = synth.make_query(3, [0, 0, 0], [(0, 1, 0), (1, 2, 1), (2, 0, 2)], synth.ISO, "triangle")
+    k4 = synth.make_query(4, [0, 0, 0, 0], [(0, 1, 0), (1, 2, 1), (2, 3, 0), (3, 0, 1), (0, 2, 2), (1, 3, 3)],
+                          synth.ISO, "4-clique")
+    o = Oracle(case["graph"], [tri])
+    m = B.Matcher(case["graph"], [tri], flags=B.F_EMIT)
+    try:
+        b0, b1 = case["batches"][0], case["batches"][1]
+        o.apply_batch(b0)
+        m.apply_batch(b0)
+        assert m.stats()["expand_tile"] == 1024
+        assert m.result(0)["n_new"] == o.count(0, False) and m.result(0)["dig_new"] == o.digest(0, False)
+        m.set_queries([k4])  # three closing edges
+        o.close()
+        o = Oracle(case["graph"], [k4])
+        o.apply_batch(b0)
+        o.apply_batch(b1)
+        m.apply_batch(b1)
+        assert m.stats()["expand_tile"] == 512
+        r = m.result(0)
+        for ph, name in ((False, "new"), (True, "expired")):
+            assert (r["n_expired"] if ph else r["n_new"]) == o.count(0, ph), name
+            assert (r["dig_expired"] if ph else r["dig_new"]) == o.digest(0, ph), name
+    finally:
+        m.close()
+        o.close()
+
+
 def test_count_only_mode_gives_same_counts_and_digests(B):
     case = synth.rmat_case(scale=10, n_init=12000, n_stream=2048, batch=1024, n_batches=2)
     assert run_parity(B, case, flags=0, check_lists=False) > 0
