@@ -74,7 +74,8 @@
 // the out-list of f(other) under (label, f(nv)); dir 1: nv -> other, in the
 // in-list of f(other). The same instances also sit in the opposite list of
 // f(nv) under (label, f(other)); the enumerator searches the shorter list.
-struct CloseDesc {
+// 16 bytes, 16-byte aligned: the expansion kernel reads one with one load.
+struct alignas(16) CloseDesc {
     uint8_t qe;
     uint8_t other;
     uint8_t nv;
@@ -82,7 +83,9 @@ struct CloseDesc {
     uint8_t masked;  // query edge index < start position: batch edges forbidden
     uint8_t pad[3];
     int32_t label;   // -1 = any label
+    uint32_t pad2;
 };
+static_assert(sizeof(CloseDesc) == 16, "one 16-byte load per closing edge");
 
 // One level of the search maps one new query vertex `vtx` through its anchor
 // edge: the candidates are the entries of f(from)'s out-list (dir 0, query

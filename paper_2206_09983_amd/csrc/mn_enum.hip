@@ -976,9 +976,24 @@ __device__ inline PlanHead plan_head(const SeedPlan* P) {
     return H;
 }
 
+// 16 bytes of a plan read with one load. Left alone, the compiler splits
+// such a load into one narrow load per field the caller uses, and the
+// expansion's time goes with its count of load instructions; the empty asm
+// takes every word, so the load stays whole.
+__device__ inline uint4 load_whole16(const void* p) {
+    uint4 v = *reinterpret_cast<const uint4*>(p);
+    asm("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+    return v;
+}
+
 // Level L of plan P, one 16-byte load.
 __device__ inline LevelDesc load_level(const SeedPlan* P, uint32_t L) {
-    return __builtin_bit_cast(LevelDesc, *reinterpret_cast<const uint4*>(&P->lv[L]));
+    return __builtin_bit_cast(LevelDesc, load_whole16(&P->lv[L]));
+}
+
+// Closing edge c of plan P, one 16-byte load.
+__device__ inline CloseDesc load_close(const SeedPlan* P, uint32_t c) {
+    return __builtin_bit_cast(CloseDesc, load_whole16(&P->close[c]));
 }
 
 // Byte i (< 16) of a 16-byte vector.
@@ -1271,7 +1286,7 @@ __device__ inline uint64_t closed_mult(const GraphView& g, const SeedPlan* P, co
 #pragma unroll
     for (uint32_t c = 0; c < NA; c++) {
         if (c < (uint32_t)NC && c < n_close) {
-            const CloseDesc cd = P->close[c];
+            const CloseDesc cd = load_close(P, c);
             uint32_t n;
             if (c >= lv.c_begin && c < lv.c_end) {
                 const RunIt it = run_open(g, cd, st[c], rcol(R, 1 + cd.other, r), w);
@@ -1303,7 +1318,7 @@ __device__ inline void emit_closed_tuple(const GraphView& g, const SeedPlan* P, 
         hq[c] = 0xFFu;
         hk[c] = 0;
         if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
-            const CloseDesc cd = P->close[c];
+            const CloseDesc cd = load_close(P, c);
             const bool sw = (st[c] & RUN_SWAP) != 0;
             hq[c] = cd.qe;
             hk[c] = g.keys(sw ? 1u - cd.dir : (uint32_t)cd.dir)[st[c] & ~RUN_SWAP];
@@ -1468,7 +1483,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
             for (uint32_t c = 0; c < NA; c++) {
                 if (ok && c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
-                    const CloseDesc cd = P->close[c];
+                    const CloseDesc cd = load_close(P, c);
                     st[c] = close_find(g, cd, rcol(in, 1 + cd.other, r), w, K.probes);
                     if (st[c] == NO_RUN) ok = false;
                 }
@@ -1507,7 +1522,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
                     for (uint32_t c = 0; c < NA; c++)
                         if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
-                            st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
+                            st[c] = rcol(in, 1 + in.wv + load_close(P, c).qe, r);
                     mult = close_mult<NC>(g, *P, B, st, K.probes, lv.qe, H.temporal ? g.keys(lv.dir)[p] : 0ull);
                 }
             }
@@ -1590,7 +1605,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
                     if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
-                        const CloseDesc cd = P->close[c];
+                        const CloseDesc cd = load_close(P, c);
                         wcol(out, 1 + out.wv + cd.qe, dst, st[c]);
                         wkey(out, cd.qe, dst, close_word(g, cd, st[c], rcol(in, 1 + cd.other, r), w, K.probes));
                     }
@@ -1629,7 +1644,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
                     if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
-                        st[c] = rcol(in, 1 + in.wv + P->close[c].qe, r);
+                        st[c] = rcol(in, 1 + in.wv + load_close(P, c).qe, r);
                 uint32_t unused = 0;
                 const uint64_t mult = close_mult<NC>(g, *P, B, st, unused, lv.qe, akey);
                 emit_tuples<NC>(g, *P, B, st, mult, lv.qe, akey, pos, po, K, dA, dB);
