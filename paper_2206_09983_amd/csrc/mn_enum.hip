@@ -963,8 +963,7 @@ struct PlanHead {
     uint32_t q, n_qe, n_levels, sem, n_close, temporal, vf_base;
 };
 
-__device__ inline PlanHead plan_head(const SeedPlan* P) {
-    const uint4 h = *reinterpret_cast<const uint4*>(P);
+__device__ inline PlanHead plan_head_of(const uint4& h) {
     PlanHead H;
     H.q = h.x & 0xFFFFu;
     H.n_qe = h.x >> 24;
@@ -975,6 +974,8 @@ __device__ inline PlanHead plan_head(const SeedPlan* P) {
     H.vf_base = h.w;
     return H;
 }
+
+__device__ inline PlanHead plan_head(const SeedPlan* P) { return plan_head_of(*reinterpret_cast<const uint4*>(P)); }
 
 // 16 bytes of a plan read with one load. Left alone, the compiler splits
 // such a load into one narrow load per field the caller uses, and the
@@ -991,9 +992,43 @@ __device__ inline LevelDesc load_level(const SeedPlan* P, uint32_t L) {
     return __builtin_bit_cast(LevelDesc, load_whole16(&P->lv[L]));
 }
 
-// Closing edge c of plan P, one 16-byte load.
-__device__ inline CloseDesc load_close(const SeedPlan* P, uint32_t c) {
-    return __builtin_bit_cast(CloseDesc, load_whole16(&P->close[c]));
+// 16 bytes at an address every active lane of the wave shares, read by the
+// scalar unit: the vector memory path, which bounds the expansion by the
+// data it returns per lane, is left out. Plans are not written while a
+// kernel that reads them runs.
+__device__ inline uint4 load_uniform16(const void* p) {
+    const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)p;
+    return make_uint4(q[0], q[1], q[2], q[3]);
+}
+
+// 16 bytes at byte `at` (the same for every lane) of plan pl: by the scalar
+// unit when every active lane of the wave takes the same plan, else one
+// vector load per lane.
+__device__ inline uint4 plan_words(const SeedPlan* plans, uint32_t pl, uint32_t at) {
+    const uint32_t pl0 = __builtin_amdgcn_readfirstlane(pl);
+    if (__ballot(pl != pl0) == 0) return load_uniform16(reinterpret_cast<const char*>(plans + pl0) + at);
+    return load_whole16(reinterpret_cast<const char*>(plans + pl) + at);
+}
+
+// Level L and header of plan P. When every active lane of the wave takes the
+// same plan (the rows of one parent sit next to each other, so most waves
+// do), both come from scalar loads; otherwise each lane loads its own.
+__device__ inline void plan_level(const SeedPlan* plans, uint32_t pl, uint32_t L, LevelDesc& lv, PlanHead& H) {
+    const uint32_t pl0 = __builtin_amdgcn_readfirstlane(pl);
+    if (__ballot(pl != pl0) == 0) {
+        const SeedPlan* P = plans + pl0;
+        lv = __builtin_bit_cast(LevelDesc, load_uniform16(&P->lv[L]));
+        H = plan_head_of(load_uniform16(P));
+    } else {
+        lv = load_level(plans + pl, L);
+        H = plan_head(plans + pl);
+    }
+}
+
+// Closing edge c of plan pl, one 16-byte load (scalar when the wave's
+// active lanes share the plan).
+__device__ inline CloseDesc load_close(const SeedPlan* plans, uint32_t pl, uint32_t c) {
+    return __builtin_bit_cast(CloseDesc, plan_words(plans, pl, offsetof(SeedPlan, close) + c * sizeof(CloseDesc)));
 }
 
 // Byte i (< 16) of a 16-byte vector.
@@ -1056,12 +1091,13 @@ __global__ __launch_bounds__(MN_BLOCK) void k_level_range(GraphView g, RowsView 
     // the grid is bounded (the row count may be known on the device only):
     // it strides over the rows
     for (uint32_t r = blockIdx.x * MN_BLOCK + threadIdx.x; r < n && !A.dead; r += gridDim.x * MN_BLOCK) {
-        const SeedPlan* P = &g.plans[rcol(R, 0, r)];
-        const LevelDesc lv = load_level(P, L);
+        const uint32_t pl = rcol(R, 0, r);
+        const LevelDesc lv =
+            __builtin_bit_cast(LevelDesc, plan_words(g.plans, pl, offsetof(SeedPlan, lv) + L * sizeof(LevelDesc)));
         if (R.hpre) {
             // a row whose embeddings end at this level and are all tree edges:
             // its digest chains up to the anchor edge, once for all its candidates
-            const PlanHead H = plan_head(P);
+            const PlanHead H = plan_head_of(plan_words(g.plans, pl, 0));
             if (L + 1 == H.n_levels && H.n_close == 0 && !H.temporal) {
                 uint64_t hA, hB;
                 digest_prefix(R, r, H.q, lv.qe, hA, hB);
@@ -1278,7 +1314,7 @@ __device__ inline void emit_tree_tuple(const RowsView& R, uint32_t r, uint32_t n
 // from the row's words for edges resolved at earlier levels (close_word) and
 // by a walk for those this level resolves (st[c], its new vertex mapped to w).
 template <int NC>
-__device__ inline uint64_t closed_mult(const GraphView& g, const SeedPlan* P, const RowsView& R, uint32_t r,
+__device__ inline uint64_t closed_mult(const GraphView& g, uint32_t pl, const RowsView& R, uint32_t r,
                                        const LevelDesc& lv, uint32_t n_close, const uint32_t* st, uint32_t w,
                                        uint32_t& probes) {
     constexpr int NA = NC > 0 ? NC : 1;
@@ -1286,7 +1322,7 @@ __device__ inline uint64_t closed_mult(const GraphView& g, const SeedPlan* P, co
 #pragma unroll
     for (uint32_t c = 0; c < NA; c++) {
         if (c < (uint32_t)NC && c < n_close) {
-            const CloseDesc cd = load_close(P, c);
+            const CloseDesc cd = load_close(g.plans, pl, c);
             uint32_t n;
             if (c >= lv.c_begin && c < lv.c_end) {
                 const RunIt it = run_open(g, cd, st[c], rcol(R, 1 + cd.other, r), w);
@@ -1306,7 +1342,7 @@ __device__ inline uint64_t closed_mult(const GraphView& g, const SeedPlan* P, co
 // resolves at their first accepted instances and akey at the anchor aqe;
 // both digest chains from query q's seeds. Written at `row` when emitting.
 template <int NC>
-__device__ inline void emit_closed_tuple(const GraphView& g, const SeedPlan* P, const RowsView& R, uint32_t r,
+__device__ inline void emit_closed_tuple(const GraphView& g, uint32_t pl, const RowsView& R, uint32_t r,
                                          uint32_t q, uint32_t nqe, const LevelDesc& lv, const uint32_t* st,
                                          uint64_t akey, uint64_t* row, bool write, Cnt& K, uint64_t& dA,
                                          uint64_t& dB) {
@@ -1318,7 +1354,7 @@ __device__ inline void emit_closed_tuple(const GraphView& g, const SeedPlan* P, 
         hq[c] = 0xFFu;
         hk[c] = 0;
         if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
-            const CloseDesc cd = load_close(P, c);
+            const CloseDesc cd = load_close(g.plans, pl, c);
             const bool sw = (st[c] & RUN_SWAP) != 0;
             hq[c] = cd.qe;
             hk[c] = g.keys(sw ? 1u - cd.dir : (uint32_t)cd.dir)[st[c] & ~RUN_SWAP];
@@ -1427,8 +1463,9 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
         for (uint32_t c = 0; c < NA; c++) st[c] = 0;
         const SeedPlan* P = g.plans;
+        uint32_t pl = 0;  // plan of the candidate's row
         if (ok) {
-            uint32_t base, pl;
+            uint32_t base;
             if (staged) {
                 const uint32_t a = row_in_lds(s_rel, span, idx);
                 r = rlo + a;
@@ -1441,8 +1478,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
                 pl = rcol(in, 0, r);
             }
             P = &g.plans[pl];
-            lv = load_level(P, L);
-            H = plan_head(P);
+            plan_level(g.plans, pl, L, lv, H);
             p = base;
             const uint64_t e = g.adjs(lv.dir)[p];
             K.entries++;
@@ -1456,7 +1492,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
             if (ok && H.sem == MN_SEM_ISO) {
                 // the images of the L + 2 mapped query vertices, loaded together
                 // (the trip count is the launch's, the same for every lane)
-                const uint4 mv = *reinterpret_cast<const uint4*>(P->mapped);
+                const uint4 mv = plan_words(g.plans, pl, offsetof(SeedPlan, mapped));
                 uint32_t img[MN_MAXQV];
 #pragma unroll
                 for (uint32_t m = 0; m < MN_MAXQV; m++)
@@ -1483,7 +1519,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
             for (uint32_t c = 0; c < NA; c++) {
                 if (ok && c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
-                    const CloseDesc cd = load_close(P, c);
+                    const CloseDesc cd = load_close(g.plans, pl, c);
                     st[c] = close_find(g, cd, rcol(in, 1 + cd.other, r), w, K.probes);
                     if (st[c] == NO_RUN) ok = false;
                 }
@@ -1508,7 +1544,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
                     mult = 1;
                 } else if (NC <= 4 && !H.temporal) {
                     // (plans with more closing edges keep the general path's registers)
-                    mult = closed_mult<NC>(g, P, in, r, lv, H.n_close, st, w, K.probes);
+                    mult = closed_mult<NC>(g, pl, in, r, lv, H.n_close, st, w, K.probes);
                     if (mult == 1) w |= CK_ONE;  // pass 2 writes the one embedding from the row
                 } else {
                     Bind B;
@@ -1522,7 +1558,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
                     for (uint32_t c = 0; c < NA; c++)
                         if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
-                            st[c] = rcol(in, 1 + in.wv + load_close(P, c).qe, r);
+                            st[c] = rcol(in, 1 + in.wv + load_close(g.plans, pl, c).qe, r);
                     mult = close_mult<NC>(g, *P, B, st, K.probes, lv.qe, H.temporal ? g.keys(lv.dir)[p] : 0ull);
                 }
             }
@@ -1571,9 +1607,11 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
         const uint32_t loc = t < t1 ? s_loc[idx] : NO_LOC;
         if (loc == NO_LOC) continue;
         const uint32_t r = s_r[idx], w = s_w[idx], p = s_p[idx];
-        const SeedPlan* P = &g.plans[staged ? (uint32_t)s_pl[r - rlo] : rcol(in, 0, r)];
-        const LevelDesc lv = load_level(P, L);
-        const PlanHead H = plan_head(P);
+        const uint32_t pl = staged ? (uint32_t)s_pl[r - rlo] : rcol(in, 0, r);
+        const SeedPlan* P = &g.plans[pl];
+        LevelDesc lv;
+        PlanHead H;
+        plan_level(g.plans, pl, L, lv, H);
         const uint64_t akey = g.keys(lv.dir)[p];
         const bool last = L + 1 == H.n_levels;
         uint32_t st[NA];
@@ -1605,7 +1643,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
                     if (c < (uint32_t)NC && c >= lv.c_begin && c < lv.c_end) {
-                        const CloseDesc cd = load_close(P, c);
+                        const CloseDesc cd = load_close(g.plans, pl, c);
                         wcol(out, 1 + out.wv + cd.qe, dst, st[c]);
                         wkey(out, cd.qe, dst, close_word(g, cd, st[c], rcol(in, 1 + cd.other, r), w, K.probes));
                     }
@@ -1630,7 +1668,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
             } else if (NC > 0 && NC <= 4 && (w & CK_ONE)) {
                 const OutView& ov = po.outs[q];
                 const bool write = po.emit && pos < ov.cap[po.phase];
-                emit_closed_tuple<NC>(g, P, in, r, q, H.n_qe, lv, st, akey, ov.keys[po.phase] + pos * H.n_qe, write, K,
+                emit_closed_tuple<NC>(g, pl, in, r, q, H.n_qe, lv, st, akey, ov.keys[po.phase] + pos * H.n_qe, write, K,
                                       dA, dB);
             } else {
                 Bind B;
@@ -1644,7 +1682,7 @@ __global__ __launch_bounds__(BT, ex_min_waves(BT, NC)) void k_expand(GraphView g
 #pragma unroll
                 for (uint32_t c = 0; c < NA; c++)
                     if (c < (uint32_t)NC && c < H.n_close && !(c >= lv.c_begin && c < lv.c_end))
-                        st[c] = rcol(in, 1 + in.wv + load_close(P, c).qe, r);
+                        st[c] = rcol(in, 1 + in.wv + load_close(g.plans, pl, c).qe, r);
                 uint32_t unused = 0;
                 const uint64_t mult = close_mult<NC>(g, *P, B, st, unused, lv.qe, akey);
                 emit_tuples<NC>(g, *P, B, st, mult, lv.qe, akey, pos, po, K, dA, dB);
