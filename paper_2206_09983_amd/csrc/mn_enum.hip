@@ -1020,8 +1020,13 @@ __device__ inline void plan_level(const SeedPlan* plans, uint32_t pl, uint32_t L
         lv = __builtin_bit_cast(LevelDesc, load_uniform16(&P->lv[L]));
         H = plan_head_of(load_uniform16(P));
     } else {
-        lv = load_level(plans + pl, L);
-        H = plan_head(plans + pl);
+        // both loads issued before either is waited for: one asm takes all
+        // their words, so each stays one 16-byte load (see load_whole16)
+        uint4 a = *reinterpret_cast<const uint4*>(&plans[pl].lv[L]);
+        uint4 h = *reinterpret_cast<const uint4*>(plans + pl);
+        asm("" : "+v"(a.x), "+v"(a.y), "+v"(a.z), "+v"(a.w), "+v"(h.x), "+v"(h.y), "+v"(h.z), "+v"(h.w));
+        lv = __builtin_bit_cast(LevelDesc, a);
+        H = plan_head_of(h);
     }
 }
 
